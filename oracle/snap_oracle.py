@@ -1,0 +1,415 @@
+"""Plain FP64 CPU oracle for the SNAP finite-volume right-hand side.
+
+TEST INFRASTRUCTURE ONLY. This module is the correctness reference for the
+HIP library: only the test-suite, the smoke check and the benchmark's
+CPU-baseline leg may import it. It shares no code with the GPU path; the two
+meet only in the seeded inputs of the ``workloads`` module.
+
+It is written for readability, not speed: whole-array torch CPU operations in
+float64 (so that torch autograd yields the discrete adjoint), each step in
+the order the paper gives it:
+
+1. ghost cells from the boundary conditions (Sec. 5 names a solid lower
+   boundary and doubly periodic domains; the ghost-cell form is the reading
+   below);
+2. conserved -> primitive variables per cell (App. B, single-gas reduction
+   with passive tracers, gamma = gamma_d);
+3. per direction, fifth-order WENO reconstruction of the left and right face
+   states from primitive variables (Sec. 4.2, eq. weno5 and the stencil
+   equations for Q-/Q+ with m = 3), pressure and density reconstructed as
+   perturbations from the hydrostatic reference (Sec. 4.1);
+4. per face, the LMARS flux (Sec. 4.1, eqs. rp and ru);
+5. flux divergence and gravity body force (Sec. 4, eq. forward; Sec. 2,
+   momentum and total-energy equations);
+6. the three-stage TVD Runge-Kutta step (Sec. 4.3).
+
+Readings of points the paper leaves open (each also listed in the design
+notes of the repository):
+
+* WENO nonlinear weights: the classic Jiang-Shu form the paper cites,
+  alpha_k = d_k / (eps + beta_k)^2 with the Jiang-Shu smoothness
+  indicators; eps is an input (default 1e-6).
+* Reconstructed variables in every direction: rho' = rho - rhobar_k, u, v,
+  w, p' = p - pbar_k and tracer mass fractions; face values restore
+  rho = rhobar_f + rho', p = pbar_f + p' with the face reference for
+  z faces and the level reference for x/y faces.
+* LMARS averages: rho c -> (rho- + rho+)/2 * (c- + c+)/2, with c = sqrt(gamma p / rho)
+  from full face pressure and density.
+* LMARS pressure: perturbation pressure in every direction (for x/y faces
+  the level reference cancels exactly in the divergence); momentum source
+  -g (rho - rhobar_k), equal to -rho g plus the divergence of the
+  reference face pressure because rhobar_k is discretely hydrostatic.
+* LMARS upwinding: the advected vector (rho, rho u, rho v, rho w, E + p,
+  rho q) is taken from the left state when u* > 0, the right state when
+  u* < 0, and the mean of both when u* == 0.
+* Boundaries: periodic = wrap copy; reflecting = mirror of the conserved
+  state with the normal momentum negated.
+* Tracers are passive: p = (gamma - 1)(E - K).
+"""
+from __future__ import annotations
+
+import math
+from typing import Callable, Sequence
+
+import numpy as np
+import torch
+
+F64 = torch.float64
+G = 3
+BC_PERIODIC = 0
+BC_REFLECT = 1
+
+
+def _t(x) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(F64)
+    return torch.as_tensor(np.asarray(x, dtype=np.float64), dtype=F64)
+
+
+def _gy(grid) -> int:
+    return 0 if grid.ny == 1 else G
+
+
+def _axes(grid):
+    """Active sweep directions as (array axis, velocity component, spacing, bc, n).
+
+    Array axes of a field are (z, y, x) = (0, 1, 2). The y direction is
+    skipped for 2-D x-z problems (ny == 1).
+    """
+    out = [(2, 0, grid.dx, grid.bc[0], grid.nx)]
+    if grid.ny > 1:
+        out.append((1, 1, grid.dy, grid.bc[1], grid.ny))
+    out.append((0, 2, grid.dz, grid.bc[2], grid.nz))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Boundary conditions
+# ---------------------------------------------------------------------------
+
+def fill_ghosts(q: torch.Tensor, grid) -> torch.Tensor:
+    """Return a copy of the padded state with all ghost layers filled.
+
+    Periodic: ghost cell i takes the value of interior cell i mod n.
+    Reflecting: ghost cell at distance m outside a wall takes the value of
+    the interior cell at distance m inside it, with the momentum component
+    normal to the wall negated.
+    """
+    q = _t(q)
+    for arr_axis, comp, _, bc, n in _axes(grid):
+        ax = arr_axis + 1                       # axis in q (field axis first)
+        size = q.shape[ax]
+        g = (size - n) // 2
+        src = list(range(size))
+        sign = torch.ones(size, dtype=F64)
+        for m in range(g):
+            lo, hi = g - 1 - m, g + n + m
+            if bc == BC_PERIODIC:
+                src[lo] = g + (n - 1 - m) % n
+                src[hi] = g + m % n
+            else:
+                src[lo] = g + min(m, n - 1)
+                src[hi] = g + max(n - 1 - m, 0)
+                sign[lo] = -1.0
+                sign[hi] = -1.0
+        idx = torch.tensor(src, dtype=torch.long)
+        q = torch.index_select(q, ax, idx)
+        if bc == BC_REFLECT:
+            shp = [1] * q.dim()
+            shp[ax] = size
+            s = sign.reshape(shp)
+            normal = q[1 + comp:2 + comp] * s
+            q = torch.cat([q[:1 + comp], normal, q[2 + comp:]], dim=0)
+    return q
+
+
+# ---------------------------------------------------------------------------
+# Thermodynamics (App. B)
+# ---------------------------------------------------------------------------
+
+def cons_to_prim(q: torch.Tensor, grid) -> dict:
+    """Primitive variables of every cell of a padded state (App. B).
+
+    The evaluation order is fixed and shared in writing with the GPU path:
+    inv = 1/rho; u = (rho u) inv (likewise v, w); K = ((rho u) u + (rho v) v)
+    + (rho w) w, times 1/2; p = (gamma - 1)(E - K); p' = p - pbar_k;
+    rho' = rho - rhobar_k; q_i = rho_i inv.
+    """
+    rho, mx, my, mz, E = q[0], q[1], q[2], q[3], q[4]
+    inv = 1.0 / rho
+    u = mx * inv
+    v = my * inv
+    w = mz * inv
+    K = 0.5 * ((mx * u + my * v) + mz * w)
+    p = (grid.gamma - 1.0) * (E - K)
+    rbar = _t(grid.rhobar_cell).reshape(-1, 1, 1)
+    pbar = _t(grid.pbar_cell).reshape(-1, 1, 1)
+    prim = {"rho": rho, "u": u, "v": v, "w": w, "p": p,
+            "rp": rho - rbar, "pp": p - pbar,
+            "q": [q[5 + t] * inv for t in range(grid.ntracer)]}
+    return prim
+
+
+def prim_to_cons_energy(rho, u, v, w, p, gamma):
+    """Total energy of a single-gas parcel (App. B with A = 0): E = p/(gamma-1) + K."""
+    return p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+
+
+# ---------------------------------------------------------------------------
+# WENO5 reconstruction (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+LINEAR_WEIGHTS = (0.1, 0.6, 0.3)
+
+
+def weno5_substencils(a, b, c, d, e):
+    """The three third-order candidate values of eq. weno5.
+
+    Arguments are Q_{i-3}, Q_{i-2}, Q_{i-1}, Q_i, Q_{i+1}; the values
+    approximate the left state at face i-1/2.
+    """
+    q0 = (1.0 / 3.0) * a - (7.0 / 6.0) * b + (11.0 / 6.0) * c
+    q1 = -(1.0 / 6.0) * b + (5.0 / 6.0) * c + (1.0 / 3.0) * d
+    q2 = (1.0 / 3.0) * c + (5.0 / 6.0) * d - (1.0 / 6.0) * e
+    return q0, q1, q2
+
+
+def weno5_smoothness(a, b, c, d, e):
+    """Jiang-Shu smoothness indicators of the three candidate stencils.
+
+    beta_k is the sum over l = 1, 2 of the integral over the target cell of
+    h^(2l-1) (d^l p_k / dx^l)^2 for the quadratic p_k fitted to the cell
+    averages of candidate stencil k (the form the paper cites for the
+    weights); written out for uniform spacing.
+    """
+    b0 = (13.0 / 12.0) * (a - 2.0 * b + c) ** 2 + 0.25 * (a - 4.0 * b + 3.0 * c) ** 2
+    b1 = (13.0 / 12.0) * (b - 2.0 * c + d) ** 2 + 0.25 * (b - d) ** 2
+    b2 = (13.0 / 12.0) * (c - 2.0 * d + e) ** 2 + 0.25 * (3.0 * c - 4.0 * d + e) ** 2
+    return b0, b1, b2
+
+
+def weno5_weights(a, b, c, d, e, eps: float, linear: bool = False):
+    """Normalised convex weights (the paper's alpha_0..alpha_2 of eq. weno5)."""
+    if linear:
+        one = torch.ones_like(_t(a)) if isinstance(a, torch.Tensor) else 1.0
+        return tuple(wk * one for wk in LINEAR_WEIGHTS)
+    b0, b1, b2 = weno5_smoothness(a, b, c, d, e)
+    a0 = LINEAR_WEIGHTS[0] / (eps + b0) ** 2
+    a1 = LINEAR_WEIGHTS[1] / (eps + b1) ** 2
+    a2 = LINEAR_WEIGHTS[2] / (eps + b2) ** 2
+    s = a0 + a1 + a2
+    return a0 / s, a1 / s, a2 / s
+
+
+def weno5(a, b, c, d, e, eps: float = 1e-6, linear: bool = False):
+    """I_weno(Q_{i-3}, Q_{i-2}, Q_{i-1}, Q_i, Q_{i+1}): eq. weno5."""
+    q0, q1, q2 = weno5_substencils(a, b, c, d, e)
+    w0, w1, w2 = weno5_weights(a, b, c, d, e, eps, linear)
+    return w0 * q0 + w1 * q1 + w2 * q2
+
+
+def reconstruct_faces(v: torch.Tensor, axis: int, n: int, eps: float, linear: bool):
+    """Left and right states at the n+1 faces i-1/2 (i = 0..n) along ``axis``.
+
+    ``v`` is padded by G cells on both ends of ``axis``. The left state is
+    I(Q_{i-3}, ..., Q_{i+1}) and the right state I(Q_{i+2}, ..., Q_{i-2}),
+    the stencil equations of Sec. 4 with m = 3.
+    """
+    def sl(o):  # Q_{i+o} for i = 0..n, padded index G + i + o
+        return v.narrow(axis, G + o, n + 1)
+    left = weno5(sl(-3), sl(-2), sl(-1), sl(0), sl(1), eps, linear)
+    right = weno5(sl(2), sl(1), sl(0), sl(-1), sl(-2), eps, linear)
+    return left, right
+
+
+# ---------------------------------------------------------------------------
+# LMARS (Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def lmars_flux(L: dict, R: dict, normal: int, gamma: float, ntracer: int):
+    """LMARS numerical flux at a face from left/right primitive face states.
+
+    Each state holds full density ``rho``, velocity ``u``/``v``/``w``, full
+    pressure ``p``, perturbation pressure ``pp`` and tracer mass fractions
+    ``q``. Returns the flux of (rho, rho u, rho v, rho w, E, rho q_i).
+    """
+    vel = ("u", "v", "w")
+    unL, unR = L[vel[normal]], R[vel[normal]]
+    cL = torch.sqrt(gamma * L["p"] / L["rho"])
+    cR = torch.sqrt(gamma * R["p"] / R["rho"])
+    rho_avg = 0.5 * (L["rho"] + R["rho"])
+    c_avg = 0.5 * (cL + cR)
+    rc = rho_avg * c_avg
+    pstar = 0.5 * (L["pp"] + R["pp"]) - 0.5 * rc * (unR - unL)      # eq. rp
+    ustar = 0.5 * (unL + unR) - (R["pp"] - L["pp"]) / (2.0 * rc)    # eq. ru
+
+    def advected(S):
+        E = prim_to_cons_energy(S["rho"], S["u"], S["v"], S["w"], S["p"], gamma)
+        return ([S["rho"], S["rho"] * S["u"], S["rho"] * S["v"], S["rho"] * S["w"], E + S["p"]]
+                + [S["rho"] * qt for qt in S["q"]])
+
+    phiL, phiR = advected(L), advected(R)
+    flux = []
+    for m, (fl, fr) in enumerate(zip(phiL, phiR)):
+        up = torch.where(ustar > 0, fl, torch.where(ustar < 0, fr, 0.5 * (fl + fr)))
+        f = ustar * up
+        if m == 1 + normal:
+            f = f + pstar
+        flux.append(f)
+    return flux, pstar, ustar
+
+
+# ---------------------------------------------------------------------------
+# Right-hand side (Sec. 4, eq. forward)
+# ---------------------------------------------------------------------------
+
+def _interior_slices(grid, keep_axis: int):
+    """Slices selecting interior cells on every array axis except ``keep_axis``."""
+    gy = _gy(grid)
+    sl = [slice(G, G + grid.nz), slice(gy, gy + grid.ny), slice(G, G + grid.nx)]
+    sl[keep_axis] = slice(None)
+    return tuple(sl)
+
+
+def rhs_filled(qf: torch.Tensor, grid) -> torch.Tensor:
+    """Right-hand side of the interior cells from a state whose ghosts are filled.
+
+    Returns a tensor of shape (nvar, nz, ny, nx):
+    R = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d + body force.
+    """
+    qf = _t(qf)
+    prim = cons_to_prim(qf, grid)
+    names = ["rp", "u", "v", "w", "pp"]
+    nvar = grid.nvar
+    R = [torch.zeros((grid.nz, grid.ny, grid.nx), dtype=F64) for _ in range(nvar)]
+    eps, lin = grid.weno_eps, bool(grid.weno_linear)
+    for arr_axis, comp, h, _, n in _axes(grid):
+        sl = _interior_slices(grid, arr_axis)
+        fields = [prim[k][sl] for k in names] + [qt[sl] for qt in prim["q"]]
+        rec = [reconstruct_faces(f, arr_axis, n, eps, lin) for f in fields]
+        # reference values at the faces of this direction
+        if arr_axis == 0:
+            rref = _t(grid.rhobar_face).reshape(-1, 1, 1)
+            pref = _t(grid.pbar_face).reshape(-1, 1, 1)
+        else:
+            rref = _t(grid.rhobar_cell)[G:G + grid.nz].reshape(-1, 1, 1)
+            pref = _t(grid.pbar_cell)[G:G + grid.nz].reshape(-1, 1, 1)
+        states = []
+        for side in (0, 1):
+            S = {"rho": rref + rec[0][side], "u": rec[1][side], "v": rec[2][side],
+                 "w": rec[3][side], "pp": rec[4][side], "p": pref + rec[4][side],
+                 "q": [r[side] for r in rec[5:]]}
+            states.append(S)
+        flux, _, _ = lmars_flux(states[0], states[1], comp, grid.gamma, grid.ntracer)
+        for m in range(nvar):
+            F = flux[m]
+            dF = F.narrow(arr_axis, 1, n) - F.narrow(arr_axis, 0, n)
+            R[m] = R[m] - dF / h
+    # gravity along -z: momentum -g (rho - rhobar_k), energy -g (rho w)
+    isl = (slice(G, G + grid.nz), slice(_gy(grid), _gy(grid) + grid.ny), slice(G, G + grid.nx))
+    R[3] = R[3] - grid.grav * prim["rp"][isl]
+    R[4] = R[4] - grid.grav * qf[3][isl]
+    return torch.stack(R)
+
+
+def rhs(q, grid) -> torch.Tensor:
+    """Right-hand side (nvar, nz, ny, nx) of a padded state; ghosts filled first."""
+    return rhs_filled(fill_ghosts(_t(q), grid), grid)
+
+
+# ---------------------------------------------------------------------------
+# Time stepping (Sec. 4.3)
+# ---------------------------------------------------------------------------
+
+def _interior(q, grid):
+    gy = _gy(grid)
+    return q[:, G:G + grid.nz, gy:gy + grid.ny, G:G + grid.nx]
+
+
+def _with_interior(q, grid, new_interior):
+    gy = _gy(grid)
+    out = q.clone()
+    out[:, G:G + grid.nz, gy:gy + grid.ny, G:G + grid.nx] = new_interior
+    return out
+
+
+def rk3(rhs_fn: Callable[[torch.Tensor], torch.Tensor], y0: torch.Tensor, dt: float) -> torch.Tensor:
+    """Three-stage TVD Runge-Kutta step of Sec. 4.3 for a generic ODE y' = f(y)."""
+    y1 = y0 + dt * rhs_fn(y0)
+    y2 = 0.75 * y0 + 0.25 * (y1 + dt * rhs_fn(y1))
+    return (1.0 / 3.0) * y0 + (2.0 / 3.0) * (y2 + dt * rhs_fn(y2))
+
+
+def rk3_step(q, grid, dt: float) -> torch.Tensor:
+    """One SSP-RK3 step of the padded state; returns the new padded state.
+
+    The ghost layers of the result are filled from its interior.
+    """
+    q = _t(q)
+    qn = _interior(q, grid)
+
+    def f(y_int):
+        return rhs(_with_interior(q, grid, y_int), grid)
+
+    new = rk3(f, qn, dt)
+    return fill_ghosts(_with_interior(q, grid, new), grid)
+
+
+def run(q, grid, dt: float, nsteps: int) -> torch.Tensor:
+    for _ in range(nsteps):
+        q = rk3_step(q, grid, dt)
+    return q
+
+
+# ---------------------------------------------------------------------------
+# Time step and diagnostics
+# ---------------------------------------------------------------------------
+
+def cfl_dt(q, grid, cfl: float) -> float:
+    """dt = cfl / max over interior cells of sum_d (|u_d| + c) / dx_d."""
+    q = _interior(_t(q), grid)
+    rho, mx, my, mz, E = q[0], q[1], q[2], q[3], q[4]
+    inv = 1.0 / rho
+    u, v, w = mx * inv, my * inv, mz * inv
+    K = 0.5 * ((mx * u + my * v) + mz * w)
+    p = (grid.gamma - 1.0) * (E - K)
+    c = torch.sqrt(grid.gamma * p / rho)
+    s = (torch.abs(u) + c) / grid.dx
+    if grid.ny > 1:
+        s = s + (torch.abs(v) + c) / grid.dy
+    s = s + (torch.abs(w) + c) / grid.dz
+    bad = ~(rho > 0) | ~(p > 0) | ~torch.isfinite(s)
+    if bool(bad.any()):
+        raise FloatingPointError("non-positive or non-finite density or pressure")
+    return float(cfl / s.max())
+
+
+def conservation_sums(q, grid) -> np.ndarray:
+    """Plain sums over interior cells of every conserved field (float64)."""
+    qi = _interior(_t(q), grid)
+    return qi.reshape(grid.nvar, -1).sum(dim=1).numpy()
+
+
+# ---------------------------------------------------------------------------
+# Discrete adjoint (torch autograd through the oracle)
+# ---------------------------------------------------------------------------
+
+def rhs_adjoint(q, grid, rhs_bar) -> torch.Tensor:
+    """q_bar = J(q)^T rhs_bar for the interior cells (ghosts folded back).
+
+    Returns a tensor of shape (nvar, nz, ny, nx).
+    """
+    q = _t(q)
+    qi = _interior(q, grid).clone().requires_grad_(True)
+    r = rhs(_with_interior(q.detach(), grid, qi), grid)
+    (g,) = torch.autograd.grad(r, qi, _t(rhs_bar))
+    return g
+
+
+def rk3_step_adjoint(q, grid, dt: float, q_bar) -> torch.Tensor:
+    """dL/dQ^n from dL/dQ^{n+1} (interior arrays) through one RK3 step."""
+    q = _t(q)
+    qi = _interior(q, grid).clone().requires_grad_(True)
+    out = rk3_step(_with_interior(q.detach(), grid, qi), grid, dt)
+    (g,) = torch.autograd.grad(_interior(out, grid), qi, _t(q_bar))
+    return g

@@ -1,0 +1,97 @@
+"""Planted mistakes: each test plants one plausible error in the oracle (on the
+CPU, via monkeypatch) and checks that a pin of the oracle catches it."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import snap_oracle as O
+from tests import test_oracle_lmars as TL
+from tests import test_oracle_weno as TW
+
+
+def test_swapped_linear_weights_break_polynomial_exactness(monkeypatch):
+    assert max(TW._face_errors(4, linear=True)) < 1e-13
+    monkeypatch.setattr(O, "LINEAR_WEIGHTS", (0.3, 0.6, 0.1))
+    assert max(TW._face_errors(3, linear=True)) > 1e-6
+
+
+def test_wrong_smoothness_coefficient_breaks_jiang_shu_pin(monkeypatch):
+    orig = O.weno5_smoothness
+
+    def bad(a, b, c, d, e):
+        b0, b1, b2 = orig(a, b, c, d, e)
+        return b0 - (1.0 / 12.0) * (a - 2.0 * b + c) ** 2, b1, b2   # 13/12 -> 1
+    monkeypatch.setattr(O, "weno5_smoothness", bad)
+    with pytest.raises(AssertionError):
+        TW.test_smoothness_indicators_equal_jiang_shu_integrals()
+
+
+def test_wrong_substencil_breaks_fifth_order(monkeypatch):
+    orig = O.weno5_substencils
+
+    def bad(a, b, c, d, e):
+        q0, q1, q2 = orig(a, b, c, d, e)
+        return q0, q1, q2 + 1e-3 * (c - d)          # a small wrong term in one candidate
+    monkeypatch.setattr(O, "weno5_substencils", bad)
+    with pytest.raises(AssertionError):
+        TW.test_weno5_fifth_order_on_smooth_data()
+
+
+def test_flipped_pressure_term_in_ustar_breaks_riemann_pin(monkeypatch):
+    orig = O.lmars_flux
+
+    def bad(L, R, normal, gamma, ntracer):
+        L2, R2 = dict(L), dict(R)
+        # exchanging only the perturbation pressures flips the sign of the
+        # pressure-difference term of u*
+        L2["pp"], R2["pp"] = R["pp"], L["pp"]
+        return orig(L2, R2, normal, gamma, ntracer)
+    monkeypatch.setattr(O, "lmars_flux", bad)
+    with pytest.raises(AssertionError):
+        TL.test_lmars_star_state_matches_exact_riemann_to_second_order()
+
+
+def test_swapped_rk3_weights_break_amplification_pin(monkeypatch):
+    def bad(rhs_fn, y0, dt):
+        y1 = y0 + dt * rhs_fn(y0)
+        y2 = 0.25 * y0 + 0.75 * (y1 + dt * rhs_fn(y1))
+        return (1.0 / 3.0) * y0 + (2.0 / 3.0) * (y2 + dt * rhs_fn(y2))
+    monkeypatch.setattr(O, "rk3", bad)
+    from tests import test_oracle_rk3 as TR
+    with pytest.raises(AssertionError):
+        TR.test_amplification_polynomial_real()
+
+
+def test_unsigned_wall_mirror_breaks_mass_conservation(monkeypatch):
+    orig = O.fill_ghosts
+
+    def bad(q, grid):
+        qf = orig(q, grid).clone()
+        G, nz = O.G, grid.nz
+        for k in list(range(G)) + list(range(G + nz, 2 * G + nz)):
+            qf[3, k] = -qf[3, k]            # undo the sign flip of the wall-normal momentum
+        return qf
+    g, q = W.bubble_2d(nx=16, nz=16)
+    g.interior(q)[3] += 0.3 * g.interior(q)[0]        # flow towards the walls
+    s0 = O.conservation_sums(q, g)[0]
+    good = abs(O.conservation_sums(O.rk3_step(q, g, 0.3), g)[0] - s0) / s0
+    monkeypatch.setattr(O, "fill_ghosts", bad)
+    planted = abs(O.conservation_sums(O.rk3_step(q, g, 0.3), g)[0] - s0) / s0
+    assert good < 1e-14 and planted > 1e-6, (good, planted)
+
+
+def test_dropped_kinetic_energy_breaks_round_trip(monkeypatch):
+    orig = O.cons_to_prim
+
+    def bad(q, grid):
+        prim = orig(q, grid)
+        prim["p"] = (grid.gamma - 1.0) * q[4]
+        prim["pp"] = prim["p"] - O._t(grid.pbar_cell).reshape(-1, 1, 1)
+        return prim
+    monkeypatch.setattr(O, "cons_to_prim", bad)
+    from tests import test_oracle_eos_adjoint as TE
+    with pytest.raises(AssertionError):
+        TE.test_prim_cons_round_trip()

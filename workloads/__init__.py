@@ -1,0 +1,379 @@
+"""Seeded synthetic workloads for the SNAP finite-volume hot path.
+
+This module is shared by the CPU oracle and by the HIP path (tests and the
+benchmark). It holds the grid description, the hydrostatic base states and
+the seeded initial conditions, and nothing of the right-hand side itself:
+no reconstruction, no Riemann solver, no flux divergence, no time stepping.
+
+State layout (both sides): a float array ``q[nvar][nz+2G][ny+2Gy][nx+2G]``
+with x fastest, ``G = 3`` ghost layers (the 6-cell face stencil of the
+fifth-order reconstruction, Sec. 4, eqs. for Q-/Q+ with m = 3) and
+``Gy = 0`` when ``ny == 1`` (2-D x-z problems carry no y ghosts).
+Field order: (rho, rho*u, rho*v, rho*w, E, rho_tracer_1 .. rho_tracer_NT),
+the conserved vector of App. B with total density and total energy.
+
+Initial conditions are built from primitive fields with the single-gas
+energy relation E = p/(gamma-1) + rho*|u|^2/2 (App. B, passive-tracer
+reduction); gravity acts along -z.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+G = 3                      # ghost layers
+BC_PERIODIC = 0
+BC_REFLECT = 1
+MAX_TRACERS = 8
+RGAS = 8.314462618         # J / (mol K)
+
+
+@dataclasses.dataclass
+class Grid:
+    """Structured grid, physical constants and hydrostatic reference profiles.
+
+    ``rhobar_cell``/``pbar_cell`` have ``nz + 2G`` entries (ghost levels
+    included, mirrored for a reflecting z boundary and wrapped for a periodic
+    one); ``rhobar_face``/``pbar_face`` have ``nz + 1`` entries, index ``k``
+    being the face between levels ``k-1`` and ``k``.
+    """
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    gamma: float = 1.4
+    grav: float = 9.81
+    ntracer: int = 0
+    bc: Tuple[int, int, int] = (BC_PERIODIC, BC_PERIODIC, BC_REFLECT)
+    weno_eps: float = 1e-6
+    weno_linear: bool = False
+    rhobar_cell: Optional[np.ndarray] = None
+    pbar_cell: Optional[np.ndarray] = None
+    rhobar_face: Optional[np.ndarray] = None
+    pbar_face: Optional[np.ndarray] = None
+
+    @property
+    def nvar(self) -> int:
+        return 5 + self.ntracer
+
+    @property
+    def gy(self) -> int:
+        return 0 if self.ny == 1 else G
+
+    @property
+    def shape(self) -> Tuple[int, int, int, int]:
+        """Padded state shape (nvar, nz+2G, ny+2Gy, nx+2G)."""
+        return (self.nvar, self.nz + 2 * G, self.ny + 2 * self.gy, self.nx + 2 * G)
+
+    @property
+    def interior_shape(self) -> Tuple[int, int, int, int]:
+        return (self.nvar, self.nz, self.ny, self.nx)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def interior(self, q):
+        """View of the interior cells of a padded state array."""
+        gy = self.gy
+        return q[:, G:G + self.nz, gy:gy + self.ny, G:G + self.nx]
+
+    def copy(self, **kw) -> "Grid":
+        return dataclasses.replace(self, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Base states
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class DryIsentropic:
+    """Isentropic dry atmosphere: theta = theta0 everywhere, p = p0 at z = 0."""
+    theta0: float = 300.0
+    p0: float = 1.0e5
+    rd: float = 287.0
+    cp: float = 1004.5
+    grav: float = 9.81
+
+    def temperature(self, z):
+        return self.theta0 - (self.grav / self.cp) * np.asarray(z, dtype=np.float64)
+
+    def pressure(self, z):
+        return self.p0 * (self.temperature(z) / self.theta0) ** (self.cp / self.rd)
+
+    def density(self, z):
+        return self.pressure(z) / (self.rd * self.temperature(z))
+
+    def theta(self, z):
+        return np.full_like(np.asarray(z, dtype=np.float64), self.theta0)
+
+
+@dataclasses.dataclass
+class AdiabatIsothermal:
+    """Dry adiabat from (T0, p0) at z = 0 up to pressure p_top, isothermal above."""
+    t0: float
+    p0: float
+    p_top: float
+    rd: float
+    cp: float
+    grav: float
+
+    @property
+    def t_top(self) -> float:
+        return self.t0 * (self.p_top / self.p0) ** (self.rd / self.cp)
+
+    @property
+    def z_top(self) -> float:
+        return (self.t0 - self.t_top) * self.cp / self.grav
+
+    def temperature(self, z):
+        z = np.asarray(z, dtype=np.float64)
+        return np.where(z < self.z_top, self.t0 - (self.grav / self.cp) * z, self.t_top)
+
+    def pressure(self, z):
+        z = np.asarray(z, dtype=np.float64)
+        t = self.temperature(z)
+        p_ad = self.p0 * (np.maximum(t, self.t_top) / self.t0) ** (self.cp / self.rd)
+        h = self.rd * self.t_top / self.grav
+        p_iso = self.p_top * np.exp(-(z - self.z_top) / h)
+        return np.where(z < self.z_top, p_ad, p_iso)
+
+    def density(self, z):
+        return self.pressure(z) / (self.rd * self.temperature(z))
+
+    def theta(self, z):
+        return self.temperature(z) * (self.p0 / self.pressure(z)) ** (self.rd / self.cp)
+
+    def z_of_pressure(self, p):
+        """Height at which the base-state pressure equals ``p``."""
+        if p >= self.p_top:
+            t = self.t0 * (p / self.p0) ** (self.rd / self.cp)
+            return (self.t0 - t) * self.cp / self.grav
+        h = self.rd * self.t_top / self.grav
+        return self.z_top + h * math.log(self.p_top / p)
+
+
+def _pad_levels(interior: np.ndarray, bc_z: int) -> np.ndarray:
+    """Extend a per-level profile by G ghost levels: mirrored or wrapped."""
+    nz = interior.shape[0]
+    out = np.empty(nz + 2 * G, dtype=np.float64)
+    out[G:G + nz] = interior
+    for m in range(G):
+        if bc_z == BC_REFLECT:
+            out[G - 1 - m] = interior[min(m, nz - 1)]
+            out[G + nz + m] = interior[max(nz - 1 - m, 0)]
+        else:
+            out[G - 1 - m] = interior[(nz - 1 - m) % nz]
+            out[G + nz + m] = interior[m % nz]
+    return out
+
+
+def reference_profiles(base, nz: int, dz: float, grav: float, bc_z: int = BC_REFLECT):
+    """Hydrostatic reference profiles on the grid.
+
+    Face pressure and density are the analytic base state at face heights,
+    the cell pressure is the analytic value at the cell centre, and the cell
+    density is defined by the discrete hydrostatic balance of the two
+    bounding face pressures, (p_{k-1/2} - p_{k+1/2}) / (g dz), so that the
+    perturbation form of the vertical momentum flux with the source
+    -g (rho - rhobar_k) equals the full-pressure flux with the source
+    -rho g (Sec. 2, momentum equation; Sec. 4.1, perturbation pressure).
+    For g = 0 the cell density is the analytic value at the cell centre.
+    """
+    zf = np.arange(nz + 1, dtype=np.float64) * dz
+    zc = (np.arange(nz, dtype=np.float64) + 0.5) * dz
+    pf = base.pressure(zf)
+    rf = base.density(zf)
+    pc = base.pressure(zc)
+    if grav != 0.0:
+        rc = (pf[:-1] - pf[1:]) / (grav * dz)
+    else:
+        rc = base.density(zc)
+    return _pad_levels(rc, bc_z), _pad_levels(pc, bc_z), rf.copy(), pf.copy()
+
+
+def uniform_references(nz: int, rho0: float, p0: float):
+    return (np.full(nz + 2 * G, rho0), np.full(nz + 2 * G, p0),
+            np.full(nz + 1, rho0), np.full(nz + 1, p0))
+
+
+# ---------------------------------------------------------------------------
+# Initial conditions (host, FP64)
+# ---------------------------------------------------------------------------
+
+def state_from_primitives(grid: Grid, rho, u, v, w, p, tracers: Sequence = ()):
+    """Padded conserved state from interior primitive fields of shape (nz, ny, nx).
+
+    Ghost cells are left at zero: every library call fills them.
+    """
+    q = np.zeros(grid.shape, dtype=np.float64)
+    qi = grid.interior(q)
+    rho = np.broadcast_to(rho, (grid.nz, grid.ny, grid.nx))
+    qi[0] = rho
+    qi[1] = rho * u
+    qi[2] = rho * v
+    qi[3] = rho * w
+    qi[4] = p / (grid.gamma - 1.0) + 0.5 * rho * (np.asarray(u) ** 2 + np.asarray(v) ** 2 + np.asarray(w) ** 2)
+    for t, qt in enumerate(tracers):
+        qi[5 + t] = rho * qt
+    return q
+
+
+def rest_fields(grid: Grid):
+    """Hydrostatic rest: rho = cell reference density, p = cell reference pressure."""
+    rc = grid.rhobar_cell[G:G + grid.nz][:, None, None]
+    pc = grid.pbar_cell[G:G + grid.nz][:, None, None]
+    shp = (grid.nz, grid.ny, grid.nx)
+    return np.broadcast_to(rc, shp).copy(), np.broadcast_to(pc, shp).copy()
+
+
+def theta_perturbed_density(rho_ref, theta_ref, dtheta):
+    """Density after a potential-temperature perturbation at constant pressure.
+
+    At fixed p, rho is inversely proportional to T and hence to theta
+    (potential temperature, App. C).
+    """
+    return rho_ref * theta_ref / (theta_ref + dtheta)
+
+
+def cell_centres(n: int, d: float):
+    return (np.arange(n, dtype=np.float64) + 0.5) * d
+
+
+def bubble_dtheta(grid: Grid, amp: float, radius: float, xc: float, zc: float, yc: Optional[float] = None):
+    """Cosine-squared bubble: amp * cos^2(pi L / 2) for L = |x - xc| / radius <= 1."""
+    x = cell_centres(grid.nx, grid.dx)[None, None, :]
+    z = cell_centres(grid.nz, grid.dz)[:, None, None]
+    r2 = (x - xc) ** 2 + (z - zc) ** 2
+    if grid.ny > 1 and yc is not None:
+        y = cell_centres(grid.ny, grid.dy)[None, :, None]
+        r2 = r2 + (y - yc) ** 2
+    L = np.sqrt(r2) / radius
+    d = np.where(L <= 1.0, amp * np.cos(0.5 * np.pi * np.minimum(L, 1.0)) ** 2, 0.0)
+    return np.broadcast_to(d, (grid.nz, grid.ny, grid.nx)).copy()
+
+
+def dry_grid(nx, ny, nz, lx, ly, lz, bc=(BC_PERIODIC, BC_PERIODIC, BC_REFLECT),
+             base: Optional[DryIsentropic] = None, **kw) -> Tuple[Grid, DryIsentropic]:
+    base = base or DryIsentropic()
+    gamma = base.cp / (base.cp - base.rd)
+    grid = Grid(nx=nx, ny=ny, nz=nz, dx=lx / nx, dy=ly / ny, dz=lz / nz,
+                gamma=gamma, grav=base.grav, bc=tuple(bc), **kw)
+    rc, pc, rf, pf = reference_profiles(base, nz, grid.dz, base.grav, bc[2])
+    grid.rhobar_cell, grid.pbar_cell, grid.rhobar_face, grid.pbar_face = rc, pc, rf, pf
+    return grid, base
+
+
+def bubble_2d(nx=64, nz=64, lx=20e3, lz=10e3, amp=2.0, radius=2e3, zc=2e3, xc=None):
+    """2-D dry rising bubble on an x-z grid (periodic x, reflecting z)."""
+    grid, base = dry_grid(nx, 1, nz, lx, 1.0, lz, bc=(BC_PERIODIC, BC_PERIODIC, BC_REFLECT))
+    grid.dy = 1.0
+    rho, p = rest_fields(grid)
+    dth = bubble_dtheta(grid, amp, radius, lx / 2 if xc is None else xc, zc)
+    rho = theta_perturbed_density(rho, base.theta0, dth)
+    q = state_from_primitives(grid, rho, 0.0, 0.0, 0.0, p)
+    return grid, q
+
+
+def convection_3d(nx=256, ny=256, nz=128, lx=20e3, ly=20e3, lz=10e3, noise=0.1, nlev=10, seed=1):
+    """3-D dry convection: seeded uniform theta noise in the lowest levels."""
+    grid, base = dry_grid(nx, ny, nz, lx, ly, lz)
+    rho, p = rest_fields(grid)
+    rng = np.random.default_rng(seed)
+    dth = np.zeros((nz, ny, nx))
+    k = min(nlev, nz)
+    dth[:k] = rng.uniform(-noise, noise, size=(k, ny, nx))
+    rho = theta_perturbed_density(rho, base.theta0, dth)
+    q = state_from_primitives(grid, rho, 0.0, 0.0, 0.0, p)
+    return grid, q, dth
+
+
+JOVIAN_MU = 2.3e-3       # kg/mol
+JOVIAN_CP = 12400.0      # J/(kg K)
+JOVIAN_G = 24.79         # m/s^2
+
+
+def jovian_base() -> AdiabatIsothermal:
+    rd = RGAS / JOVIAN_MU
+    return AdiabatIsothermal(t0=800.0, p0=200e5, p_top=0.2e5, rd=rd, cp=JOVIAN_CP, grav=JOVIAN_G)
+
+
+def jovian_3d(nx=512, ny=512, nz=256, dxy=5.5e3, lz=400e3, seed_q=2, seed_theta=3,
+              condense_p=(7e5, 0.7e5), noise=0.1, nlev=10):
+    """3-D Jovian-like column: H2-He gas, two vapours and two (zero) clouds."""
+    base = jovian_base()
+    gamma = base.cp / (base.cp - base.rd)
+    grid = Grid(nx=nx, ny=ny, nz=nz, dx=dxy, dy=dxy, dz=lz / nz, gamma=gamma,
+                grav=base.grav, ntracer=4, bc=(BC_PERIODIC, BC_PERIODIC, BC_REFLECT))
+    rc, pc, rf, pf = reference_profiles(base, nz, grid.dz, base.grav, BC_REFLECT)
+    grid.rhobar_cell, grid.pbar_cell, grid.rhobar_face, grid.pbar_face = rc, pc, rf, pf
+    rho, p = rest_fields(grid)
+    zc = cell_centres(nz, grid.dz)
+    rng = np.random.default_rng(seed_q)
+    tr = []
+    for pc_ in condense_p:
+        zcond = base.z_of_pressure(pc_)
+        qv = 10.0 ** rng.uniform(-4.0, -2.0, size=(nz, ny, nx))
+        qv[zc >= zcond] = 0.0
+        tr.append(qv)
+    tr.append(np.zeros((nz, ny, nx)))
+    tr.append(np.zeros((nz, ny, nx)))
+    rng_t = np.random.default_rng(seed_theta)
+    dth = np.zeros((nz, ny, nx))
+    k = min(nlev, nz)
+    dth[:k] = rng_t.uniform(-noise, noise, size=(k, ny, nx))
+    th = base.theta(zc)[:, None, None]
+    rho = theta_perturbed_density(rho, th, dth)
+    q = state_from_primitives(grid, rho, 0.0, 0.0, 0.0, p, tr)
+    return grid, q
+
+
+ENSEMBLE_SIZES = ((128, 128), (256, 128), (384, 192), (512, 256))
+
+
+def ensemble_2d(n=64, seed=4, lx=20e3, lz=10e3, sizes=ENSEMBLE_SIZES):
+    """Ensemble of 2-D bubbles with seeded sizes, amplitudes and radii."""
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, len(sizes), size=n)
+    amps = rng.uniform(0.5, 3.0, size=n)
+    radii = rng.uniform(1e3, 3e3, size=n)
+    members = []
+    for m in range(n):
+        nx, nz = sizes[idx[m]]
+        members.append(bubble_2d(nx=nx, nz=nz, lx=lx, lz=lz, amp=float(amps[m]), radius=float(radii[m])))
+    return members
+
+
+def random_smooth_state(grid: Grid, seed: int, amp_rho=0.02, amp_u=5.0, amp_p=50.0, amp_q=1e-3):
+    """Seeded smooth-plus-noise perturbation of hydrostatic rest, all fields active.
+
+    Used for parity cases where every term of the right-hand side is nonzero.
+    """
+    rng = np.random.default_rng(seed)
+    rho, p = rest_fields(grid)
+    shp = (grid.nz, grid.ny, grid.nx)
+    x = cell_centres(grid.nx, 1.0 / grid.nx)[None, None, :]
+    y = cell_centres(grid.ny, 1.0 / grid.ny)[None, :, None]
+    z = cell_centres(grid.nz, 1.0 / grid.nz)[:, None, None]
+
+    def field(scale):
+        ph = rng.uniform(0, 2 * np.pi, size=3)
+        smooth = np.sin(2 * np.pi * x + ph[0]) * np.cos(2 * np.pi * y + ph[1]) * np.sin(np.pi * z + ph[2])
+        return scale * (np.broadcast_to(smooth, shp) + 0.3 * rng.standard_normal(shp))
+
+    rho = rho * (1.0 + field(amp_rho))
+    u = field(amp_u)
+    v = field(amp_u) if grid.ny > 1 else np.zeros(shp)
+    w = field(amp_u)
+    p = p + field(amp_p)
+    trs = [np.abs(field(amp_q)) + amp_q for _ in range(grid.ntracer)]
+    return state_from_primitives(grid, rho, u, v, w, p, trs)
+
+
+def seeded_normal(shape, seed: int):
+    return np.random.default_rng(seed).standard_normal(shape)
