@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the WENO5 + LMARS SSP-RK3 step on one MI355X.
+
+Workload: 3-D dry convection, 256 x 256 x 128 cells (20 x 20 x 10 km), five
+conserved variables, isentropic 300 K hydrostatic base state, seeded uniform
+theta noise of +-0.1 K in the lowest 10 levels, periodic in x and y, rigid
+lids in z, CFL 0.9. One timed step = the CFL time step (one reduction over the
+state) + one three-stage SSP-RK3 step (three ghost fills + three fused stage
+kernels). The state lives in HBM before the timed region starts.
+
+The FP64 path is the headline (`value`); the FP32 form (FP32 storage and
+stencil arithmetic, FP64 reference state and E -> p inversion) runs on the
+same workload and is reported under `variants.f32`.
+
+Roofline of the dominant kernel (the fused stage kernel): algorithmic HBM
+bytes per launch = (8/3) * nvar * sizeof(element) * cells (stage 1 reads Q and
+writes Q1, stages 2 and 3 read Q_s and Q^n and write the next state; 8 state
+passes per step, averaged over the three launches), divided by the kernel's
+average launch duration from hipEvents recorded around every stage launch of
+the timed region on the launch stream.
+
+CPU baseline: the FP64 oracle (PyTorch CPU, all host threads of this process)
+on a bounded sample of the same workload: 2 SSP-RK3 steps of a 128 x 128 x 128
+column block cut from the same initial state (periodic in x and y).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s of WENO5+LMARS RK3 step (FP32 vs FP64), % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+NX, NY, NZ = 256, 256, 128
+CFL = 0.9
+
+
+def stage_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1901_02955_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(dtype_name: str):
+    """HBM bytes per stage launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs.
+
+    Returns None unless the counters were taken on the current kernel sources.
+    """
+    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("sources_digest") != stage_sources_digest():
+        return None
+    key = f"bytes_per_launch_{dtype_name}"
+    return float(vals[key]) if key in vals else None
+
+
+def run_gpu(dtype, steps: int, warmup: int):
+    import torch
+
+    import paper_1901_02955_amd as snap
+    import workloads as wl
+
+    grid, q, _ = wl.convection_3d(NX, NY, NZ)
+    dg = snap.device_grid(grid, dtype=dtype)
+    qd = torch.as_tensor(q).to(dtype).cuda().contiguous()
+    del q
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+    for _ in range(warmup):
+        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
+        snap.snap_rk3_step(dg, qd, dt, work)
+    torch.cuda.synchronize()
+    snap.snap_stage_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
+        snap.snap_rk3_step(dg, qd, dt, work)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, launches = snap.snap_stage_timing_read()
+    snap.snap_stage_timing_enable(False)
+    cells = NX * NY * NZ
+    esize = 8 if dtype == torch.float64 else 4
+    nvar = dg.nvar
+    bytes_per_launch = 8.0 / 3.0 * nvar * esize * cells
+    avg_launch_s = stage_ms / 1e3 / max(launches, 1)
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    name = "f64" if dtype == torch.float64 else "f32"
+    traffic = measured_traffic(name)
+    res = {
+        "value": cells * steps / elapsed,
+        "ms_per_step": elapsed / steps * 1e3,
+        "stage_kernel_avg_ms": avg_launch_s * 1e3,
+        "stage_launches": launches,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "final_dt": dt,
+    }
+    del qd, work, cw
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_cpu_baseline():
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as wl
+
+    nthreads = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        nthreads = min(nthreads, int(env))
+    torch.set_num_threads(nthreads)
+    grid, q, _ = wl.convection_3d(NX, NY, NZ)
+    b = 128
+    sub = grid.copy(nx=b, ny=b)
+    qs = np.zeros(sub.shape)
+    G = wl.G
+    sub.interior(qs)[...] = grid.interior(q)[:, :, :b, :b]
+    del q
+    dt = oracle.cfl_dt(qs, sub, CFL)
+    nsteps = 2
+    t0 = time.perf_counter()
+    oracle.run(qs, sub, dt, nsteps)
+    el = time.perf_counter() - t0
+    return {
+        "value": b * b * NZ * nsteps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": f"{nsteps} SSP-RK3 steps (FP64) of a {b}x{b}x{NZ} column block cut from the "
+                  f"same initial state, periodic in x and y ({el:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the hot path is a single-GPU kernel here; "
+              "run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    f64 = run_gpu(torch.float64, args.steps, args.warmup)
+    out = {
+        "metric": METRIC,
+        "value": f64["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3-D dry convection 256x256x128 (20x20x10 km), FP64, 5 conserved vars, "
+                        "periodic x/y, rigid lids, CFL 0.9 (dt per step), WENO5+LMARS, SSP-RK3",
+            "nx": NX, "ny": NY, "nz": NZ, "nvar": 5, "cfl": CFL,
+        },
+        "roofline": f64["roofline"],
+        "stage_kernel_avg_ms": f64["stage_kernel_avg_ms"],
+    }
+    if not args.no_f32:
+        f32 = run_gpu(torch.float32, args.steps, args.warmup)
+        out["variants"] = {"f32": {
+            "value": f32["value"], "ms_per_step": f32["ms_per_step"], "dtype": "f32",
+            "stage_kernel_avg_ms": f32["stage_kernel_avg_ms"], "roofline": f32["roofline"],
+        }}
+        out["f32_speedup"] = f32["value"] / f64["value"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

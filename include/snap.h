@@ -1,0 +1,202 @@
+/*
+ * libsnap: C-ABI of the SNAP finite-volume hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The library advances the compressible Euler equations with total energy as
+ * the prognostic variable and passive tracer densities (Li & Chen, "Simulating
+ * Non-hydrostatic atmospheres on Planets", Sec. 2 and App. B): a conserved state
+ * Y = (rho, rho u, rho v, rho w, E, rho_1 .. rho_NT) on a collocated structured
+ * grid (Sec. 4, eq. forward), fifth-order WENO reconstruction of primitive
+ * variables at cell faces (Sec. 4.2, eq. weno5), the LMARS face flux (Sec. 4.1,
+ * eqs. rp and ru), the flux divergence and the gravity body force (Sec. 4, eq.
+ * forward), and the three-stage TVD Runge-Kutta step (Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers are DEVICE pointers unless an argument is documented as host memory.
+ * The caller owns and allocates every buffer; the library never allocates or
+ * frees device memory. Scratch memory comes in through `work`, sized by
+ * snap_workspace_bytes() for the matching operation.
+ *
+ * State layout: q[nvar][nz + 2 ng][ny + 2 gy][nx + 2 ng], x fastest, ng = 3
+ * ghost layers (the six-cell face stencil of the fifth-order reconstruction,
+ * Sec. 4, stencil equations for Q- and Q+ with m = 3), gy = ng for 3-D and
+ * gy = 0 when ny == 1 (2-D x-z problems have no y ghosts and no y sweep).
+ * Field order: rho, rho*u, rho*v, rho*w, E, then ntracer tracer densities.
+ * Element type: double for SNAP_F64, float for SNAP_F32.
+ *
+ * Ghost layers of q are library scratch: every call that reads q overwrites
+ * them from the interior according to `bc`. Interior cells of q are read-only
+ * except in the time-stepping calls.
+ *
+ * Calls are asynchronous on `stream` (a hipStream_t, NULL = default stream),
+ * except snap_cfl_dt and snap_conservation_sums, which return host values and
+ * synchronise that stream. Validation of every argument happens on the host
+ * before any HIP call: an invalid call returns SNAP_E_INVALID and touches no
+ * device state. A failed HIP call returns SNAP_E_DEVICE. The message of the
+ * last error of the calling thread is returned by snap_last_error().
+ */
+#ifndef SNAP_H
+#define SNAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SNAP_ABI_VERSION 1
+
+/* return codes */
+#define SNAP_OK 0
+#define SNAP_E_INVALID (-1)     /* bad argument, detected on the host before any HIP call */
+#define SNAP_E_UNSUPPORTED (-2) /* e.g. ntracer > SNAP_MAX_TRACERS */
+#define SNAP_E_DEVICE (-3)      /* a HIP launch or runtime call failed */
+#define SNAP_E_STATE (-4)       /* non-finite or non-positive density or pressure found */
+
+/* element types */
+#define SNAP_F64 0
+#define SNAP_F32 1
+
+/* boundary conditions per axis */
+#define SNAP_BC_PERIODIC 0 /* ghost cell i takes interior cell i mod n */
+#define SNAP_BC_REFLECT 1  /* mirror of the conserved state, normal momentum negated */
+
+#define SNAP_NG 3
+#define SNAP_MAX_TRACERS 8
+
+/* operations for snap_workspace_bytes */
+#define SNAP_OP_RHS 0
+#define SNAP_OP_RK3 1
+#define SNAP_OP_CFL 2
+#define SNAP_OP_SUMS 3
+#define SNAP_OP_RHS_ADJ 4
+#define SNAP_OP_RK3_ADJ 5
+
+/*
+ * Grid, physical constants and hydrostatic reference profiles.
+ *
+ * nx, ny, nz     interior cells, each >= 1; ny == 1 selects a 2-D x-z problem.
+ * ng             must be SNAP_NG.
+ * ntracer        passive tracer densities, 0 .. SNAP_MAX_TRACERS; nvar = 5 + ntracer.
+ *                Tracers do not enter the equation of state: with no condensate
+ *                mass and vapour gas constants equal to the dry one the mixture
+ *                relation of App. B reduces to p = (gamma - 1)(E - K).
+ * dtype          SNAP_F64 or SNAP_F32 element type of q, rhs and work.
+ * bc[3]          boundary condition of the x, y and z axes (bc[1] ignored in 2-D).
+ * weno_linear    1 = linear weights (0.1, 0.6, 0.3) of Sec. 4.2 (fifth-order
+ *                polynomial reconstruction), 0 = nonlinear Jiang-Shu weights.
+ * dx, dy, dz     cell sizes in metres, > 0 (dy ignored in 2-D).
+ * gamma          ratio of specific heats, > 1.
+ * grav           gravitational acceleration >= 0, acting along -z.
+ * weno_eps       regulariser of the nonlinear weights, > 0 (1e-6 is customary).
+ * rhobar_cell,   DEVICE, nz + 2 ng doubles each: reference density and pressure
+ * pbar_cell      of every level, ghost levels included (the caller mirrors them
+ *                for a reflecting z axis and wraps them for a periodic one).
+ * rhobar_face,   DEVICE, nz + 1 doubles each: reference density and pressure at
+ * pbar_face      the z faces; index k is the face between levels k-1 and k.
+ *
+ * Density and pressure are reconstructed as perturbations rho - rhobar and
+ * p - pbar of the level (the vertical perturbation pressure of Sec. 4.1); face
+ * values add back the face reference on z faces and the level reference on x
+ * and y faces. The gravity source is -g (rho - rhobar_k) on vertical momentum
+ * and -g rho w on energy, which equals the full-pressure form when rhobar_k is
+ * the discretely hydrostatic (pbar_{k-1/2} - pbar_{k+1/2}) / (g dz).
+ */
+typedef struct snap_grid {
+  int32_t nx, ny, nz;
+  int32_t ng;
+  int32_t ntracer;
+  int32_t dtype;
+  int32_t bc[3];
+  int32_t weno_linear;
+  double dx, dy, dz;
+  double gamma, grav;
+  double weno_eps;
+  const double* rhobar_cell;
+  const double* pbar_cell;
+  const double* rhobar_face;
+  const double* pbar_face;
+} snap_grid;
+
+/* Thread-local message of the last failed call of this thread ("" if none). */
+const char* snap_last_error(void);
+
+/* SNAP_ABI_VERSION of the loaded library. */
+int snap_abi_version(void);
+
+/*
+ * Bytes of device workspace `work` needed by operation `op` (SNAP_OP_*) on grid
+ * g; 0 if none is needed. Returns 0 and sets the last error for an invalid grid.
+ * SNAP_OP_RK3 needs two padded state arrays, SNAP_OP_CFL and SNAP_OP_SUMS a few
+ * hundred kilobytes of reduction partials.
+ */
+size_t snap_workspace_bytes(const snap_grid* g, int op);
+
+/*
+ * Fill the ghost layers of q (padded layout, dtype of g) from its interior
+ * according to g->bc: periodic = wrap copy; reflecting = mirror image of the
+ * conserved state with the momentum component normal to the wall negated
+ * (boundary conditions named in Sec. 5; the ghost-cell form is this library's
+ * reading). Corner ghosts take the composition of the per-axis maps.
+ */
+int snap_fill_ghosts(const snap_grid* g, void* q, void* stream);
+
+/*
+ * Right-hand side of the semi-discrete system (Sec. 4, eq. forward with the
+ * Riemann flux of Sec. 4.1 and the reconstruction of Sec. 4.2):
+ *   rhs = -sum_d (F_{+1/2} - F_{-1/2}) / dx_d + body force
+ * for every interior cell.
+ * q    padded state (ghosts overwritten, interior read).
+ * rhs  interior array rhs[nvar][nz][ny][nx], x fastest, overwritten.
+ */
+int snap_rhs(const snap_grid* g, void* q, void* rhs, void* stream);
+
+/*
+ * One three-stage TVD Runge-Kutta step (Sec. 4.3) of the full multi-direction
+ * right-hand side with a fixed time step dt (host value, finite and > 0):
+ *   Q1 = Q + dt R(Q); Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1));
+ *   Q <- 1/3 Q + 2/3 (Q2 + dt R(Q2)).
+ * q     padded state: interior in = Q^n, interior out = Q^{n+1}; ghost layers on
+ *       return are unspecified (snap_fill_ghosts refreshes them).
+ * work  device workspace of snap_workspace_bytes(g, SNAP_OP_RK3) bytes.
+ */
+int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stream);
+
+/*
+ * Largest stable step dt = cfl / max over interior cells of
+ *   sum_d (|u_d| + c) / dx_d,  c = sqrt(gamma p / rho)
+ * (the time-step rule is this library's reading; the paper gives none).
+ * dt_host  HOST pointer receiving dt. The call synchronises `stream`.
+ * Returns SNAP_E_STATE (and leaves *dt_host untouched) if any interior cell has
+ * a non-finite or non-positive density or pressure.
+ * work  device workspace of snap_workspace_bytes(g, SNAP_OP_CFL) bytes.
+ */
+int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_host, void* stream);
+
+/*
+ * Sums over interior cells of every conserved field, accumulated in double
+ * precision in a fixed order (mass and total energy are conserved by the
+ * flux form, Sec. 4, eq. forward).
+ * sums_host  HOST array of nvar doubles. The call synchronises `stream`.
+ * work  device workspace of snap_workspace_bytes(g, SNAP_OP_SUMS) bytes.
+ */
+int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums_host, void* stream);
+
+/*
+ * Benchmark instrumentation of the fused stage kernel (the kernel that
+ * evaluates the right-hand side and applies one Runge-Kutta stage).
+ * snap_stage_timing_enable(1) discards earlier records and brackets every later
+ * stage-kernel launch with two hipEvents recorded on the launch stream;
+ * snap_stage_timing_enable(0) stops recording. snap_stage_timing_read waits for
+ * the recorded events and returns, in HOST memory, the summed duration in
+ * milliseconds and the number of timed launches. Process-wide, thread-safe.
+ */
+int snap_stage_timing_enable(int enable);
+int snap_stage_timing_read(double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNAP_H */

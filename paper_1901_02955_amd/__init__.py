@@ -1,0 +1,262 @@
+"""MI355X-native SNAP hot path: thin ctypes binding of the libsnap C-ABI.
+
+Every function here marshals arguments and calls the library entry point of
+the same name (``include/snap.h``); all arithmetic runs in the HIP kernels.
+PyTorch supplies device memory and the current HIP stream only. There is no
+fallback: if the library cannot be loaded or a call fails, a ``SnapError`` is
+raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+__all__ = [
+    "SnapError", "DeviceGrid", "device_grid", "lib", "workspace",
+    "snap_fill_ghosts", "snap_rhs", "snap_rk3_step", "snap_cfl_dt",
+    "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
+    "snap_stage_timing_enable", "snap_stage_timing_read",
+    "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
+    "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
+]
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsnap.so")
+
+SNAP_OK = 0
+SNAP_E_INVALID = -1
+SNAP_E_UNSUPPORTED = -2
+SNAP_E_DEVICE = -3
+SNAP_E_STATE = -4
+SNAP_F64 = 0
+SNAP_F32 = 1
+SNAP_BC_PERIODIC = 0
+SNAP_BC_REFLECT = 1
+SNAP_NG = 3
+SNAP_MAX_TRACERS = 8
+SNAP_OP_RHS = 0
+SNAP_OP_RK3 = 1
+SNAP_OP_CFL = 2
+SNAP_OP_SUMS = 3
+SNAP_OP_RHS_ADJ = 4
+SNAP_OP_RK3_ADJ = 5
+
+_ERROR_NAMES = {
+    SNAP_E_INVALID: "SNAP_E_INVALID", SNAP_E_UNSUPPORTED: "SNAP_E_UNSUPPORTED",
+    SNAP_E_DEVICE: "SNAP_E_DEVICE", SNAP_E_STATE: "SNAP_E_STATE",
+}
+
+
+class SnapError(RuntimeError):
+    """A libsnap call returned an error code."""
+
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class SnapGridC(ctypes.Structure):
+    """Mirror of ``snap_grid`` in include/snap.h."""
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("ng", ctypes.c_int32), ("ntracer", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 3), ("weno_linear", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("grav", ctypes.c_double), ("weno_eps", ctypes.c_double),
+        ("rhobar_cell", ctypes.c_void_p), ("pbar_cell", ctypes.c_void_p),
+        ("rhobar_face", ctypes.c_void_p), ("pbar_face", ctypes.c_void_p),
+    ]
+
+
+_P = ctypes.c_void_p
+_GP = ctypes.POINTER(SnapGridC)
+_SIGNATURES = {
+    "snap_last_error": (ctypes.c_char_p, []),
+    "snap_abi_version": (ctypes.c_int, []),
+    "snap_workspace_bytes": (ctypes.c_size_t, [_GP, ctypes.c_int]),
+    "snap_fill_ghosts": (ctypes.c_int, [_GP, _P, _P]),
+    "snap_rhs": (ctypes.c_int, [_GP, _P, _P, _P]),
+    "snap_rk3_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P]),
+    "snap_cfl_dt": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "snap_stage_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "snap_stage_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsnap.so (building it first only if it is absent)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                from . import build as _build
+                _build.build()
+            handle = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGNATURES.items():
+                fn = getattr(handle, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = handle
+        return _lib
+
+
+def _check(code: int):
+    if code != SNAP_OK:
+        raise SnapError(code, lib().snap_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class DeviceGrid:
+    """A ``snap_grid`` plus device copies of its reference profiles.
+
+    Built from plain values; ``device_grid`` builds one from any object with
+    the same attribute names (nx, ny, nz, dx, dy, dz, gamma, grav, ntracer, bc,
+    weno_eps, weno_linear, rhobar_cell, pbar_cell, rhobar_face, pbar_face).
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
+                 gamma: float, grav: float, ntracer: int, bc: Sequence[int],
+                 weno_eps: float, weno_linear: bool, rhobar_cell, pbar_cell,
+                 rhobar_face, pbar_face, dtype: torch.dtype = torch.float64,
+                 device: Optional[torch.device] = None):
+        if dtype not in (torch.float64, torch.float32):
+            raise ValueError("dtype must be torch.float64 or torch.float32")
+        device = torch.device(device or "cuda")
+        self.device = device
+        self.dtype = dtype
+        self.nx, self.ny, self.nz, self.ntracer = int(nx), int(ny), int(nz), int(ntracer)
+        refs = []
+        for arr in (rhobar_cell, pbar_cell, rhobar_face, pbar_face):
+            t = torch.as_tensor(np.ascontiguousarray(np.asarray(arr, dtype=np.float64)))
+            refs.append(t.to(device))
+        self._refs = refs
+        c = SnapGridC()
+        c.nx, c.ny, c.nz, c.ng = self.nx, self.ny, self.nz, SNAP_NG
+        c.ntracer = self.ntracer
+        c.dtype = SNAP_F64 if dtype == torch.float64 else SNAP_F32
+        for d in range(3):
+            c.bc[d] = int(bc[d])
+        c.weno_linear = 1 if weno_linear else 0
+        c.dx, c.dy, c.dz = float(dx), float(dy), float(dz)
+        c.gamma, c.grav, c.weno_eps = float(gamma), float(grav), float(weno_eps)
+        c.rhobar_cell, c.pbar_cell, c.rhobar_face, c.pbar_face = (r.data_ptr() for r in refs)
+        self.c = c
+
+    @property
+    def nvar(self) -> int:
+        return 5 + self.ntracer
+
+    @property
+    def gy(self) -> int:
+        return 0 if self.ny == 1 else SNAP_NG
+
+    @property
+    def shape(self):
+        return (self.nvar, self.nz + 2 * SNAP_NG, self.ny + 2 * self.gy, self.nx + 2 * SNAP_NG)
+
+    @property
+    def interior_shape(self):
+        return (self.nvar, self.nz, self.ny, self.nx)
+
+    def ptr(self):
+        return ctypes.byref(self.c)
+
+    def _check_state(self, q: torch.Tensor, name: str = "q", shape=None):
+        shape = tuple(shape or self.shape)
+        if not isinstance(q, torch.Tensor) or q.device.type != "cuda":
+            raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+        if q.dtype != self.dtype:
+            raise ValueError(f"{name} has dtype {q.dtype}, grid expects {self.dtype}")
+        if tuple(q.shape) != shape or not q.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {shape}, got {tuple(q.shape)}")
+
+
+def device_grid(g, dtype: torch.dtype = torch.float64, device=None) -> DeviceGrid:
+    return DeviceGrid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.gamma, g.grav, g.ntracer, g.bc,
+                      g.weno_eps, g.weno_linear, g.rhobar_cell, g.pbar_cell, g.rhobar_face,
+                      g.pbar_face, dtype=dtype, device=device)
+
+
+def snap_abi_version() -> int:
+    return int(lib().snap_abi_version())
+
+
+def snap_workspace_bytes(grid: DeviceGrid, op: int) -> int:
+    n = int(lib().snap_workspace_bytes(grid.ptr(), int(op)))
+    err = lib().snap_last_error().decode()
+    if n == 0 and err:
+        raise SnapError(SNAP_E_INVALID, err)
+    return n
+
+
+def workspace(grid: DeviceGrid, op: int) -> torch.Tensor:
+    """Device workspace tensor (uint8) for operation ``op``."""
+    n = snap_workspace_bytes(grid, op)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=grid.device)
+
+
+def snap_fill_ghosts(grid: DeviceGrid, q: torch.Tensor, stream=None) -> None:
+    grid._check_state(q)
+    _check(lib().snap_fill_ghosts(grid.ptr(), ctypes.c_void_p(q.data_ptr()), _stream(stream)))
+
+
+def snap_rhs(grid: DeviceGrid, q: torch.Tensor, rhs: torch.Tensor, stream=None) -> None:
+    grid._check_state(q)
+    grid._check_state(rhs, "rhs", grid.interior_shape)
+    _check(lib().snap_rhs(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
+                          ctypes.c_void_p(rhs.data_ptr()), _stream(stream)))
+
+
+def snap_rk3_step(grid: DeviceGrid, q: torch.Tensor, dt: float, work: torch.Tensor,
+                  stream=None) -> None:
+    grid._check_state(q)
+    if work.numel() < snap_workspace_bytes(grid, SNAP_OP_RK3):
+        raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3)")
+    _check(lib().snap_rk3_step(grid.ptr(), ctypes.c_void_p(q.data_ptr()), ctypes.c_double(dt),
+                               ctypes.c_void_p(work.data_ptr()), _stream(stream)))
+
+
+def snap_cfl_dt(grid: DeviceGrid, q: torch.Tensor, cfl: float, work: torch.Tensor,
+                stream=None) -> float:
+    grid._check_state(q)
+    out = ctypes.c_double(0.0)
+    _check(lib().snap_cfl_dt(grid.ptr(), ctypes.c_void_p(q.data_ptr()), ctypes.c_double(cfl),
+                             ctypes.c_void_p(work.data_ptr()), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def snap_conservation_sums(grid: DeviceGrid, q: torch.Tensor, work: torch.Tensor,
+                           stream=None) -> np.ndarray:
+    grid._check_state(q)
+    out = (ctypes.c_double * grid.nvar)()
+    _check(lib().snap_conservation_sums(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
+                                        ctypes.c_void_p(work.data_ptr()), out, _stream(stream)))
+    return np.array(out[:], dtype=np.float64)
+
+
+def snap_stage_timing_enable(enable: bool) -> None:
+    _check(lib().snap_stage_timing_enable(1 if enable else 0))
+
+
+def snap_stage_timing_read():
+    """(summed milliseconds, number of launches) of the timed stage kernels."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().snap_stage_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,379 @@
+// C-ABI entry points of libsnap: argument validation, workspace layout and
+// kernel dispatch. Every argument is checked on the host before the first HIP
+// call, so an invalid call never touches the device.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/snap.h"
+#include "snap_internal.h"
+
+using namespace snap;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return SNAP_OK;
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+bool is3d(const snap_grid* g) { return g->ny > 1; }
+int nvar_of(const snap_grid* g) { return 5 + g->ntracer; }
+size_t elem_of(const snap_grid* g) { return g->dtype == SNAP_F64 ? 8 : 4; }
+
+long long padded_cells(const snap_grid* g) {
+  const long long nyp = is3d(g) ? g->ny + 2 * SNAP_NG : 1;
+  return (long long)(g->nx + 2 * SNAP_NG) * nyp * (g->nz + 2 * SNAP_NG);
+}
+
+size_t padded_bytes(const snap_grid* g) {
+  return (size_t)padded_cells(g) * nvar_of(g) * elem_of(g);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_grid(const snap_grid* g) {
+  if (!g) return fail(SNAP_E_INVALID, "grid pointer is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+    return fail(SNAP_E_INVALID, "grid sizes must be >= 1 (nx=%d ny=%d nz=%d)", g->nx, g->ny, g->nz);
+  if (g->nx > (1 << 24) || g->ny > (1 << 24) || g->nz > (1 << 24))
+    return fail(SNAP_E_INVALID, "grid size above 2^24 cells along an axis");
+  if (g->ng != SNAP_NG) return fail(SNAP_E_INVALID, "ng must be %d (got %d)", SNAP_NG, g->ng);
+  if (g->ntracer < 0) return fail(SNAP_E_INVALID, "ntracer must be >= 0 (got %d)", g->ntracer);
+  if (g->ntracer > SNAP_MAX_TRACERS)
+    return fail(SNAP_E_UNSUPPORTED, "ntracer %d exceeds %d", g->ntracer, SNAP_MAX_TRACERS);
+  if (g->dtype != SNAP_F64 && g->dtype != SNAP_F32)
+    return fail(SNAP_E_INVALID, "dtype must be SNAP_F64 or SNAP_F32 (got %d)", g->dtype);
+  for (int d = 0; d < 3; ++d) {
+    if (d == 1 && !is3d(g)) continue;
+    if (g->bc[d] != SNAP_BC_PERIODIC && g->bc[d] != SNAP_BC_REFLECT)
+      return fail(SNAP_E_INVALID, "bc[%d] must be periodic or reflecting (got %d)", d, g->bc[d]);
+  }
+  if (g->weno_linear != 0 && g->weno_linear != 1)
+    return fail(SNAP_E_INVALID, "weno_linear must be 0 or 1");
+  if (!finite_pos(g->dx) || !finite_pos(g->dz) || (is3d(g) && !finite_pos(g->dy)))
+    return fail(SNAP_E_INVALID, "cell sizes must be finite and > 0");
+  if (!isfinite(g->gamma) || !(g->gamma > 1.0))
+    return fail(SNAP_E_INVALID, "gamma must be finite and > 1");
+  if (!isfinite(g->grav) || !(g->grav >= 0.0))
+    return fail(SNAP_E_INVALID, "grav must be finite and >= 0");
+  if (!finite_pos(g->weno_eps)) return fail(SNAP_E_INVALID, "weno_eps must be finite and > 0");
+  if (!g->rhobar_cell || !g->pbar_cell || !g->rhobar_face || !g->pbar_face)
+    return fail(SNAP_E_INVALID, "reference profile pointer is NULL");
+  const double total = (double)padded_cells(g) * nvar_of(g);
+  if (total > 9.0e18 / 8.0) return fail(SNAP_E_INVALID, "state too large");
+  return SNAP_OK;
+}
+
+int device_fail(const char* what) {
+  const hipError_t e = hipGetLastError();
+  return fail(SNAP_E_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+StageArgs stage_args(const snap_grid* g) {
+  StageArgs a;
+  memset(&a, 0, sizeof a);
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG;
+  const long long nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.ry = g->nx;
+  a.rz = (long long)g->nx * g->ny;
+  a.rv = a.rz * g->nz;
+  a.dxi = 1.0 / g->dx;
+  a.dyi = d3 ? 1.0 / g->dy : 0.0;
+  a.dzi = 1.0 / g->dz;
+  a.gamma = g->gamma;
+  a.gm1 = g->gamma - 1.0;
+  a.inv_gm1 = 1.0 / (g->gamma - 1.0);
+  a.grav = g->grav;
+  a.eps = g->weno_eps;
+  a.linear = g->weno_linear;
+  a.rbar_c = g->rhobar_cell;
+  a.pbar_c = g->pbar_cell;
+  a.rbar_f = g->rhobar_face;
+  a.pbar_f = g->pbar_face;
+  return a;
+}
+
+// Tiling of the stage launch; returns the number of workgroups.
+int stage_tiling(const snap_grid* g, StageArgs& a) {
+  const bool d3 = is3d(g);
+  const TileShape t = g->dtype == SNAP_F64 ? tile_f64(nvar_of(g)) : tile_f32(nvar_of(g));
+  a.tiles_x = (g->nx + t.tx - 1) / t.tx;
+  if (!d3) {
+    a.tiles_y = (g->nz + t.ty - 1) / t.ty;
+    a.nchunk = 1;
+    a.tz = g->nz;
+    return a.tiles_x * a.tiles_y;
+  }
+  a.tiles_y = (g->ny + t.ty - 1) / t.ty;
+  const int tiles = a.tiles_x * a.tiles_y;
+  // enough workgroups to fill 256 CUs several times over; chunks of >= 8 levels
+  int nchunk = (2048 + tiles - 1) / tiles;
+  const int maxchunk = (g->nz + 7) / 8;
+  if (nchunk > maxchunk) nchunk = maxchunk;
+  if (nchunk < 1) nchunk = 1;
+  a.tz = (g->nz + nchunk - 1) / nchunk;
+  a.nchunk = (g->nz + a.tz - 1) / a.tz;
+  return tiles * a.nchunk;
+}
+
+// Optional timing of the stage kernels: while enabled, each stage launch is
+// bracketed by a pair of hipEvents recorded on the launch stream.
+struct StageTiming {
+  std::mutex m;
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // start, stop, start, stop, ...
+  size_t used = 0;
+};
+StageTiming g_timing;
+
+int timing_mark(hipStream_t st) {
+  if (g_timing.used == g_timing.ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return device_fail("hipEventCreate");
+    g_timing.ev.push_back(e);
+  }
+  if (hipEventRecord(g_timing.ev[g_timing.used], st) != hipSuccess)
+    return device_fail("hipEventRecord");
+  ++g_timing.used;
+  return SNAP_OK;
+}
+
+int run_stage(const snap_grid* g, StageArgs a, hipStream_t st) {
+  const int nb = stage_tiling(g, a);
+  std::unique_lock<std::mutex> lk(g_timing.m);
+  const bool timed = g_timing.on;
+  if (!timed) lk.unlock();
+  if (timed) {
+    const int r = timing_mark(st);
+    if (r) return r;
+  }
+  const int r = g->dtype == SNAP_F64 ? launch_stage_f64(g->ntracer, is3d(g), a, nb, st)
+                                     : launch_stage_f32(g->ntracer, is3d(g), a, nb, st);
+  if (r != 0) return device_fail("stage kernel launch");
+  if (timed) return timing_mark(st);
+  return SNAP_OK;
+}
+
+int fill(const snap_grid* g, void* q, hipStream_t st) {
+  GhostArgs a;
+  const bool d3 = is3d(g);
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.nxp = g->nx + 2 * SNAP_NG;
+  a.nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.d3 = d3;
+  a.nvar = nvar_of(g);
+  a.bcx = g->bc[0];
+  a.bcy = g->bc[1];
+  a.bcz = g->bc[2];
+  a.sy = a.nxp;
+  a.sz = (long long)a.nxp * a.nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  return launch_fill_ghosts(g->dtype, q, a, st) == 0 ? SNAP_OK : device_fail("ghost fill launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* snap_last_error(void) { return g_err.c_str(); }
+
+int snap_abi_version(void) { return SNAP_ABI_VERSION; }
+
+size_t snap_workspace_bytes(const snap_grid* g, int op) {
+  if (check_grid(g) != SNAP_OK) return 0;
+  switch (op) {
+    case SNAP_OP_RHS: return 0;
+    case SNAP_OP_RK3: return 2 * align256(padded_bytes(g));
+    case SNAP_OP_CFL: return 256;
+    case SNAP_OP_SUMS:
+      return align256((size_t)SUM_BLOCKS * nvar_of(g) * sizeof(double)) +
+             align256(nvar_of(g) * sizeof(double));
+    default: fail(SNAP_E_INVALID, "unknown workspace operation %d", op); return 0;
+  }
+}
+
+int snap_stage_timing_enable(int enable) {
+  std::lock_guard<std::mutex> lk(g_timing.m);
+  g_timing.on = enable != 0;
+  g_timing.used = 0;
+  return ok();
+}
+
+int snap_stage_timing_read(double* total_ms, int64_t* launches) {
+  if (!total_ms || !launches) return fail(SNAP_E_INVALID, "total_ms or launches is NULL");
+  std::lock_guard<std::mutex> lk(g_timing.m);
+  double sum = 0.0;
+  for (size_t i = 0; i + 1 < g_timing.used; i += 2) {
+    if (hipEventSynchronize(g_timing.ev[i + 1]) != hipSuccess)
+      return device_fail("hipEventSynchronize");
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, g_timing.ev[i], g_timing.ev[i + 1]) != hipSuccess)
+      return device_fail("hipEventElapsedTime");
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = (int64_t)(g_timing.used / 2);
+  return ok();
+}
+
+int snap_fill_ghosts(const snap_grid* g, void* q, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q) return fail(SNAP_E_INVALID, "q is NULL");
+  r = fill(g, q, (hipStream_t)stream);
+  return r ? r : ok();
+}
+
+int snap_rhs(const snap_grid* g, void* q, void* rhs, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !rhs) return fail(SNAP_E_INVALID, "q or rhs is NULL");
+  if (q == rhs) return fail(SNAP_E_INVALID, "rhs must not alias q");
+  const hipStream_t st = (hipStream_t)stream;
+  if ((r = fill(g, q, st))) return r;
+  StageArgs a = stage_args(g);
+  a.qs = q;
+  a.qn = nullptr;
+  a.out = rhs;
+  a.rhs_mode = 1;
+  if ((r = run_stage(g, a, st))) return r;
+  return ok();
+}
+
+int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q) return fail(SNAP_E_INVALID, "q is NULL");
+  if (!work) return fail(SNAP_E_INVALID, "work is NULL");
+  if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
+  const hipStream_t st = (hipStream_t)stream;
+  char* w = static_cast<char*>(work);
+  void* q1 = w;
+  void* q2 = w + align256(padded_bytes(g));
+  StageArgs a = stage_args(g);
+  a.dt = dt;
+  a.rhs_mode = 0;
+  // Q1 = Q + dt R(Q)
+  if ((r = fill(g, q, st))) return r;
+  a.qs = q;
+  a.qn = nullptr;
+  a.out = q1;
+  a.ca = 0.0;
+  a.cb = 1.0;
+  if ((r = run_stage(g, a, st))) return r;
+  // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1))
+  if ((r = fill(g, q1, st))) return r;
+  a.qs = q1;
+  a.qn = q;
+  a.out = q2;
+  a.ca = 0.75;
+  a.cb = 0.25;
+  if ((r = run_stage(g, a, st))) return r;
+  // Q <- 1/3 Q + 2/3 (Q2 + dt R(Q2)), in place (each cell reads only its own Q)
+  if ((r = fill(g, q2, st))) return r;
+  a.qs = q2;
+  a.qn = q;
+  a.out = q;
+  a.ca = 1.0 / 3.0;
+  a.cb = 2.0 / 3.0;
+  if ((r = run_stage(g, a, st))) return r;
+  return ok();
+}
+
+int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_host,
+                void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !work || !dt_host) return fail(SNAP_E_INVALID, "q, work or dt_host is NULL");
+  if (!finite_pos(cfl)) return fail(SNAP_E_INVALID, "cfl must be finite and > 0");
+  const hipStream_t st = (hipStream_t)stream;
+  CflArgs a;
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.d3 = d3;
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.gamma = g->gamma;
+  a.gm1 = g->gamma - 1.0;
+  a.dx = g->dx;
+  a.dy = g->dy;
+  a.dz = g->dz;
+  unsigned long long* dmax = static_cast<unsigned long long*>(work);
+  if (launch_cfl(g->dtype, q, a, dmax, st)) return device_fail("cfl kernel launch");
+  unsigned long long bits = 0;
+  if (hipMemcpyAsync(&bits, dmax, sizeof bits, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return device_fail("cfl copy");
+  if (hipStreamSynchronize(st) != hipSuccess) return device_fail("cfl synchronize");
+  double smax;
+  memcpy(&smax, &bits, sizeof smax);
+  if (bits >= 0x7FF0000000000000ULL || !(smax > 0.0))
+    return fail(SNAP_E_STATE, "non-finite or non-positive density or pressure in the state");
+  *dt_host = cfl / smax;
+  return ok();
+}
+
+int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums_host,
+                           void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !work || !sums_host) return fail(SNAP_E_INVALID, "q, work or sums_host is NULL");
+  const hipStream_t st = (hipStream_t)stream;
+  SumArgs a;
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.nvar = nvar_of(g);
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  double* part = static_cast<double*>(work);
+  double* out = reinterpret_cast<double*>(static_cast<char*>(work) +
+                                          align256((size_t)SUM_BLOCKS * a.nvar * sizeof(double)));
+  if (launch_sums(g->dtype, q, a, part, out, st)) return device_fail("sums kernel launch");
+  if (hipMemcpyAsync(sums_host, out, a.nvar * sizeof(double), hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
+    return device_fail("sums copy");
+  if (hipStreamSynchronize(st) != hipSuccess) return device_fail("sums synchronize");
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,210 @@
+// Ghost-cell fill, CFL time step and conservation sums.
+#include "snap_internal.h"
+
+namespace snap {
+
+// Source index along one axis for padded-coordinate index `idx` (interior
+// coordinates, ghosts outside [0, n)). Periodic: idx mod n. Reflecting: the
+// mirror image across the wall (clamped to the interior for n < 3).
+__device__ __forceinline__ int ghost_src(int idx, int n, int bc, bool& flip) {
+  flip = false;
+  if (idx >= 0 && idx < n) return idx;
+  if (bc == 0) return ((idx % n) + n) % n;
+  flip = true;
+  if (idx < 0) return min(-1 - idx, n - 1);
+  return max(2 * n - 1 - idx, 0);
+}
+
+// One thread per ghost cell; the ghost cells are enumerated as three disjoint
+// regions: z ghost levels (all y, x), y ghost rows of interior levels (all x),
+// x ghost columns of interior rows.
+template <typename T>
+__global__ void k_fill_ghosts(T* __restrict__ q, GhostArgs a) {
+  const long long nzr = 6LL * a.nyp * a.nxp;
+  const long long nyr = a.d3 ? (long long)a.nz * 6 * a.nxp : 0;
+  const long long nxr = (long long)a.nz * a.ny * 6;
+  const long long total = nzr + nyr + nxr;
+  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
+       g += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    if (g < nzr) {
+      const int ip = g % a.nxp;
+      const long long r = g / a.nxp;
+      const int jp = r % a.nyp;
+      const int kg = r / a.nyp;
+      i = ip - NG;
+      j = jp - a.gy;
+      k = kg < 3 ? kg - 3 : a.nz + kg - 3;
+    } else if (g < nzr + nyr) {
+      const long long h = g - nzr;
+      const int ip = h % a.nxp;
+      const long long r = h / a.nxp;
+      const int jg = r % 6;
+      k = r / 6;
+      i = ip - NG;
+      j = jg < 3 ? jg - 3 : a.ny + jg - 3;
+    } else {
+      const long long h = g - nzr - nyr;
+      const int ig = h % 6;
+      const long long r = h / 6;
+      j = r % a.ny;
+      k = r / a.ny;
+      i = ig < 3 ? ig - 3 : a.nx + ig - 3;
+    }
+    bool fx, fy = false, fz;
+    const int si = ghost_src(i, a.nx, a.bcx, fx);
+    const int sj = a.d3 ? ghost_src(j, a.ny, a.bcy, fy) : 0;
+    const int sk = ghost_src(k, a.nz, a.bcz, fz);
+    const long long dst = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+    const long long src = (long long)(sk + NG) * a.sz + (long long)(sj + a.gy) * a.sy + (si + NG);
+    for (int v = 0; v < a.nvar; ++v) {
+      T x = q[src + v * a.sv];
+      if ((v == 1 && fx) || (v == 2 && fy) || (v == 3 && fz)) x = -x;
+      q[dst + v * a.sv] = x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CFL: per-cell signal speed sum_d (|u_d| + c) / dx_d in double precision,
+// written with the same operation order as the conserved -> primitive
+// conversion, reduced to its maximum. A cell with rho <= 0 or p <= 0 (or NaN)
+// contributes NaN, whose bit pattern exceeds every finite double and +inf when
+// compared as an unsigned integer, so the reduction flags it.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ULL;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
+                                             unsigned long long* __restrict__ out) {
+  unsigned long long b = 0ULL;  // bit pattern of the running maximum
+  const long long n = (long long)a.nx * a.ny * a.nz;
+  for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
+    const int i = c % a.nx;
+    const long long r = c / a.nx;
+    const int j = r % a.ny;
+    const int k = r / a.ny;
+    const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+    double s;
+    {
+#pragma clang fp contract(off)
+      const double rho = q[o], mx = q[o + a.sv], my = q[o + 2 * a.sv], mz = q[o + 3 * a.sv];
+      const double E = q[o + 4 * a.sv];
+      const double inv = 1.0 / rho;
+      const double u = mx * inv, v = my * inv, w = mz * inv;
+      const double K = 0.5 * ((mx * u + my * v) + mz * w);
+      const double p = a.gm1 * (E - K);
+      const double cs = sqrt(a.gamma * p / rho);
+      s = (fabs(u) + cs) / a.dx;
+      if (a.d3) s = s + (fabs(v) + cs) / a.dy;
+      s = s + (fabs(w) + cs) / a.dz;
+      if (!(rho > 0.0) || !(p > 0.0)) s = __builtin_nan("");
+    }
+    const unsigned long long sb = (unsigned long long)__double_as_longlong(s);
+    b = sb > b ? sb : b;
+  }
+  // wave reduction of the unsigned bit patterns
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o2 = __shfl_xor(b, off, 64);
+    b = o2 > b ? o2 : b;
+  }
+  __shared__ unsigned long long red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long x = red[0];
+    for (int wv = 1; wv < 4; ++wv) x = red[wv] > x ? red[wv] : x;
+    atomicMax(out, x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Conservation sums: fixed grid of SUM_BLOCKS blocks, each summing a fixed
+// strided subset of the interior in double precision and reducing it with a
+// fixed tree; a single block then adds the partials in block order. The result
+// is therefore reproducible from run to run.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_sums_partial(const T* __restrict__ q, SumArgs a,
+                                                      double* __restrict__ part) {
+  __shared__ double red[256];
+  const long long n = (long long)a.nx * a.ny * a.nz;
+  for (int v = 0; v < a.nvar; ++v) {
+    double acc = 0.0;
+    for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
+      const int i = c % a.nx;
+      const long long r = c / a.nx;
+      const int j = r % a.ny;
+      const int k = r / a.ny;
+      const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+      acc += static_cast<double>(q[o + v * a.sv]);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)v * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_sums_final(const double* __restrict__ part, int nblk, int nvar,
+                             double* __restrict__ out) {
+  const int v = threadIdx.x;
+  if (v < nvar) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(long long)v * nblk + b];
+    out[v] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st) {
+  const long long total = 6LL * a.nyp * a.nxp + (a.d3 ? (long long)a.nz * 6 * a.nxp : 0) +
+                          (long long)a.nz * a.ny * 6;
+  long long nb = (total + 255) / 256;
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fill_ghosts<double>, dim3((unsigned)nb), dim3(256), 0, st,
+                       static_cast<double*>(q), a);
+  else
+    hipLaunchKernelGGL(k_fill_ghosts<float>, dim3((unsigned)nb), dim3(256), 0, st,
+                       static_cast<float*>(q), a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out, 1);
+  const long long n = (long long)a.nx * a.ny * a.nz;
+  long long nb = (n + 255) / 256;
+  if (nb > CFL_BLOCKS) nb = CFL_BLOCKS;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_cfl<double>, dim3((unsigned)nb), dim3(256), 0, st,
+                       static_cast<const double*>(q), a, out);
+  else
+    hipLaunchKernelGGL(k_cfl<float>, dim3((unsigned)nb), dim3(256), 0, st,
+                       static_cast<const float*>(q), a, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double* out,
+                hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_sums_partial<double>, dim3(SUM_BLOCKS), dim3(256), 0, st,
+                       static_cast<const double*>(q), a, part);
+  else
+    hipLaunchKernelGGL(k_sums_partial<float>, dim3(SUM_BLOCKS), dim3(256), 0, st,
+                       static_cast<const float*>(q), a, part);
+  hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(64), 0, st, part, SUM_BLOCKS, a.nvar, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace snap

@@ -1,0 +1,189 @@
+// Device building blocks of the SNAP right-hand side for gfx950.
+//
+// cons_to_prim : conserved -> primitive variables of one cell (App. B, with the
+//                single-gas reduction that makes tracers passive).
+// weno5_cell   : both face values of one cell from its five-cell window
+//                (Sec. 4.2, eq. weno5, Jiang-Shu nonlinear weights).
+// lmars_flux   : LMARS flux at one face (Sec. 4.1, eqs. rp and ru).
+//
+// Primitive vector layout x[NV]: 0 = rho - rhobar, 1..3 = u, v, w,
+// 4 = p - pbar, 5.. = tracer mass fractions rho_i / rho.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snap {
+
+constexpr int NG = 3;
+
+// ---------------------------------------------------------------------------
+// Conserved -> primitive (App. B). The arithmetic runs in double whatever the
+// storage type, and in one fixed order with no fused multiply-add, because the
+// pressure perturbation p - pbar cancels strongly against the kinetic energy
+// and the reference pressure:
+//   inv = 1/rho; u = (rho u) inv (v, w alike); K = ((rho u) u + (rho v) v)
+//   + (rho w) w, times 1/2; p = (gamma - 1)(E - K); p' = p - pbar;
+//   rho' = rho - rhobar; q_i = rho_i inv.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void cons_to_prim(const double (&c)[NV], double rbar, double pbar,
+                                             double gm1, double (&x)[NV]) {
+#pragma clang fp contract(off)
+  const double inv = 1.0 / c[0];
+  const double u = c[1] * inv;
+  const double v = c[2] * inv;
+  const double w = c[3] * inv;
+  const double K = 0.5 * ((c[1] * u + c[2] * v) + c[3] * w);
+  const double p = gm1 * (c[4] - K);
+  x[0] = c[0] - rbar;
+  x[1] = u;
+  x[2] = v;
+  x[3] = w;
+  x[4] = p - pbar;
+#pragma unroll
+  for (int t = 5; t < NV; ++t) x[t] = c[t] * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Fifth-order WENO of one cell j from v_{j-2}, .., v_{j+2} = a, b, c, d, e.
+//
+// qm = left state at face j+1/2 (the paper's I_weno(Q_{i-3}..Q_{i+1}) for
+//      face i-1/2 with i = j+1);
+// qp = right state at face j-1/2 (I_weno of the mirrored stencil).
+//
+// Both share the three Jiang-Shu smoothness indicators of cell j (integrals
+// of the squared first and second derivatives of the candidate quadratics
+// over the cell). The candidate values are written as c plus differences so a
+// uniform window returns c exactly; the linear weights are (0.1, 0.6, 0.3) for
+// qm and mirrored for qp (the values that turn eq. weno5 into the printed
+// fifth-order polynomial interpolant). Nonlinear weights:
+//   w_k = (d_k / s_k^2) / sum_m (d_m / s_m^2),  s_k = eps + beta_k,
+// evaluated as d_k t_k / sum_m d_m t_m with t_k the product of the other two
+// s_m^2 (one division shared by both faces in double precision). The s_k are
+// first scaled by the same power of two, which is exact and leaves the weights
+// unchanged while keeping the products inside the exponent range.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T pow2_scale_of_max(T s0, T s1, T s2);
+
+template <>
+__device__ __forceinline__ double pow2_scale_of_max<double>(double s0, double s1, double s2) {
+  const double m = fmax(fmax(s0, s1), s2);
+  const int e = __builtin_amdgcn_frexp_exp(m);
+  return __builtin_ldexp(1.0, -e);
+}
+
+template <>
+__device__ __forceinline__ float pow2_scale_of_max<float>(float s0, float s1, float s2) {
+  const float m = fmaxf(fmaxf(s0, s1), s2);
+  const int e = __builtin_amdgcn_frexp_expf(m);
+  return __builtin_ldexpf(1.0f, -e);
+}
+
+template <typename T>
+__device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool linear, T& qm,
+                                           T& qp) {
+  const T da = a - c, db = b - c, dd = d - c, de = e - c;
+  // candidate values minus c, times 6
+  const T m0 = T(2) * da - T(7) * db;   // (2a - 7b + 11c) - 6c
+  const T m1 = T(2) * dd - db;          // (-b + 5c + 2d) - 6c
+  const T m2 = T(5) * dd - de;          // (2c + 5d - e) - 6c
+  const T p0 = T(2) * de - T(7) * dd;   // mirrored stencil
+  const T p1 = T(2) * db - dd;
+  const T p2 = T(5) * db - da;
+  const T sixth = T(1) / T(6);
+  if (linear) {
+    qm = c + (T(0.1) * m0 + T(0.6) * m1 + T(0.3) * m2) * sixth;
+    qp = c + (T(0.1) * p0 + T(0.6) * p1 + T(0.3) * p2) * sixth;
+    return;
+  }
+  const T k13 = T(13) / T(12);
+  const T u0 = da - T(2) * db, v0 = da - T(4) * db;
+  const T u1 = db + dd, v1 = db - dd;
+  const T u2 = de - T(2) * dd, v2 = de - T(4) * dd;
+  const T b0 = k13 * u0 * u0 + T(0.25) * v0 * v0;
+  const T b1 = k13 * u1 * u1 + T(0.25) * v1 * v1;
+  const T b2 = k13 * u2 * u2 + T(0.25) * v2 * v2;
+  T s0 = eps + b0, s1 = eps + b1, s2 = eps + b2;
+  const T sc = pow2_scale_of_max<T>(s0, s1, s2);
+  s0 *= sc;
+  s1 *= sc;
+  s2 *= sc;
+  const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
+  const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
+  // left state at j+1/2: weights (0.1, 0.6, 0.3) on stencils (0, 1, 2)
+  const T n0 = T(0.1) * t0, n1 = T(0.6) * t1, n2 = T(0.3) * t2;
+  const T denm = n0 + n1 + n2;
+  const T numm = n0 * m0 + n1 * m1 + n2 * m2;
+  // right state at j-1/2: mirrored stencil k uses beta_{2-k}
+  const T r0 = T(0.1) * t2, r1 = T(0.6) * t1, r2 = T(0.3) * t0;
+  const T denp = r0 + r1 + r2;
+  const T nump = r0 * p0 + r1 * p1 + r2 * p2;
+  if constexpr (sizeof(T) == 8) {
+    const T inv = sixth / (denm * denp);
+    qm = c + numm * (denp * inv);
+    qp = c + nump * (denm * inv);
+  } else {
+    qm = c + numm * sixth / denm;
+    qp = c + nump * sixth / denp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LMARS flux at one face (Sec. 4.1, eqs. rp and ru).
+//
+// xl, xr   reconstructed primitive face states (layout above) on the left and
+//          right side; density and pressure are perturbations.
+// nrm      index of the normal velocity in x (1 = x, 2 = y, 3 = z faces).
+// rref, pref  reference density and pressure of the face; full values are
+//          rho = rref + rho', p = pref + p'.
+// Sound speed c = sqrt(gamma p / rho) from full face values; the acoustic
+// impedance rho c is the product of the side averages of rho and c. The
+// interface pressure and velocity use the perturbation pressure:
+//   p* = (p'_L + p'_R)/2 - (rho c)/2 (u_R - u_L)
+//   u* = (u_L + u_R)/2 - (p'_R - p'_L) / (2 rho c)
+// The advected vector (rho, rho u, rho v, rho w, E + p, rho q_i) comes from the
+// upwind side (left if u* > 0, else right; at u* == 0 every advective term is
+// zero, so the side does not matter); p* is added to the normal momentum flux.
+// ---------------------------------------------------------------------------
+template <typename T, int NV>
+__device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV], int nrm, T rref,
+                                           T pref, T gamma, T inv_gm1, T (&f)[NV]) {
+  const T rl = rref + xl[0], rr = rref + xr[0];
+  const T pl = pref + xl[4], pr = pref + xr[4];
+  const T unl = xl[nrm], unr = xr[nrm];
+  const T cl = sqrt(gamma * pl / rl);
+  const T cr = sqrt(gamma * pr / rr);
+  const T rc = (T(0.5) * (rl + rr)) * (T(0.5) * (cl + cr));
+  const T pstar = T(0.5) * (xl[4] + xr[4]) - T(0.5) * rc * (unr - unl);
+  const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) / (T(2) * rc);
+  const bool left = ustar > T(0);
+  const T rs = left ? rl : rr;
+  const T ps = left ? pl : pr;
+  const T us = left ? xl[1] : xr[1];
+  const T vs = left ? xl[2] : xr[2];
+  const T ws = left ? xl[3] : xr[3];
+  const T E = ps * inv_gm1 + T(0.5) * rs * (us * us + vs * vs + ws * ws);
+  const T mflux = ustar * rs;
+  f[0] = mflux;
+  f[1] = ustar * (rs * us);
+  f[2] = ustar * (rs * vs);
+  f[3] = ustar * (rs * ws);
+  f[4] = ustar * (E + ps);
+#pragma unroll
+  for (int t = 5; t < NV; ++t) f[t] = ustar * (rs * (left ? xl[t] : xr[t]));
+  f[nrm] += pstar;
+}
+
+// Block index -> logical tile with consecutive logical tiles on one XCD.
+// The hardware hands block b to XCD b % 8; this inverts that so that each XCD
+// works on a contiguous range of tiles (neighbours share halos in its L2).
+__device__ __forceinline__ int xcd_logical_block(int b, int nblk) {
+  constexpr int NXCD = 8;
+  const int per = nblk / NXCD, rem = nblk % NXCD;
+  const int x = b % NXCD, idx = b / NXCD;
+  return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+}  // namespace snap

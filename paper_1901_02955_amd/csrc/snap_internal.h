@@ -1,0 +1,46 @@
+// Internal declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "snap_stage.h"
+
+namespace snap {
+
+constexpr int CFL_BLOCKS = 1024;
+constexpr int SUM_BLOCKS = 512;
+
+struct GhostArgs {
+  int nx, ny, nz, nxp, nyp, gy, d3, nvar;
+  int bcx, bcy, bcz;
+  long long sy, sz, sv;
+};
+
+struct CflArgs {
+  int nx, ny, nz, gy, d3;
+  long long sy, sz, sv;
+  double gamma, gm1, dx, dy, dz;
+};
+
+struct SumArgs {
+  int nx, ny, nz, gy, nvar;
+  long long sy, sz, sv;
+};
+
+// Tile shape of the stage kernels for an element size and variable count.
+struct TileShape {
+  int tx, ty;
+};
+TileShape tile_f64(int nv);
+TileShape tile_f32(int nv);
+
+// Launchers; each returns 0 on success, -1 if the launch failed.
+int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st);
+int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
+               hipStream_t st);
+int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double* out,
+                hipStream_t st);
+
+}  // namespace snap

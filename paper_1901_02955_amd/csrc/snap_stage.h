@@ -1,0 +1,401 @@
+// Fused right-hand-side / Runge-Kutta stage kernels.
+//
+// One launch evaluates the full right-hand side of Sec. 4 (eq. forward) for a
+// block of cells and either stores it (rhs mode) or applies one stage of the
+// TVD Runge-Kutta step of Sec. 4.3 (stage mode):
+//     out = ca * Qn + cb * (Qs + dt * R(Qs)).
+// Face states and fluxes never leave the chip: primitive variables of a plane
+// of cells and the face values / fluxes of its two in-plane directions are
+// staged through LDS, and (3-D) the vertical direction is marched with a
+// per-thread register window of five levels.
+//
+// 3-D kernel: a workgroup owns a TX x TY column tile and a chunk of levels;
+//   it walks up the chunk, and per level
+//     (P) writes the primitives of the tile and its 3-cell x/y halo to LDS,
+//     (R) reconstructs every cell of the tile plus one halo cell on each side
+//         in x and in y (WENO5, both faces of the cell),
+//     (L) evaluates LMARS at every x and y face of the tile,
+//     (D) forms the divergence with the vertical flux difference that the
+//         thread's own register window produced, adds gravity, and writes.
+// 2-D (x-z) kernel: a workgroup owns a TX x TZ tile of the x-z plane and runs
+//   the same P/R/L/D phases once, with z as the second in-plane axis.
+#pragma once
+
+#include "snap_device.h"
+
+namespace snap {
+
+struct StageArgs {
+  const void* qs;   // padded state whose right-hand side is taken (ghosts filled)
+  const void* qn;   // padded Q^n for the stage combination (may alias out); unused if ca == 0
+  void* out;        // padded next state (stage mode) or interior rhs (rhs mode)
+  int rhs_mode;     // 1: out = R (interior layout); 0: stage combination (padded layout)
+  double ca, cb, dt;
+  int nx, ny, nz;
+  int gy;                  // 3 in 3-D, 0 in 2-D
+  long long sy, sz, sv;    // padded strides (elements)
+  long long ry, rz, rv;    // interior (rhs) strides
+  int tiles_x, tiles_y, nchunk, tz;
+  double dxi, dyi, dzi;    // 1 / spacing
+  double gamma, gm1, inv_gm1, grav, eps;
+  int linear;
+  const double* rbar_c;  // nz + 6
+  const double* pbar_c;
+  const double* rbar_f;  // nz + 1
+  const double* pbar_f;
+};
+
+template <typename T>
+__device__ __forceinline__ double to_d(T v) {
+  return static_cast<double>(v);
+}
+
+// Load the NV conserved values of padded element offset `off` and convert them
+// to primitives with the level references (rb, pb).
+template <typename T, int NV>
+__device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off, long long sv,
+                                          double rb, double pb, double gm1, T (&x)[NV]) {
+  double c[NV], xd[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
+  cons_to_prim<NV>(c, rb, pb, gm1, xd);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+}
+
+// Output of one interior cell: either R itself or the stage combination.
+template <typename T, int NV>
+__device__ __forceinline__ void write_cell(const StageArgs& a, const T* __restrict__ qs,
+                                           long long poff, long long roff, const T (&R)[NV]) {
+  if (a.rhs_mode) {
+    T* __restrict__ o = static_cast<T*>(a.out);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o[roff + v * a.rv] = R[v];
+    return;
+  }
+  const T dt = static_cast<T>(a.dt), ca = static_cast<T>(a.ca), cb = static_cast<T>(a.cb);
+  T* o = static_cast<T*>(a.out);
+  const T* qn = static_cast<const T*>(a.qn);
+  if (a.ca != 0.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T t = qs[poff + v * a.sv] + dt * R[v];
+      o[poff + v * a.sv] = ca * qn[poff + v * a.sv] + cb * t;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T t = qs[poff + v * a.sv] + dt * R[v];
+      o[poff + v * a.sv] = cb * t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS plane shared by both kernels: primitives with a 3-cell halo and the
+// face values / fluxes of the two in-plane axes ("x" and "second").
+// ---------------------------------------------------------------------------
+template <typename T, int NV, int TX, int TY>
+struct Plane {
+  T P[NV][TY + 6][TX + 6];
+  T XL[NV][TY][TX + 1];   // left state at x face f (after LMARS: flux)
+  T XR[NV][TY][TX + 1];   // right state at x face f
+  T SL[NV][TY + 1][TX];   // left state at second-axis face f (after LMARS: flux)
+  T SR[NV][TY + 1][TX];
+};
+
+// Phase R: WENO5 of every cell of the tile plus one halo cell on each side of
+// both in-plane axes. w x h is the active part of the tile.
+template <typename T, int NV, int TX, int TY>
+__device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w, int h, T eps,
+                                                  bool linear) {
+  constexpr int NTHR = TX * TY;
+  const int nrx = (w + 2) * h;
+  const int nrs = w * (h + 2);
+  for (int it = threadIdx.x; it < nrx + nrs; it += NTHR) {
+    if (it < nrx) {
+      const int ii = it % (w + 2) - 1, jj = it / (w + 2);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const T* row = &S.P[v][jj + 3][ii + 1];
+        T qm, qp;
+        weno5_cell<T>(row[0], row[1], row[2], row[3], row[4], eps, linear, qm, qp);
+        if (ii < w) S.XL[v][jj][ii + 1] = qm;
+        if (ii >= 0) S.XR[v][jj][ii] = qp;
+      }
+    } else {
+      const int r = it - nrx;
+      const int ii = r % w, jj = r / w - 1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T qm, qp;
+        weno5_cell<T>(S.P[v][jj + 1][ii + 3], S.P[v][jj + 2][ii + 3], S.P[v][jj + 3][ii + 3],
+                      S.P[v][jj + 4][ii + 3], S.P[v][jj + 5][ii + 3], eps, linear, qm, qp);
+        if (jj < h) S.SL[v][jj + 1][ii] = qm;
+        if (jj >= 0) S.SR[v][jj][ii] = qp;
+      }
+    }
+  }
+}
+
+// Phase L: LMARS at every x face and every second-axis face of the tile.
+// Reference density / pressure: x faces use the level of their row (xref);
+// second-axis faces use sref(face row).
+template <typename T, int NV, int TX, int TY, typename XRef, typename SRef>
+__device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int h, int snrm,
+                                            T gamma, T inv_gm1, XRef xref, SRef sref) {
+  constexpr int NTHR = TX * TY;
+  const int nfx = (w + 1) * h;
+  const int nfs = w * (h + 1);
+  for (int it = threadIdx.x; it < nfx + nfs; it += NTHR) {
+    T xl[NV], xr[NV], f[NV];
+    if (it < nfx) {
+      const int fi = it % (w + 1), jj = it / (w + 1);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        xl[v] = S.XL[v][jj][fi];
+        xr[v] = S.XR[v][jj][fi];
+      }
+      T rr, pr;
+      xref(jj, rr, pr);
+      lmars_flux<T, NV>(xl, xr, 1, rr, pr, gamma, inv_gm1, f);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) S.XL[v][jj][fi] = f[v];
+    } else {
+      const int r = it - nfx;
+      const int ii = r % w, fj = r / w;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        xl[v] = S.SL[v][fj][ii];
+        xr[v] = S.SR[v][fj][ii];
+      }
+      T rr, pr;
+      sref(fj, rr, pr);
+      lmars_flux<T, NV>(xl, xr, snrm, rr, pr, gamma, inv_gm1, f);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) S.SL[v][fj][ii] = f[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3-D kernel
+// ---------------------------------------------------------------------------
+template <typename T, int NT, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY) k_stage3d(StageArgs a) {
+  constexpr int NV = 5 + NT;
+  __shared__ Plane<T, NV, TX, TY> S;
+  const T* __restrict__ qs = static_cast<const T*>(a.qs);
+
+  const int tid = threadIdx.x;
+  const int ti = tid % TX, tj = tid / TX;
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tx = L % a.tiles_x;
+  const int rr_ = L / a.tiles_x;
+  const int ty = rr_ % a.tiles_y;
+  const int kc = rr_ / a.tiles_y;
+  const int i0 = tx * TX, j0 = ty * TY;
+  const int k0 = kc * a.tz;
+  const int k1 = min(k0 + a.tz, a.nz);
+  const int w = min(TX, a.nx - i0), h = min(TY, a.ny - j0);
+  const bool act = ti < w && tj < h;
+  const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
+  const T inv_gm1 = static_cast<T>(a.inv_gm1);
+  const T dxi = static_cast<T>(a.dxi), dyi = static_cast<T>(a.dyi), dzi = static_cast<T>(a.dzi);
+  const bool linear = a.linear != 0;
+
+  // padded offset of (i, j, k) with interior coordinates (k may be a ghost level)
+  auto poff = [&](int i, int j, int k) -> long long {
+    return (long long)(k + NG) * a.sz + (long long)(j + NG) * a.sy + (i + NG);
+  };
+  const int ic = i0 + (act ? ti : 0), jc = j0 + (act ? tj : 0);
+
+  T W[5][NV];     // primitives of levels s-1 .. s+3 (own column)
+  T qmc[NV];      // left state at the next vertical face
+  T fzc[NV];      // vertical flux at the lower face of the current level
+  T dfz[NV];      // vertical flux difference of the current level
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    qmc[v] = T(0);
+    fzc[v] = T(0);
+    dfz[v] = T(0);
+  }
+  if (act) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int k = k0 - 3 + l;
+      load_prim<T, NV>(qs, poff(ic, jc, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, W[l]);
+    }
+  }
+
+  for (int s = k0 - 2; s < k1; ++s) {
+    // ---- vertical direction, own column ------------------------------------
+    if (act) {
+      load_prim<T, NV>(qs, poff(ic, jc, s + 3), a.sv, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG],
+                       a.gm1, W[4]);
+      T qmn[NV], qpn[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        weno5_cell<T>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, linear, qmn[v], qpn[v]);
+      if (s >= k0 - 1) {
+        // face s+1/2 = z-face index s+1
+        T fz[NV];
+        lmars_flux<T, NV>(qmc, qpn, 3, static_cast<T>(a.rbar_f[s + 1]),
+                          static_cast<T>(a.pbar_f[s + 1]), gamma, inv_gm1, fz);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          dfz[v] = fz[v] - fzc[v];
+          fzc[v] = fz[v];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qmc[v] = qmn[v];
+    }
+
+    if (s >= k0) {
+      // ---- (P) primitives of level s: own cell from the window, halo loaded -
+      const double rbs = a.rbar_c[s + NG], pbs = a.pbar_c[s + NG];
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.P[v][tj + 3][ti + 3] = W[1][v];
+      }
+      {
+        const int nhx = 6 * h, nh = 6 * h + 6 * w;
+        for (int it = tid; it < nh; it += TX * TY) {
+          int ii, jj;
+          if (it < nhx) {
+            const int m = it % 6;
+            jj = it / 6;
+            ii = m < 3 ? m - 3 : w + m - 3;
+          } else {
+            const int r = it - nhx;
+            const int m = r % 6;
+            ii = r / 6;
+            jj = m < 3 ? m - 3 : h + m - 3;
+          }
+          T x[NV];
+          load_prim<T, NV>(qs, poff(i0 + ii, j0 + jj, s), a.sv, rbs, pbs, a.gm1, x);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) S.P[v][jj + 3][ii + 3] = x[v];
+        }
+      }
+      __syncthreads();
+      // ---- (R) WENO5 in x and y ---------------------------------------------
+      phase_reconstruct<T, NV, TX, TY>(S, w, h, eps, linear);
+      __syncthreads();
+      // ---- (L) LMARS at x and y faces (level references) ---------------------
+      const T rbT = static_cast<T>(rbs), pbT = static_cast<T>(pbs);
+      auto lev = [&](int, T& r, T& p) {
+        r = rbT;
+        p = pbT;
+      };
+      phase_lmars<T, NV, TX, TY>(S, w, h, 2, gamma, inv_gm1, lev, lev);
+      __syncthreads();
+      // ---- (D) divergence, gravity, output -----------------------------------
+      if (act) {
+        T R[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          T r = -((S.XL[v][tj][ti + 1] - S.XL[v][tj][ti]) * dxi);
+          r = r - (S.SL[v][tj + 1][ti] - S.SL[v][tj][ti]) * dyi;
+          R[v] = r - dfz[v] * dzi;
+        }
+        const long long po = poff(ic, jc, s);
+        const T grav = static_cast<T>(a.grav);
+        R[3] = R[3] - grav * W[1][0];
+        R[4] = R[4] - grav * qs[po + 3 * a.sv];
+        const long long ro = (long long)s * a.rz + (long long)jc * a.ry + ic;
+        write_cell<T, NV>(a, qs, po, ro, R);
+      }
+    }
+    // shift the window
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) W[l][v] = W[l + 1][v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2-D (x-z) kernel: TX x TZ tile of the plane, z is the second in-plane axis.
+// ---------------------------------------------------------------------------
+template <typename T, int NT, int TX, int TZ>
+__global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
+  constexpr int NV = 5 + NT;
+  __shared__ Plane<T, NV, TX, TZ> S;
+  const T* __restrict__ qs = static_cast<const T*>(a.qs);
+
+  const int tid = threadIdx.x;
+  const int ti = tid % TX, tk = tid / TX;
+  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tx = L % a.tiles_x;
+  const int tzi = L / a.tiles_x;
+  const int i0 = tx * TX, k0 = tzi * TZ;
+  const int w = min(TX, a.nx - i0), h = min(TZ, a.nz - k0);
+  const bool act = ti < w && tk < h;
+  const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
+  const T inv_gm1 = static_cast<T>(a.inv_gm1);
+  const T dxi = static_cast<T>(a.dxi), dzi = static_cast<T>(a.dzi);
+  const bool linear = a.linear != 0;
+
+  auto poff = [&](int i, int k) -> long long { return (long long)(k + NG) * a.sz + (i + NG); };
+
+  // ---- (P) primitives of the tile and its halo --------------------------------
+  {
+    const int nown = TX * TZ;
+    const int nhx = 6 * h, nh = nhx + 6 * w;
+    for (int it = tid; it < nown + nh; it += TX * TZ) {
+      int ii, kk;
+      if (it < nown) {
+        ii = it % TX;
+        kk = it / TX;
+        if (ii >= w || kk >= h) continue;
+      } else if (it < nown + nhx) {
+        const int r = it - nown;
+        const int m = r % 6;
+        kk = r / 6;
+        ii = m < 3 ? m - 3 : w + m - 3;
+      } else {
+        const int r = it - nown - nhx;
+        const int m = r % 6;
+        ii = r / 6;
+        kk = m < 3 ? m - 3 : h + m - 3;
+      }
+      const int k = k0 + kk;
+      T x[NV];
+      load_prim<T, NV>(qs, poff(i0 + ii, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, x);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) S.P[v][kk + 3][ii + 3] = x[v];
+    }
+  }
+  __syncthreads();
+  phase_reconstruct<T, NV, TX, TZ>(S, w, h, eps, linear);
+  __syncthreads();
+  auto xref = [&](int kk, T& r, T& p) {
+    r = static_cast<T>(a.rbar_c[k0 + kk + NG]);
+    p = static_cast<T>(a.pbar_c[k0 + kk + NG]);
+  };
+  auto zref = [&](int fk, T& r, T& p) {
+    r = static_cast<T>(a.rbar_f[k0 + fk]);
+    p = static_cast<T>(a.pbar_f[k0 + fk]);
+  };
+  phase_lmars<T, NV, TX, TZ>(S, w, h, 3, gamma, inv_gm1, xref, zref);
+  __syncthreads();
+  if (act) {
+    T R[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T r = -((S.XL[v][tk][ti + 1] - S.XL[v][tk][ti]) * dxi);
+      R[v] = r - (S.SL[v][tk + 1][ti] - S.SL[v][tk][ti]) * dzi;
+    }
+    const int i = i0 + ti, k = k0 + tk;
+    const long long po = poff(i, k);
+    const T grav = static_cast<T>(a.grav);
+    R[3] = R[3] - grav * S.P[0][tk + 3][ti + 3];
+    R[4] = R[4] - grav * qs[po + 3 * a.sv];
+    const long long ro = (long long)k * a.rz + i;
+    write_cell<T, NV>(a, qs, po, ro, R);
+  }
+}
+
+}  // namespace snap

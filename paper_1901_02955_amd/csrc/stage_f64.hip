@@ -1,0 +1,12 @@
+// Stage kernels, double precision.
+#include "stage_launch.h"
+
+namespace snap {
+
+int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st) {
+  return launch_stage_t<double>(ntracer, d3, a, nblocks, st);
+}
+
+TileShape tile_f64(int nv) { return tile_t<double>(nv); }
+
+}  // namespace snap

@@ -1,0 +1,63 @@
+// Instantiation and dispatch of the stage kernels for one element type.
+// Included once by stage_f64.hip (T = double) and once by stage_f32.hip
+// (T = float) so that the two instantiation sets compile in parallel.
+#pragma once
+
+#include "snap_internal.h"
+
+namespace snap {
+
+// LDS bytes of one Plane per variable: (TY+6)(TX+6) + 2 TY (TX+1) + 2 (TY+1) TX
+// elements. The shapes keep one workgroup's plane at or below 64 KiB.
+template <typename T, int NT>
+struct TileFor {
+  static constexpr int NV = 5 + NT;
+  static constexpr int BYTES = sizeof(T) * NV;
+  static constexpr bool BIG = BYTES * 1572 <= 65536;   // 16 x 16
+  static constexpr bool MID = BYTES * 868 <= 65536;    // 16 x 8
+  static constexpr int TX = BIG || MID ? 16 : 8;
+  static constexpr int TY = BIG ? 16 : (MID ? 8 : 8);
+};
+
+template <typename T, int NT>
+int launch_nt(bool d3, const StageArgs& a, int nblocks, hipStream_t st) {
+  constexpr int TX = TileFor<T, NT>::TX, TY = TileFor<T, NT>::TY;
+  if (d3)
+    hipLaunchKernelGGL((k_stage3d<T, NT, TX, TY>), dim3(nblocks), dim3(TX * TY), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_stage2d<T, NT, TX, TY>), dim3(nblocks), dim3(TX * TY), 0, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int launch_stage_t(int ntracer, bool d3, const StageArgs& a, int nblocks, hipStream_t st) {
+  switch (ntracer) {
+    case 0: return launch_nt<T, 0>(d3, a, nblocks, st);
+    case 1: return launch_nt<T, 1>(d3, a, nblocks, st);
+    case 2: return launch_nt<T, 2>(d3, a, nblocks, st);
+    case 3: return launch_nt<T, 3>(d3, a, nblocks, st);
+    case 4: return launch_nt<T, 4>(d3, a, nblocks, st);
+    case 5: return launch_nt<T, 5>(d3, a, nblocks, st);
+    case 6: return launch_nt<T, 6>(d3, a, nblocks, st);
+    case 7: return launch_nt<T, 7>(d3, a, nblocks, st);
+    case 8: return launch_nt<T, 8>(d3, a, nblocks, st);
+    default: return -1;
+  }
+}
+
+template <typename T>
+TileShape tile_t(int nv) {
+  switch (nv - 5) {
+    case 0: return {TileFor<T, 0>::TX, TileFor<T, 0>::TY};
+    case 1: return {TileFor<T, 1>::TX, TileFor<T, 1>::TY};
+    case 2: return {TileFor<T, 2>::TX, TileFor<T, 2>::TY};
+    case 3: return {TileFor<T, 3>::TX, TileFor<T, 3>::TY};
+    case 4: return {TileFor<T, 4>::TX, TileFor<T, 4>::TY};
+    case 5: return {TileFor<T, 5>::TX, TileFor<T, 5>::TY};
+    case 6: return {TileFor<T, 6>::TX, TileFor<T, 6>::TY};
+    case 7: return {TileFor<T, 7>::TX, TileFor<T, 7>::TY};
+    default: return {TileFor<T, 8>::TX, TileFor<T, 8>::TY};
+  }
+}
+
+}  // namespace snap

@@ -1,0 +1,66 @@
+"""Seeded parity cases shared by the GPU tests (inputs only; no arithmetic of the method).
+
+Each case is a (grid, padded state, dt) triple built from the ``workloads``
+generators. Sizes are chosen so that the oracle finishes in seconds while the
+GPU kernels still see several tiles and ragged edges along every axis.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+import workloads as wl
+
+# (name, nx, ny, nz, ntracer, bc, lx, ly, lz, linear, seed)
+SPECS = [
+    ("2d_bubble_64x64", None),
+    ("2d_smooth_37x29_nt3", dict(nx=37, ny=1, nz=29, nt=3, bc=(0, 0, 1), seed=11)),
+    ("2d_reflect_21x19", dict(nx=21, ny=1, nz=19, nt=0, bc=(1, 0, 1), seed=12)),
+    ("2d_narrow_1x8", dict(nx=1, ny=1, nz=8, nt=0, bc=(0, 0, 1), seed=13)),
+    ("2d_thin_19x2", dict(nx=19, ny=1, nz=2, nt=1, bc=(1, 0, 1), seed=14)),
+    ("3d_smooth_35x21x19", dict(nx=35, ny=21, nz=19, nt=0, bc=(0, 0, 1), seed=21)),
+    ("3d_tracers_20x18x24_nt4", dict(nx=20, ny=18, nz=24, nt=4, bc=(1, 0, 1), seed=22)),
+    ("3d_linear_17x9x11", dict(nx=17, ny=9, nz=11, nt=1, bc=(0, 1, 1), seed=23, linear=True)),
+    ("3d_nt8_10x12x9", dict(nx=10, ny=12, nz=9, nt=8, bc=(0, 0, 1), seed=24)),
+    ("3d_periodic_z_12x10x14", dict(nx=12, ny=10, nz=14, nt=2, bc=(0, 0, 0), seed=25, grav=0.0)),
+    ("3d_small_2x3x4", dict(nx=2, ny=3, nz=4, nt=0, bc=(1, 1, 1), seed=26)),
+]
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    grid: wl.Grid
+    q: np.ndarray
+    dt: float
+
+
+def build_case(name: str, spec) -> Case:
+    if spec is None:
+        grid, q = wl.bubble_2d()
+        return Case(name, grid, q, 0.25)
+    nx, ny, nz = spec["nx"], spec["ny"], spec["nz"]
+    lx, ly, lz = 200.0 * nx, 200.0 * ny, 150.0 * nz
+    grav = spec.get("grav", 9.81)
+    if grav == 0.0:
+        base = wl.DryIsentropic(grav=0.0)
+        grid, _ = wl.dry_grid(nx, ny, nz, lx, ly, lz, bc=spec["bc"], base=base)
+        rc, pc, rf, pf = wl.uniform_references(nz, 1.1, 9.5e4)
+        grid.rhobar_cell, grid.pbar_cell, grid.rhobar_face, grid.pbar_face = rc, pc, rf, pf
+        grid.grav = 0.0
+    else:
+        grid, _ = wl.dry_grid(nx, ny, nz, lx, ly, lz, bc=spec["bc"])
+    if ny == 1:
+        grid.dy = 1.0
+    grid.ntracer = spec["nt"]
+    grid.weno_linear = bool(spec.get("linear", False))
+    q = wl.random_smooth_state(grid, spec["seed"])
+    return Case(name, grid, q, 0.2)
+
+
+def all_cases():
+    return [build_case(n, s) for n, s in SPECS]
+
+
+CASE_NAMES = [n for n, _ in SPECS]

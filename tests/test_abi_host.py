@@ -1,0 +1,145 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* the shared library loads and exports every function declared in include/snap.h;
+* every invalid argument is rejected with its error code before any HIP call
+  (a fake, never dereferenced device address stands in for the reference
+  profiles and buffers);
+* workspace sizes follow the documented layout.
+"""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1901_02955_amd as snap
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "snap.h")
+FAKE = 0x10000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(snap_[a-z0-9_]+)\s*\(", text)))
+
+
+def exported_symbols():
+    out = subprocess.run(["nm", "-D", "--defined-only", snap.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    return {line.split()[-1] for line in out.splitlines() if " T " in line}
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = snap.lib()
+    decl = declared_functions()
+    assert "snap_rhs" in decl and "snap_rk3_step" in decl
+    exported = exported_symbols()
+    missing = [f for f in decl if f not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    for f in decl:
+        getattr(lib, f)
+    assert lib.snap_abi_version() == 1
+
+
+def good_grid(**kw):
+    c = snap.SnapGridC()
+    c.nx, c.ny, c.nz, c.ng, c.ntracer, c.dtype = 16, 12, 10, 3, 2, snap.SNAP_F64
+    c.bc[0], c.bc[1], c.bc[2] = 0, 0, 1
+    c.weno_linear = 0
+    c.dx, c.dy, c.dz = 100.0, 100.0, 50.0
+    c.gamma, c.grav, c.weno_eps = 1.4, 9.81, 1e-6
+    c.rhobar_cell = c.pbar_cell = c.rhobar_face = c.pbar_face = FAKE
+    for k, v in kw.items():
+        if k == "bc":
+            for d in range(3):
+                c.bc[d] = v[d]
+        else:
+            setattr(c, k, v)
+    return c
+
+
+BAD_GRIDS = [
+    dict(nx=0), dict(ny=0), dict(nz=-1), dict(ng=2), dict(ng=4), dict(ntracer=-1),
+    dict(dtype=2), dict(bc=(2, 0, 1)), dict(bc=(0, 5, 1)), dict(bc=(0, 0, -1)),
+    dict(weno_linear=2), dict(dx=0.0), dict(dy=-1.0), dict(dz=math.nan), dict(dx=math.inf),
+    dict(gamma=1.0), dict(gamma=math.nan), dict(grav=-1.0), dict(grav=math.inf),
+    dict(weno_eps=0.0), dict(weno_eps=-1e-6), dict(rhobar_cell=None), dict(pbar_face=None),
+    dict(nx=1 << 25),
+]
+
+
+@pytest.mark.parametrize("kw", BAD_GRIDS, ids=[str(k) for k in BAD_GRIDS])
+def test_invalid_grid_rejected_by_every_entry_point(kw):
+    lib = snap.lib()
+    g = ctypes.byref(good_grid(**kw))
+    P = ctypes.c_void_p(FAKE)
+    d = ctypes.c_double(0.0)
+    sums = (ctypes.c_double * 16)()
+    calls = [
+        lambda: lib.snap_fill_ghosts(g, P, None),
+        lambda: lib.snap_rhs(g, P, ctypes.c_void_p(FAKE * 2), None),
+        lambda: lib.snap_rk3_step(g, P, 0.1, P, None),
+        lambda: lib.snap_cfl_dt(g, P, 0.9, P, ctypes.byref(d), None),
+        lambda: lib.snap_conservation_sums(g, P, P, sums, None),
+    ]
+    for call in calls:
+        assert call() == snap.SNAP_E_INVALID
+        assert lib.snap_last_error().decode()
+    assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) == 0
+
+
+def test_null_grid_and_too_many_tracers():
+    lib = snap.lib()
+    assert lib.snap_rhs(None, ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), None) == snap.SNAP_E_INVALID
+    assert b"NULL" in lib.snap_last_error()
+    g = ctypes.byref(good_grid(ntracer=9))
+    assert lib.snap_rhs(g, ctypes.c_void_p(FAKE), ctypes.c_void_p(2 * FAKE), None) == snap.SNAP_E_UNSUPPORTED
+
+
+def test_invalid_buffers_and_scalars():
+    lib = snap.lib()
+    g = ctypes.byref(good_grid())
+    P = ctypes.c_void_p(FAKE)
+    d = ctypes.c_double(0.0)
+    sums = (ctypes.c_double * 16)()
+    assert lib.snap_rhs(g, None, P, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rhs(g, P, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rhs(g, P, P, None) == snap.SNAP_E_INVALID          # rhs aliases q
+    assert lib.snap_fill_ghosts(g, None, None) == snap.SNAP_E_INVALID
+    for dt in (0.0, -1.0, math.nan, math.inf):
+        assert lib.snap_rk3_step(g, P, dt, P, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step(g, P, 0.1, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step(g, None, 0.1, P, None) == snap.SNAP_E_INVALID
+    for cfl in (0.0, -0.5, math.nan):
+        assert lib.snap_cfl_dt(g, P, cfl, P, ctypes.byref(d), None) == snap.SNAP_E_INVALID
+    assert lib.snap_cfl_dt(g, P, 0.9, None, ctypes.byref(d), None) == snap.SNAP_E_INVALID
+    assert lib.snap_cfl_dt(g, P, 0.9, P, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_conservation_sums(g, P, None, sums, None) == snap.SNAP_E_INVALID
+    assert lib.snap_conservation_sums(g, P, P, None, None) == snap.SNAP_E_INVALID
+
+
+def test_two_d_ignores_y_spacing_and_bc():
+    """ny == 1 is a 2-D x-z problem: dy and bc[1] are not validated."""
+    lib = snap.lib()
+    g = good_grid(ny=1, dy=0.0, bc=(0, 7, 1))
+    # a valid 2-D grid passes validation, so only the workspace query is made here
+    assert lib.snap_workspace_bytes(ctypes.byref(g), snap.SNAP_OP_RK3) > 0
+
+
+def test_workspace_sizes():
+    lib = snap.lib()
+    for dtype, es in ((snap.SNAP_F64, 8), (snap.SNAP_F32, 4)):
+        c = good_grid(dtype=dtype)
+        g = ctypes.byref(c)
+        padded = (c.nx + 6) * (c.ny + 6) * (c.nz + 6) * (5 + c.ntracer) * es
+        a256 = (padded + 255) // 256 * 256
+        assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) == 2 * a256
+        assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RHS) == 0
+        assert lib.snap_workspace_bytes(g, snap.SNAP_OP_CFL) >= 8
+        assert lib.snap_workspace_bytes(g, snap.SNAP_OP_SUMS) >= 8 * (5 + c.ntracer)
+    assert lib.snap_workspace_bytes(ctypes.byref(good_grid()), 99) == 0
+    assert b"unknown" in lib.snap_last_error()
