@@ -12,16 +12,21 @@ The FP64 path is the headline (`value`); the FP32 form (FP32 storage and
 stencil arithmetic, FP64 reference state and E -> p inversion) runs on the
 same workload and is reported under `variants.f32`.
 
-Roofline of the dominant kernel (the fused stage kernel): algorithmic HBM
-bytes per launch = (8/3) * nvar * sizeof(element) * cells (stage 1 reads Q and
-writes Q1, stages 2 and 3 read Q_s and Q^n and write the next state; 8 state
-passes per step, averaged over the three launches), divided by the kernel's
-average launch duration from hipEvents recorded around every stage launch of
-the timed region on the launch stream.
+Roofline of the dominant kernel (the fused stage kernel), both from the
+kernel's average launch duration (hipEvents recorded around every stage launch
+of the timed region, on the launch stream):
+* `roofline` (bound "alu": the measured HBM traffic is far below the memory
+  roofline, the kernel is limited by vector-ALU issue): algorithmic flops per
+  launch = algorithmic_flops_per_cell_stage() x cells, against the MI355X
+  vector peak of the element type;
+* `hbm_roofline`: algorithmic HBM bytes per launch = (8/3) * nvar *
+  sizeof(element) * cells (stage 1 reads Q and writes Q1, stages 2 and 3 read
+  Q_s and Q^n and write the next state: 8 state passes per step, averaged over
+  the three launches), against 8 TB/s.
 
 CPU baseline: the FP64 oracle (PyTorch CPU, all host threads of this process)
-on a bounded sample of the same workload: 2 SSP-RK3 steps of a 128 x 128 x 128
-column block cut from the same initial state (periodic in x and y).
+on a bounded sample of the same workload: the first 2 SSP-RK3 steps of the
+same 256 x 256 x 128 initial state.
 """
 from __future__ import annotations
 
@@ -39,6 +44,24 @@ METRIC = "cell-updates/s of WENO5+LMARS RK3 step (FP32 vs FP64), % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 NX, NY, NZ = 256, 256, 128
 CFL = 0.9
+
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (FMA = 2 flops)
+FP32_PEAK_TFLOPS = 157.3    # MI355X vector FP32 (counts packed FP32, which this build does not emit)
+
+
+def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int) -> int:
+    """Floating-point operations of one right-hand side + stage update of one cell.
+
+    Counted from the method's formulas (+, -, *, /, sqrt = 1 flop each, a fused
+    multiply-add = 2), with no halo redundancy, address arithmetic or data
+    movement: conserved -> primitive 14 + NT; WENO5 per variable and direction
+    (both faces of the cell, shared smoothness indicators) 78; LMARS per face
+    37 + NT; divergence 3 per variable and direction; gravity 4; Runge-Kutta
+    combination 4 per variable averaged over the three stages.
+    """
+    nv = 5 + ntracer
+    return (14 + ntracer) + ndir * nv * 78 + ndir * (37 + ntracer) + ndir * 3 * nv + 4 + 4 * nv
 
 
 def stage_sources_digest() -> str:
@@ -103,9 +126,12 @@ def run_gpu(dtype, steps: int, warmup: int):
     esize = 8 if dtype == torch.float64 else 4
     nvar = dg.nvar
     bytes_per_launch = 8.0 / 3.0 * nvar * esize * cells
+    flops_per_launch = algorithmic_flops_per_cell_stage(dg.ntracer, 3) * cells
     avg_launch_s = stage_ms / 1e3 / max(launches, 1)
-    achieved = bytes_per_launch / avg_launch_s / 1e9
+    gbs = bytes_per_launch / avg_launch_s / 1e9
+    tflops = flops_per_launch / avg_launch_s / 1e12
     name = "f64" if dtype == torch.float64 else "f32"
+    peak = FP64_PEAK_TFLOPS if name == "f64" else FP32_PEAK_TFLOPS
     traffic = measured_traffic(name)
     res = {
         "value": cells * steps / elapsed,
@@ -113,9 +139,12 @@ def run_gpu(dtype, steps: int, warmup: int):
         "stage_kernel_avg_ms": avg_launch_s * 1e3,
         "stage_launches": launches,
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "bound": "alu", "achieved": tflops, "peak": peak, "unit": "TFLOP/s",
+            "frac": tflops / peak, "traffic": traffic,
+        },
+        "hbm_roofline": {
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "final_dt": dt,
     }
@@ -137,10 +166,9 @@ def run_cpu_baseline():
         nthreads = min(nthreads, int(env))
     torch.set_num_threads(nthreads)
     grid, q, _ = wl.convection_3d(NX, NY, NZ)
-    b = 128
+    b = 256
     sub = grid.copy(nx=b, ny=b)
     qs = np.zeros(sub.shape)
-    G = wl.G
     sub.interior(qs)[...] = grid.interior(q)[:, :, :b, :b]
     del q
     dt = oracle.cfl_dt(qs, sub, CFL)
@@ -151,8 +179,8 @@ def run_cpu_baseline():
     return {
         "value": b * b * NZ * nsteps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
         "kind": "oracle",
-        "sample": f"{nsteps} SSP-RK3 steps (FP64) of a {b}x{b}x{NZ} column block cut from the "
-                  f"same initial state, periodic in x and y ({el:.1f} s)",
+        "sample": f"the first {nsteps} SSP-RK3 steps (FP64) of the same {b}x{b}x{NZ} initial "
+                  f"state ({el:.1f} s)",
     }
 
 
@@ -163,6 +191,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--variant", choices=("both", "f64", "f32"), default="both",
+                    help="f64 or f32 alone (for profiling runs); the JSON line then carries that form")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one device-to-device copy of 512 MiB (a known byte count "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path is a single-GPU kernel here; "
@@ -174,6 +207,21 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.variant == "f32":
+        f32 = run_gpu(torch.float32, args.steps, args.warmup)
+        print(json.dumps({"metric": METRIC, "value": f32["value"], "unit": "cell-updates/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": f32["ms_per_step"], "dtype": "f32",
+                          "roofline": f32["roofline"],
+                          "stage_kernel_avg_ms": f32["stage_kernel_avg_ms"]}), flush=True)
+        return
     f64 = run_gpu(torch.float64, args.steps, args.warmup)
     out = {
         "metric": METRIC,
@@ -194,13 +242,15 @@ def main():
             "nx": NX, "ny": NY, "nz": NZ, "nvar": 5, "cfl": CFL,
         },
         "roofline": f64["roofline"],
+        "hbm_roofline": f64["hbm_roofline"],
         "stage_kernel_avg_ms": f64["stage_kernel_avg_ms"],
     }
-    if not args.no_f32:
+    if not args.no_f32 and args.variant == "both":
         f32 = run_gpu(torch.float32, args.steps, args.warmup)
         out["variants"] = {"f32": {
             "value": f32["value"], "ms_per_step": f32["ms_per_step"], "dtype": "f32",
             "stage_kernel_avg_ms": f32["stage_kernel_avg_ms"], "roofline": f32["roofline"],
+            "hbm_roofline": f32["hbm_roofline"],
         }}
         out["f32_speedup"] = f32["value"] / f64["value"]
     if not args.no_cpu_baseline:

@@ -89,7 +89,8 @@ extern "C" {
  * dx, dy, dz     cell sizes in metres, > 0 (dy ignored in 2-D).
  * gamma          ratio of specific heats, > 1.
  * grav           gravitational acceleration >= 0, acting along -z.
- * weno_eps       regulariser of the nonlinear weights, > 0 (1e-6 is customary).
+ * weno_eps       regulariser of the nonlinear weights, in [1e-30, 1e30] (1e-6 is
+ *                customary).
  * rhobar_cell,   DEVICE, nz + 2 ng doubles each: reference density and pressure
  * pbar_cell      of every level, ghost levels included (the caller mirrors them
  *                for a reflecting z axis and wraps them for a periodic one).

@@ -26,7 +26,8 @@ __all__ = [
 ]
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libsnap.so")
+# SNAP_LIBRARY selects another build of the same C-ABI (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SNAP_LIBRARY") or os.path.join(PKG, "libsnap.so")
 
 SNAP_OK = 0
 SNAP_E_INVALID = -1

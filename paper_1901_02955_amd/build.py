@@ -52,20 +52,25 @@ def _compile(src: str, extra: list[str]) -> str:
     return obj
 
 
-def build(extra_flags: list[str] | None = None, jobs: int | None = None) -> str:
-    """Compile every HIP source for gfx950 and link ``libsnap.so`` in the package directory."""
+def build(extra_flags: list[str] | None = None, jobs: int | None = None,
+          out: str | None = None, build_dir: str | None = None) -> str:
+    """Compile every HIP source for gfx950 and link ``libsnap.so`` (or ``out``)."""
+    global BUILD_DIR
+    if build_dir:
+        BUILD_DIR = build_dir
     os.makedirs(BUILD_DIR, exist_ok=True)
     extra = list(extra_flags or [])
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 8)
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

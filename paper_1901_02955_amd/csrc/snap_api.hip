@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -76,7 +77,8 @@ int check_grid(const snap_grid* g) {
     return fail(SNAP_E_INVALID, "gamma must be finite and > 1");
   if (!isfinite(g->grav) || !(g->grav >= 0.0))
     return fail(SNAP_E_INVALID, "grav must be finite and >= 0");
-  if (!finite_pos(g->weno_eps)) return fail(SNAP_E_INVALID, "weno_eps must be finite and > 0");
+  if (!(g->weno_eps >= 1e-30 && g->weno_eps <= 1e30))
+    return fail(SNAP_E_INVALID, "weno_eps must lie in [1e-30, 1e30]");
   if (!g->rhobar_cell || !g->pbar_cell || !g->rhobar_face || !g->pbar_face)
     return fail(SNAP_E_INVALID, "reference profile pointer is NULL");
   const double total = (double)padded_cells(g) * nvar_of(g);
@@ -121,6 +123,31 @@ StageArgs stage_args(const snap_grid* g) {
   return a;
 }
 
+// Co-resident stage workgroups on the current device (compute units x
+// workgroups per compute unit), cached per device, dtype and variable count.
+int resident_slots(const snap_grid* g) {
+  static std::mutex m;
+  static std::vector<std::vector<int>> cache;  // [device][key]
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const int key = (g->dtype * 2 + (is3d(g) ? 1 : 0)) * 16 + g->ntracer;
+  std::lock_guard<std::mutex> lk(m);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1);
+  auto& c = cache[dev];
+  if (c.empty()) c.assign(64, 0);
+  if (c[key] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    int per = g->dtype == SNAP_F64 ? occupancy_f64(g->ntracer, is3d(g))
+                                   : occupancy_f32(g->ntracer, is3d(g));
+    if (per <= 0) per = 1;
+    c[key] = cus * per;
+  }
+  return c[key];
+}
+
 // Tiling of the stage launch; returns the number of workgroups.
 int stage_tiling(const snap_grid* g, StageArgs& a) {
   const bool d3 = is3d(g);
@@ -134,12 +161,30 @@ int stage_tiling(const snap_grid* g, StageArgs& a) {
   }
   a.tiles_y = (g->ny + t.ty - 1) / t.ty;
   const int tiles = a.tiles_x * a.tiles_y;
-  // enough workgroups to fill 256 CUs several times over; chunks of >= 8 levels
-  int nchunk = (2048 + tiles - 1) / tiles;
-  const int maxchunk = (g->nz + 7) / 8;
-  if (nchunk > maxchunk) nchunk = maxchunk;
-  if (nchunk < 1) nchunk = 1;
-  a.tz = (g->nz + nchunk - 1) / nchunk;
+  // Split the levels into chunks. Every chunk pays a warm-up of about one
+  // level (two extra vertical reconstructions and primitive loads), and the
+  // launch runs in rounds of `slots` co-resident workgroups; pick the chunk
+  // count that minimises rounds x (levels per chunk + 1).
+  const int slots = resident_slots(g);
+  int best = 1;
+  double best_cost = 1e300;
+  const int maxchunk = g->nz / 4 > 1 ? g->nz / 4 : 1;
+  for (int nc = 1; nc <= maxchunk; ++nc) {
+    const int tz = (g->nz + nc - 1) / nc;
+    const long long blocks = (long long)tiles * ((g->nz + tz - 1) / tz);
+    if (blocks > (1LL << 30)) break;
+    const long long rounds = (blocks + slots - 1) / slots;
+    const double cost = (double)rounds * (tz + 1);
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = nc;
+    }
+  }
+  if (const char* env = getenv("SNAP_STAGE_CHUNKS")) {
+    const int nc = atoi(env);
+    if (nc >= 1) best = nc < g->nz ? nc : g->nz;
+  }
+  a.tz = (g->nz + best - 1) / best;
   a.nchunk = (g->nz + a.tz - 1) / a.tz;
   return tiles * a.nchunk;
 }

@@ -46,6 +46,36 @@ __device__ __forceinline__ void cons_to_prim(const double (&c)[NV], double rbar,
 }
 
 // ---------------------------------------------------------------------------
+// Reciprocal and square root for the stencil arithmetic.
+// Double precision: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by
+// two Newton-Raphson steps, e <- 1 - d r, r <- r + r e for the reciprocal and
+// the coupled Goldschmidt form g = y h, r = h / 2, e = 1/2 - g r,
+// g <- g + g e, r <- r + r e for the square root. Both land within a couple of
+// ulp of the correctly rounded result at a third of the instruction count of
+// the IEEE sequences. Single precision: the hardware estimates (1 ulp).
+// Arguments are positive and normal on every call site.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp_fast(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_fast(float d) { return __builtin_amdgcn_rcpf(d); }
+
+__device__ __forceinline__ double sqrt_fast(double y) {
+  const double h = __builtin_amdgcn_rsq(y);
+  double g = y * h, r = 0.5 * h;
+  double e = fma(-g, r, 0.5);
+  g = fma(g, e, g);
+  r = fma(r, e, r);
+  e = fma(-g, r, 0.5);
+  return fma(g, e, g);
+}
+__device__ __forceinline__ float sqrt_fast(float y) { return y * __builtin_amdgcn_rsqf(y); }
+
+// ---------------------------------------------------------------------------
 // Fifth-order WENO of one cell j from v_{j-2}, .., v_{j+2} = a, b, c, d, e.
 //
 // qm = left state at face j+1/2 (the paper's I_weno(Q_{i-3}..Q_{i+1}) for
@@ -60,27 +90,11 @@ __device__ __forceinline__ void cons_to_prim(const double (&c)[NV], double rbar,
 // fifth-order polynomial interpolant). Nonlinear weights:
 //   w_k = (d_k / s_k^2) / sum_m (d_m / s_m^2),  s_k = eps + beta_k,
 // evaluated as d_k t_k / sum_m d_m t_m with t_k the product of the other two
-// s_m^2 (one division shared by both faces in double precision). The s_k are
-// first scaled by the same power of two, which is exact and leaves the weights
-// unchanged while keeping the products inside the exponent range.
+// s_m^2. Double precision shares one reciprocal between both faces (s_k^8 is
+// far inside the exponent range for eps >= 1e-30 and beta < 1e30). Single
+// precision first scales the s_k by the power of two of their maximum, which
+// is exact and leaves the weights unchanged while keeping the products in range.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T pow2_scale_of_max(T s0, T s1, T s2);
-
-template <>
-__device__ __forceinline__ double pow2_scale_of_max<double>(double s0, double s1, double s2) {
-  const double m = fmax(fmax(s0, s1), s2);
-  const int e = __builtin_amdgcn_frexp_exp(m);
-  return __builtin_ldexp(1.0, -e);
-}
-
-template <>
-__device__ __forceinline__ float pow2_scale_of_max<float>(float s0, float s1, float s2) {
-  const float m = fmaxf(fmaxf(s0, s1), s2);
-  const int e = __builtin_amdgcn_frexp_expf(m);
-  return __builtin_ldexpf(1.0f, -e);
-}
-
 template <typename T>
 __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool linear, T& qm,
                                            T& qp) {
@@ -102,14 +116,16 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool 
   const T u0 = da - T(2) * db, v0 = da - T(4) * db;
   const T u1 = db + dd, v1 = db - dd;
   const T u2 = de - T(2) * dd, v2 = de - T(4) * dd;
-  const T b0 = k13 * u0 * u0 + T(0.25) * v0 * v0;
-  const T b1 = k13 * u1 * u1 + T(0.25) * v1 * v1;
-  const T b2 = k13 * u2 * u2 + T(0.25) * v2 * v2;
-  T s0 = eps + b0, s1 = eps + b1, s2 = eps + b2;
-  const T sc = pow2_scale_of_max<T>(s0, s1, s2);
-  s0 *= sc;
-  s1 *= sc;
-  s2 *= sc;
+  T s0 = eps + (k13 * u0 * u0 + T(0.25) * v0 * v0);
+  T s1 = eps + (k13 * u1 * u1 + T(0.25) * v1 * v1);
+  T s2 = eps + (k13 * u2 * u2 + T(0.25) * v2 * v2);
+  if constexpr (sizeof(T) == 4) {
+    const float mx = fmaxf(fmaxf(s0, s1), s2);
+    const float sc = __builtin_amdgcn_ldexpf(1.0f, -__builtin_amdgcn_frexp_expf(mx));
+    s0 *= sc;
+    s1 *= sc;
+    s2 *= sc;
+  }
   const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
   const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
   // left state at j+1/2: weights (0.1, 0.6, 0.3) on stencils (0, 1, 2)
@@ -121,12 +137,12 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool 
   const T denp = r0 + r1 + r2;
   const T nump = r0 * p0 + r1 * p1 + r2 * p2;
   if constexpr (sizeof(T) == 8) {
-    const T inv = sixth / (denm * denp);
+    const T inv = sixth * rcp_fast(denm * denp);
     qm = c + numm * (denp * inv);
     qp = c + nump * (denm * inv);
   } else {
-    qm = c + numm * sixth / denm;
-    qp = c + nump * sixth / denp;
+    qm = c + numm * (sixth * rcp_fast(denm));
+    qp = c + nump * (sixth * rcp_fast(denp));
   }
 }
 
@@ -153,11 +169,11 @@ __device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV],
   const T rl = rref + xl[0], rr = rref + xr[0];
   const T pl = pref + xl[4], pr = pref + xr[4];
   const T unl = xl[nrm], unr = xr[nrm];
-  const T cl = sqrt(gamma * pl / rl);
-  const T cr = sqrt(gamma * pr / rr);
+  const T cl = sqrt_fast(gamma * pl * rcp_fast(rl));
+  const T cr = sqrt_fast(gamma * pr * rcp_fast(rr));
   const T rc = (T(0.5) * (rl + rr)) * (T(0.5) * (cl + cr));
   const T pstar = T(0.5) * (xl[4] + xr[4]) - T(0.5) * rc * (unr - unl);
-  const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) / (T(2) * rc);
+  const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) * (T(0.5) * rcp_fast(rc));
   const bool left = ustar > T(0);
   const T rs = left ? rl : rr;
   const T ps = left ? pl : pr;
@@ -167,12 +183,12 @@ __device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV],
   const T E = ps * inv_gm1 + T(0.5) * rs * (us * us + vs * vs + ws * ws);
   const T mflux = ustar * rs;
   f[0] = mflux;
-  f[1] = ustar * (rs * us);
-  f[2] = ustar * (rs * vs);
-  f[3] = ustar * (rs * ws);
+  f[1] = mflux * us;
+  f[2] = mflux * vs;
+  f[3] = mflux * ws;
   f[4] = ustar * (E + ps);
 #pragma unroll
-  for (int t = 5; t < NV; ++t) f[t] = ustar * (rs * (left ? xl[t] : xr[t]));
+  for (int t = 5; t < NV; ++t) f[t] = mflux * (left ? xl[t] : xr[t]);
   f[nrm] += pstar;
 }
 

@@ -33,6 +33,8 @@ struct TileShape {
 };
 TileShape tile_f64(int nv);
 TileShape tile_f32(int nv);
+int occupancy_f64(int ntracer, bool d3);
+int occupancy_f32(int ntracer, bool d3);
 
 // Launchers; each returns 0 on success, -1 if the launch failed.
 int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);

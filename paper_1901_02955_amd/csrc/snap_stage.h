@@ -92,98 +92,174 @@ __device__ __forceinline__ void write_cell(const StageArgs& a, const T* __restri
 }
 
 // ---------------------------------------------------------------------------
-// LDS plane shared by both kernels: primitives with a 3-cell halo and the
-// face values / fluxes of the two in-plane axes ("x" and "second").
+// LDS plane shared by both kernels: primitives with a 3-cell halo and, per
+// in-plane axis, one value per face (first the left face state, then, after
+// the LMARS phase, the flux). The right face state of each face stays in the
+// registers of the thread that reconstructed it; reconstruction items of the
+// last round (beyond RREG rounds) park it in QS instead.
+//
+// Work items of the reconstruction and LMARS phases (same list, same thread):
+//   x items: cells ii = -1 .. TX along each row jj = 0 .. TY-1;
+//   second-axis items: cells jj = -1 .. TY along each column ii = 0 .. TX-1.
+// Item (cell c) writes the left state of face c+1 and keeps the right state
+// of face c; in the LMARS phase it evaluates face c (for c >= 0).
 // ---------------------------------------------------------------------------
+template <int TX, int TY>
+struct PlaneItems {
+  static constexpr int NTHR = TX * TY;
+  static constexpr int NRX = (TX + 2) * TY;
+  static constexpr int NRS = TX * (TY + 2);
+  static constexpr int NR = NRX + NRS;
+  static constexpr int ROUNDS = (NR + NTHR - 1) / NTHR;
+  static constexpr int RREG = ROUNDS < 2 ? ROUNDS : 2;
+  static constexpr int NSPILL = NR - RREG * NTHR > 0 ? NR - RREG * NTHR : 1;
+};
+
 template <typename T, int NV, int TX, int TY>
 struct Plane {
   T P[NV][TY + 6][TX + 6];
-  T XL[NV][TY][TX + 1];   // left state at x face f (after LMARS: flux)
-  T XR[NV][TY][TX + 1];   // right state at x face f
-  T SL[NV][TY + 1][TX];   // left state at second-axis face f (after LMARS: flux)
-  T SR[NV][TY + 1][TX];
+  T FX[NV][TY][TX + 1];
+  T FY[NV][TY + 1][TX];
+  T QS[PlaneItems<TX, TY>::NSPILL][NV];
 };
 
-// Phase R: WENO5 of every cell of the tile plus one halo cell on each side of
-// both in-plane axes. w x h is the active part of the tile.
+// Thread index used for item lists: the waves of a workgroup take turns at
+// the rounds that not every wave gets (e.g. 576 items over 4 waves), rotated
+// by block so that co-resident workgroups put the extra round on different
+// SIMDs.
+template <int NTHR>
+__device__ __forceinline__ int item_thread() {
+  if constexpr (NTHR % 64 == 0 && NTHR >= 128)
+    return (threadIdx.x + 64 * (blockIdx.x % (NTHR / 64))) % NTHR;
+  else
+    return threadIdx.x;
+}
+
+// Decode item `it` into (axis, ii, jj); returns false if the cell lies outside
+// the active w x h part of a ragged tile.
+template <int TX, int TY>
+__device__ __forceinline__ bool plane_item(int it, int w, int h, bool& xaxis, int& ii, int& jj) {
+  using I = PlaneItems<TX, TY>;
+  if (it < I::NRX) {
+    xaxis = true;
+    ii = it % (TX + 2) - 1;
+    jj = it / (TX + 2);
+    return ii <= w && jj < h;
+  }
+  const int r = it - I::NRX;
+  xaxis = false;
+  ii = r % TX;
+  jj = r / TX - 1;
+  return ii < w && jj <= h;
+}
+
+// Phase R: WENO5 of every item cell; left states to LDS, right states kept.
 template <typename T, int NV, int TX, int TY>
 __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w, int h, T eps,
-                                                  bool linear) {
-  constexpr int NTHR = TX * TY;
-  const int nrx = (w + 2) * h;
-  const int nrs = w * (h + 2);
-  for (int it = threadIdx.x; it < nrx + nrs; it += NTHR) {
-    if (it < nrx) {
-      const int ii = it % (w + 2) - 1, jj = it / (w + 2);
+                                                  bool linear,
+                                                  T (&QP)[PlaneItems<TX, TY>::RREG][NV]) {
+  using I = PlaneItems<TX, TY>;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const T* row = &S.P[v][jj + 3][ii + 1];
-        T qm, qp;
-        weno5_cell<T>(row[0], row[1], row[2], row[3], row[4], eps, linear, qm, qp);
-        if (ii < w) S.XL[v][jj][ii + 1] = qm;
-        if (ii >= 0) S.XR[v][jj][ii] = qp;
+  for (int r = 0; r < I::ROUNDS; ++r) {
+    const int it = item_thread<I::NTHR>() + r * I::NTHR;
+    bool xa;
+    int ii, jj;
+    if (it < I::NR && plane_item<TX, TY>(it, w, h, xa, ii, jj)) {
+      T qp[NV];
+      if (xa) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T* row = &S.P[v][jj + 3][ii + 1];
+          T qm;
+          weno5_cell<T>(row[0], row[1], row[2], row[3], row[4], eps, linear, qm, qp[v]);
+          if (ii < w) S.FX[v][jj][ii + 1] = qm;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          T qm;
+          weno5_cell<T>(S.P[v][jj + 1][ii + 3], S.P[v][jj + 2][ii + 3], S.P[v][jj + 3][ii + 3],
+                        S.P[v][jj + 4][ii + 3], S.P[v][jj + 5][ii + 3], eps, linear, qm, qp[v]);
+          if (jj < h) S.FY[v][jj + 1][ii] = qm;
+        }
       }
-    } else {
-      const int r = it - nrx;
-      const int ii = r % w, jj = r / w - 1;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        T qm, qp;
-        weno5_cell<T>(S.P[v][jj + 1][ii + 3], S.P[v][jj + 2][ii + 3], S.P[v][jj + 3][ii + 3],
-                      S.P[v][jj + 4][ii + 3], S.P[v][jj + 5][ii + 3], eps, linear, qm, qp);
-        if (jj < h) S.SL[v][jj + 1][ii] = qm;
-        if (jj >= 0) S.SR[v][jj][ii] = qp;
+        if (r < I::RREG)
+          QP[r < I::RREG ? r : 0][v] = qp[v];
+        else
+          S.QS[it - I::RREG * I::NTHR][v] = qp[v];
       }
     }
   }
 }
 
-// Phase L: LMARS at every x face and every second-axis face of the tile.
-// Reference density / pressure: x faces use the level of their row (xref);
-// second-axis faces use sref(face row).
+// Phase L: LMARS at every face of the tile, by the item that holds its right
+// state. x faces use the reference of their row (xref); second-axis faces use
+// sref(face index).
 template <typename T, int NV, int TX, int TY, typename XRef, typename SRef>
 __device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int h, int snrm,
-                                            T gamma, T inv_gm1, XRef xref, SRef sref) {
-  constexpr int NTHR = TX * TY;
-  const int nfx = (w + 1) * h;
-  const int nfs = w * (h + 1);
-  for (int it = threadIdx.x; it < nfx + nfs; it += NTHR) {
-    T xl[NV], xr[NV], f[NV];
-    if (it < nfx) {
-      const int fi = it % (w + 1), jj = it / (w + 1);
+                                            T gamma, T inv_gm1, XRef xref, SRef sref,
+                                            const T (&QP)[PlaneItems<TX, TY>::RREG][NV]) {
+  using I = PlaneItems<TX, TY>;
+#pragma unroll
+  for (int r = 0; r < I::ROUNDS; ++r) {
+    const int it = item_thread<I::NTHR>() + r * I::NTHR;
+    bool xa;
+    int ii, jj;
+    if (it < I::NR && plane_item<TX, TY>(it, w, h, xa, ii, jj) && ii >= 0 && jj >= 0) {
+      T xl[NV], xr[NV], f[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        xl[v] = S.XL[v][jj][fi];
-        xr[v] = S.XR[v][jj][fi];
+        xr[v] = r < I::RREG ? QP[r < I::RREG ? r : 0][v] : S.QS[it - I::RREG * I::NTHR][v];
+        xl[v] = xa ? S.FX[v][jj][ii] : S.FY[v][jj][ii];
       }
       T rr, pr;
-      xref(jj, rr, pr);
-      lmars_flux<T, NV>(xl, xr, 1, rr, pr, gamma, inv_gm1, f);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) S.XL[v][jj][fi] = f[v];
-    } else {
-      const int r = it - nfx;
-      const int ii = r % w, fj = r / w;
+      if (xa)
+        xref(jj, rr, pr);
+      else
+        sref(jj, rr, pr);
+      lmars_flux<T, NV>(xl, xr, xa ? 1 : snrm, rr, pr, gamma, inv_gm1, f);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        xl[v] = S.SL[v][fj][ii];
-        xr[v] = S.SR[v][fj][ii];
+        if (xa)
+          S.FX[v][jj][ii] = f[v];
+        else
+          S.FY[v][jj][ii] = f[v];
       }
-      T rr, pr;
-      sref(fj, rr, pr);
-      lmars_flux<T, NV>(xl, xr, snrm, rr, pr, gamma, inv_gm1, f);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) S.SL[v][fj][ii] = f[v];
     }
   }
+}
+
+// Halo item it of the plane: 6 cells beyond each x edge of every row, then 6
+// beyond each second-axis edge of every column. Returns false outside the
+// active part of a ragged tile.
+template <int TX, int TY>
+__device__ __forceinline__ bool halo_item(int it, int w, int h, int& ii, int& jj) {
+  if (it < 6 * TY) {
+    const int m = it % 6;
+    jj = it / 6;
+    ii = m < 3 ? m - 3 : w + m - 3;
+    return jj < h;
+  }
+  const int r = it - 6 * TY;
+  const int m = r % 6;
+  ii = r / 6;
+  jj = m < 3 ? m - 3 : h + m - 3;
+  return ii < w;
 }
 
 // ---------------------------------------------------------------------------
 // 3-D kernel
 // ---------------------------------------------------------------------------
+#ifndef SNAP_STAGE3D_WAVES_PER_EU
+#define SNAP_STAGE3D_WAVES_PER_EU 1
+#endif
+
 template <typename T, int NT, int TX, int TY>
-__global__ void __launch_bounds__(TX* TY) k_stage3d(StageArgs a) {
+__global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(StageArgs a) {
   constexpr int NV = 5 + NT;
+  using I = PlaneItems<TX, TY>;
   __shared__ Plane<T, NV, TX, TY> S;
   const T* __restrict__ qs = static_cast<const T*>(a.qs);
 
@@ -211,14 +287,12 @@ __global__ void __launch_bounds__(TX* TY) k_stage3d(StageArgs a) {
   const int ic = i0 + (act ? ti : 0), jc = j0 + (act ? tj : 0);
 
   T W[5][NV];     // primitives of levels s-1 .. s+3 (own column)
-  T qmc[NV];      // left state at the next vertical face
+  T qmc[NV];      // left state at the vertical face above the current level
   T fzc[NV];      // vertical flux at the lower face of the current level
-  T dfz[NV];      // vertical flux difference of the current level
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     qmc[v] = T(0);
     fzc[v] = T(0);
-    dfz[v] = T(0);
   }
   if (act) {
 #pragma unroll
@@ -228,17 +302,48 @@ __global__ void __launch_bounds__(TX* TY) k_stage3d(StageArgs a) {
     }
   }
 
+  T QP[I::RREG][NV];
   for (int s = k0 - 2; s < k1; ++s) {
-    // ---- vertical direction, own column ------------------------------------
-    if (act) {
+    if (act)
       load_prim<T, NV>(qs, poff(ic, jc, s + 3), a.sv, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG],
                        a.gm1, W[4]);
+    if (s >= k0) {
+      // ---- (P) primitives of level s: own cell from the window, halo loaded -
+      const double rbs = a.rbar_c[s + NG], pbs = a.pbar_c[s + NG];
+      if (act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.P[v][tj + 3][ti + 3] = W[1][v];
+      }
+      for (int it = item_thread<I::NTHR>(); it < 6 * (TX + TY); it += I::NTHR) {
+        int ii, jj;
+        if (halo_item<TX, TY>(it, w, h, ii, jj)) {
+          T x[NV];
+          load_prim<T, NV>(qs, poff(i0 + ii, j0 + jj, s), a.sv, rbs, pbs, a.gm1, x);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) S.P[v][jj + 3][ii + 3] = x[v];
+        }
+      }
+      __syncthreads();
+      // ---- (R) WENO5 in x and y ---------------------------------------------
+      phase_reconstruct<T, NV, TX, TY>(S, w, h, eps, linear, QP);
+      __syncthreads();
+      // ---- (L) LMARS at x and y faces (level references) ---------------------
+      const T rbT = static_cast<T>(rbs), pbT = static_cast<T>(pbs);
+      auto lev = [&](int, T& r, T& p) {
+        r = rbT;
+        p = pbT;
+      };
+      phase_lmars<T, NV, TX, TY>(S, w, h, 2, gamma, inv_gm1, lev, lev, QP);
+      __syncthreads();
+    }
+    // ---- vertical direction, own column: face s+1/2 (z-face index s+1) -------
+    T dfz[NV];
+    if (act) {
       T qmn[NV], qpn[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         weno5_cell<T>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, linear, qmn[v], qpn[v]);
       if (s >= k0 - 1) {
-        // face s+1/2 = z-face index s+1
         T fz[NV];
         lmars_flux<T, NV>(qmc, qpn, 3, static_cast<T>(a.rbar_f[s + 1]),
                           static_cast<T>(a.pbar_f[s + 1]), gamma, inv_gm1, fz);
@@ -251,62 +356,21 @@ __global__ void __launch_bounds__(TX* TY) k_stage3d(StageArgs a) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) qmc[v] = qmn[v];
     }
-
-    if (s >= k0) {
-      // ---- (P) primitives of level s: own cell from the window, halo loaded -
-      const double rbs = a.rbar_c[s + NG], pbs = a.pbar_c[s + NG];
-      if (act) {
+    // ---- (D) divergence, gravity, output -------------------------------------
+    if (s >= k0 && act) {
+      T R[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S.P[v][tj + 3][ti + 3] = W[1][v];
+      for (int v = 0; v < NV; ++v) {
+        T r = -((S.FX[v][tj][ti + 1] - S.FX[v][tj][ti]) * dxi);
+        r = r - (S.FY[v][tj + 1][ti] - S.FY[v][tj][ti]) * dyi;
+        R[v] = r - dfz[v] * dzi;
       }
-      {
-        const int nhx = 6 * h, nh = 6 * h + 6 * w;
-        for (int it = tid; it < nh; it += TX * TY) {
-          int ii, jj;
-          if (it < nhx) {
-            const int m = it % 6;
-            jj = it / 6;
-            ii = m < 3 ? m - 3 : w + m - 3;
-          } else {
-            const int r = it - nhx;
-            const int m = r % 6;
-            ii = r / 6;
-            jj = m < 3 ? m - 3 : h + m - 3;
-          }
-          T x[NV];
-          load_prim<T, NV>(qs, poff(i0 + ii, j0 + jj, s), a.sv, rbs, pbs, a.gm1, x);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) S.P[v][jj + 3][ii + 3] = x[v];
-        }
-      }
-      __syncthreads();
-      // ---- (R) WENO5 in x and y ---------------------------------------------
-      phase_reconstruct<T, NV, TX, TY>(S, w, h, eps, linear);
-      __syncthreads();
-      // ---- (L) LMARS at x and y faces (level references) ---------------------
-      const T rbT = static_cast<T>(rbs), pbT = static_cast<T>(pbs);
-      auto lev = [&](int, T& r, T& p) {
-        r = rbT;
-        p = pbT;
-      };
-      phase_lmars<T, NV, TX, TY>(S, w, h, 2, gamma, inv_gm1, lev, lev);
-      __syncthreads();
-      // ---- (D) divergence, gravity, output -----------------------------------
-      if (act) {
-        T R[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          T r = -((S.XL[v][tj][ti + 1] - S.XL[v][tj][ti]) * dxi);
-          r = r - (S.SL[v][tj + 1][ti] - S.SL[v][tj][ti]) * dyi;
-          R[v] = r - dfz[v] * dzi;
-        }
-        const long long po = poff(ic, jc, s);
-        const T grav = static_cast<T>(a.grav);
-        R[3] = R[3] - grav * W[1][0];
-        R[4] = R[4] - grav * qs[po + 3 * a.sv];
-        const long long ro = (long long)s * a.rz + (long long)jc * a.ry + ic;
-        write_cell<T, NV>(a, qs, po, ro, R);
-      }
+      const long long po = poff(ic, jc, s);
+      const T grav = static_cast<T>(a.grav);
+      R[3] = R[3] - grav * W[1][0];
+      R[4] = R[4] - grav * qs[po + 3 * a.sv];
+      const long long ro = (long long)s * a.rz + (long long)jc * a.ry + ic;
+      write_cell<T, NV>(a, qs, po, ro, R);
     }
     // shift the window
 #pragma unroll
@@ -322,6 +386,7 @@ __global__ void __launch_bounds__(TX* TY) k_stage3d(StageArgs a) {
 template <typename T, int NT, int TX, int TZ>
 __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
   constexpr int NV = 5 + NT;
+  using I = PlaneItems<TX, TZ>;
   __shared__ Plane<T, NV, TX, TZ> S;
   const T* __restrict__ qs = static_cast<const T*>(a.qs);
 
@@ -341,26 +406,16 @@ __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
   auto poff = [&](int i, int k) -> long long { return (long long)(k + NG) * a.sz + (i + NG); };
 
   // ---- (P) primitives of the tile and its halo --------------------------------
-  {
-    const int nown = TX * TZ;
-    const int nhx = 6 * h, nh = nhx + 6 * w;
-    for (int it = tid; it < nown + nh; it += TX * TZ) {
-      int ii, kk;
-      if (it < nown) {
-        ii = it % TX;
-        kk = it / TX;
-        if (ii >= w || kk >= h) continue;
-      } else if (it < nown + nhx) {
-        const int r = it - nown;
-        const int m = r % 6;
-        kk = r / 6;
-        ii = m < 3 ? m - 3 : w + m - 3;
-      } else {
-        const int r = it - nown - nhx;
-        const int m = r % 6;
-        ii = r / 6;
-        kk = m < 3 ? m - 3 : h + m - 3;
-      }
+  if (act) {
+    const int k = k0 + tk;
+    T x[NV];
+    load_prim<T, NV>(qs, poff(i0 + ti, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, x);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S.P[v][tk + 3][ti + 3] = x[v];
+  }
+  for (int it = item_thread<I::NTHR>(); it < 6 * (TX + TZ); it += I::NTHR) {
+    int ii, kk;
+    if (halo_item<TX, TZ>(it, w, h, ii, kk)) {
       const int k = k0 + kk;
       T x[NV];
       load_prim<T, NV>(qs, poff(i0 + ii, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, x);
@@ -369,7 +424,8 @@ __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
     }
   }
   __syncthreads();
-  phase_reconstruct<T, NV, TX, TZ>(S, w, h, eps, linear);
+  T QP[I::RREG][NV];
+  phase_reconstruct<T, NV, TX, TZ>(S, w, h, eps, linear, QP);
   __syncthreads();
   auto xref = [&](int kk, T& r, T& p) {
     r = static_cast<T>(a.rbar_c[k0 + kk + NG]);
@@ -379,14 +435,14 @@ __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
     r = static_cast<T>(a.rbar_f[k0 + fk]);
     p = static_cast<T>(a.pbar_f[k0 + fk]);
   };
-  phase_lmars<T, NV, TX, TZ>(S, w, h, 3, gamma, inv_gm1, xref, zref);
+  phase_lmars<T, NV, TX, TZ>(S, w, h, 3, gamma, inv_gm1, xref, zref, QP);
   __syncthreads();
   if (act) {
     T R[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const T r = -((S.XL[v][tk][ti + 1] - S.XL[v][tk][ti]) * dxi);
-      R[v] = r - (S.SL[v][tk + 1][ti] - S.SL[v][tk][ti]) * dzi;
+      const T r = -((S.FX[v][tk][ti + 1] - S.FX[v][tk][ti]) * dxi);
+      R[v] = r - (S.FY[v][tk + 1][ti] - S.FY[v][tk][ti]) * dzi;
     }
     const int i = i0 + ti, k = k0 + tk;
     const long long po = poff(i, k);

@@ -10,4 +10,6 @@ int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t
 
 TileShape tile_f32(int nv) { return tile_t<float>(nv); }
 
+int occupancy_f32(int ntracer, bool d3) { return occupancy_t<float>(ntracer, d3); }
+
 }  // namespace snap

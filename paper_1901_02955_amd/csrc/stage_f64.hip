@@ -9,4 +9,6 @@ int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t
 
 TileShape tile_f64(int nv) { return tile_t<double>(nv); }
 
+int occupancy_f64(int ntracer, bool d3) { return occupancy_t<double>(ntracer, d3); }
+
 }  // namespace snap

@@ -7,16 +7,21 @@
 
 namespace snap {
 
-// LDS bytes of one Plane per variable: (TY+6)(TX+6) + 2 TY (TX+1) + 2 (TY+1) TX
-// elements. The shapes keep one workgroup's plane at or below 64 KiB.
+// Tile shape per element type and variable count: the largest of 16 x 16,
+// 16 x 8 and 8 x 8 whose LDS plane stays within 56 KiB, so that at least two
+// (usually three) workgroups share a compute unit's 160 KiB of LDS.
 template <typename T, int NT>
 struct TileFor {
   static constexpr int NV = 5 + NT;
-  static constexpr int BYTES = sizeof(T) * NV;
-  static constexpr bool BIG = BYTES * 1572 <= 65536;   // 16 x 16
-  static constexpr bool MID = BYTES * 868 <= 65536;    // 16 x 8
+  static constexpr bool BIG = sizeof(Plane<T, NV, 16, 16>) <= 56 * 1024;
+  static constexpr bool MID = sizeof(Plane<T, NV, 16, 8>) <= 56 * 1024;
+#if defined(SNAP_TILE_X) && defined(SNAP_TILE_Y)
+  static constexpr int TX = NT == 0 ? SNAP_TILE_X : (BIG || MID ? 16 : 8);
+  static constexpr int TY = NT == 0 ? SNAP_TILE_Y : (BIG ? 16 : 8);
+#else
   static constexpr int TX = BIG || MID ? 16 : 8;
-  static constexpr int TY = BIG ? 16 : (MID ? 8 : 8);
+  static constexpr int TY = BIG ? 16 : 8;
+#endif
 };
 
 template <typename T, int NT>
@@ -27,6 +32,33 @@ int launch_nt(bool d3, const StageArgs& a, int nblocks, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_stage2d<T, NT, TX, TY>), dim3(nblocks), dim3(TX * TY), 0, st, a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T, int NT>
+int occupancy_nt(bool d3) {
+  constexpr int TX = TileFor<T, NT>::TX, TY = TileFor<T, NT>::TY;
+  int n = 0;
+  const void* k = d3 ? reinterpret_cast<const void*>(&k_stage3d<T, NT, TX, TY>)
+                     : reinterpret_cast<const void*>(&k_stage2d<T, NT, TX, TY>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, TX * TY, 0) != hipSuccess) return 0;
+  return n;
+}
+
+// Workgroups of the stage kernel that fit on one compute unit (0 if unknown).
+template <typename T>
+int occupancy_t(int ntracer, bool d3) {
+  switch (ntracer) {
+    case 0: return occupancy_nt<T, 0>(d3);
+    case 1: return occupancy_nt<T, 1>(d3);
+    case 2: return occupancy_nt<T, 2>(d3);
+    case 3: return occupancy_nt<T, 3>(d3);
+    case 4: return occupancy_nt<T, 4>(d3);
+    case 5: return occupancy_nt<T, 5>(d3);
+    case 6: return occupancy_nt<T, 6>(d3);
+    case 7: return occupancy_nt<T, 7>(d3);
+    case 8: return occupancy_nt<T, 8>(d3);
+    default: return 0;
+  }
 }
 
 template <typename T>
