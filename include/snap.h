@@ -165,6 +165,38 @@ int snap_rhs(const snap_grid* g, void* q, void* rhs, void* stream);
 int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stream);
 
 /*
+ * Discrete adjoint of the right-hand side (reverse mode of snap_rhs, i.e. of
+ * Sec. 4 eq. forward with the fluxes of Sec. 4.1 and the reconstruction of
+ * Sec. 4.2, ghost cells being functions of the interior through `bc`):
+ *   q_bar = J(q)^T rhs_bar,  J = d rhs / d (interior of q).
+ * q        padded state at which J is taken (ghosts overwritten, interior read).
+ * rhs_bar  interior array [nvar][nz][ny][nx], read.
+ * q_bar    interior array [nvar][nz][ny][nx], overwritten; must not alias q or
+ *          rhs_bar.
+ * At an interface velocity u* of exactly zero, where the upwind choice of LMARS
+ * switches sides, the derivative of the advective flux with respect to u* uses
+ * the mean of both sides' advected vectors (the one-sided derivatives differ
+ * there). The result is reproducible bit for bit (no atomics).
+ * work  device workspace of snap_workspace_bytes(g, SNAP_OP_RHS_ADJ) bytes.
+ */
+int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_bar, void* work,
+                     void* stream);
+
+/*
+ * Adjoint of one snap_rk3_step with the same fixed dt (dt is not a variable of
+ * differentiation): given q_bar = dL/dQ^{n+1}, overwrite it with dL/dQ^n.
+ * The stage states Q1 and Q2 are recomputed from q_n; then, reversing the
+ * three stages of Sec. 4.3,
+ *   B2 = 2/3 (q_bar + dt J(Q2)^T q_bar);  B1 = 1/4 (B2 + dt J(Q1)^T B2);
+ *   q_bar <- q_bar/3 + 3/4 B2 + B1 + dt J(Q^n)^T B1.
+ * q_n    padded state Q^n (ghosts overwritten, interior read).
+ * q_bar  interior array [nvar][nz][ny][nx], in: dL/dQ^{n+1}, out: dL/dQ^n.
+ * work   device workspace of snap_workspace_bytes(g, SNAP_OP_RK3_ADJ) bytes.
+ */
+int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar, void* work,
+                          void* stream);
+
+/*
  * Largest stable step dt = cfl / max over interior cells of
  *   sum_d (|u_d| + c) / dx_d,  c = sqrt(gamma p / rho)
  * (the time-step rule is this library's reading; the paper gives none).

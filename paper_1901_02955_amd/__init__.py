@@ -20,7 +20,8 @@ __all__ = [
     "SnapError", "DeviceGrid", "device_grid", "lib", "workspace",
     "snap_fill_ghosts", "snap_rhs", "snap_rk3_step", "snap_cfl_dt",
     "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
-    "snap_stage_timing_enable", "snap_stage_timing_read",
+    "snap_stage_timing_enable", "snap_stage_timing_read", "snap_rhs_adjoint",
+    "snap_rk3_step_adjoint", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ",
     "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
 ]
@@ -86,6 +87,8 @@ _SIGNATURES = {
     "snap_rk3_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P]),
     "snap_cfl_dt": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "snap_rhs_adjoint": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P]),
+    "snap_rk3_step_adjoint": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P, _P]),
     "snap_stage_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "snap_stage_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),
@@ -249,6 +252,30 @@ def snap_conservation_sums(grid: DeviceGrid, q: torch.Tensor, work: torch.Tensor
     _check(lib().snap_conservation_sums(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
                                         ctypes.c_void_p(work.data_ptr()), out, _stream(stream)))
     return np.array(out[:], dtype=np.float64)
+
+
+def snap_rhs_adjoint(grid: DeviceGrid, q: torch.Tensor, rhs_bar: torch.Tensor,
+                     q_bar: torch.Tensor, work: torch.Tensor, stream=None) -> None:
+    grid._check_state(q)
+    grid._check_state(rhs_bar, "rhs_bar", grid.interior_shape)
+    grid._check_state(q_bar, "q_bar", grid.interior_shape)
+    if work.numel() < snap_workspace_bytes(grid, SNAP_OP_RHS_ADJ):
+        raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RHS_ADJ)")
+    _check(lib().snap_rhs_adjoint(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
+                                  ctypes.c_void_p(rhs_bar.data_ptr()),
+                                  ctypes.c_void_p(q_bar.data_ptr()),
+                                  ctypes.c_void_p(work.data_ptr()), _stream(stream)))
+
+
+def snap_rk3_step_adjoint(grid: DeviceGrid, q_n: torch.Tensor, dt: float, q_bar: torch.Tensor,
+                          work: torch.Tensor, stream=None) -> None:
+    grid._check_state(q_n)
+    grid._check_state(q_bar, "q_bar", grid.interior_shape)
+    if work.numel() < snap_workspace_bytes(grid, SNAP_OP_RK3_ADJ):
+        raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3_ADJ)")
+    _check(lib().snap_rk3_step_adjoint(grid.ptr(), ctypes.c_void_p(q_n.data_ptr()),
+                                       ctypes.c_double(dt), ctypes.c_void_p(q_bar.data_ptr()),
+                                       ctypes.c_void_p(work.data_ptr()), _stream(stream)))
 
 
 def snap_stage_timing_enable(enable: bool) -> None:

@@ -1,0 +1,73 @@
+"""Differentiable multi-step SSP-RK3 integration on the GPU (torch.autograd).
+
+``rk3_run(grid, q0, dt, nsteps, checkpoint_every)`` advances a padded state by
+``nsteps`` calls of ``snap_rk3_step`` and, under autograd, back-propagates
+through them with ``snap_rk3_step_adjoint`` (the discrete adjoint of the
+three-stage scheme of Sec. 4.3 with fixed dt). Memory is bounded by step
+checkpointing: the forward pass keeps the state every ``checkpoint_every``
+steps; the backward pass re-runs each segment from its checkpoint, keeping the
+segment's states, and then walks it in reverse.
+
+Only the interior of the state carries gradients: the library overwrites ghost
+layers from the interior on every call, so the gradient with respect to the
+ghost layers of ``q0`` is zero, and ghost layers of the output (unspecified
+after a step) receive no gradient.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (SNAP_NG, SNAP_OP_RK3, SNAP_OP_RK3_ADJ, DeviceGrid, snap_rk3_step,
+               snap_rk3_step_adjoint, workspace)
+
+
+def _interior(grid: DeviceGrid, q: torch.Tensor) -> torch.Tensor:
+    g = SNAP_NG
+    gy = grid.gy
+    return q[:, g:g + grid.nz, gy:gy + grid.ny, g:g + grid.nx]
+
+
+class _SnapRK3Run(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q0: torch.Tensor, grid: DeviceGrid, dt: float, nsteps: int,
+                checkpoint_every: int):
+        work = workspace(grid, SNAP_OP_RK3)
+        q = q0.detach().clone()
+        checkpoints = []
+        for n in range(nsteps):
+            if n % checkpoint_every == 0:
+                checkpoints.append(q.clone())
+            snap_rk3_step(grid, q, dt, work)
+        ctx.grid, ctx.dt, ctx.nsteps, ctx.every = grid, dt, nsteps, checkpoint_every
+        ctx.checkpoints = checkpoints
+        return q
+
+    @staticmethod
+    def backward(ctx, grad_out: torch.Tensor):
+        grid, dt, nsteps, every = ctx.grid, ctx.dt, ctx.nsteps, ctx.every
+        work = workspace(grid, SNAP_OP_RK3)
+        awork = workspace(grid, SNAP_OP_RK3_ADJ)
+        qbar = _interior(grid, grad_out).contiguous().clone()
+        for seg in range(len(ctx.checkpoints) - 1, -1, -1):
+            start = seg * every
+            stop = min(start + every, nsteps)
+            states = [ctx.checkpoints[seg].clone()]
+            for _ in range(start, stop - 1):
+                nxt = states[-1].clone()
+                snap_rk3_step(grid, nxt, dt, work)
+                states.append(nxt)
+            for t in range(stop - start - 1, -1, -1):
+                snap_rk3_step_adjoint(grid, states[t], dt, qbar, awork)
+            del states
+        grad_in = torch.zeros_like(grad_out)
+        _interior(grid, grad_in).copy_(qbar)
+        ctx.checkpoints = None
+        return grad_in, None, None, None, None
+
+
+def rk3_run(grid: DeviceGrid, q0: torch.Tensor, dt: float, nsteps: int,
+            checkpoint_every: int = 20) -> torch.Tensor:
+    """State after ``nsteps`` SSP-RK3 steps of fixed ``dt``; differentiable in q0's interior."""
+    if nsteps < 1 or checkpoint_every < 1:
+        raise ValueError("nsteps and checkpoint_every must be >= 1")
+    return _SnapRK3Run.apply(q0, grid, float(dt), int(nsteps), int(checkpoint_every))

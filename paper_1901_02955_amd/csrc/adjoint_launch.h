@@ -1,0 +1,84 @@
+// Dispatch of the adjoint kernels for one element type (included once per type).
+#pragma once
+
+#include "snap_adjoint.h"
+#include "snap_internal.h"
+
+namespace snap {
+
+inline unsigned adj_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+template <typename T, int NV>
+int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, hipStream_t st) {
+  const T* qs = static_cast<const T*>(q);
+  const T* r = static_cast<const T*>(rb);
+  T* W = static_cast<T*>(w.W);
+  T* P = static_cast<T*>(w.P);
+  T* S = static_cast<T*>(w.S);
+  T* C = static_cast<T*>(w.C);
+  const long long np = a.sv;
+  hipLaunchKernelGGL((k_adj_prims<T, NV>), dim3(adj_blocks(np)), dim3(256), 0, st, qs, a, W);
+  hipLaunchKernelGGL((k_adj_zero<T>), dim3(adj_blocks(np * NV)), dim3(256), 0, st, P, np * NV);
+  for (int d = 0; d < 3; ++d) {
+    if (d == 1 && !a.d3) continue;
+    const DirBox fb = dir_box(a, d, 1), rbx = dir_box(a, d, 2), gb = dir_box(a, d, 6);
+    hipLaunchKernelGGL((k_adj_faces<T, NV>), dim3(adj_blocks(fb.total)), dim3(256), 0, st, W, r,
+                       a, d, S);
+    hipLaunchKernelGGL((k_adj_recon<T, NV>), dim3(adj_blocks(rbx.total)), dim3(256), 0, st, W, S,
+                       a, d, C);
+    hipLaunchKernelGGL((k_adj_gather<T, NV>), dim3(adj_blocks(gb.total)), dim3(256), 0, st, C, a,
+                       d, 1, P);
+  }
+  // the conserved cotangent reuses W (dead after the reconstruction passes)
+  hipLaunchKernelGGL((k_adj_cons<T, NV>), dim3(adj_blocks(np)), dim3(256), 0, st, qs, P, r, a, W);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T, int NV>
+int adj_fold_nv(const AdjWork& w, const AdjArgs& a, void* out, int mode, double alpha,
+                double beta, hipStream_t st) {
+  const long long n = (long long)a.nx * a.ny * a.nz;
+  hipLaunchKernelGGL((k_adj_fold<T, NV>), dim3(adj_blocks(n)), dim3(256), 0, st,
+                     static_cast<const T*>(w.W), a, static_cast<T*>(out), mode, alpha, beta);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T>
+int adj_rhs_t(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
+              int mode, double alpha, double beta, hipStream_t st) {
+  int r = -1;
+  switch (a.nvar) {
+#define SNAP_ADJ_CASE(NVV)                                                      \
+  case NVV:                                                                     \
+    r = adj_rhs_nv<T, NVV>(w, a, q, rb, st);                                    \
+    if (r == 0) r = adj_fold_nv<T, NVV>(w, a, out, mode, alpha, beta, st);      \
+    break;
+    SNAP_ADJ_CASE(5)
+    SNAP_ADJ_CASE(6)
+    SNAP_ADJ_CASE(7)
+    SNAP_ADJ_CASE(8)
+    SNAP_ADJ_CASE(9)
+    SNAP_ADJ_CASE(10)
+    SNAP_ADJ_CASE(11)
+    SNAP_ADJ_CASE(12)
+    SNAP_ADJ_CASE(13)
+#undef SNAP_ADJ_CASE
+    default: r = -1;
+  }
+  return r;
+}
+
+template <typename T>
+int adj_combine_t(void* out, const void* x, const void* y, const void* z, double ca, double cb,
+                  double cc, long long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_adj_combine<T>), dim3(adj_blocks(n)), dim3(256), 0, st,
+                     static_cast<T*>(out), static_cast<const T*>(x), static_cast<const T*>(y),
+                     static_cast<const T*>(z), ca, cb, cc, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace snap

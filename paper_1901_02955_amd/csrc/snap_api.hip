@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/snap.h"
+#include "snap_adjoint.h"
 #include "snap_internal.h"
 
 using namespace snap;
@@ -247,6 +248,100 @@ int fill(const snap_grid* g, void* q, hipStream_t st) {
   return launch_fill_ghosts(g->dtype, q, a, st) == 0 ? SNAP_OK : device_fail("ghost fill launch");
 }
 
+AdjArgs adj_args(const snap_grid* g) {
+  AdjArgs a;
+  memset(&a, 0, sizeof a);
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.d3 = d3;
+  a.nvar = nvar_of(g);
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.ry = g->nx;
+  a.rz = (long long)g->nx * g->ny;
+  a.rv = a.rz * g->nz;
+  a.dxi[0] = 1.0 / g->dx;
+  a.dxi[1] = d3 ? 1.0 / g->dy : 0.0;
+  a.dxi[2] = 1.0 / g->dz;
+  a.gamma = g->gamma;
+  a.gm1 = g->gamma - 1.0;
+  a.inv_gm1 = 1.0 / (g->gamma - 1.0);
+  a.grav = g->grav;
+  a.eps = g->weno_eps;
+  a.linear = g->weno_linear;
+  for (int d = 0; d < 3; ++d) a.bc[d] = g->bc[d];
+  a.rbar_c = g->rhobar_cell;
+  a.pbar_c = g->pbar_cell;
+  a.rbar_f = g->rhobar_face;
+  a.pbar_f = g->pbar_face;
+  return a;
+}
+
+size_t interior_bytes(const snap_grid* g) {
+  return (size_t)g->nx * g->ny * g->nz * nvar_of(g) * elem_of(g);
+}
+
+// Layout of the right-hand-side adjoint workspace: W and P (padded state
+// size each), S (2 nvar values per face of the largest direction) and C
+// (5 nvar values per reconstructed cell of the largest direction).
+struct AdjLayout {
+  size_t w, p, s, c, total;
+};
+
+AdjLayout adj_layout(const snap_grid* g) {
+  const AdjArgs a = adj_args(g);
+  long long fmax = 0, rmax = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (d == 1 && !a.d3) continue;
+    const long long f = dir_box(a, d, 1).total, r = dir_box(a, d, 2).total;
+    fmax = f > fmax ? f : fmax;
+    rmax = r > rmax ? r : rmax;
+  }
+  AdjLayout L;
+  L.w = 0;
+  L.p = L.w + align256(padded_bytes(g));
+  L.s = L.p + align256(padded_bytes(g));
+  L.c = L.s + align256((size_t)2 * a.nvar * fmax * elem_of(g));
+  L.total = L.c + align256((size_t)5 * a.nvar * rmax * elem_of(g));
+  return L;
+}
+
+AdjWork adj_work(const snap_grid* g, void* base) {
+  const AdjLayout L = adj_layout(g);
+  char* b = static_cast<char*>(base);
+  AdjWork w;
+  w.W = b + L.w;
+  w.P = b + L.p;
+  w.S = b + L.s;
+  w.C = b + L.c;
+  return w;
+}
+
+// q_bar-like interior array: out = mode 0: J^T rb; 1: out + J^T rb;
+// 2: alpha out + beta J^T rb. q must have its ghosts filled.
+int run_adj_rhs(const snap_grid* g, void* q, const void* rb, void* out, int mode, double alpha,
+                double beta, void* work, hipStream_t st) {
+  const AdjArgs a = adj_args(g);
+  const AdjWork w = adj_work(g, work);
+  const int r = g->dtype == SNAP_F64
+                    ? launch_adj_rhs_f64(w, a, q, rb, out, mode, alpha, beta, st)
+                    : launch_adj_rhs_f32(w, a, q, rb, out, mode, alpha, beta, st);
+  return r == 0 ? SNAP_OK : device_fail("adjoint kernel launch");
+}
+
+int run_combine(const snap_grid* g, void* out, const void* x, const void* y, const void* z,
+                double ca, double cb, double cc, hipStream_t st) {
+  const long long n = (long long)g->nx * g->ny * g->nz * nvar_of(g);
+  const int r = g->dtype == SNAP_F64 ? launch_adj_combine_f64(out, x, y, z, ca, cb, cc, n, st)
+                                     : launch_adj_combine_f32(out, x, y, z, ca, cb, cc, n, st);
+  return r == 0 ? SNAP_OK : device_fail("combine kernel launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -264,6 +359,10 @@ size_t snap_workspace_bytes(const snap_grid* g, int op) {
     case SNAP_OP_SUMS:
       return align256((size_t)SUM_BLOCKS * nvar_of(g) * sizeof(double)) +
              align256(nvar_of(g) * sizeof(double));
+    case SNAP_OP_RHS_ADJ: return adj_layout(g).total;
+    case SNAP_OP_RK3_ADJ:
+      return 2 * align256(padded_bytes(g)) + 2 * align256(interior_bytes(g)) +
+             adj_layout(g).total;
     default: fail(SNAP_E_INVALID, "unknown workspace operation %d", op); return 0;
   }
 }
@@ -353,6 +452,65 @@ int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stre
   a.ca = 1.0 / 3.0;
   a.cb = 2.0 / 3.0;
   if ((r = run_stage(g, a, st))) return r;
+  return ok();
+}
+
+int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_bar, void* work,
+                     void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !rhs_bar || !q_bar || !work)
+    return fail(SNAP_E_INVALID, "q, rhs_bar, q_bar or work is NULL");
+  if (q_bar == q || q_bar == rhs_bar) return fail(SNAP_E_INVALID, "q_bar must not alias q or rhs_bar");
+  const hipStream_t st = (hipStream_t)stream;
+  if ((r = fill(g, q, st))) return r;
+  if ((r = run_adj_rhs(g, q, rhs_bar, q_bar, 0, 0.0, 1.0, work, st))) return r;
+  return ok();
+}
+
+int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar, void* work,
+                          void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q_n || !q_bar || !work) return fail(SNAP_E_INVALID, "q_n, q_bar or work is NULL");
+  if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
+  const hipStream_t st = (hipStream_t)stream;
+  char* b = static_cast<char*>(work);
+  void* q1 = b;
+  void* q2 = b + align256(padded_bytes(g));
+  void* b2 = b + 2 * align256(padded_bytes(g));
+  void* b1 = static_cast<char*>(b2) + align256(interior_bytes(g));
+  void* aw = static_cast<char*>(b1) + align256(interior_bytes(g));
+  // recompute the stage states Q1 and Q2 of the forward step
+  StageArgs a = stage_args(g);
+  a.dt = dt;
+  a.rhs_mode = 0;
+  if ((r = fill(g, q_n, st))) return r;
+  a.qs = q_n;
+  a.qn = nullptr;
+  a.out = q1;
+  a.ca = 0.0;
+  a.cb = 1.0;
+  if ((r = run_stage(g, a, st))) return r;
+  if ((r = fill(g, q1, st))) return r;
+  a.qs = q1;
+  a.qn = q_n;
+  a.out = q2;
+  a.ca = 0.75;
+  a.cb = 0.25;
+  if ((r = run_stage(g, a, st))) return r;
+  // Q3 = Q/3 + 2/3 (Q2 + dt R(Q2)):  B2 = 2/3 (Qb3 + dt J(Q2)^T Qb3)
+  if ((r = run_combine(g, b2, q_bar, nullptr, nullptr, 1.0, 0.0, 0.0, st))) return r;
+  if ((r = fill(g, q2, st))) return r;
+  if ((r = run_adj_rhs(g, q2, q_bar, b2, 2, 2.0 / 3.0, 2.0 / 3.0 * dt, aw, st))) return r;
+  // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1)):  B1 = 1/4 (B2 + dt J(Q1)^T B2)
+  if ((r = run_combine(g, b1, b2, nullptr, nullptr, 1.0, 0.0, 0.0, st))) return r;
+  if ((r = fill(g, q1, st))) return r;
+  if ((r = run_adj_rhs(g, q1, b2, b1, 2, 0.25, 0.25 * dt, aw, st))) return r;
+  // Q1 = Q + dt R(Q):  Qb = Qb3/3 + 3/4 B2 + B1 + dt J(Q)^T B1
+  if ((r = run_combine(g, q_bar, q_bar, b2, b1, 1.0 / 3.0, 0.75, 1.0, st))) return r;
+  if ((r = fill(g, q_n, st))) return r;
+  if ((r = run_adj_rhs(g, q_n, b1, q_bar, 2, 1.0, dt, aw, st))) return r;
   return ok();
 }
 

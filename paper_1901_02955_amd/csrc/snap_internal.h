@@ -36,7 +36,25 @@ TileShape tile_f32(int nv);
 int occupancy_f64(int ntracer, bool d3);
 int occupancy_f32(int ntracer, bool d3);
 
+struct AdjArgs;
+
+// Workspace pointers of one right-hand-side adjoint.
+struct AdjWork {
+  void* W;   // padded primitives, then padded conserved cotangent
+  void* P;   // padded primitive cotangent
+  void* S;   // face-state cotangents of one direction
+  void* C;   // stencil-input cotangents of one direction
+};
+
 // Launchers; each returns 0 on success, -1 if the launch failed.
+int launch_adj_rhs_f64(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb,
+                       void* out, int mode, double alpha, double beta, hipStream_t st);
+int launch_adj_rhs_f32(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb,
+                       void* out, int mode, double alpha, double beta, hipStream_t st);
+int launch_adj_combine_f64(void* out, const void* x, const void* y, const void* z, double ca,
+                           double cb, double cc, long long n, hipStream_t st);
+int launch_adj_combine_f32(void* out, const void* x, const void* y, const void* z, double ca,
+                           double cb, double cc, long long n, hipStream_t st);
 int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st);

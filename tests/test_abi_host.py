@@ -85,6 +85,8 @@ def test_invalid_grid_rejected_by_every_entry_point(kw):
         lambda: lib.snap_rk3_step(g, P, 0.1, P, None),
         lambda: lib.snap_cfl_dt(g, P, 0.9, P, ctypes.byref(d), None),
         lambda: lib.snap_conservation_sums(g, P, P, sums, None),
+        lambda: lib.snap_rhs_adjoint(g, P, ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE), P, None),
+        lambda: lib.snap_rk3_step_adjoint(g, P, 0.1, ctypes.c_void_p(2 * FAKE), P, None),
     ]
     for call in calls:
         assert call() == snap.SNAP_E_INVALID
@@ -120,6 +122,13 @@ def test_invalid_buffers_and_scalars():
     assert lib.snap_cfl_dt(g, P, 0.9, P, None, None) == snap.SNAP_E_INVALID
     assert lib.snap_conservation_sums(g, P, None, sums, None) == snap.SNAP_E_INVALID
     assert lib.snap_conservation_sums(g, P, P, None, None) == snap.SNAP_E_INVALID
+    Q2, Q3 = ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE)
+    assert lib.snap_rhs_adjoint(g, P, Q2, P, Q3, None) == snap.SNAP_E_INVALID     # q_bar aliases q
+    assert lib.snap_rhs_adjoint(g, P, Q2, Q2, Q3, None) == snap.SNAP_E_INVALID    # q_bar aliases rhs_bar
+    assert lib.snap_rhs_adjoint(g, P, Q2, Q3, None, None) == snap.SNAP_E_INVALID
+    for dt in (0.0, -1.0, math.nan):
+        assert lib.snap_rk3_step_adjoint(g, P, dt, Q2, Q3, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_adjoint(g, P, 0.1, None, Q3, None) == snap.SNAP_E_INVALID
 
 
 def test_two_d_ignores_y_spacing_and_bc():
@@ -141,5 +150,9 @@ def test_workspace_sizes():
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RHS) == 0
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_CFL) >= 8
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_SUMS) >= 8 * (5 + c.ntracer)
+        adj = lib.snap_workspace_bytes(g, snap.SNAP_OP_RHS_ADJ)
+        assert adj >= 2 * padded + 7 * (5 + c.ntracer) * (c.nx + 1) * c.ny * c.nz * es
+        interior = c.nx * c.ny * c.nz * (5 + c.ntracer) * es
+        assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3_ADJ) >= adj + 2 * padded + 2 * interior
     assert lib.snap_workspace_bytes(ctypes.byref(good_grid()), 99) == 0
     assert b"unknown" in lib.snap_last_error()

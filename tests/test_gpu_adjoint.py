@@ -1,0 +1,204 @@
+"""GPU parity of the discrete adjoint against the oracle's autograd adjoint.
+
+Bars (FP64):
+* snap_rhs_adjoint within 1e-11 per field of the oracle's J^T r_bar, relative
+  to the largest magnitude of that field (the reverse sweep sums up to 15
+  contributions per cell in a different order from autograd, and the forward
+  face states it linearises around use the refined reciprocal / square root,
+  a couple of ulp away from the oracle's);
+* snap_rk3_step_adjoint within the same bar;
+* dot-product identity <w, J v> = <J^T w, v> with J v from Richardson-
+  extrapolated central differences of the GPU forward right-hand side
+  (relative agreement 1e-6, the truncation and rounding error of the quotient);
+* the adjoint is reproducible bit for bit;
+* the checkpointed multi-step autograd function matches step-by-step adjoints
+  and a finite-difference directional derivative of the loss.
+States at rest are left out: there the interface velocity u* is rounding noise
+around zero, where LMARS switches its upwind side, so two correct evaluation
+orders may linearise on different sides of the switch.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_02955_amd as snap
+from paper_1901_02955_amd.autograd import rk3_run
+import workloads as wl
+from tests import cases as C
+from tests.test_gpu_parity import field_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL_ADJ = 1e-11
+ADJ_CASES = ["2d_smooth_37x29_nt3", "2d_reflect_21x19", "2d_thin_19x2", "3d_smooth_35x21x19",
+             "3d_tracers_20x18x24_nt4", "3d_linear_17x9x11", "3d_nt8_10x12x9",
+             "3d_periodic_z_12x10x14", "3d_small_2x3x4"]
+
+
+def case(name):
+    return C.build_case(name, dict(C.SPECS)[name])
+
+
+@pytest.mark.parametrize("name", ADJ_CASES)
+def test_rhs_adjoint_fp64(name):
+    c = case(name)
+    print(f"[adjoint] rhs {name}", flush=True)
+    rbar = wl.seeded_normal(c.grid.interior_shape, 100)
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    rb = torch.as_tensor(rbar).cuda()
+    qb = torch.empty_like(rb)
+    work = snap.workspace(dg, snap.SNAP_OP_RHS_ADJ)
+    snap.snap_rhs_adjoint(dg, qd, rb, qb, work)
+    ref = oracle.rhs_adjoint(c.q, c.grid, rbar).numpy()
+    errs = field_errors(qb.cpu().numpy(), ref)
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= TOL_ADJ for e in errs), errs
+
+
+@pytest.mark.parametrize("name", ["2d_smooth_37x29_nt3", "3d_smooth_35x21x19",
+                                  "3d_tracers_20x18x24_nt4", "3d_small_2x3x4"])
+def test_rk3_step_adjoint_fp64(name):
+    c = case(name)
+    print(f"[adjoint] rk3 {name}", flush=True)
+    qbar_next = wl.seeded_normal(c.grid.interior_shape, 101)
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    qb = torch.as_tensor(qbar_next).cuda().contiguous()
+    work = snap.workspace(dg, snap.SNAP_OP_RK3_ADJ)
+    snap.snap_rk3_step_adjoint(dg, qd, c.dt, qb, work)
+    ref = oracle.rk3_step_adjoint(c.q, c.grid, c.dt, qbar_next).numpy()
+    errs = field_errors(qb.cpu().numpy(), ref)
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= TOL_ADJ for e in errs), errs
+
+
+@pytest.mark.parametrize("name", ["2d_smooth_37x29_nt3", "3d_smooth_35x21x19"])
+def test_dot_product_identity_gpu(name):
+    c = case(name)
+    g = c.grid
+    dg = snap.device_grid(g)
+    v = wl.seeded_normal(g.interior_shape, 102)
+    w = wl.seeded_normal(g.interior_shape, 103)
+    qi = g.interior(c.q)
+    v *= np.abs(qi).reshape(g.nvar, -1).max(axis=1)[:, None, None, None]
+    rhs = torch.empty(dg.interior_shape, dtype=torch.float64, device="cuda")
+
+    def R(qq):
+        snap.snap_rhs(dg, torch.as_tensor(qq).cuda(), rhs)
+        return rhs.cpu().numpy().copy()
+
+    jv = richardson_jvp(lambda s: R(shifted(g, c.q, v, s)), 1e-7)
+    qb = torch.empty(dg.interior_shape, dtype=torch.float64, device="cuda")
+    snap.snap_rhs_adjoint(dg, torch.as_tensor(c.q).cuda(), torch.as_tensor(w).cuda(), qb,
+                          snap.workspace(dg, snap.SNAP_OP_RHS_ADJ))
+    lhs = float(np.sum(w * jv))
+    rhs_ = float(np.sum(qb.cpu().numpy() * v))
+    print(f"[adjoint] dot {name}: {lhs:.12e} vs {rhs_:.12e}", flush=True)
+    assert abs(lhs - rhs_) <= 1e-6 * max(abs(lhs), abs(rhs_))
+
+
+def shifted(g, q, v, s):
+    qq = q.copy()
+    g.interior(qq)[...] += s * v
+    return qq
+
+
+def richardson_jvp(f, h):
+    """Directional derivative of f at s = 0 by central differences at h and h/2,
+    Richardson-extrapolated: the Jiang-Shu weights are strongly curved where a
+    stencil's differences are small, so the h^2 term must be removed to reach
+    1e-6 relative agreement."""
+    def central(hh):
+        return (f(hh) - f(-hh)) / (2.0 * hh)
+    return (4.0 * central(0.5 * h) - central(h)) / 3.0
+
+
+def test_rhs_adjoint_deterministic():
+    c = case("3d_tracers_20x18x24_nt4")
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    rb = torch.as_tensor(wl.seeded_normal(c.grid.interior_shape, 104)).cuda()
+    work = snap.workspace(dg, snap.SNAP_OP_RHS_ADJ)
+    a, b = torch.empty_like(rb), torch.empty_like(rb)
+    snap.snap_rhs_adjoint(dg, qd, rb, a, work)
+    snap.snap_rhs_adjoint(dg, qd, rb, b, work)
+    assert torch.equal(a, b)
+
+
+def test_rhs_adjoint_fp32():
+    c = case("3d_smooth_35x21x19")
+    rbar = wl.seeded_normal(c.grid.interior_shape, 105)
+    dg = snap.device_grid(c.grid, dtype=torch.float32)
+    q32 = torch.as_tensor(c.q).float()
+    qb = torch.empty(dg.interior_shape, dtype=torch.float32, device="cuda")
+    snap.snap_rhs_adjoint(dg, q32.cuda(), torch.as_tensor(rbar).float().cuda(), qb,
+                          snap.workspace(dg, snap.SNAP_OP_RHS_ADJ))
+    ref = oracle.rhs_adjoint(q32.double().numpy(), c.grid,
+                             torch.as_tensor(rbar).float().double().numpy()).numpy()
+    errs = field_errors(qb.cpu().double().numpy(), ref)
+    print("[adjoint] fp32 errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-3 for e in errs), errs
+
+
+def _loss(grid, q):
+    """Kinetic energy of the upper half of the levels (interior)."""
+    g0 = snap.SNAP_NG
+    gy = 0 if grid.ny == 1 else g0
+    qi = q[:, g0:g0 + grid.nz, gy:gy + grid.ny, g0:g0 + grid.nx]
+    top = qi[:, grid.nz // 2:]
+    return 0.5 * ((top[1] ** 2 + top[2] ** 2 + top[3] ** 2) / top[0]).sum()
+
+
+def test_checkpointed_autograd_matches_finite_differences():
+    grid, q, _ = wl.convection_3d(16, 12, 20, lx=1250.0, ly=940.0, lz=1560.0, noise=0.5, seed=3)
+    # A seeded velocity field keeps the interface velocities away from zero,
+    # where the upwind side of LMARS switches and the map has a kink; a seeded
+    # 50 Pa pressure perturbation keeps p' far above sqrt(eps), the scale on
+    # which the Jiang-Shu weights of p' bend (a state at constant pressure has
+    # p' at round-off, and any finite step in E would straddle that bend).
+    qi = grid.interior(q)
+    vel = 1.0 + 2.0 * wl.seeded_normal((3,) + qi.shape[1:], 7) ** 2
+    qi[1:4] = qi[0] * vel
+    qi[4] += 0.5 * qi[0] * (vel ** 2).sum(axis=0)
+    qi[4] += 50.0 * wl.seeded_normal(qi.shape[1:], 8) / (grid.gamma - 1.0)
+    dg = snap.device_grid(grid)
+    dt = oracle.cfl_dt(q, grid, 0.9)
+    nsteps, every = 7, 3
+    q0 = torch.as_tensor(q).cuda().requires_grad_(True)
+    out = rk3_run(dg, q0, dt, nsteps, every)
+    L = _loss(grid, out)
+    L.backward()
+    grad = q0.grad.detach().cpu().numpy()
+    # ghosts carry no gradient
+    mask = np.ones(grid.shape, dtype=bool)
+    grid.interior(mask)[...] = False
+    assert np.all(grad[mask] == 0.0)
+    # same as stepping the adjoint by hand without checkpoints
+    qd = torch.as_tensor(q).cuda()
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    states = []
+    for _ in range(nsteps):
+        states.append(qd.clone())
+        snap.snap_rk3_step(dg, qd, dt, work)
+    qn = qd.clone().requires_grad_(True)
+    _loss(grid, qn).backward()
+    qb = grid.interior(qn.grad).contiguous().clone()
+    aw = snap.workspace(dg, snap.SNAP_OP_RK3_ADJ)
+    for t in range(nsteps - 1, -1, -1):
+        snap.snap_rk3_step_adjoint(dg, states[t], dt, qb, aw)
+    assert torch.equal(grid.interior(q0.grad), qb)
+    # central finite differences along seeded directions
+    def loss_of(qq):
+        qd = torch.as_tensor(qq).cuda()
+        for _ in range(nsteps):
+            snap.snap_rk3_step(dg, qd, dt, work)
+        return float(_loss(grid, qd))
+    for seed in range(4):
+        d = wl.seeded_normal(grid.interior_shape, 200 + seed)
+        d *= np.abs(grid.interior(q)).reshape(grid.nvar, -1).max(axis=1)[:, None, None, None]
+        fd = richardson_jvp(lambda s: loss_of(shifted(grid, q, d, s)), 1e-7)
+        ad = float(np.sum(grid.interior(grad) * d))
+        print(f"[adjoint] FD {fd:.10e}  AD {ad:.10e}", flush=True)
+        assert abs(fd - ad) <= 1e-5 * max(abs(fd), abs(ad))
