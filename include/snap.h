@@ -217,6 +217,28 @@ int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_
 int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums_host, void* stream);
 
 /*
+ * Ensemble of independent 2-D (ny == 1) domains advanced by one SSP-RK3 step
+ * each (Sec. 4.3), with per-member grids, states and time steps. Every stage
+ * is one batched ghost-fill launch and one persistent stage launch for all
+ * members: `nblocks` workgroups walk the (member, tile) work items round-robin
+ * (0 = as many as fit on the device at once). Members must share dtype and
+ * ntracer; 3-D members return SNAP_E_UNSUPPORTED; 1 <= n <= 65535.
+ * gs       HOST array of n grids (each with its own DEVICE reference profiles).
+ * q        HOST array of n DEVICE pointers to padded member states (in Q^n,
+ *          out Q^{n+1}; ghost layers unspecified on return).
+ * dt_host  HOST array of n time steps, each finite and > 0.
+ * variant  tile shape (snap_batched_tile_variant); 0 is the single-domain
+ *          default, 1..5 are alternatives (ntracer == 0 only) for autotuning.
+ * work     device workspace of snap_batched_workspace_bytes(gs, n) bytes; it
+ *          holds the descriptor tables (copied from the host on each call)
+ *          and two stage states per member.
+ */
+size_t snap_batched_workspace_bytes(const snap_grid* gs, int n);
+int snap_batched_tile_variant(int dtype, int ntracer, int variant, int* tx, int* tz);
+int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const double* dt_host,
+                          int variant, int nblocks, void* work, void* stream);
+
+/*
  * Benchmark instrumentation of the fused stage kernel (the kernel that
  * evaluates the right-hand side and applies one Runge-Kutta stage).
  * snap_stage_timing_enable(1) discards earlier records and brackets every later

@@ -22,6 +22,8 @@ __all__ = [
     "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
     "snap_stage_timing_enable", "snap_stage_timing_read", "snap_rhs_adjoint",
     "snap_rk3_step_adjoint", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ",
+    "snap_batched_workspace_bytes", "snap_batched_tile_variant", "snap_rk3_step_batched",
+    "batched_workspace",
     "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
 ]
@@ -89,6 +91,13 @@ _SIGNATURES = {
     "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_rhs_adjoint": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P]),
     "snap_rk3_step_adjoint": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P, _P]),
+    "snap_batched_workspace_bytes": (ctypes.c_size_t, [_GP, ctypes.c_int]),
+    "snap_batched_tile_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_int),
+                                                 ctypes.POINTER(ctypes.c_int)]),
+    "snap_rk3_step_batched": (ctypes.c_int, [_GP, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                             ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                             ctypes.c_int, _P, _P]),
     "snap_stage_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "snap_stage_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),
@@ -276,6 +285,49 @@ def snap_rk3_step_adjoint(grid: DeviceGrid, q_n: torch.Tensor, dt: float, q_bar:
     _check(lib().snap_rk3_step_adjoint(grid.ptr(), ctypes.c_void_p(q_n.data_ptr()),
                                        ctypes.c_double(dt), ctypes.c_void_p(q_bar.data_ptr()),
                                        ctypes.c_void_p(work.data_ptr()), _stream(stream)))
+
+
+def _grid_array(grids):
+    arr = (SnapGridC * len(grids))()
+    for m, g in enumerate(grids):
+        arr[m] = g.c
+    return arr
+
+
+def snap_batched_workspace_bytes(grids) -> int:
+    n = int(lib().snap_batched_workspace_bytes(_grid_array(grids), len(grids)))
+    if n == 0:
+        raise SnapError(SNAP_E_INVALID, lib().snap_last_error().decode())
+    return n
+
+
+def batched_workspace(grids) -> torch.Tensor:
+    return torch.empty(snap_batched_workspace_bytes(grids), dtype=torch.uint8,
+                       device=grids[0].device)
+
+
+def snap_batched_tile_variant(dtype: int, ntracer: int, variant: int):
+    """(tx, tz) of a batched tile variant, or None if it is unavailable."""
+    tx, tz = ctypes.c_int(0), ctypes.c_int(0)
+    code = lib().snap_batched_tile_variant(int(dtype), int(ntracer), int(variant),
+                                           ctypes.byref(tx), ctypes.byref(tz))
+    if code == SNAP_E_UNSUPPORTED:
+        return None
+    _check(code)
+    return tx.value, tz.value
+
+
+def snap_rk3_step_batched(grids, qs, dts, work: torch.Tensor, variant: int = 0,
+                          nblocks: int = 0, stream=None) -> None:
+    if not (len(grids) == len(qs) == len(dts)) or not grids:
+        raise ValueError("grids, qs and dts must be non-empty and of equal length")
+    for g, q in zip(grids, qs):
+        g._check_state(q)
+    ptrs = (ctypes.c_void_p * len(qs))(*[q.data_ptr() for q in qs])
+    dta = (ctypes.c_double * len(dts))(*[float(d) for d in dts])
+    _check(lib().snap_rk3_step_batched(_grid_array(grids), len(grids), ptrs, dta, int(variant),
+                                       int(nblocks), ctypes.c_void_p(work.data_ptr()),
+                                       _stream(stream)))
 
 
 def snap_stage_timing_enable(enable: bool) -> None:

@@ -228,23 +228,10 @@ int run_stage(const snap_grid* g, StageArgs a, hipStream_t st) {
   return SNAP_OK;
 }
 
+GhostArgs ghost_args(const snap_grid* g);
+
 int fill(const snap_grid* g, void* q, hipStream_t st) {
-  GhostArgs a;
-  const bool d3 = is3d(g);
-  a.nx = g->nx;
-  a.ny = g->ny;
-  a.nz = g->nz;
-  a.nxp = g->nx + 2 * SNAP_NG;
-  a.nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
-  a.gy = d3 ? SNAP_NG : 0;
-  a.d3 = d3;
-  a.nvar = nvar_of(g);
-  a.bcx = g->bc[0];
-  a.bcy = g->bc[1];
-  a.bcz = g->bc[2];
-  a.sy = a.nxp;
-  a.sz = (long long)a.nxp * a.nyp;
-  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  const GhostArgs a = ghost_args(g);
   return launch_fill_ghosts(g->dtype, q, a, st) == 0 ? SNAP_OK : device_fail("ghost fill launch");
 }
 
@@ -340,6 +327,67 @@ int run_combine(const snap_grid* g, void* out, const void* x, const void* y, con
   const int r = g->dtype == SNAP_F64 ? launch_adj_combine_f64(out, x, y, z, ca, cb, cc, n, st)
                                      : launch_adj_combine_f32(out, x, y, z, ca, cb, cc, n, st);
   return r == 0 ? SNAP_OK : device_fail("combine kernel launch");
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble of 2-D domains
+// ---------------------------------------------------------------------------
+int check_batch(const snap_grid* gs, int n) {
+  if (!gs) return fail(SNAP_E_INVALID, "grid array is NULL");
+  if (n < 1 || n > 65535) return fail(SNAP_E_INVALID, "member count must lie in [1, 65535]");
+  for (int m = 0; m < n; ++m) {
+    int r = check_grid(&gs[m]);
+    if (r) return fail(r, "member %d: %s", m, g_err.c_str());
+    if (is3d(&gs[m]))
+      return fail(SNAP_E_UNSUPPORTED, "member %d is 3-D: the batched step takes 2-D members", m);
+    if (gs[m].dtype != gs[0].dtype || gs[m].ntracer != gs[0].ntracer)
+      return fail(SNAP_E_INVALID, "member %d differs in dtype or ntracer from member 0", m);
+  }
+  return SNAP_OK;
+}
+
+struct BatchLayout {
+  size_t descs, ghosts, first, members, total;
+  std::vector<size_t> q1, q2;
+};
+
+BatchLayout batch_layout(const snap_grid* gs, int n) {
+  BatchLayout L;
+  L.descs = 0;
+  L.ghosts = align256((size_t)3 * n * sizeof(StageArgs));
+  L.first = L.ghosts + align256((size_t)3 * n * sizeof(GhostDesc));
+  L.members = L.first + align256((size_t)(n + 1) * sizeof(int));
+  size_t off = L.members;
+  L.q1.resize(n);
+  L.q2.resize(n);
+  for (int m = 0; m < n; ++m) {
+    L.q1[m] = off;
+    off += align256(padded_bytes(&gs[m]));
+    L.q2[m] = off;
+    off += align256(padded_bytes(&gs[m]));
+  }
+  L.total = off;
+  return L;
+}
+
+GhostArgs ghost_args(const snap_grid* g) {
+  GhostArgs a;
+  const bool d3 = is3d(g);
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.nxp = g->nx + 2 * SNAP_NG;
+  a.nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.d3 = d3;
+  a.nvar = nvar_of(g);
+  a.bcx = g->bc[0];
+  a.bcy = g->bc[1];
+  a.bcz = g->bc[2];
+  a.sy = a.nxp;
+  a.sz = (long long)a.nxp * a.nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  return a;
 }
 
 }  // namespace
@@ -511,6 +559,98 @@ int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar,
   if ((r = run_combine(g, q_bar, q_bar, b2, b1, 1.0 / 3.0, 0.75, 1.0, st))) return r;
   if ((r = fill(g, q_n, st))) return r;
   if ((r = run_adj_rhs(g, q_n, b1, q_bar, 2, 1.0, dt, aw, st))) return r;
+  return ok();
+}
+
+size_t snap_batched_workspace_bytes(const snap_grid* gs, int n) {
+  if (check_batch(gs, n) != SNAP_OK) return 0;
+  return batch_layout(gs, n).total;
+}
+
+int snap_batched_tile_variant(int dtype, int ntracer, int variant, int* tx, int* tz) {
+  if (!tx || !tz) return fail(SNAP_E_INVALID, "tx or tz is NULL");
+  if (dtype != SNAP_F64 && dtype != SNAP_F32) return fail(SNAP_E_INVALID, "bad dtype");
+  if (ntracer < 0 || ntracer > SNAP_MAX_TRACERS) return fail(SNAP_E_INVALID, "bad ntracer");
+  const TileShape t = batched_tile(dtype, ntracer, variant);
+  if (t.tx == 0) return fail(SNAP_E_UNSUPPORTED, "tile variant %d unavailable", variant);
+  *tx = t.tx;
+  *tz = t.ty;
+  return ok();
+}
+
+int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const double* dt_host,
+                          int variant, int nblocks, void* work, void* stream) {
+  int r = check_batch(gs, n);
+  if (r) return r;
+  if (!q || !dt_host || !work) return fail(SNAP_E_INVALID, "q, dt_host or work is NULL");
+  for (int m = 0; m < n; ++m) {
+    if (!q[m]) return fail(SNAP_E_INVALID, "q[%d] is NULL", m);
+    if (!finite_pos(dt_host[m])) return fail(SNAP_E_INVALID, "dt[%d] must be finite and > 0", m);
+  }
+  if (nblocks < 0) return fail(SNAP_E_INVALID, "nblocks must be >= 0");
+  const int dtype = gs[0].dtype, nt = gs[0].ntracer;
+  const TileShape t = batched_tile(dtype, nt, variant);
+  if (t.tx == 0) return fail(SNAP_E_UNSUPPORTED, "tile variant %d unavailable", variant);
+  const hipStream_t st = (hipStream_t)stream;
+  const BatchLayout L = batch_layout(gs, n);
+  char* base = static_cast<char*>(work);
+
+  // host-side descriptor tables: 3 stages x n members, then the item offsets
+  thread_local std::vector<char> host;
+  host.assign(L.members, 0);
+  StageArgs* hd = reinterpret_cast<StageArgs*>(host.data() + L.descs);
+  GhostDesc* hg = reinterpret_cast<GhostDesc*>(host.data() + L.ghosts);
+  int* hf = reinterpret_cast<int*>(host.data() + L.first);
+  long long items = 0, max_ghosts = 0;
+  for (int m = 0; m < n; ++m) {
+    const snap_grid* g = &gs[m];
+    StageArgs a = stage_args(g);
+    a.tiles_x = (g->nx + t.tx - 1) / t.tx;
+    a.tiles_y = (g->nz + t.ty - 1) / t.ty;
+    a.nchunk = 1;
+    a.tz = g->nz;
+    a.dt = dt_host[m];
+    a.rhs_mode = 0;
+    void* q1 = base + L.q1[m];
+    void* q2 = base + L.q2[m];
+    StageArgs s1 = a, s2 = a, s3 = a;
+    s1.qs = q[m], s1.qn = nullptr, s1.out = q1, s1.ca = 0.0, s1.cb = 1.0;
+    s2.qs = q1, s2.qn = q[m], s2.out = q2, s2.ca = 0.75, s2.cb = 0.25;
+    s3.qs = q2, s3.qn = q[m], s3.out = q[m], s3.ca = 1.0 / 3.0, s3.cb = 2.0 / 3.0;
+    hd[m] = s1;
+    hd[n + m] = s2;
+    hd[2 * n + m] = s3;
+    const GhostArgs ga = ghost_args(g);
+    hg[m] = GhostDesc{ga, q[m]};
+    hg[n + m] = GhostDesc{ga, q1};
+    hg[2 * n + m] = GhostDesc{ga, q2};
+    hf[m] = (int)items;
+    items += (long long)a.tiles_x * a.tiles_y;
+    const long long ng = 6LL * ga.nyp * ga.nxp + (long long)ga.nz * ga.ny * 6;
+    max_ghosts = ng > max_ghosts ? ng : max_ghosts;
+  }
+  if (items > (1LL << 30)) return fail(SNAP_E_INVALID, "too many tiles in the batch");
+  hf[n] = (int)items;
+  if (hipMemcpyAsync(base, host.data(), L.members, hipMemcpyHostToDevice, st) != hipSuccess)
+    return device_fail("descriptor copy");
+  int nb = nblocks;
+  if (nb == 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int per = batched_occupancy(dtype, nt, variant);
+    nb = cus * (per > 0 ? per : 1);
+  }
+  if (nb > items) nb = (int)items;
+  const StageArgs* dd = reinterpret_cast<const StageArgs*>(base + L.descs);
+  const GhostDesc* dg = reinterpret_cast<const GhostDesc*>(base + L.ghosts);
+  const int* df = reinterpret_cast<const int*>(base + L.first);
+  for (int s = 0; s < 3; ++s) {
+    if (launch_fill_ghosts_batched(dtype, dg + s * n, n, max_ghosts, st))
+      return device_fail("batched ghost fill launch");
+    if (launch_stage2d_batched(dtype, nt, variant, dd + s * n, df, n, nb, st))
+      return device_fail("batched stage launch");
+  }
   return ok();
 }
 

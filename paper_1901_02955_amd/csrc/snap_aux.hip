@@ -17,15 +17,16 @@ __device__ __forceinline__ int ghost_src(int idx, int n, int bc, bool& flip) {
 
 // One thread per ghost cell; the ghost cells are enumerated as three disjoint
 // regions: z ghost levels (all y, x), y ghost rows of interior levels (all x),
-// x ghost columns of interior rows.
+// x ghost columns of interior rows. Threads start at `first` and stride by
+// `stride` over the enumeration.
 template <typename T>
-__global__ void k_fill_ghosts(T* __restrict__ q, GhostArgs a) {
+__device__ __forceinline__ void fill_ghosts_range(T* __restrict__ q, const GhostArgs& a,
+                                                  long long first, long long stride) {
   const long long nzr = 6LL * a.nyp * a.nxp;
   const long long nyr = a.d3 ? (long long)a.nz * 6 * a.nxp : 0;
   const long long nxr = (long long)a.nz * a.ny * 6;
   const long long total = nzr + nyr + nxr;
-  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
-       g += (long long)gridDim.x * blockDim.x) {
+  for (long long g = first; g < total; g += stride) {
     int i, j, k;
     if (g < nzr) {
       const int ip = g % a.nxp;
@@ -63,6 +64,21 @@ __global__ void k_fill_ghosts(T* __restrict__ q, GhostArgs a) {
       q[dst + v * a.sv] = x;
     }
   }
+}
+
+template <typename T>
+__global__ void k_fill_ghosts(T* __restrict__ q, GhostArgs a) {
+  fill_ghosts_range<T>(q, a, blockIdx.x * (long long)blockDim.x + threadIdx.x,
+                       (long long)gridDim.x * blockDim.x);
+}
+
+// All members of an ensemble: member blockIdx.y.
+template <typename T>
+__global__ void k_fill_ghosts_batched(const GhostDesc* __restrict__ d) {
+  const GhostDesc g = d[blockIdx.y];
+  fill_ghosts_range<T>(static_cast<T*>(g.q), g.a,
+                       blockIdx.x * (long long)blockDim.x + threadIdx.x,
+                       (long long)gridDim.x * blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -180,6 +196,18 @@ int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int launch_fill_ghosts_batched(int dtype, const GhostDesc* d, int n, long long max_ghosts,
+                               hipStream_t st) {
+  long long nb = (max_ghosts + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_fill_ghosts_batched<double>, dim3((unsigned)nb, n), dim3(256), 0, st, d);
+  else
+    hipLaunchKernelGGL(k_fill_ghosts_batched<float>, dim3((unsigned)nb, n), dim3(256), 0, st, d);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out, 1);
@@ -205,6 +233,35 @@ int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double
                        static_cast<const float*>(q), a, part);
   hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(64), 0, st, part, SUM_BLOCKS, a.nvar, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace snap
+
+namespace snap {
+
+TileShape batched_tile_f64(int ntracer, int v);
+TileShape batched_tile_f32(int ntracer, int v);
+int batched_occupancy_f64(int ntracer, int v);
+int batched_occupancy_f32(int ntracer, int v);
+int launch_stage2d_batched_f64(int ntracer, int v, const StageArgs* d, const int* first, int n,
+                               int nb, hipStream_t st);
+int launch_stage2d_batched_f32(int ntracer, int v, const StageArgs* d, const int* first, int n,
+                               int nb, hipStream_t st);
+
+TileShape batched_tile(int dtype, int ntracer, int variant) {
+  if (variant < 0 || variant >= BATCH_VARIANTS) return TileShape{0, 0};
+  return dtype == 0 ? batched_tile_f64(ntracer, variant) : batched_tile_f32(ntracer, variant);
+}
+
+int batched_occupancy(int dtype, int ntracer, int variant) {
+  return dtype == 0 ? batched_occupancy_f64(ntracer, variant)
+                    : batched_occupancy_f32(ntracer, variant);
+}
+
+int launch_stage2d_batched(int dtype, int ntracer, int variant, const StageArgs* descs,
+                           const int* first, int n, int nblocks, hipStream_t st) {
+  return dtype == 0 ? launch_stage2d_batched_f64(ntracer, variant, descs, first, n, nblocks, st)
+                    : launch_stage2d_batched_f32(ntracer, variant, descs, first, n, nblocks, st);
 }
 
 }  // namespace snap

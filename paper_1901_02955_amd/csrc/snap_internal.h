@@ -16,6 +16,12 @@ struct GhostArgs {
   long long sy, sz, sv;
 };
 
+// Ghost fill of one ensemble member.
+struct GhostDesc {
+  GhostArgs a;
+  void* q;
+};
+
 struct CflArgs {
   int nx, ny, nz, gy, d3;
   long long sy, sz, sv;
@@ -58,6 +64,15 @@ int launch_adj_combine_f32(void* out, const void* x, const void* y, const void* 
 int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st);
+int launch_fill_ghosts_batched(int dtype, const GhostDesc* d, int n, long long max_ghosts,
+                               hipStream_t st);
+
+// Batched (ensemble) 2-D stage kernel: tile variant v of the element type.
+constexpr int BATCH_VARIANTS = 6;
+TileShape batched_tile(int dtype, int ntracer, int variant);   // {0, 0}: unavailable
+int batched_occupancy(int dtype, int ntracer, int variant);
+int launch_stage2d_batched(int dtype, int ntracer, int variant, const StageArgs* descs,
+                           const int* first, int n, int nblocks, hipStream_t st);
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st);
 int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double* out,

@@ -381,18 +381,18 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 }
 
 // ---------------------------------------------------------------------------
-// 2-D (x-z) kernel: TX x TZ tile of the plane, z is the second in-plane axis.
+// 2-D (x-z) tile: TX x TZ tile number L of the plane, z is the second in-plane
+// axis. Shared by the single-domain kernel and the batched (ensemble) kernel.
 // ---------------------------------------------------------------------------
 template <typename T, int NT, int TX, int TZ>
-__global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
+__device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
+                                             Plane<T, 5 + NT, TX, TZ>& S) {
   constexpr int NV = 5 + NT;
   using I = PlaneItems<TX, TZ>;
-  __shared__ Plane<T, NV, TX, TZ> S;
   const T* __restrict__ qs = static_cast<const T*>(a.qs);
 
   const int tid = threadIdx.x;
   const int ti = tid % TX, tk = tid / TX;
-  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
   const int tx = L % a.tiles_x;
   const int tzi = L / a.tiles_x;
   const int i0 = tx * TX, k0 = tzi * TZ;
@@ -451,6 +451,37 @@ __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
     R[4] = R[4] - grav * qs[po + 3 * a.sv];
     const long long ro = (long long)k * a.rz + i;
     write_cell<T, NV>(a, qs, po, ro, R);
+  }
+}
+
+template <typename T, int NT, int TX, int TZ>
+__global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
+  __shared__ Plane<T, 5 + NT, TX, TZ> S;
+  stage2d_tile<T, NT, TX, TZ>(a, xcd_logical_block(blockIdx.x, gridDim.x), S);
+}
+
+// Ensemble of 2-D domains in one persistent launch: work item w is tile
+// w - first[m] of member m (first[m] <= w < first[m+1]); every block walks the
+// items w = blockIdx.x, blockIdx.x + gridDim.x, ... A barrier closes every tile:
+// its last phase still reads the primitive plane (density perturbation for the
+// gravity source) that the next tile's first phase overwrites.
+template <typename T, int NT, int TX, int TZ>
+__global__ void __launch_bounds__(TX* TZ) k_stage2d_batched(const StageArgs* __restrict__ descs,
+                                                            const int* __restrict__ first, int n) {
+  __shared__ Plane<T, 5 + NT, TX, TZ> S;
+  const int total = first[n];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int lo = 0, hi = n;   // first[lo] <= w < first[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (first[mid] <= w)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const StageArgs a = descs[lo];
+    stage2d_tile<T, NT, TX, TZ>(a, w - first[lo], S);
+    __syncthreads();
   }
 }
 

@@ -156,3 +156,47 @@ def test_workspace_sizes():
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3_ADJ) >= adj + 2 * padded + 2 * interior
     assert lib.snap_workspace_bytes(ctypes.byref(good_grid()), 99) == 0
     assert b"unknown" in lib.snap_last_error()
+
+
+def test_batched_validation():
+    lib = snap.lib()
+    arr = (snap.SnapGridC * 3)(good_grid(ny=1), good_grid(ny=1, nx=7), good_grid(ny=1, nz=5))
+    qs = (ctypes.c_void_p * 3)(FAKE, 2 * FAKE, 3 * FAKE)
+    dts = (ctypes.c_double * 3)(0.1, 0.2, 0.3)
+    W = ctypes.c_void_p(4 * FAKE)
+    assert lib.snap_batched_workspace_bytes(arr, 3) > 0
+    assert lib.snap_batched_workspace_bytes(arr, 0) == 0
+    assert lib.snap_batched_workspace_bytes(None, 3) == 0
+    assert lib.snap_rk3_step_batched(arr, 0, qs, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_batched(arr, 3, None, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_batched(arr, 3, qs, None, 0, 0, W, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_batched(arr, 3, qs, dts, 0, 0, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_batched(arr, 3, qs, dts, 0, -1, W, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_batched(arr, 3, qs, dts, 99, 0, W, None) == snap.SNAP_E_UNSUPPORTED
+    bad_dt = (ctypes.c_double * 3)(0.1, -0.2, 0.3)
+    assert lib.snap_rk3_step_batched(arr, 3, qs, bad_dt, 0, 0, W, None) == snap.SNAP_E_INVALID
+    null_q = (ctypes.c_void_p * 3)(FAKE, None, 3 * FAKE)
+    assert lib.snap_rk3_step_batched(arr, 3, null_q, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
+    mixed = (snap.SnapGridC * 2)(good_grid(ny=1), good_grid(ny=1, dtype=snap.SNAP_F32))
+    assert lib.snap_rk3_step_batched(mixed, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
+    three_d = (snap.SnapGridC * 2)(good_grid(ny=1), good_grid())
+    assert lib.snap_rk3_step_batched(three_d, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_UNSUPPORTED
+    bad_member = (snap.SnapGridC * 2)(good_grid(ny=1), good_grid(ny=1, dx=0.0))
+    assert lib.snap_rk3_step_batched(bad_member, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
+    assert b"member 1" in lib.snap_last_error()
+    tx, tz = ctypes.c_int(0), ctypes.c_int(0)
+    assert lib.snap_batched_tile_variant(snap.SNAP_F32, 0, 0, ctypes.byref(tx), ctypes.byref(tz)) == 0
+    assert (tx.value, tz.value) == (16, 16)
+    assert lib.snap_batched_tile_variant(snap.SNAP_F32, 0, 2, ctypes.byref(tx), ctypes.byref(tz)) == 0
+    assert (tx.value, tz.value) == (64, 4)
+    assert lib.snap_batched_tile_variant(snap.SNAP_F32, 4, 2, ctypes.byref(tx), ctypes.byref(tz)) == snap.SNAP_E_UNSUPPORTED
+    assert lib.snap_batched_tile_variant(snap.SNAP_F64, 0, 6, ctypes.byref(tx), ctypes.byref(tz)) == snap.SNAP_E_UNSUPPORTED
+
+
+def test_batched_workspace_layout():
+    lib = snap.lib()
+    gs = [good_grid(ny=1, nx=20, nz=16), good_grid(ny=1, nx=37, nz=21, dtype=snap.SNAP_F64)]
+    arr = (snap.SnapGridC * 2)(*gs)
+    total = lib.snap_batched_workspace_bytes(arr, 2)
+    states = sum(2 * (((g.nx + 6) * (g.nz + 6) * (5 + g.ntracer) * 8 + 255) // 256 * 256) for g in gs)
+    assert states < total <= states + 4 * 256 + 8 * 1024
