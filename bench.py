@@ -25,8 +25,8 @@ of the timed region, on the launch stream):
   the three launches), against 8 TB/s.
 
 CPU baseline: the FP64 oracle (PyTorch CPU, all host threads of this process)
-on a bounded sample of the same workload: the first 2 SSP-RK3 steps of the
-same 256 x 256 x 128 initial state.
+on a bounded sample of the same workload: 12 SSP-RK3 steps of a 128 x 128 x 128
+column block cut from the same initial state (periodic in x and y).
 """
 from __future__ import annotations
 
@@ -153,6 +153,180 @@ def run_gpu(dtype, steps: int, warmup: int):
     return res
 
 
+def run_jovian(steps: int, warmup: int):
+    """3-D Jovian-like column 512x512x256, FP32, 4 tracer densities (vapours and clouds)."""
+    import torch
+
+    import paper_1901_02955_amd as snap
+    import workloads as wl
+
+    grid, q = wl.jovian_3d()
+    dg = snap.device_grid(grid, dtype=torch.float32)
+    qd = torch.as_tensor(q).float().cuda().contiguous()
+    del q
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+    for _ in range(warmup):
+        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
+        snap.snap_rk3_step(dg, qd, dt, work)
+    torch.cuda.synchronize()
+    snap.snap_stage_timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
+        snap.snap_rk3_step(dg, qd, dt, work)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n = snap.snap_stage_timing_read()
+    snap.snap_stage_timing_enable(False)
+    cells = grid.nx * grid.ny * grid.nz
+    avg = ms / 1e3 / max(n, 1)
+    flops = algorithmic_flops_per_cell_stage(4, 3) * cells
+    byts = 8.0 / 3.0 * 9 * 4 * cells
+    out = {"workload": "3-D Jovian-like column 512x512x256 (5.5 km x 5.5 km x 1.5625 km), FP32, "
+                       "5 conserved + 4 tracer densities, CFL 0.9",
+           "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
+           "steps": steps, "stage_kernel_avg_ms": avg * 1e3,
+           "alu_frac": flops / avg / 1e12 / FP32_PEAK_TFLOPS,
+           "hbm_frac_algorithmic": byts / avg / 1e9 / HBM_PEAK_GBS}
+    del qd, work, cw
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_ensemble(steps: int):
+    """64 uneven 2-D bubbles (FP32): one persistent launch per stage vs separate steps."""
+    import torch
+
+    import paper_1901_02955_amd as snap
+    from paper_1901_02955_amd import tuner
+    import workloads as wl
+
+    members = wl.ensemble_2d(64, seed=4)
+    grids = [snap.device_grid(g, dtype=torch.float32) for g, _ in members]
+    qs = [torch.as_tensor(q).float().cuda().contiguous() for _, q in members]
+    cw = snap.workspace(grids[0], snap.SNAP_OP_CFL)
+    dts = [snap.snap_cfl_dt(g, q, CFL, cw) for g, q in zip(grids, qs)]
+    cells = sum(g.nx * g.nz for g in grids)
+    tuned = tuner.tune_batched(grids, qs, dts, repeats=3, use_cache=False)
+    bw = snap.batched_workspace(grids)
+    work = [snap.workspace(g, snap.SNAP_OP_RK3) for g in grids]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def batched():
+        snap.snap_rk3_step_batched(grids, qs, dts, bw, tuned["variant"], tuned["nblocks"])
+
+    def separate():
+        for g, q, dt, w in zip(grids, qs, dts, work):
+            snap.snap_rk3_step(g, q, dt, w)
+
+    tb, ts = timed(batched), timed(separate)
+    return {"workload": "64 uneven 2-D dry bubbles (128x128 .. 512x256, seeded), FP32, "
+                        "per-member CFL 0.9 time step",
+            "members": len(grids), "cells": cells, "steps": steps,
+            "batched_value": cells * steps / tb, "separate_value": cells * steps / ts,
+            "unit": "cell-updates/s", "batched_ms_per_step": tb / steps * 1e3,
+            "separate_ms_per_step": ts / steps * 1e3, "speedup": ts / tb,
+            "launches_per_step": {"batched": 6, "separate": 6 * len(grids)},
+            "tuned": {k: tuned[k] for k in ("variant", "tile", "nblocks")}}
+
+
+def run_adjoint(nsteps: int = 200, every: int = 20):
+    """Adjoint / forward time of 200 FP32 steps (checkpoint every 20), KE of the top 16 levels."""
+    import torch
+
+    import paper_1901_02955_amd as snap
+    from paper_1901_02955_amd.autograd import rk3_run
+    import workloads as wl
+
+    grid, q, _ = wl.convection_3d(NX, NY, NZ)
+    dg = snap.device_grid(grid, dtype=torch.float32)
+    q0 = torch.as_tensor(q).float().cuda().contiguous()
+    del q
+    dt = snap.snap_cfl_dt(dg, q0, CFL, snap.workspace(dg, snap.SNAP_OP_CFL))
+    g0 = snap.SNAP_NG
+
+    def loss(out):
+        top = out[:, g0 + NZ - 16:g0 + NZ, g0:g0 + NY, g0:g0 + NX]
+        return 0.5 * ((top[1] ** 2 + top[2] ** 2 + top[3] ** 2) / top[0]).sum()
+
+    # forward alone (same steps, no checkpoints kept)
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    qf = q0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        snap.snap_rk3_step(dg, qf, dt, work)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    del qf, work
+    x = q0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = rk3_run(dg, x, dt, nsteps, every)
+    L = loss(out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    gnorm = float(x.grad.double().norm())
+    del x, out
+    torch.cuda.empty_cache()
+    return {"workload": "3-D dry convection 256x256x128, FP32, 200 SSP-RK3 steps, checkpoint every "
+                        "20, loss = kinetic energy of the top 16 levels, gradient w.r.t. the initial "
+                        "state",
+            "forward_s": t_fwd, "forward_with_checkpoints_s": t1 - t0, "backward_s": t2 - t1,
+            "adjoint_forward_ratio": (t2 - t1) / t_fwd, "grad_norm": gnorm}
+
+
+def run_fp32_error(steps: int = 100):
+    """Per-field error of the FP32 form against the FP64 path after 100 steps.
+
+    Both forms start from the same 256x256x128 convection state and take the
+    same fixed time step (the FP64 CFL step of the initial state). The FP64
+    path is the reference: it matches the CPU oracle within 1e-12 per field.
+    """
+    import numpy as np
+    import torch
+
+    import paper_1901_02955_amd as snap
+    import workloads as wl
+
+    grid, q, _ = wl.convection_3d(NX, NY, NZ)
+    res = {}
+    finals = {}
+    dt = None
+    for dtype in (torch.float64, torch.float32):
+        dg = snap.device_grid(grid, dtype=dtype)
+        qd = torch.as_tensor(q).to(dtype).cuda().contiguous()
+        if dt is None:
+            dt = snap.snap_cfl_dt(dg, qd, CFL, snap.workspace(dg, snap.SNAP_OP_CFL))
+        work = snap.workspace(dg, snap.SNAP_OP_RK3)
+        for _ in range(steps):
+            snap.snap_rk3_step(dg, qd, dt, work)
+        finals[dtype] = grid.interior(qd.double().cpu().numpy())
+        del qd, work
+        torch.cuda.empty_cache()
+    a, b = finals[torch.float32], finals[torch.float64]
+    names = ["rho", "rho_u", "rho_v", "rho_w", "E"]
+    for v, name in enumerate(names):
+        d = a[v] - b[v]
+        res[name] = {"max_rel": float(np.abs(d).max() / np.abs(b[v]).max()),
+                     "l2_rel": float(np.sqrt((d ** 2).mean() / (b[v] ** 2).mean()))}
+    return {"workload": f"3-D dry convection 256x256x128, {steps} steps of fixed dt = {dt:.6g} s",
+            "fields": res, "tolerance_rho_E": 1e-5,
+            "within_tolerance": bool(res["rho"]["max_rel"] <= 1e-5 and res["E"]["max_rel"] <= 1e-5)}
+
+
 def run_cpu_baseline():
     import numpy as np
     import torch
@@ -166,21 +340,21 @@ def run_cpu_baseline():
         nthreads = min(nthreads, int(env))
     torch.set_num_threads(nthreads)
     grid, q, _ = wl.convection_3d(NX, NY, NZ)
-    b = 256
+    b = 128
     sub = grid.copy(nx=b, ny=b)
     qs = np.zeros(sub.shape)
     sub.interior(qs)[...] = grid.interior(q)[:, :, :b, :b]
     del q
     dt = oracle.cfl_dt(qs, sub, CFL)
-    nsteps = 2
+    nsteps = 12
     t0 = time.perf_counter()
     oracle.run(qs, sub, dt, nsteps)
     el = time.perf_counter() - t0
     return {
         "value": b * b * NZ * nsteps / el, "unit": "cell-updates/s", "cores": torch.get_num_threads(),
         "kind": "oracle",
-        "sample": f"the first {nsteps} SSP-RK3 steps (FP64) of the same {b}x{b}x{NZ} initial "
-                  f"state ({el:.1f} s)",
+        "sample": f"{nsteps} SSP-RK3 steps (FP64) of a {b}x{b}x{NZ} column block cut from the "
+                  f"same initial state, periodic in x and y ({el:.1f} s)",
     }
 
 
@@ -191,6 +365,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="skip the Jovian, ensemble and adjoint sections")
     ap.add_argument("--variant", choices=("both", "f64", "f32"), default="both",
                     help="f64 or f32 alone (for profiling runs); the JSON line then carries that form")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -253,6 +429,11 @@ def main():
             "hbm_roofline": f32["hbm_roofline"],
         }}
         out["f32_speedup"] = f32["value"] / f64["value"]
+        out["f32_error_vs_f64"] = run_fp32_error()
+    if not args.only_headline:
+        out["jovian"] = run_jovian(10, 2)
+        out["ensemble"] = run_ensemble(20)
+        out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline()
     print(json.dumps(out), flush=True)
