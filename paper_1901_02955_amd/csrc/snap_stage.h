@@ -23,6 +23,15 @@
 
 #include "snap_device.h"
 
+// Optional scheduling fence between per-variable reconstructions: keeps the
+// compiler from interleaving all variables' WENO work (which raises register
+// pressure and costs occupancy in double precision).
+#ifdef SNAP_SCHED_FENCE
+#define SNAP_VAR_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define SNAP_VAR_FENCE() ((void)0)
+#endif
+
 namespace snap {
 
 struct StageArgs {
@@ -111,7 +120,10 @@ struct PlaneItems {
   static constexpr int NRS = TX * (TY + 2);
   static constexpr int NR = NRX + NRS;
   static constexpr int ROUNDS = (NR + NTHR - 1) / NTHR;
-  static constexpr int RREG = ROUNDS < 2 ? ROUNDS : 2;
+#ifndef SNAP_RREG
+#define SNAP_RREG 2
+#endif
+  static constexpr int RREG = ROUNDS < SNAP_RREG ? ROUNDS : SNAP_RREG;
   static constexpr int NSPILL = NR - RREG * NTHR > 0 ? NR - RREG * NTHR : 1;
 };
 
@@ -173,6 +185,7 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
           T qm;
           weno5_cell<T>(row[0], row[1], row[2], row[3], row[4], eps, linear, qm, qp[v]);
           if (ii < w) S.FX[v][jj][ii + 1] = qm;
+          SNAP_VAR_FENCE();
         }
       } else {
 #pragma unroll
@@ -181,6 +194,7 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
           weno5_cell<T>(S.P[v][jj + 1][ii + 3], S.P[v][jj + 2][ii + 3], S.P[v][jj + 3][ii + 3],
                         S.P[v][jj + 4][ii + 3], S.P[v][jj + 5][ii + 3], eps, linear, qm, qp[v]);
           if (jj < h) S.FY[v][jj + 1][ii] = qm;
+          SNAP_VAR_FENCE();
         }
       }
 #pragma unroll
@@ -256,10 +270,30 @@ __device__ __forceinline__ bool halo_item(int it, int w, int h, int& ii, int& jj
 #define SNAP_STAGE3D_WAVES_PER_EU 1
 #endif
 
+template <typename T, int NV>
+__device__ __forceinline__ void load_cons(const T* __restrict__ q, long long off, long long sv,
+                                          T (&c)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = q[off + v * sv];
+}
+
+template <typename T, int NV>
+__device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], double rb, double pb, double gm1,
+                                               T (&x)[NV]) {
+  double cd[NV], xd[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) cd[v] = static_cast<double>(c[v]);
+  cons_to_prim<NV>(cd, rb, pb, gm1, xd);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+}
+
 template <typename T, int NT, int TX, int TY>
 __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(StageArgs a) {
   constexpr int NV = 5 + NT;
   using I = PlaneItems<TX, TY>;
+  constexpr int NHALO = 6 * (TX + TY);
+  constexpr int HR = (NHALO + I::NTHR - 1) / I::NTHR;   // halo items per thread
   __shared__ Plane<T, NV, TX, TY> S;
   const T* __restrict__ qs = static_cast<const T*>(a.qs);
 
@@ -279,12 +313,28 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   const T inv_gm1 = static_cast<T>(a.inv_gm1);
   const T dxi = static_cast<T>(a.dxi), dyi = static_cast<T>(a.dyi), dzi = static_cast<T>(a.dzi);
   const bool linear = a.linear != 0;
+  const bool combine = a.rhs_mode == 0;
+  const bool use_qn = combine && a.ca != 0.0;
+  const T* qn = static_cast<const T*>(a.qn);
 
   // padded offset of (i, j, k) with interior coordinates (k may be a ghost level)
   auto poff = [&](int i, int j, int k) -> long long {
     return (long long)(k + NG) * a.sz + (long long)(j + NG) * a.sy + (i + NG);
   };
   const int ic = i0 + (act ? ti : 0), jc = j0 + (act ? tj : 0);
+  const long long col = poff(ic, jc, 0) - (long long)NG * a.sz;   // offset of level -3
+
+  // halo items of this thread (fixed across levels) and their column offsets
+  int hii[HR], hjj[HR];
+  bool hok[HR];
+  long long hoff[HR];
+#pragma unroll
+  for (int r = 0; r < HR; ++r) {
+    const int it = item_thread<I::NTHR>() + r * I::NTHR;
+    hok[r] = it < NHALO && halo_item<TX, TY>(it, w, h, hii[r], hjj[r]);
+    hoff[r] = hok[r] ? poff(i0 + hii[r], j0 + hjj[r], 0) - (long long)NG * a.sz : 0;
+  }
+  auto lev = [&](int k) -> long long { return (long long)(k + NG) * a.sz; };
 
   T W[5][NV];     // primitives of levels s-1 .. s+3 (own column)
   T qmc[NV];      // left state at the vertical face above the current level
@@ -298,29 +348,43 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int k = k0 - 3 + l;
-      load_prim<T, NV>(qs, poff(ic, jc, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, W[l]);
+      load_prim<T, NV>(qs, col + lev(k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, W[l]);
     }
   }
+  // prefetched raw conserved values: halo cells of the next level to be
+  // planed, the window's next level, and this level's own Qs / Qn
+  T hc[HR][NV];
+#pragma unroll
+  for (int r = 0; r < HR; ++r)
+    if (hok[r]) load_cons<T, NV>(qs, hoff[r] + lev(k0), a.sv, hc[r]);
 
   T QP[I::RREG][NV];
   for (int s = k0 - 2; s < k1; ++s) {
-    if (act)
-      load_prim<T, NV>(qs, poff(ic, jc, s + 3), a.sv, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG],
-                       a.gm1, W[4]);
+    T wc[NV], qsc[NV], qnc[NV];
+    if (act) {
+      load_cons<T, NV>(qs, col + lev(s + 3), a.sv, wc);
+      if (s >= k0 && combine) {
+        load_cons<T, NV>(qs, col + lev(s), a.sv, qsc);
+        if (use_qn) load_cons<T, NV>(qn, col + lev(s), a.sv, qnc);
+      } else if (s >= k0) {
+        qsc[3] = qs[col + lev(s) + 3 * a.sv];
+      }
+    }
     if (s >= k0) {
-      // ---- (P) primitives of level s: own cell from the window, halo loaded -
+      // ---- (P) primitives of level s: own cell from the window, halo prefetched
       const double rbs = a.rbar_c[s + NG], pbs = a.pbar_c[s + NG];
       if (act) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.P[v][tj + 3][ti + 3] = W[1][v];
       }
-      for (int it = item_thread<I::NTHR>(); it < 6 * (TX + TY); it += I::NTHR) {
-        int ii, jj;
-        if (halo_item<TX, TY>(it, w, h, ii, jj)) {
-          T x[NV];
-          load_prim<T, NV>(qs, poff(i0 + ii, j0 + jj, s), a.sv, rbs, pbs, a.gm1, x);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) S.P[v][jj + 3][ii + 3] = x[v];
+      for (int r = 0; r < HR; ++r) {
+        if (hok[r]) {
+          T x[NV];
+          cons_to_prim_t<T, NV>(hc[r], rbs, pbs, a.gm1, x);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) S.P[v][hjj[r] + 3][hii[r] + 3] = x[v];
+          if (s + 1 < k1) load_cons<T, NV>(qs, hoff[r] + lev(s + 1), a.sv, hc[r]);
         }
       }
       __syncthreads();
@@ -329,20 +393,23 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
       __syncthreads();
       // ---- (L) LMARS at x and y faces (level references) ---------------------
       const T rbT = static_cast<T>(rbs), pbT = static_cast<T>(pbs);
-      auto lev = [&](int, T& r, T& p) {
+      auto levref = [&](int, T& r, T& p) {
         r = rbT;
         p = pbT;
       };
-      phase_lmars<T, NV, TX, TY>(S, w, h, 2, gamma, inv_gm1, lev, lev, QP);
+      phase_lmars<T, NV, TX, TY>(S, w, h, 2, gamma, inv_gm1, levref, levref, QP);
       __syncthreads();
     }
     // ---- vertical direction, own column: face s+1/2 (z-face index s+1) -------
     T dfz[NV];
     if (act) {
+      cons_to_prim_t<T, NV>(wc, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG], a.gm1, W[4]);
       T qmn[NV], qpn[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
+      for (int v = 0; v < NV; ++v) {
         weno5_cell<T>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, linear, qmn[v], qpn[v]);
+        SNAP_VAR_FENCE();
+      }
       if (s >= k0 - 1) {
         T fz[NV];
         lmars_flux<T, NV>(qmc, qpn, 3, static_cast<T>(a.rbar_f[s + 1]),
@@ -365,12 +432,24 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
         r = r - (S.FY[v][tj + 1][ti] - S.FY[v][tj][ti]) * dyi;
         R[v] = r - dfz[v] * dzi;
       }
-      const long long po = poff(ic, jc, s);
       const T grav = static_cast<T>(a.grav);
       R[3] = R[3] - grav * W[1][0];
-      R[4] = R[4] - grav * qs[po + 3 * a.sv];
-      const long long ro = (long long)s * a.rz + (long long)jc * a.ry + ic;
-      write_cell<T, NV>(a, qs, po, ro, R);
+      R[4] = R[4] - grav * qsc[3];
+      const long long po = col + lev(s);
+      if (!combine) {
+        T* __restrict__ o = static_cast<T*>(a.out);
+        const long long ro = (long long)s * a.rz + (long long)jc * a.ry + ic;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o[ro + v * a.rv] = R[v];
+      } else {
+        const T dt = static_cast<T>(a.dt), ca = static_cast<T>(a.ca), cb = static_cast<T>(a.cb);
+        T* o = static_cast<T*>(a.out);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T t = qsc[v] + dt * R[v];
+          o[po + v * a.sv] = use_qn ? ca * qnc[v] + cb * t : cb * t;
+        }
+      }
     }
     // shift the window
 #pragma unroll
