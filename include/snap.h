@@ -129,7 +129,8 @@ int snap_abi_version(void);
 /*
  * Bytes of device workspace `work` needed by operation `op` (SNAP_OP_*) on grid
  * g; 0 if none is needed. Returns 0 and sets the last error for an invalid grid.
- * SNAP_OP_RK3 needs two padded state arrays, SNAP_OP_CFL and SNAP_OP_SUMS a few
+ * SNAP_OP_RK3 and SNAP_OP_RHS_ADJ need two padded state arrays, SNAP_OP_RK3_ADJ
+ * four padded plus two interior arrays, SNAP_OP_CFL and SNAP_OP_SUMS a few
  * hundred kilobytes of reduction partials.
  */
 size_t snap_workspace_bytes(const snap_grid* g, int op);

@@ -12,37 +12,39 @@ inline unsigned adj_blocks(long long n) {
   return (unsigned)(b < 1 ? 1 : b);
 }
 
+template <typename T, int NV, bool XDIR>
+void adj_line_launch(const T* W, const T* r, const AdjArgs& a, int d, T* P, hipStream_t st) {
+  constexpr int LN = LineShape<T, NV, XDIR>::LN, TL = LineShape<T, NV, XDIR>::TL;
+  const LineGeom g = line_geom(a, d);
+  const long long blocks = ((g.nlines + LN - 1) / LN) * ((g.nd + TL - 1) / TL);
+  hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR>), dim3((unsigned)blocks), dim3(LN * TL), 0,
+                     st, W, r, a, d, P);
+}
+
 template <typename T, int NV>
 int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, hipStream_t st) {
   const T* qs = static_cast<const T*>(q);
   const T* r = static_cast<const T*>(rb);
   T* W = static_cast<T*>(w.W);
   T* P = static_cast<T*>(w.P);
-  T* S = static_cast<T*>(w.S);
-  T* C = static_cast<T*>(w.C);
   const long long np = a.sv;
-  hipLaunchKernelGGL((k_adj_prims<T, NV>), dim3(adj_blocks(np)), dim3(256), 0, st, qs, a, W);
+  const int nxp = a.nx + 2 * NG, rows = (a.nz + 2 * NG) * (a.d3 ? a.ny + 2 * NG : 1);
+  const dim3 pgrid(rows, (nxp + 255) / 256);
+  hipLaunchKernelGGL((k_adj_prims<T, NV>), pgrid, dim3(256), 0, st, qs, a, W);
   hipLaunchKernelGGL((k_adj_zero<T>), dim3(adj_blocks(np * NV)), dim3(256), 0, st, P, np * NV);
-  for (int d = 0; d < 3; ++d) {
-    if (d == 1 && !a.d3) continue;
-    const DirBox fb = dir_box(a, d, 1), rbx = dir_box(a, d, 2), gb = dir_box(a, d, 6);
-    hipLaunchKernelGGL((k_adj_faces<T, NV>), dim3(adj_blocks(fb.total)), dim3(256), 0, st, W, r,
-                       a, d, S);
-    hipLaunchKernelGGL((k_adj_recon<T, NV>), dim3(adj_blocks(rbx.total)), dim3(256), 0, st, W, S,
-                       a, d, C);
-    hipLaunchKernelGGL((k_adj_gather<T, NV>), dim3(adj_blocks(gb.total)), dim3(256), 0, st, C, a,
-                       d, 1, P);
-  }
-  // the conserved cotangent reuses W (dead after the reconstruction passes)
-  hipLaunchKernelGGL((k_adj_cons<T, NV>), dim3(adj_blocks(np)), dim3(256), 0, st, qs, P, r, a, W);
+  adj_line_launch<T, NV, true>(W, r, a, 0, P, st);
+  if (a.d3) adj_line_launch<T, NV, false>(W, r, a, 1, P, st);
+  adj_line_launch<T, NV, false>(W, r, a, 2, P, st);
+  // the conserved cotangent reuses W (dead after the line passes)
+  hipLaunchKernelGGL((k_adj_cons<T, NV>), pgrid, dim3(256), 0, st, qs, P, r, a, W);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T, int NV>
 int adj_fold_nv(const AdjWork& w, const AdjArgs& a, void* out, int mode, double alpha,
                 double beta, hipStream_t st) {
-  const long long n = (long long)a.nx * a.ny * a.nz;
-  hipLaunchKernelGGL((k_adj_fold<T, NV>), dim3(adj_blocks(n)), dim3(256), 0, st,
+  const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
+  hipLaunchKernelGGL((k_adj_fold<T, NV>), fgrid, dim3(256), 0, st,
                      static_cast<const T*>(w.W), a, static_cast<T*>(out), mode, alpha, beta);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

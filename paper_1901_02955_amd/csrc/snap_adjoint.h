@@ -4,19 +4,13 @@
 // conserved -> primitive map of App. B) with respect to the interior state,
 // ghost cells being functions of the interior through the boundary conditions.
 //
-// The reverse sweep is split into gather-only kernels (no atomics, so the
-// result is reproducible bit for bit):
+// The reverse sweep uses no atomics, so the result is reproducible bit for bit:
 //   k_adj_prims      primitives of every padded cell (as in the forward pass);
-//   k_adj_faces<d>   per face of direction d: recompute both WENO face states,
-//                    LMARS forward and reverse with the flux cotangent
-//                    F_bar = (r_bar[right cell] - r_bar[left cell]) / dx_d;
-//                    store the cotangents of the two face states;
-//   k_adj_recon<d>   per reconstructed cell (one beyond each end of every
-//                    line): WENO5 reverse seeded by the cotangents of its two
-//                    face values; store the cotangents of its 5 inputs;
-//   k_adj_gather<d>  per cell of the line (ghosts included): add the
-//                    contributions of the (up to) 5 reconstructions that read
-//                    it, in a fixed order, into the primitive cotangent;
+//   k_adj_line<d>    per direction d, per tile of lines: recompute the WENO
+//                    face states, LMARS forward and reverse with the flux
+//                    cotangent F_bar = (r_bar[right cell] - r_bar[left cell]) / dx_d,
+//                    WENO5 reverse to the five stencil inputs, and a fixed-order
+//                    gather of those contributions into the primitive cotangent;
 //   k_adj_cons       per padded cell: gravity terms and the reverse of the
 //                    conserved -> primitive map (double precision);
 //   k_adj_fold       per interior cell: its own cotangent plus those of the
@@ -119,7 +113,7 @@ __device__ __forceinline__ void weno5_cell_adj(T a, T b, T c, T d, T e, T eps, b
     const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
     const T n0 = T(0.1) * t0, n1 = T(0.6) * t1, n2 = T(0.3) * t2;
     const T r0 = T(0.1) * t2, r1 = T(0.6) * t1, r2 = T(0.3) * t0;
-    const T idm = T(1) / (n0 + n1 + n2), idp = T(1) / (r0 + r1 + r2);
+    const T idm = rcp_fast(n0 + n1 + n2), idp = rcp_fast(r0 + r1 + r2);
     const T wm0 = n0 * idm, wm1 = n1 * idm, wm2 = n2 * idm;
     const T wp0 = r0 * idp, wp1 = r1 * idp, wp2 = r2 * idp;
     const T Mm = wm0 * m0 + wm1 * m1 + wm2 * m2;   // 6 (qm - c)
@@ -175,10 +169,11 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
   const T rl = rref + xl[0], rr = rref + xr[0];
   const T pl = pref + xl[4], pr = pref + xr[4];
   const T unl = xl[nrm], unr = xr[nrm];
-  const T cl = sqrt(gamma * pl / rl), cr = sqrt(gamma * pr / rr);
+  const T irl = rcp_fast(rl), irr = rcp_fast(rr);
+  const T cl = sqrt_fast(gamma * pl * irl), cr = sqrt_fast(gamma * pr * irr);
   const T ra = T(0.5) * (rl + rr), ca = T(0.5) * (cl + cr);
   const T rc = ra * ca;
-  const T hh = T(1) / (T(2) * rc);
+  const T hh = T(0.5) * rcp_fast(rc);
   const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) * hh;
   // advected vectors of both sides
   auto adv = [&](const T (&x)[NV], T r, T p, T (&phi)[NV]) {
@@ -199,27 +194,34 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
 #pragma unroll
   for (int m = 0; m < NV; ++m) usb += fb[m] * (wl * phl[m] + (T(1) - wl) * phr[m]);
   const T psb = fb[nrm];
-  // advected-vector cotangents of the upwind side (zero at u* == 0)
-  if (ustar != T(0)) {
+  // advected-vector cotangents of the upwind side (zero at u* == 0); the side
+  // is selected element by element so that both state arrays stay in registers
+  {
     const bool left = ustar > T(0);
-    const T(&x)[NV] = left ? xl : xr;
-    T(&xb)[NV] = left ? xlb : xrb;
-    const T r = left ? rl : rr;
-    T phb[NV];
+    T x[NV], phb[NV], sb[NV];
 #pragma unroll
-    for (int m = 0; m < NV; ++m) phb[m] = ustar * fb[m];
+    for (int m = 0; m < NV; ++m) {
+      x[m] = left ? xl[m] : xr[m];
+      phb[m] = ustar * fb[m];
+    }
+    const T r = left ? rl : rr;
     const T k = T(0.5) * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
-    T rb = phb[0] + phb[1] * x[1] + phb[2] * x[2] + phb[3] * x[3] + phb[4] * k;
+    T rbs = phb[0] + phb[1] * x[1] + phb[2] * x[2] + phb[3] * x[3] + phb[4] * k;
 #pragma unroll
     for (int t = 5; t < NV; ++t) {
-      rb += phb[t] * x[t];
-      xb[t] += phb[t] * r;
+      rbs += phb[t] * x[t];
+      sb[t] = phb[t] * r;
     }
-    xb[0] += rb;
-    xb[1] += phb[1] * r + phb[4] * r * x[1];
-    xb[2] += phb[2] * r + phb[4] * r * x[2];
-    xb[3] += phb[3] * r + phb[4] * r * x[3];
-    xb[4] += phb[4] * (inv_gm1 + T(1));
+    sb[0] = rbs;
+    sb[1] = phb[1] * r + phb[4] * r * x[1];
+    sb[2] = phb[2] * r + phb[4] * r * x[2];
+    sb[3] = phb[3] * r + phb[4] * r * x[3];
+    sb[4] = phb[4] * (inv_gm1 + T(1));
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      xlb[m] += left ? sb[m] : T(0);
+      xrb[m] += left ? T(0) : sb[m];
+    }
   }
   // u* = (unl + unr)/2 - (p'_R - p'_L) hh,  hh = 1 / (2 rc)
   T rcb = T(0);
@@ -238,11 +240,12 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
   const T rab = rcb * ca, cab = rcb * ra;
   T rlb = T(0.5) * rab, rrb = T(0.5) * rab;
   const T clb = T(0.5) * cab, crb = T(0.5) * cab;
-  // c = sqrt(gamma p / rho): dc/dp = c / (2p), dc/drho = -c / (2 rho)
-  xlb[4] += clb * cl / (T(2) * pl);
-  rlb += -clb * cl / (T(2) * rl);
-  xrb[4] += crb * cr / (T(2) * pr);
-  rrb += -crb * cr / (T(2) * rr);
+  // c = sqrt(gamma p / rho): dc/dp = c / (2p) = gamma / (2 rho c), dc/drho = -c / (2 rho)
+  const T hcl = T(0.5) * clb * irl, hcr = T(0.5) * crb * irr;
+  xlb[4] += hcl * gamma * rcp_fast(cl);
+  rlb += -hcl * cl;
+  xrb[4] += hcr * gamma * rcp_fast(cr);
+  rrb += -hcr * cr;
   xlb[0] += rlb;
   xrb[0] += rrb;
 }
@@ -252,149 +255,20 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
 // ---------------------------------------------------------------------------
 
 // Primitives of every padded cell (ghost corners included, harmlessly).
+// Grid: x over padded rows (nz+6)(ny+2gy), y over the padded row.
 template <typename T, int NV>
 __global__ void __launch_bounds__(256) k_adj_prims(const T* __restrict__ q, AdjArgs a,
                                                    T* __restrict__ W) {
-  const long long n = a.sv;
-  const long long nxp = a.nx + 2 * NG, nyp = a.d3 ? a.ny + 2 * NG : 1;
-  for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
-    const int kp = (int)(c / (nxp * nyp));
-    T x[NV];
-    load_prim<T, NV>(q, c, a.sv, a.rbar_c[kp], a.pbar_c[kp], a.gm1, x);
+  const int nxp = a.nx + 2 * NG, nyp = a.d3 ? a.ny + 2 * NG : 1;
+  const int ip = blockIdx.y * 256 + threadIdx.x;
+  if (ip >= nxp) return;
+  const int row = blockIdx.x;
+  const int kp = row / nyp;
+  const long long c = (long long)row * nxp + ip;
+  T x[NV];
+  load_prim<T, NV>(q, c, a.sv, a.rbar_c[kp], a.pbar_c[kp], a.gm1, x);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) W[c + v * a.sv] = x[v];
-  }
-}
-
-// Face pass of direction d: cotangents of the left and right face states.
-template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_adj_faces(const T* __restrict__ W,
-                                                   const T* __restrict__ rb, AdjArgs a, int d,
-                                                   T* __restrict__ S) {
-  const DirBox fb = dir_box(a, d, 1);
-  const long long sd = d == 0 ? 1 : (d == 1 ? a.sy : a.sz);   // padded stride along d
-  const long long rd = d == 0 ? 1 : (d == 1 ? a.ry : a.rz);   // interior stride along d
-  const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
-  const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
-  const T inv_gm1 = static_cast<T>(a.inv_gm1), hi = static_cast<T>(a.dxi[d]);
-  const bool linear = a.linear != 0;
-  for (long long g = blockIdx.x * 256LL + threadIdx.x; g < fb.total;
-       g += (long long)gridDim.x * 256) {
-    int x, y, z;
-    box_coords(fb, g, x, y, z);
-    const int f = d == 0 ? x : (d == 1 ? y : z);   // face f: between cells f-1 and f
-    // interior coordinates of the cell right of the face
-    const long long pc = padded_off(a, x, y, z);   // cell f (padded, may be ghost nd)
-    T xl[NV], xr[NV], fbar[NV], xlb[NV], xrb[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T* w = W + v * a.sv + pc;
-      T qp_unused, qm_unused;
-      // left state: qm of cell f-1 (stencil f-3 .. f+1)
-      weno5_cell<T>(w[-3 * sd], w[-2 * sd], w[-sd], w[0], w[sd], eps, linear, xl[v], qp_unused);
-      // right state: qp of cell f (stencil f-2 .. f+2)
-      weno5_cell<T>(w[-2 * sd], w[-sd], w[0], w[sd], w[2 * sd], eps, linear, qm_unused, xr[v]);
-      xlb[v] = T(0);
-      xrb[v] = T(0);
-    }
-    // flux cotangent: R_c = -(F_{c+1} - F_c) / dx  =>  F_bar_f = (r_bar_f - r_bar_{f-1}) / dx
-    const long long ro = (long long)z * a.rz + (long long)y * a.ry + x;   // valid if f < nd
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T right = f < nd ? rb[ro + v * a.rv] : T(0);
-      const T left = f > 0 ? rb[ro - rd + v * a.rv] : T(0);
-      fbar[v] = (right - left) * hi;
-    }
-    T rref, pref;
-    if (d == 2) {
-      rref = static_cast<T>(a.rbar_f[f]);
-      pref = static_cast<T>(a.pbar_f[f]);
-    } else {
-      rref = static_cast<T>(a.rbar_c[z + NG]);
-      pref = static_cast<T>(a.pbar_c[z + NG]);
-    }
-    lmars_flux_adj<T, NV>(xl, xr, d + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      S[(2 * v) * fb.total + g] = xlb[v];
-      S[(2 * v + 1) * fb.total + g] = xrb[v];
-    }
-  }
-}
-
-// Reconstruction pass of direction d: cotangents of the 5 stencil inputs of
-// every reconstructed cell j = -1 .. nd (box coordinate j + 1).
-template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_adj_recon(const T* __restrict__ W,
-                                                   const T* __restrict__ S, AdjArgs a, int d,
-                                                   T* __restrict__ C) {
-  const DirBox rbx = dir_box(a, d, 2);
-  const DirBox fb = dir_box(a, d, 1);
-  const long long sd = d == 0 ? 1 : (d == 1 ? a.sy : a.sz);
-  const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
-  const T eps = static_cast<T>(a.eps);
-  const bool linear = a.linear != 0;
-  for (long long g = blockIdx.x * 256LL + threadIdx.x; g < rbx.total;
-       g += (long long)gridDim.x * 256) {
-    int x, y, z;
-    box_coords(rbx, g, x, y, z);
-    int c[3] = {x, y, z};
-    const int j = c[d] - 1;   // reconstructed cell
-    c[d] = j;
-    const long long pc = padded_off(a, c[0], c[1], c[2]);
-    // face j+1 (left state = qm_j) and face j (right state = qp_j)
-    int f1[3] = {c[0], c[1], c[2]}, f0[3] = {c[0], c[1], c[2]};
-    f1[d] = j + 1;
-    f0[d] = j;
-    const bool has1 = j + 1 <= nd;
-    const bool has0 = j >= 0;
-    const long long g1 = has1 ? box_index(fb, f1[0], f1[1], f1[2]) : 0;
-    const long long g0 = has0 ? box_index(fb, f0[0], f0[1], f0[2]) : 0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T gm = has1 ? S[(2 * v) * fb.total + g1] : T(0);
-      const T gp = has0 ? S[(2 * v + 1) * fb.total + g0] : T(0);
-      const T* w = W + v * a.sv + pc;
-      T out[5];
-      weno5_cell_adj<T>(w[-2 * sd], w[-sd], w[0], w[sd], w[2 * sd], eps, linear, gm, gp, out);
-#pragma unroll
-      for (int o = 0; o < 5; ++o) C[((long long)o * NV + v) * rbx.total + g] = out[o];
-    }
-  }
-}
-
-// Gather of direction d into the primitive cotangent P (padded layout, every
-// cell of the cross-shaped stencil region): P[c] (+)= sum_{o} C[o][j = c + 2 - o].
-template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_adj_gather(const T* __restrict__ C, AdjArgs a, int d,
-                                                    int accumulate, T* __restrict__ P) {
-  const DirBox rbx = dir_box(a, d, 2);
-  const DirBox gb = dir_box(a, d, 6);   // cells -3 .. nd+2 along d
-  const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
-  for (long long g = blockIdx.x * 256LL + threadIdx.x; g < gb.total;
-       g += (long long)gridDim.x * 256) {
-    int x, y, z;
-    box_coords(gb, g, x, y, z);
-    int c[3] = {x, y, z};
-    const int cd = c[d] - 3;
-    c[d] = cd;
-    const long long pc = padded_off(a, c[0], c[1], c[2]);
-    T acc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = accumulate ? P[pc + v * a.sv] : T(0);
-#pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      const int j = cd + 2 - o;   // reconstruction whose input o is this cell
-      if (j < -1 || j > nd) continue;
-      int r[3] = {c[0], c[1], c[2]};
-      r[d] = j + 1;
-      const long long gr = box_index(rbx, r[0], r[1], r[2]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += C[((long long)o * NV + v) * rbx.total + gr];
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) P[pc + v * a.sv] = acc[v];
-  }
+  for (int v = 0; v < NV; ++v) W[c + v * a.sv] = x[v];
 }
 
 template <typename T>
@@ -416,6 +290,235 @@ __global__ void __launch_bounds__(256) k_adj_combine(T* __restrict__ out, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused adjoint of one direction d for a tile of LN lines x TL cells along d.
+// In LDS: (A) left/right face states of the reconstructed cells the tile
+// needs, (B) LMARS forward and reverse at its faces with the flux cotangent
+// from r_bar, (C) WENO5 reverse of its reconstructed cells (the cotangents of
+// their five inputs), (D) for every cell of the tile (and the ghost cells
+// beyond a domain edge) the fixed-order sum of the contributions that reach
+// it, added into the primitive cotangent P. Deterministic: every sum has one
+// fixed order and the directions run as separate launches.
+// ---------------------------------------------------------------------------
+template <typename T, int NV, int LN, int TL>
+struct LineTile {
+  static constexpr int NA = TL + 6;   // reconstructed cells -3 .. TL+2 (relative)
+  static constexpr int NF = TL + 5;   // faces -2 .. TL+2
+  static constexpr int NC = TL + 4;   // reverse-reconstructed cells -2 .. TL+1
+  T QM[NV][LN][NA];   // left state at face j+1 of reconstructed cell j
+  T QP[NV][LN][NA];   // right state at face j
+  T XL[NV][LN][NF];   // cotangent of the left state at face f
+  T XR[NV][LN][NF];   // cotangent of the right state at face f
+  T C[5][NV][LN][NC]; // cotangents of the five inputs of reconstructed cell j
+  long long pbase[LN];  // padded offset of position 0 of each line
+  long long rbase[LN];  // interior offset of position 0 of each line
+  int lev[LN];          // level (z index) of each line (x and y lines)
+};
+
+// Tile shape per element type, variable count and direction (x lines are
+// contiguous; y and z lines are consecutive in x): the largest of a few
+// shapes whose LineTile stays within 64 KiB.
+template <typename T, int NV, bool XDIR>
+struct LineShape {
+  static constexpr bool A = sizeof(LineTile<T, NV, (XDIR ? 4 : 8), (XDIR ? 64 : 32)>) <= 65536;
+  static constexpr bool B = sizeof(LineTile<T, NV, (XDIR ? 4 : 8), (XDIR ? 32 : 16)>) <= 65536;
+  static constexpr int LN = A ? (XDIR ? 4 : 8) : (B ? (XDIR ? 4 : 8) : (XDIR ? 2 : 8));
+  static constexpr int TL = A ? (XDIR ? 64 : 32) : (B ? (XDIR ? 32 : 16) : (XDIR ? 32 : 8));
+};
+
+struct LineGeom {
+  int d;          // direction
+  int nd;         // cells along d
+  long long nlines;
+  long long sd;   // padded stride along d
+  long long rd;   // interior stride along d
+};
+
+__host__ __device__ inline LineGeom line_geom(const AdjArgs& a, int d) {
+  LineGeom g;
+  g.d = d;
+  g.nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
+  g.nlines = d == 0 ? (long long)a.ny * a.nz : (d == 1 ? (long long)a.nx * a.nz : (long long)a.nx * a.ny);
+  g.sd = d == 0 ? 1 : (d == 1 ? a.sy : a.sz);
+  g.rd = d == 0 ? 1 : (d == 1 ? a.ry : a.rz);
+  return g;
+}
+
+// interior coordinates (i, j, k) of position p on line L of direction d
+__device__ __forceinline__ void line_cell(const AdjArgs& a, const LineGeom& g, long long L, int p,
+                                          int& i, int& j, int& k) {
+  if (g.d == 0) {
+    i = p;
+    j = (int)(L % a.ny);
+    k = (int)(L / a.ny);
+  } else if (g.d == 1) {
+    i = (int)(L % a.nx);
+    j = p;
+    k = (int)(L / a.nx);
+  } else {
+    i = (int)(L % a.nx);
+    j = (int)(L / a.nx);
+    k = p;
+  }
+}
+
+template <typename T, int NV, int LN, int TL, bool XDIR>
+__global__ void __launch_bounds__(LN* TL) k_adj_line(const T* __restrict__ W,
+                                                     const T* __restrict__ rb, AdjArgs a, int d,
+                                                     T* __restrict__ P) {
+  using Tile = LineTile<T, NV, LN, TL>;
+  constexpr int NTHR = LN * TL;
+  __shared__ Tile S;
+  const LineGeom g = line_geom(a, d);
+  const long long nseg = (g.nd + TL - 1) / TL;
+  const long long lt = blockIdx.x / nseg;
+  const int seg = (int)(blockIdx.x % nseg);
+  const long long L0 = lt * LN;
+  const int c0 = seg * TL;
+  const int c1 = min(c0 + TL, g.nd);
+  const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
+  // constant indices only: a runtime index into the argument struct would
+  // copy it to scratch memory
+  const T inv_gm1 = static_cast<T>(a.inv_gm1);
+  const T hi = static_cast<T>(d == 0 ? a.dxi[0] : (d == 1 ? a.dxi[1] : a.dxi[2]));
+  const bool linear = a.linear != 0;
+  // item (l, p) of a phase with np positions: x lines run p fastest, y/z lines l fastest
+  auto decode = [&](int it, int np, int& l, int& p) {
+    if (XDIR) {
+      l = it / np;
+      p = it % np;
+    } else {
+      l = it % LN;
+      p = it / LN;
+    }
+  };
+  // line tables: offsets of position 0 of every line of the tile
+  if (threadIdx.x < LN && L0 + threadIdx.x < g.nlines) {
+    int i, j, k;
+    line_cell(a, g, L0 + threadIdx.x, 0, i, j, k);
+    S.pbase[threadIdx.x] = padded_off(a, i, j, k);
+    S.rbase[threadIdx.x] = (long long)k * a.rz + (long long)j * a.ry + i;
+    S.lev[threadIdx.x] = k;
+  }
+  __syncthreads();
+  // (A) face states of reconstructed cells j = c0-3 .. c0+TL+2 that exist (-1 .. nd)
+  for (int it = threadIdx.x; it < LN * Tile::NA; it += NTHR) {
+    int l, p;
+    decode(it, Tile::NA, l, p);
+    const int jg = c0 - 3 + p;
+    if (L0 + l >= g.nlines || jg < -1 || jg > g.nd) continue;
+    const long long pc = S.pbase[l] + jg * g.sd;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T* w = W + v * a.sv + pc;
+      T qm, qp;
+      weno5_cell<T>(w[-2 * g.sd], w[-g.sd], w[0], w[g.sd], w[2 * g.sd], eps, linear, qm, qp);
+      S.QM[v][l][p] = qm;
+      S.QP[v][l][p] = qp;
+    }
+  }
+  __syncthreads();
+  // (B) LMARS forward + reverse at faces f = c0-2 .. c0+TL+2 that exist (0 .. nd)
+  for (int it = threadIdx.x; it < LN * Tile::NF; it += NTHR) {
+    int l, p;
+    decode(it, Tile::NF, l, p);
+    const int fg = c0 - 2 + p;
+    if (L0 + l >= g.nlines) continue;
+    T xlb[NV], xrb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xlb[v] = T(0);
+      xrb[v] = T(0);
+    }
+    if (fg >= 0 && fg <= g.nd) {
+      T xl[NV], xr[NV], fbar[NV];
+      // face fg: left state = qm of cell fg-1 (index p), right = qp of cell fg (index p+1)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        xl[v] = S.QM[v][l][p];
+        xr[v] = S.QP[v][l][p + 1];
+      }
+      const long long ro = S.rbase[l] + (fg < g.nd ? fg : g.nd - 1) * g.rd;   // cell min(fg, nd-1)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const T right = fg < g.nd ? rb[ro + v * a.rv] : T(0);
+        const long long lo = fg < g.nd ? ro - g.rd : ro;   // cell fg-1
+        const T left = fg > 0 ? rb[lo + v * a.rv] : T(0);
+        fbar[v] = (right - left) * hi;
+      }
+      T rref, pref;
+      if (d == 2) {
+        rref = static_cast<T>(a.rbar_f[fg]);
+        pref = static_cast<T>(a.pbar_f[fg]);
+      } else {
+        rref = static_cast<T>(a.rbar_c[S.lev[l] + NG]);
+        pref = static_cast<T>(a.pbar_c[S.lev[l] + NG]);
+      }
+      lmars_flux_adj<T, NV>(xl, xr, d + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      S.XL[v][l][p] = xlb[v];
+      S.XR[v][l][p] = xrb[v];
+    }
+  }
+  __syncthreads();
+  // (C) WENO5 reverse of reconstructed cells j = c0-2 .. c0+TL+1 that exist (-1 .. nd)
+  for (int it = threadIdx.x; it < LN * Tile::NC; it += NTHR) {
+    int l, p;
+    decode(it, Tile::NC, l, p);
+    const int jg = c0 - 2 + p;
+    const bool ok = L0 + l < g.nlines && jg >= -1 && jg <= g.nd;
+    if (!ok) {
+      if (L0 + l < g.nlines) {
+#pragma unroll
+        for (int o = 0; o < 5; ++o)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) S.C[o][v][l][p] = T(0);
+      }
+      continue;
+    }
+    const long long pc = S.pbase[l] + jg * g.sd;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      // qm_j is the left state of face j+1 (XL index p+1); qp_j the right state of face j (XR index p)
+      const T gm = S.XL[v][l][p + 1];
+      const T gp = S.XR[v][l][p];
+      const T* w = W + v * a.sv + pc;
+      T out[5];
+      weno5_cell_adj<T>(w[-2 * g.sd], w[-g.sd], w[0], w[g.sd], w[2 * g.sd], eps, linear, gm, gp,
+                        out);
+#pragma unroll
+      for (int o = 0; o < 5; ++o) S.C[o][v][l][p] = out[o];
+    }
+  }
+  __syncthreads();
+  // (D) cells of the tile, plus the ghost cells beyond a domain edge
+  const int lo = c0 == 0 ? -3 : c0;
+  const int hiend = c1 == g.nd ? g.nd + 3 : c1;
+  const int npos = hiend - lo;
+  for (int it = threadIdx.x; it < LN * (TL + 6); it += NTHR) {
+    int l, p;
+    decode(it, TL + 6, l, p);
+    if (p >= npos || L0 + l >= g.nlines) continue;
+    const int cg = lo + p;
+    const long long pc = S.pbase[l] + cg * g.sd;
+    T acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = P[pc + v * a.sv];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+      const int jg = cg + 2 - o;   // reconstruction whose input o is this cell
+      if (jg < -1 || jg > g.nd) continue;
+      const int q = jg - (c0 - 2);   // its index in C
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += S.C[o][v][l][q];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) P[pc + v * a.sv] = acc[v];
+  }
+}
+
 // Per padded cell of the stencil region: gravity and the reverse of the
 // conserved -> primitive map. Writes the conserved cotangent Qb (padded).
 template <typename T, int NV>
@@ -423,19 +526,20 @@ __global__ void __launch_bounds__(256) k_adj_cons(const T* __restrict__ q,
                                                   const T* __restrict__ P,
                                                   const T* __restrict__ rb, AdjArgs a,
                                                   T* __restrict__ Qb) {
-  const long long n = a.sv;
-  const long long nxp = a.nx + 2 * NG, nyp = a.d3 ? a.ny + 2 * NG : 1;
-  for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
-    const int ip = (int)(c % nxp);
-    const long long r = c / nxp;
-    const int jp = (int)(r % nyp);
-    const int kp = (int)(r / nyp);
+  // grid: x over padded rows, y over the padded row
+  const int nxp = a.nx + 2 * NG, nyp = a.d3 ? a.ny + 2 * NG : 1;
+  const int ip = blockIdx.y * 256 + threadIdx.x;
+  if (ip >= nxp) return;
+  const int row = blockIdx.x;
+  const int jp = row % nyp, kp = row / nyp;
+  const long long c = (long long)row * nxp + ip;
+  {
     const int i = ip - NG, j = jp - a.gy, k = kp - NG;
     const int gi = (i < 0 || i >= a.nx) + (j < 0 || j >= a.ny) + (k < 0 || k >= a.nz);
     if (gi > 1) {   // corner ghosts are never read by the cross-shaped stencil
 #pragma unroll
       for (int v = 0; v < NV; ++v) Qb[c + v * a.sv] = T(0);
-      continue;
+      return;
     }
     double pb[NV], cv[NV];
 #pragma unroll
@@ -485,12 +589,13 @@ template <typename T, int NV>
 __global__ void __launch_bounds__(256) k_adj_fold(const T* __restrict__ Qb, AdjArgs a,
                                                   T* __restrict__ out, int mode, double alpha,
                                                   double beta) {
-  const long long n = (long long)a.nx * a.ny * a.nz;
-  for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
-    const int i = (int)(c % a.nx);
-    const long long r = c / a.nx;
-    const int j = (int)(r % a.ny);
-    const int k = (int)(r / a.ny);
+  // grid: x over interior rows, y over the interior row
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, k = row / a.ny;
+  const long long c = (long long)row * a.nx + i;
+  {
     double acc[NV];
     const long long pc = padded_off(a, i, j, k);
 #pragma unroll
@@ -500,6 +605,7 @@ __global__ void __launch_bounds__(256) k_adj_fold(const T* __restrict__ Qb, AdjA
       if (d == 1 && !a.d3) continue;
       const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
       const int me = d == 0 ? i : (d == 1 ? j : k);
+      if (me >= 3 && me < nd - 3) continue;   // no ghost cell copies a cell this deep
       for (int m = 0; m < 6; ++m) {
         const int gidx = m < 3 ? -1 - m : nd + (m - 3);
         if (adj_ghost_src(gidx, nd, a.bc[d]) != me) continue;

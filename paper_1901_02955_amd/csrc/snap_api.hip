@@ -273,28 +273,17 @@ size_t interior_bytes(const snap_grid* g) {
   return (size_t)g->nx * g->ny * g->nz * nvar_of(g) * elem_of(g);
 }
 
-// Layout of the right-hand-side adjoint workspace: W and P (padded state
-// size each), S (2 nvar values per face of the largest direction) and C
-// (5 nvar values per reconstructed cell of the largest direction).
+// Layout of the right-hand-side adjoint workspace: W (padded primitives, then
+// the padded conserved cotangent) and P (padded primitive cotangent).
 struct AdjLayout {
-  size_t w, p, s, c, total;
+  size_t w, p, total;
 };
 
 AdjLayout adj_layout(const snap_grid* g) {
-  const AdjArgs a = adj_args(g);
-  long long fmax = 0, rmax = 0;
-  for (int d = 0; d < 3; ++d) {
-    if (d == 1 && !a.d3) continue;
-    const long long f = dir_box(a, d, 1).total, r = dir_box(a, d, 2).total;
-    fmax = f > fmax ? f : fmax;
-    rmax = r > rmax ? r : rmax;
-  }
   AdjLayout L;
   L.w = 0;
   L.p = L.w + align256(padded_bytes(g));
-  L.s = L.p + align256(padded_bytes(g));
-  L.c = L.s + align256((size_t)2 * a.nvar * fmax * elem_of(g));
-  L.total = L.c + align256((size_t)5 * a.nvar * rmax * elem_of(g));
+  L.total = L.p + align256(padded_bytes(g));
   return L;
 }
 
@@ -304,8 +293,6 @@ AdjWork adj_work(const snap_grid* g, void* base) {
   AdjWork w;
   w.W = b + L.w;
   w.P = b + L.p;
-  w.S = b + L.s;
-  w.C = b + L.c;
   return w;
 }
 

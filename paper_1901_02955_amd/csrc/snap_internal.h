@@ -48,8 +48,6 @@ struct AdjArgs;
 struct AdjWork {
   void* W;   // padded primitives, then padded conserved cotangent
   void* P;   // padded primitive cotangent
-  void* S;   // face-state cotangents of one direction
-  void* C;   // stencil-input cotangents of one direction
 };
 
 // Launchers; each returns 0 on success, -1 if the launch failed.
