@@ -17,7 +17,8 @@ void adj_line_launch(const T* W, const T* r, const AdjArgs& a, int d, T* P, hipS
   constexpr int LN = LineShape<T, NV, XDIR>::LN, TL = LineShape<T, NV, XDIR>::TL;
   const LineGeom g = line_geom(a, d);
   const long long blocks = ((g.nlines + LN - 1) / LN) * ((g.nd + TL - 1) / TL);
-  hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR>), dim3((unsigned)blocks), dim3(LN * TL), 0,
+  hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR>), dim3((unsigned)blocks),
+                     dim3(LineTile<T, NV, LN, TL>::NTHR), 0,
                      st, W, r, a, d, P);
 }
 

@@ -70,15 +70,76 @@ __device__ __forceinline__ long long padded_off(const AdjArgs& a, int i, int j, 
 }
 
 // ---------------------------------------------------------------------------
-// Reverse of weno5_cell (same formulation as the forward): given the
-// cotangents gm of qm and gp of qp, return the cotangents of a..e.
+// WENO5 of one cell split for the reverse sweep (same formulation as
+// weno5_cell). weno5_lin returns both face values and keeps the forward
+// quantities the linearisation needs; weno5_rev maps the cotangents gm of qm
+// and gp of qp back to the five inputs a..e.
+// The smoothness sums s_k = eps + beta_k are scaled by a common power of two
+// (exact; the normalised weights do not depend on it) so that the products
+// of squared sums below stay in range in single precision.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void weno5_cell_adj(T a, T b, T c, T d, T e, T eps, bool linear, T gm,
-                                               T gp, T (&g)[5]) {
+struct WenoLin {
+  T s0, s1, s2, sc;                // scaled smoothness sums, and the scale
+  T wm0, wm1, wm2, wp0, wp1, wp2;  // normalised weights of qm and of qp
+  T idm, idp;                      // reciprocals of the unnormalised weight sums
+};
+
+template <typename T>
+__device__ __forceinline__ void weno5_lin(T a, T b, T c, T d, T e, T eps, bool linear,
+                                          WenoLin<T>& L, T& qm, T& qp) {
   const T da = a - c, db = b - c, dd = d - c, de = e - c;
   const T m0 = T(2) * da - T(7) * db, m1 = T(2) * dd - db, m2 = T(5) * dd - de;
   const T p0 = T(2) * de - T(7) * dd, p1 = T(2) * db - dd, p2 = T(5) * db - da;
+  const T sixth = T(1) / T(6);
+  if (linear) {
+    qm = c + (T(0.1) * m0 + T(0.6) * m1 + T(0.3) * m2) * sixth;
+    qp = c + (T(0.1) * p0 + T(0.6) * p1 + T(0.3) * p2) * sixth;
+    return;
+  }
+  const T k13 = T(13) / T(12);
+  const T u0 = da - T(2) * db, v0 = da - T(4) * db;
+  const T u1 = db + dd, v1 = db - dd;
+  const T u2 = de - T(2) * dd, v2 = de - T(4) * dd;
+  T s0 = eps + (k13 * u0 * u0 + T(0.25) * v0 * v0);
+  T s1 = eps + (k13 * u1 * u1 + T(0.25) * v1 * v1);
+  T s2 = eps + (k13 * u2 * u2 + T(0.25) * v2 * v2);
+  T sc;
+  if constexpr (sizeof(T) == 4) {
+    const float mx = fmaxf(fmaxf(s0, s1), s2);
+    sc = __builtin_amdgcn_ldexpf(1.0f, -__builtin_amdgcn_frexp_expf(mx));
+  } else {
+    const double mx = fmax(fmax(s0, s1), s2);
+    sc = __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(mx));
+  }
+  s0 *= sc;
+  s1 *= sc;
+  s2 *= sc;
+  const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
+  const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
+  const T n0 = T(0.1) * t0, n1 = T(0.6) * t1, n2 = T(0.3) * t2;
+  const T r0 = T(0.1) * t2, r1 = T(0.6) * t1, r2 = T(0.3) * t0;
+  const T idm = rcp_fast(n0 + n1 + n2), idp = rcp_fast(r0 + r1 + r2);
+  L.s0 = s0;
+  L.s1 = s1;
+  L.s2 = s2;
+  L.sc = sc;
+  L.wm0 = n0 * idm;
+  L.wm1 = n1 * idm;
+  L.wm2 = n2 * idm;
+  L.wp0 = r0 * idp;
+  L.wp1 = r1 * idp;
+  L.wp2 = r2 * idp;
+  L.idm = idm;
+  L.idp = idp;
+  qm = c + (L.wm0 * m0 + L.wm1 * m1 + L.wm2 * m2) * sixth;
+  qp = c + (L.wp0 * p0 + L.wp1 * p1 + L.wp2 * p2) * sixth;
+}
+
+template <typename T>
+__device__ __forceinline__ void weno5_rev(T a, T b, T c, T d, T e, bool linear,
+                                          const WenoLin<T>& L, T gm, T gp, T (&g)[5]) {
+  const T da = a - c, db = b - c, dd = d - c, de = e - c;
   const T sixth = T(1) / T(6);
   T mb0, mb1, mb2, pb0, pb1, pb2;
   T ub0 = T(0), vb0 = T(0), ub1 = T(0), vb1 = T(0), ub2 = T(0), vb2 = T(0);
@@ -90,60 +151,41 @@ __device__ __forceinline__ void weno5_cell_adj(T a, T b, T c, T d, T e, T eps, b
     pb1 = gp * T(0.6) * sixth;
     pb2 = gp * T(0.3) * sixth;
   } else {
-    const T k13 = T(13) / T(12);
-    const T u0 = da - T(2) * db, v0 = da - T(4) * db;
-    const T u1 = db + dd, v1 = db - dd;
-    const T u2 = de - T(2) * dd, v2 = de - T(4) * dd;
-    T s0 = eps + (k13 * u0 * u0 + T(0.25) * v0 * v0);
-    T s1 = eps + (k13 * u1 * u1 + T(0.25) * v1 * v1);
-    T s2 = eps + (k13 * u2 * u2 + T(0.25) * v2 * v2);
-    // common power-of-two scale (exact; the weights do not depend on it)
-    T sc = T(1);
-    if constexpr (sizeof(T) == 4) {
-      const float mx = fmaxf(fmaxf(s0, s1), s2);
-      sc = __builtin_amdgcn_ldexpf(1.0f, -__builtin_amdgcn_frexp_expf(mx));
-    } else {
-      const double mx = fmax(fmax(s0, s1), s2);
-      sc = __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(mx));
-    }
-    s0 *= sc;
-    s1 *= sc;
-    s2 *= sc;
-    const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
-    const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
-    const T n0 = T(0.1) * t0, n1 = T(0.6) * t1, n2 = T(0.3) * t2;
-    const T r0 = T(0.1) * t2, r1 = T(0.6) * t1, r2 = T(0.3) * t0;
-    const T idm = rcp_fast(n0 + n1 + n2), idp = rcp_fast(r0 + r1 + r2);
-    const T wm0 = n0 * idm, wm1 = n1 * idm, wm2 = n2 * idm;
-    const T wp0 = r0 * idp, wp1 = r1 * idp, wp2 = r2 * idp;
-    const T Mm = wm0 * m0 + wm1 * m1 + wm2 * m2;   // 6 (qm - c)
-    const T Mp = wp0 * p0 + wp1 * p1 + wp2 * p2;
-    mb0 = gm * wm0 * sixth;
-    mb1 = gm * wm1 * sixth;
-    mb2 = gm * wm2 * sixth;
-    pb0 = gp * wp0 * sixth;
-    pb1 = gp * wp1 * sixth;
-    pb2 = gp * wp2 * sixth;
+    const T m0 = T(2) * da - T(7) * db, m1 = T(2) * dd - db, m2 = T(5) * dd - de;
+    const T p0 = T(2) * de - T(7) * dd, p1 = T(2) * db - dd, p2 = T(5) * db - da;
+    const T Mm = L.wm0 * m0 + L.wm1 * m1 + L.wm2 * m2;   // 6 (qm - c)
+    const T Mp = L.wp0 * p0 + L.wp1 * p1 + L.wp2 * p2;
+    const T gms = gm * sixth, gps = gp * sixth;
+    mb0 = gms * L.wm0;
+    mb1 = gms * L.wm1;
+    mb2 = gms * L.wm2;
+    pb0 = gps * L.wp0;
+    pb1 = gps * L.wp1;
+    pb2 = gps * L.wp2;
     // cotangents of the unnormalised weights
-    const T gmD = gm * sixth * idm, gpD = gp * sixth * idp;
+    const T gmD = gms * L.idm, gpD = gps * L.idp;
     const T nb0 = gmD * (m0 - Mm), nb1 = gmD * (m1 - Mm), nb2 = gmD * (m2 - Mm);
     const T rb0 = gpD * (p0 - Mp), rb1 = gpD * (p1 - Mp), rb2 = gpD * (p2 - Mp);
     const T tb0 = T(0.1) * nb0 + T(0.3) * rb2;
-    const T tb1 = T(0.6) * nb1 + T(0.6) * rb1;
+    const T tb1 = T(0.6) * (nb1 + rb1);
     const T tb2 = T(0.3) * nb2 + T(0.1) * rb0;
+    const T q0 = L.s0 * L.s0, q1 = L.s1 * L.s1, q2 = L.s2 * L.s2;
     const T qb0 = tb1 * q2 + tb2 * q1;
     const T qb1 = tb0 * q2 + tb2 * q0;
     const T qb2 = tb0 * q1 + tb1 * q0;
-    // s_k (unscaled) cotangent = sc * 2 s'_k qb'_k ; beta_k has the same cotangent
-    const T bb0 = sc * T(2) * s0 * qb0;
-    const T bb1 = sc * T(2) * s1 * qb1;
-    const T bb2 = sc * T(2) * s2 * qb2;
-    ub0 = T(2) * k13 * u0 * bb0;
-    vb0 = T(0.5) * v0 * bb0;
-    ub1 = T(2) * k13 * u1 * bb1;
-    vb1 = T(0.5) * v1 * bb1;
-    ub2 = T(2) * k13 * u2 * bb2;
-    vb2 = T(0.5) * v2 * bb2;
+    // cotangent of beta_k (that of the unscaled s_k): sc * 2 s'_k * qb_k,
+    // times d beta / d u = 2 (13/12) u and d beta / d v = v / 2
+    const T two_sc = T(2) * L.sc;
+    const T bb0 = two_sc * L.s0 * qb0;
+    const T bb1 = two_sc * L.s1 * qb1;
+    const T bb2 = two_sc * L.s2 * qb2;
+    const T k136 = T(13) / T(6);
+    ub0 = k136 * (da - T(2) * db) * bb0;
+    vb0 = T(0.5) * (da - T(4) * db) * bb0;
+    ub1 = k136 * (db + dd) * bb1;
+    vb1 = T(0.5) * (db - dd) * bb1;
+    ub2 = k136 * (de - T(2) * dd) * bb2;
+    vb2 = T(0.5) * (de - T(4) * dd) * bb2;
   }
   const T dab = T(2) * mb0 - pb2 + ub0 + vb0;
   const T dbb = -T(7) * mb0 - mb1 + T(2) * pb1 + T(5) * pb2 - T(2) * ub0 - T(4) * vb0 + ub1 + vb1;
@@ -305,6 +347,8 @@ struct LineTile {
   static constexpr int NA = TL + 6;   // reconstructed cells -3 .. TL+2 (relative)
   static constexpr int NF = TL + 5;   // faces -2 .. TL+2
   static constexpr int NC = TL + 4;   // reverse-reconstructed cells -2 .. TL+1
+  // threads: the largest phase (NA items per line) in one round of whole waves
+  static constexpr int NTHR = (LN * NA + 63) / 64 * 64;
   T QM[NV][LN][NA];   // left state at face j+1 of reconstructed cell j
   T QP[NV][LN][NA];   // right state at face j
   T XL[NV][LN][NF];   // cotangent of the left state at face f
@@ -344,36 +388,48 @@ __host__ __device__ inline LineGeom line_geom(const AdjArgs& a, int d) {
   return g;
 }
 
-// interior coordinates (i, j, k) of position p on line L of direction d
+// interior coordinates (i, j, k) of position p on line L of direction d;
+// lines are numbered with the lower transverse axis fastest
 __device__ __forceinline__ void line_cell(const AdjArgs& a, const LineGeom& g, long long L, int p,
                                           int& i, int& j, int& k) {
+  const int n0 = g.d == 0 ? a.ny : a.nx;
+  int lo, hi;
+  if (g.nlines <= 0xffffffffLL) {
+    const unsigned u = (unsigned)L, qq = u / (unsigned)n0;
+    hi = (int)qq;
+    lo = (int)(u - qq * (unsigned)n0);
+  } else {
+    hi = (int)(L / n0);
+    lo = (int)(L - (long long)hi * n0);
+  }
   if (g.d == 0) {
     i = p;
-    j = (int)(L % a.ny);
-    k = (int)(L / a.ny);
+    j = lo;
+    k = hi;
   } else if (g.d == 1) {
-    i = (int)(L % a.nx);
+    i = lo;
     j = p;
-    k = (int)(L / a.nx);
+    k = hi;
   } else {
-    i = (int)(L % a.nx);
-    j = (int)(L / a.nx);
+    i = lo;
+    j = hi;
     k = p;
   }
 }
 
 template <typename T, int NV, int LN, int TL, bool XDIR>
-__global__ void __launch_bounds__(LN* TL) k_adj_line(const T* __restrict__ W,
-                                                     const T* __restrict__ rb, AdjArgs a, int d,
-                                                     T* __restrict__ P) {
+__global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR))
+    k_adj_line(const T* __restrict__ W, const T* __restrict__ rb, AdjArgs a, int d,
+               T* __restrict__ P) {
   using Tile = LineTile<T, NV, LN, TL>;
-  constexpr int NTHR = LN * TL;
+  constexpr int NTHR = Tile::NTHR;
+  static_assert(NTHR >= LN * Tile::NA, "one item of phase A per thread");
   __shared__ Tile S;
   const LineGeom g = line_geom(a, d);
-  const long long nseg = (g.nd + TL - 1) / TL;
-  const long long lt = blockIdx.x / nseg;
-  const int seg = (int)(blockIdx.x % nseg);
-  const long long L0 = lt * LN;
+  const unsigned nseg = (unsigned)((g.nd + TL - 1) / TL);
+  const unsigned lt = blockIdx.x / nseg;
+  const int seg = (int)(blockIdx.x - lt * nseg);
+  const long long L0 = (long long)lt * LN;
   const int c0 = seg * TL;
   const int c1 = min(c0 + TL, g.nd);
   const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
@@ -401,20 +457,34 @@ __global__ void __launch_bounds__(LN* TL) k_adj_line(const T* __restrict__ W,
     S.lev[threadIdx.x] = k;
   }
   __syncthreads();
-  // (A) face states of reconstructed cells j = c0-3 .. c0+TL+2 that exist (-1 .. nd)
-  for (int it = threadIdx.x; it < LN * Tile::NA; it += NTHR) {
-    int l, p;
-    decode(it, Tile::NA, l, p);
-    const int jg = c0 - 3 + p;
-    if (L0 + l >= g.nlines || jg < -1 || jg > g.nd) continue;
-    const long long pc = S.pbase[l] + jg * g.sd;
+  // (A) this thread's reconstructed cell jg = c0-3+pa (one per thread, -1 .. nd);
+  // the forward quantities stay in registers for its reverse in (C)
+  int la, pa;
+  decode(threadIdx.x, Tile::NA, la, pa);
+  const bool line_a = threadIdx.x < LN * Tile::NA && L0 + la < g.nlines;
+  const int ja = c0 - 3 + pa;
+  const bool cell_a = line_a && ja >= -1 && ja <= g.nd;
+  const long long pca = cell_a ? S.pbase[la] + ja * g.sd : 0;
+  WenoLin<T> lin[NV];
+  // the stencils of every variable are loaded before any arithmetic, so that
+  // all NV x 5 loads are in flight together
+  auto load_stencils = [&](T (&st)[NV][5]) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const T* w = W + v * a.sv + pc;
+      const T* w = W + v * a.sv + pca;
+#pragma unroll
+      for (int o = 0; o < 5; ++o) st[v][o] = w[(o - 2) * g.sd];
+    }
+  };
+  if (cell_a) {
+    T st[NV][5];
+    load_stencils(st);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
       T qm, qp;
-      weno5_cell<T>(w[-2 * g.sd], w[-g.sd], w[0], w[g.sd], w[2 * g.sd], eps, linear, qm, qp);
-      S.QM[v][l][p] = qm;
-      S.QP[v][l][p] = qp;
+      weno5_lin<T>(st[v][0], st[v][1], st[v][2], st[v][3], st[v][4], eps, linear, lin[v], qm, qp);
+      S.QM[v][la][pa] = qm;
+      S.QP[v][la][pa] = qp;
     }
   }
   __syncthreads();
@@ -463,33 +533,28 @@ __global__ void __launch_bounds__(LN* TL) k_adj_line(const T* __restrict__ W,
     }
   }
   __syncthreads();
-  // (C) WENO5 reverse of reconstructed cells j = c0-2 .. c0+TL+1 that exist (-1 .. nd)
-  for (int it = threadIdx.x; it < LN * Tile::NC; it += NTHR) {
-    int l, p;
-    decode(it, Tile::NC, l, p);
-    const int jg = c0 - 2 + p;
-    const bool ok = L0 + l < g.nlines && jg >= -1 && jg <= g.nd;
-    if (!ok) {
-      if (L0 + l < g.nlines) {
+  // (C) WENO5 reverse of the same cell: C index pa-1 covers cells c0-2 .. c0+TL+1
+  if (line_a && pa >= 1 && pa <= Tile::NC) {
+    const int pc = pa - 1;
+    if (cell_a) {
+      T st[NV][5];
+      load_stencils(st);
 #pragma unroll
-        for (int o = 0; o < 5; ++o)
+      for (int v = 0; v < NV; ++v) {
+        // qm_j is the left state of face j+1 (XL index pc+1); qp_j the right state of face j (XR index pc)
+        const T gm = S.XL[v][la][pc + 1];
+        const T gp = S.XR[v][la][pc];
+        T out[5];
+        weno5_rev<T>(st[v][0], st[v][1], st[v][2], st[v][3], st[v][4], linear, lin[v], gm, gp,
+                     out);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) S.C[o][v][l][p] = T(0);
+        for (int o = 0; o < 5; ++o) S.C[o][v][la][pc] = out[o];
       }
-      continue;
-    }
-    const long long pc = S.pbase[l] + jg * g.sd;
+    } else {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      // qm_j is the left state of face j+1 (XL index p+1); qp_j the right state of face j (XR index p)
-      const T gm = S.XL[v][l][p + 1];
-      const T gp = S.XR[v][l][p];
-      const T* w = W + v * a.sv + pc;
-      T out[5];
-      weno5_cell_adj<T>(w[-2 * g.sd], w[-g.sd], w[0], w[g.sd], w[2 * g.sd], eps, linear, gm, gp,
-                        out);
+      for (int o = 0; o < 5; ++o)
 #pragma unroll
-      for (int o = 0; o < 5; ++o) S.C[o][v][l][p] = out[o];
+        for (int v = 0; v < NV; ++v) S.C[o][v][la][pc] = T(0);
     }
   }
   __syncthreads();

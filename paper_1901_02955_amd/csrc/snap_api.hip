@@ -623,8 +623,9 @@ int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const doub
   int nb = nblocks;
   if (nb == 0) {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
     int per = batched_occupancy(dtype, nt, variant);
     nb = cus * (per > 0 ? per : 1);
   }
