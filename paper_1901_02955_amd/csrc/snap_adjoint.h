@@ -349,11 +349,16 @@ struct LineTile {
   static constexpr int NC = TL + 4;   // reverse-reconstructed cells -2 .. TL+1
   // threads: the largest phase (NA items per line) in one round of whole waves
   static constexpr int NTHR = (LN * NA + 63) / 64 * 64;
-  T QM[NV][LN][NA];   // left state at face j+1 of reconstructed cell j
-  T QP[NV][LN][NA];   // right state at face j
+  // the face states are dead once (B) has read them: (C) writes over them
+  union {
+    struct {
+      T QM[NV][LN][NA];   // left state at face j+1 of reconstructed cell j
+      T QP[NV][LN][NA];   // right state at face j
+    };
+    T C[5][NV][LN][NC];   // cotangents of the five inputs of reconstructed cell j
+  };
   T XL[NV][LN][NF];   // cotangent of the left state at face f
   T XR[NV][LN][NF];   // cotangent of the right state at face f
-  T C[5][NV][LN][NC]; // cotangents of the five inputs of reconstructed cell j
   long long pbase[LN];  // padded offset of position 0 of each line
   long long rbase[LN];  // interior offset of position 0 of each line
   int lev[LN];          // level (z index) of each line (x and y lines)
@@ -417,8 +422,19 @@ __device__ __forceinline__ void line_cell(const AdjArgs& a, const LineGeom& g, l
   }
 }
 
+// Optional occupancy target of the fused direction kernel (waves per SIMD);
+// 0 leaves the register budget to the compiler.
+#ifndef SNAP_ADJ_LINE_WAVES_PER_EU
+#define SNAP_ADJ_LINE_WAVES_PER_EU 0
+#endif
+#if SNAP_ADJ_LINE_WAVES_PER_EU > 0
+#define SNAP_ADJ_LINE_ATTR __attribute__((amdgpu_waves_per_eu(SNAP_ADJ_LINE_WAVES_PER_EU)))
+#else
+#define SNAP_ADJ_LINE_ATTR
+#endif
+
 template <typename T, int NV, int LN, int TL, bool XDIR>
-__global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR))
+__global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE_ATTR
     k_adj_line(const T* __restrict__ W, const T* __restrict__ rb, AdjArgs a, int d,
                T* __restrict__ P) {
   using Tile = LineTile<T, NV, LN, TL>;
