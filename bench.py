@@ -64,20 +64,24 @@ def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int) -> int:
     return (14 + ntracer) + ndir * nv * 78 + ndir * (37 + ntracer) + ndir * 3 * nv + 4 + 4 * nv
 
 
+# sources the stage kernel and its launch (tiling, z-chunks) are built from
+STAGE_SOURCES = ("snap_device.h", "snap_stage.h", "snap_internal.h", "stage_launch.h",
+                 "stage_f64.hip", "stage_f32.hip", "snap_api.hip")
+
+
 def stage_sources_digest() -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1901_02955_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in STAGE_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(dtype_name: str):
-    """HBM bytes per stage launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs.
+def _profile_value(key: str):
+    """A value of the committed counter summary of the stage kernel.
 
     Returns None unless the counters were taken on the current kernel sources.
     """
@@ -92,8 +96,12 @@ def measured_traffic(dtype_name: str):
             vals[k.strip()] = v.strip()
     if vals.get("sources_digest") != stage_sources_digest():
         return None
-    key = f"bytes_per_launch_{dtype_name}"
     return float(vals[key]) if key in vals else None
+
+
+def measured_traffic(dtype_name: str):
+    """HBM bytes per stage launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs."""
+    return _profile_value(f"bytes_per_launch_{dtype_name}")
 
 
 def run_gpu(dtype, steps: int, warmup: int):
@@ -145,7 +153,12 @@ def run_gpu(dtype, steps: int, warmup: int):
         "hbm_roofline": {
             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "measured_bytes_per_launch": traffic,
+            "measured_frac": (traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
         },
+        # VALU instructions issued / (256 CUs x one wave instruction per cycle x
+        # active cycles), from the committed SQ_INSTS_VALU / GRBM_GUI_ACTIVE run
+        "valu_utilisation": _profile_value(f"valu_issue_util_{name}"),
         "final_dt": dt,
     }
     del qd, work, cw
@@ -346,7 +359,7 @@ def run_cpu_baseline():
     sub.interior(qs)[...] = grid.interior(q)[:, :, :b, :b]
     del q
     dt = oracle.cfl_dt(qs, sub, CFL)
-    nsteps = 12
+    nsteps = 24
     t0 = time.perf_counter()
     oracle.run(qs, sub, dt, nsteps)
     el = time.perf_counter() - t0
@@ -419,6 +432,7 @@ def main():
         },
         "roofline": f64["roofline"],
         "hbm_roofline": f64["hbm_roofline"],
+        "valu_utilisation": f64["valu_utilisation"],
         "stage_kernel_avg_ms": f64["stage_kernel_avg_ms"],
     }
     if not args.no_f32 and args.variant == "both":
@@ -426,12 +440,12 @@ def main():
         out["variants"] = {"f32": {
             "value": f32["value"], "ms_per_step": f32["ms_per_step"], "dtype": "f32",
             "stage_kernel_avg_ms": f32["stage_kernel_avg_ms"], "roofline": f32["roofline"],
-            "hbm_roofline": f32["hbm_roofline"],
+            "hbm_roofline": f32["hbm_roofline"], "valu_utilisation": f32["valu_utilisation"],
         }}
         out["f32_speedup"] = f32["value"] / f64["value"]
         out["f32_error_vs_f64"] = run_fp32_error()
     if not args.only_headline:
-        out["jovian"] = run_jovian(10, 2)
+        out["jovian"] = run_jovian(50, 3)
         out["ensemble"] = run_ensemble(20)
         out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:

@@ -250,17 +250,16 @@ __device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int 
 // active part of a ragged tile.
 template <int TX, int TY>
 __device__ __forceinline__ bool halo_item(int it, int w, int h, int& ii, int& jj) {
-  if (it < 6 * TY) {
-    const int m = it % 6;
-    jj = it / 6;
-    ii = m < 3 ? m - 3 : w + m - 3;
-    return jj < h;
-  }
-  const int r = it - 6 * TY;
-  const int m = r % 6;
-  ii = r / 6;
-  jj = m < 3 ? m - 3 : h + m - 3;
-  return ii < w;
+  // selects rather than two branches that each write one of ii / jj: the
+  // compiler would merge those writes into one store through a selected
+  // address and keep ii, jj in scratch memory
+  const bool xs = it < 6 * TY;   // x halo (columns left / right of the tile)
+  const int r = xs ? it : it - 6 * TY;
+  const int m = r % 6, q = r / 6;
+  const int e = m < 3 ? m - 3 : (xs ? w : h) + m - 3;
+  ii = xs ? e : q;
+  jj = xs ? q : e;
+  return q < (xs ? h : w);
 }
 
 // ---------------------------------------------------------------------------
