@@ -44,7 +44,13 @@ notes of the repository):
   u* < 0, and the mean of both when u* == 0.
 * Boundaries: periodic = wrap copy; reflecting = mirror of the conserved
   state with the normal momentum negated.
-* Tracers are passive: p = (gamma - 1)(E - K).
+* Tracers are passive, p = (gamma - 1)(E - K), unless the grid selects the
+  mixture equation of state (App. B, eq. p2 and the effective adiabatic
+  index): tracer t is a vapour (a_t = 1/eps_t - 1) or a condensate
+  (a_t = -1), b_t = sigma_t - 1, A = sum mu_t rho_t, and
+  p = (gamma_d - 1) (1 + sum a_t q_t) / (1 + sum b_t q_t) (E - K - A);
+  at a face the same ratio with the face's mass fractions gives the
+  effective gamma of the sound speed and the internal energy p / (gamma - 1).
 """
 from __future__ import annotations
 
@@ -127,13 +133,43 @@ def fill_ghosts(q: torch.Tensor, grid) -> torch.Tensor:
 # Thermodynamics (App. B)
 # ---------------------------------------------------------------------------
 
+def mixture_coefficients(grid):
+    """(a_t, b_t, mu_t) of every tracer for the mixture equation of state
+    (App. B), or None when the tracers are passive.
+
+    a_t: 1/eps_t - 1 for a vapour (molar-mass ratio eps_t), -1 for a
+    condensate (it has mass but no partial pressure); b_t = sigma_t - 1 with
+    sigma_t the tracer's heat capacity over c_v of the dry gas; mu_t its
+    chemical potential per unit mass.
+    """
+    if getattr(grid, "eos", 0) != 1 or grid.ntracer == 0:
+        return None
+    coef = []
+    for t in range(grid.ntracer):
+        a = -1.0 if grid.tracer_kind[t] == 1 else 1.0 / grid.tracer_eps[t] - 1.0
+        coef.append((a, grid.tracer_sigma[t] - 1.0, grid.tracer_mu[t]))
+    return coef
+
+
+def mixture_ratio(qs, coef):
+    """(1 + sum_t a_t q_t) / (1 + sum_t b_t q_t), summed in tracer order (App. B)."""
+    num = 1.0
+    den = 1.0
+    for qt, (a, b, _) in zip(qs, coef):
+        num = num + a * qt
+        den = den + b * qt
+    return num / den
+
+
 def cons_to_prim(q: torch.Tensor, grid) -> dict:
     """Primitive variables of every cell of a padded state (App. B).
 
     The evaluation order is fixed and shared in writing with the GPU path:
     inv = 1/rho; u = (rho u) inv (likewise v, w); K = ((rho u) u + (rho v) v)
     + (rho w) w, times 1/2; p = (gamma - 1)(E - K); p' = p - pbar_k;
-    rho' = rho - rhobar_k; q_i = rho_i inv.
+    rho' = rho - rhobar_k; q_i = rho_i inv. With the mixture equation of
+    state: A = (mu_1 rho_1 + mu_2 rho_2) + ..., num = (1 + a_1 q_1) + ...,
+    den likewise, p = ((gamma - 1)(num / den)) ((E - K) - A).
     """
     rho, mx, my, mz, E = q[0], q[1], q[2], q[3], q[4]
     inv = 1.0 / rho
@@ -141,12 +177,19 @@ def cons_to_prim(q: torch.Tensor, grid) -> dict:
     v = my * inv
     w = mz * inv
     K = 0.5 * ((mx * u + my * v) + mz * w)
-    p = (grid.gamma - 1.0) * (E - K)
+    qs = [q[5 + t] * inv for t in range(grid.ntracer)]
+    coef = mixture_coefficients(grid)
+    if coef is None:
+        p = (grid.gamma - 1.0) * (E - K)
+    else:
+        A = coef[0][2] * q[5]
+        for t in range(1, grid.ntracer):
+            A = A + coef[t][2] * q[5 + t]
+        p = ((grid.gamma - 1.0) * mixture_ratio(qs, coef)) * ((E - K) - A)
     rbar = _t(grid.rhobar_cell).reshape(-1, 1, 1)
     pbar = _t(grid.pbar_cell).reshape(-1, 1, 1)
     prim = {"rho": rho, "u": u, "v": v, "w": w, "p": p,
-            "rp": rho - rbar, "pp": p - pbar,
-            "q": [q[5 + t] * inv for t in range(grid.ntracer)]}
+            "rp": rho - rbar, "pp": p - pbar, "q": qs}
     return prim
 
 
@@ -226,29 +269,42 @@ def reconstruct_faces(v: torch.Tensor, axis: int, n: int, eps: float, linear: bo
 # LMARS (Sec. 4.1)
 # ---------------------------------------------------------------------------
 
-def lmars_flux(L: dict, R: dict, normal: int, gamma: float, ntracer: int):
+def lmars_flux(L: dict, R: dict, normal: int, gamma: float, ntracer: int, thermo=None):
     """LMARS numerical flux at a face from left/right primitive face states.
 
     Each state holds full density ``rho``, velocity ``u``/``v``/``w``, full
     pressure ``p``, perturbation pressure ``pp`` and tracer mass fractions
     ``q``. Returns the flux of (rho, rho u, rho v, rho w, E, rho q_i).
+    ``thermo``: the mixture coefficients of ``mixture_coefficients`` (the
+    side's own effective gamma and chemical energy), or None (passive).
     """
     vel = ("u", "v", "w")
     unL, unR = L[vel[normal]], R[vel[normal]]
-    cL = torch.sqrt(gamma * L["p"] / L["rho"])
-    cR = torch.sqrt(gamma * R["p"] / R["rho"])
+
+    def gm1_of(S):   # effective gamma - 1 of a side
+        if thermo is None:
+            return gamma - 1.0
+        return (gamma - 1.0) * mixture_ratio(S["q"], thermo)
+
+    gL, gR = gm1_of(L), gm1_of(R)
+    cL = torch.sqrt((1.0 + gL) * L["p"] / L["rho"])
+    cR = torch.sqrt((1.0 + gR) * R["p"] / R["rho"])
     rho_avg = 0.5 * (L["rho"] + R["rho"])
     c_avg = 0.5 * (cL + cR)
     rc = rho_avg * c_avg
     pstar = 0.5 * (L["pp"] + R["pp"]) - 0.5 * rc * (unR - unL)      # eq. rp
     ustar = 0.5 * (unL + unR) - (R["pp"] - L["pp"]) / (2.0 * rc)    # eq. ru
 
-    def advected(S):
-        E = prim_to_cons_energy(S["rho"], S["u"], S["v"], S["w"], S["p"], gamma)
+    def advected(S, gm1):
+        if thermo is None:
+            E = prim_to_cons_energy(S["rho"], S["u"], S["v"], S["w"], S["p"], gamma)
+        else:   # E = p / (gamma_eff - 1) + K + rho sum mu_t q_t
+            E = (S["p"] / gm1 + 0.5 * S["rho"] * (S["u"] ** 2 + S["v"] ** 2 + S["w"] ** 2)
+                 + S["rho"] * sum(mu * qt for qt, (_, _, mu) in zip(S["q"], thermo)))
         return ([S["rho"], S["rho"] * S["u"], S["rho"] * S["v"], S["rho"] * S["w"], E + S["p"]]
                 + [S["rho"] * qt for qt in S["q"]])
 
-    phiL, phiR = advected(L), advected(R)
+    phiL, phiR = advected(L, gL), advected(R, gR)
     flux = []
     for m, (fl, fr) in enumerate(zip(phiL, phiR)):
         up = torch.where(ustar > 0, fl, torch.where(ustar < 0, fr, 0.5 * (fl + fr)))
@@ -300,7 +356,8 @@ def rhs_filled(qf: torch.Tensor, grid) -> torch.Tensor:
                  "w": rec[3][side], "pp": rec[4][side], "p": pref + rec[4][side],
                  "q": [r[side] for r in rec[5:]]}
             states.append(S)
-        flux, _, _ = lmars_flux(states[0], states[1], comp, grid.gamma, grid.ntracer)
+        flux, _, _ = lmars_flux(states[0], states[1], comp, grid.gamma, grid.ntracer,
+                                mixture_coefficients(grid))
         for m in range(nvar):
             F = flux[m]
             dF = F.narrow(arr_axis, 1, n) - F.narrow(arr_axis, 0, n)
@@ -368,12 +425,12 @@ def run(q, grid, dt: float, nsteps: int) -> torch.Tensor:
 def cfl_dt(q, grid, cfl: float) -> float:
     """dt = cfl / max over interior cells of sum_d (|u_d| + c) / dx_d."""
     q = _interior(_t(q), grid)
-    rho, mx, my, mz, E = q[0], q[1], q[2], q[3], q[4]
-    inv = 1.0 / rho
-    u, v, w = mx * inv, my * inv, mz * inv
-    K = 0.5 * ((mx * u + my * v) + mz * w)
-    p = (grid.gamma - 1.0) * (E - K)
-    c = torch.sqrt(grid.gamma * p / rho)
+    rho = q[0]
+    prim = cons_to_prim(q, grid.copy(rhobar_cell=np.zeros(1), pbar_cell=np.zeros(1)))
+    u, v, w, p = prim["u"], prim["v"], prim["w"], prim["p"]
+    coef = mixture_coefficients(grid)
+    gam = grid.gamma if coef is None else 1.0 + (grid.gamma - 1.0) * mixture_ratio(prim["q"], coef)
+    c = torch.sqrt(gam * p / rho)
     s = (torch.abs(u) + c) / grid.dx
     if grid.ny > 1:
         s = s + (torch.abs(v) + c) / grid.dy

@@ -95,3 +95,69 @@ def test_dropped_kinetic_energy_breaks_round_trip(monkeypatch):
     from tests import test_oracle_eos_adjoint as TE
     with pytest.raises(AssertionError):
         TE.test_prim_cons_round_trip()
+
+
+# --- mixture equation of state ----------------------------------------------
+
+def _moist_pins():
+    from tests import test_oracle_moist as TM
+    return TM
+
+
+def test_inverted_mixture_ratio_breaks_dalton_pin(monkeypatch):
+    TM = _moist_pins()
+    orig = O.mixture_ratio
+    monkeypatch.setattr(O, "mixture_ratio", lambda qs, coef: 1.0 / orig(qs, coef))
+    with pytest.raises(AssertionError):
+        TM.test_mixture_pressure_is_daltons_law()
+
+
+def test_molar_mass_ratio_not_inverted_breaks_dalton_pin(monkeypatch):
+    TM = _moist_pins()
+    orig = O.mixture_coefficients
+
+    def bad(grid):
+        coef = orig(grid)
+        if coef is None:
+            return None
+        return [((grid.tracer_eps[t] - 1.0) if grid.tracer_kind[t] == 0 else a, b, mu)
+                for t, (a, b, mu) in enumerate(coef)]          # eps - 1 instead of 1/eps - 1
+    monkeypatch.setattr(O, "mixture_coefficients", bad)
+    with pytest.raises(AssertionError):
+        TM.test_mixture_pressure_is_daltons_law()
+
+
+def test_condensate_counted_as_gas_breaks_dalton_pin(monkeypatch):
+    TM = _moist_pins()
+    orig = O.mixture_coefficients
+
+    def bad(grid):
+        coef = orig(grid)
+        if coef is None:
+            return None
+        return [(0.0 if grid.tracer_kind[t] == 1 else a, b, mu) for t, (a, b, mu) in enumerate(coef)]
+    monkeypatch.setattr(O, "mixture_coefficients", bad)
+    with pytest.raises(AssertionError):
+        TM.test_mixture_pressure_is_daltons_law()
+
+
+def test_dry_gamma_at_faces_breaks_one_gas_pin(monkeypatch):
+    TM = _moist_pins()
+    orig = O.lmars_flux
+    monkeypatch.setattr(O, "lmars_flux",
+                        lambda L, R, normal, gamma, ntracer, thermo=None: orig(L, R, normal, gamma, ntracer))
+    with pytest.raises(AssertionError):
+        TM.test_uniform_mixture_is_one_ideal_gas()
+
+
+def test_chemical_energy_dropped_at_faces_breaks_advection_pin(monkeypatch):
+    TM = _moist_pins()
+    orig = O.lmars_flux
+
+    def bad(L, R, normal, gamma, ntracer, thermo=None):
+        if thermo is not None:
+            thermo = [(a, b, 0.0) for a, b, _ in thermo]
+        return orig(L, R, normal, gamma, ntracer, thermo)
+    monkeypatch.setattr(O, "lmars_flux", bad)
+    with pytest.raises(AssertionError):
+        TM.test_chemical_energy_is_advected_with_its_tracer()

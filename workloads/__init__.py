@@ -14,7 +14,8 @@ the conserved vector of App. B with total density and total energy.
 
 Initial conditions are built from primitive fields with the single-gas
 energy relation E = p/(gamma-1) + rho*|u|^2/2 (App. B, passive-tracer
-reduction); gravity acts along -z.
+reduction), or, for a grid with the mixture equation of state, from the
+species' partial pressures and heat capacities; gravity acts along -z.
 """
 from __future__ import annotations
 
@@ -29,6 +30,10 @@ BC_PERIODIC = 0
 BC_REFLECT = 1
 MAX_TRACERS = 8
 RGAS = 8.314462618         # J / (mol K)
+EOS_PASSIVE = 0            # tracers do not enter the equation of state
+EOS_MIXTURE = 1            # ideal-gas mixture with condensates (Sec. 2, App. B)
+TRACER_VAPOUR = 0
+TRACER_CONDENSATE = 1
 
 
 @dataclasses.dataclass
@@ -56,6 +61,15 @@ class Grid:
     pbar_cell: Optional[np.ndarray] = None
     rhobar_face: Optional[np.ndarray] = None
     pbar_face: Optional[np.ndarray] = None
+    # Mixture equation of state (used when eos == EOS_MIXTURE), per tracer:
+    # kind (vapour or condensate); eps = molar mass / that of the dry gas
+    # (vapours); sigma = heat capacity at constant volume / c_v of the dry
+    # gas (c_ij / c_v,d for a condensate); mu = chemical potential (J/kg).
+    eos: int = EOS_PASSIVE
+    tracer_kind: Tuple[int, ...] = ()
+    tracer_eps: Tuple[float, ...] = ()
+    tracer_sigma: Tuple[float, ...] = ()
+    tracer_mu: Tuple[float, ...] = ()
 
     @property
     def nvar(self) -> int:
@@ -218,10 +232,31 @@ def state_from_primitives(grid: Grid, rho, u, v, w, p, tracers: Sequence = ()):
     qi[1] = rho * u
     qi[2] = rho * v
     qi[3] = rho * w
-    qi[4] = p / (grid.gamma - 1.0) + 0.5 * rho * (np.asarray(u) ** 2 + np.asarray(v) ** 2 + np.asarray(w) ** 2)
+    kin = 0.5 * rho * (np.asarray(u) ** 2 + np.asarray(v) ** 2 + np.asarray(w) ** 2)
     for t, qt in enumerate(tracers):
         qi[5 + t] = rho * qt
+    if grid.eos == EOS_MIXTURE:
+        qi[4] = mixture_internal_energy(grid, rho, p, [qi[5 + t] for t in range(grid.ntracer)]) + kin
+        for t in range(grid.ntracer):
+            qi[4] += grid.tracer_mu[t] * qi[5 + t]
+    else:
+        qi[4] = p / (grid.gamma - 1.0) + kin
     return q
+
+
+def mixture_internal_energy(grid: Grid, rho, p, rho_t):
+    """Internal energy per volume of a gas-condensate parcel at pressure p.
+
+    From the species: the temperature follows from Dalton's law,
+    p = R_d T (rho_d + sum over vapours rho_i / eps_i), and the internal
+    energy is c_v,d T (rho_d + sum over all tracers sigma_t rho_t), with
+    c_v,d = R_d / (gamma_d - 1) and rho_d = rho - sum rho_t.
+    """
+    rho_d = rho - sum(rho_t) if rho_t else rho
+    gas = rho_d + sum(r / e for r, e, k in zip(rho_t, grid.tracer_eps, grid.tracer_kind)
+                      if k == TRACER_VAPOUR)
+    heat = rho_d + sum(r * s for r, s in zip(rho_t, grid.tracer_sigma))
+    return p / (grid.gamma - 1.0) * heat / gas
 
 
 def rest_fields(grid: Grid):
