@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 1
+#define SNAP_ABI_VERSION 2
 
 /* return codes */
 #define SNAP_OK 0
@@ -65,6 +65,14 @@ extern "C" {
 #define SNAP_NG 3
 #define SNAP_MAX_TRACERS 8
 
+/* equation of state */
+#define SNAP_EOS_PASSIVE 0 /* tracers do not enter the pressure */
+#define SNAP_EOS_MIXTURE 1 /* ideal-gas mixture with condensates (Sec. 2, App. B) */
+
+/* tracer kinds under SNAP_EOS_MIXTURE */
+#define SNAP_TRACER_VAPOUR 0     /* a gas: partial pressure rho_i R_d T / eps_i */
+#define SNAP_TRACER_CONDENSATE 1 /* mass and heat capacity, no partial pressure */
+
 /* operations for snap_workspace_bytes */
 #define SNAP_OP_RHS 0
 #define SNAP_OP_RK3 1
@@ -78,10 +86,11 @@ extern "C" {
  *
  * nx, ny, nz     interior cells, each >= 1; ny == 1 selects a 2-D x-z problem.
  * ng             must be SNAP_NG.
- * ntracer        passive tracer densities, 0 .. SNAP_MAX_TRACERS; nvar = 5 + ntracer.
- *                Tracers do not enter the equation of state: with no condensate
- *                mass and vapour gas constants equal to the dry one the mixture
- *                relation of App. B reduces to p = (gamma - 1)(E - K).
+ * ntracer        tracer densities, 0 .. SNAP_MAX_TRACERS; nvar = 5 + ntracer.
+ *                Under SNAP_EOS_PASSIVE they do not enter the equation of state:
+ *                with no condensate mass and vapour heat capacities in the ratio
+ *                of their gas constants the mixture relation of App. B reduces
+ *                to p = (gamma - 1)(E - K).
  * dtype          SNAP_F64 or SNAP_F32 element type of q, rhs and work.
  * bc[3]          boundary condition of the x, y and z axes (bc[1] ignored in 2-D).
  * weno_linear    1 = linear weights (0.1, 0.6, 0.3) of Sec. 4.2 (fifth-order
@@ -96,6 +105,26 @@ extern "C" {
  *                for a reflecting z axis and wraps them for a periodic one).
  * rhobar_face,   DEVICE, nz + 1 doubles each: reference density and pressure at
  * pbar_face      the z faces; index k is the face between levels k-1 and k.
+ * eos            SNAP_EOS_PASSIVE (0; what a zero-initialised struct selects) or
+ *                SNAP_EOS_MIXTURE. With the mixture (App. B, eq. p2 and the
+ *                effective adiabatic index; gamma is then gamma_d of the dry gas)
+ *                tracer t of kind tracer_kind[t] has:
+ *                  a_t = 1/tracer_eps[t] - 1 (vapour) or -1 (condensate),
+ *                  b_t = tracer_sigma[t] - 1, chemical potential tracer_mu[t],
+ *                and with q_t = rho_t / rho, A = sum mu_t rho_t:
+ *                  p = (gamma - 1) (1 + sum a_t q_t) / (1 + sum b_t q_t) (E - K - A);
+ *                the same ratio of the face mass fractions gives each side of a
+ *                face its effective gamma (sound speed) and internal energy.
+ * tracer_eps     molar mass of a vapour over that of the dry gas, finite > 0
+ *                (ignored for condensates).
+ * tracer_sigma   heat capacity at constant volume of a vapour (of a condensate:
+ *                its heat capacity) over c_v of the dry gas, finite > 0.
+ * tracer_mu      chemical potential per unit mass, J/kg, finite (0 for gases
+ *                whose potentials are set to zero; for a condensate
+ *                mu_i - (L^r + (c_ij - c_p,i) T^r), Sec. 2, eq. muij).
+ *                The tracer fields are read only under SNAP_EOS_MIXTURE with
+ *                ntracer > 0; there the adjoint and batched entry points return
+ *                SNAP_E_UNSUPPORTED.
  *
  * Density and pressure are reconstructed as perturbations rho - rhobar and
  * p - pbar of the level (the vertical perturbation pressure of Sec. 4.1); face
@@ -118,6 +147,11 @@ typedef struct snap_grid {
   const double* pbar_cell;
   const double* rhobar_face;
   const double* pbar_face;
+  int32_t eos;
+  int32_t tracer_kind[SNAP_MAX_TRACERS];
+  double tracer_eps[SNAP_MAX_TRACERS];
+  double tracer_sigma[SNAP_MAX_TRACERS];
+  double tracer_mu[SNAP_MAX_TRACERS];
 } snap_grid;
 
 /* Thread-local message of the last failed call of this thread ("" if none). */

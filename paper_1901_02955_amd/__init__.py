@@ -26,6 +26,7 @@ __all__ = [
     "batched_workspace",
     "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
+    "SNAP_EOS_PASSIVE", "SNAP_EOS_MIXTURE", "SNAP_TRACER_VAPOUR", "SNAP_TRACER_CONDENSATE",
 ]
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -43,6 +44,11 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
+SNAP_ABI_VERSION = 2
+SNAP_EOS_PASSIVE = 0
+SNAP_EOS_MIXTURE = 1
+SNAP_TRACER_VAPOUR = 0
+SNAP_TRACER_CONDENSATE = 1
 SNAP_OP_RHS = 0
 SNAP_OP_RK3 = 1
 SNAP_OP_CFL = 2
@@ -75,6 +81,10 @@ class SnapGridC(ctypes.Structure):
         ("gamma", ctypes.c_double), ("grav", ctypes.c_double), ("weno_eps", ctypes.c_double),
         ("rhobar_cell", ctypes.c_void_p), ("pbar_cell", ctypes.c_void_p),
         ("rhobar_face", ctypes.c_void_p), ("pbar_face", ctypes.c_void_p),
+        ("eos", ctypes.c_int32), ("tracer_kind", ctypes.c_int32 * SNAP_MAX_TRACERS),
+        ("tracer_eps", ctypes.c_double * SNAP_MAX_TRACERS),
+        ("tracer_sigma", ctypes.c_double * SNAP_MAX_TRACERS),
+        ("tracer_mu", ctypes.c_double * SNAP_MAX_TRACERS),
     ]
 
 
@@ -120,6 +130,10 @@ def lib() -> ctypes.CDLL:
                 fn = getattr(handle, name)
                 fn.restype = res
                 fn.argtypes = args
+            version = int(handle.snap_abi_version())
+            if version != SNAP_ABI_VERSION:
+                raise RuntimeError(f"{LIB_PATH} has ABI version {version}, this binding needs "
+                                   f"{SNAP_ABI_VERSION}: rebuild it (python -c 'import __graft_entry__ as g; g.build()')")
             _lib = handle
         return _lib
 
@@ -140,14 +154,17 @@ class DeviceGrid:
 
     Built from plain values; ``device_grid`` builds one from any object with
     the same attribute names (nx, ny, nz, dx, dy, dz, gamma, grav, ntracer, bc,
-    weno_eps, weno_linear, rhobar_cell, pbar_cell, rhobar_face, pbar_face).
+    weno_eps, weno_linear, rhobar_cell, pbar_cell, rhobar_face, pbar_face and,
+    optionally, eos, tracer_kind, tracer_eps, tracer_sigma, tracer_mu).
     """
 
     def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
                  gamma: float, grav: float, ntracer: int, bc: Sequence[int],
                  weno_eps: float, weno_linear: bool, rhobar_cell, pbar_cell,
                  rhobar_face, pbar_face, dtype: torch.dtype = torch.float64,
-                 device: Optional[torch.device] = None):
+                 device: Optional[torch.device] = None, eos: int = SNAP_EOS_PASSIVE,
+                 tracer_kind: Sequence[int] = (), tracer_eps: Sequence[float] = (),
+                 tracer_sigma: Sequence[float] = (), tracer_mu: Sequence[float] = ()):
         if dtype not in (torch.float64, torch.float32):
             raise ValueError("dtype must be torch.float64 or torch.float32")
         device = torch.device(device or "cuda")
@@ -169,6 +186,13 @@ class DeviceGrid:
         c.dx, c.dy, c.dz = float(dx), float(dy), float(dz)
         c.gamma, c.grav, c.weno_eps = float(gamma), float(grav), float(weno_eps)
         c.rhobar_cell, c.pbar_cell, c.rhobar_face, c.pbar_face = (r.data_ptr() for r in refs)
+        c.eos = int(eos)
+        for t, (k, e, sg, mu) in enumerate(zip(tracer_kind, tracer_eps, tracer_sigma, tracer_mu)):
+            if t >= SNAP_MAX_TRACERS:
+                raise ValueError(f"at most {SNAP_MAX_TRACERS} tracers")
+            c.tracer_kind[t], c.tracer_eps[t] = int(k), float(e)
+            c.tracer_sigma[t], c.tracer_mu[t] = float(sg), float(mu)
+        self.eos = int(eos)
         self.c = c
 
     @property
@@ -203,7 +227,10 @@ class DeviceGrid:
 def device_grid(g, dtype: torch.dtype = torch.float64, device=None) -> DeviceGrid:
     return DeviceGrid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.gamma, g.grav, g.ntracer, g.bc,
                       g.weno_eps, g.weno_linear, g.rhobar_cell, g.pbar_cell, g.rhobar_face,
-                      g.pbar_face, dtype=dtype, device=device)
+                      g.pbar_face, dtype=dtype, device=device,
+                      eos=getattr(g, "eos", SNAP_EOS_PASSIVE),
+                      tracer_kind=getattr(g, "tracer_kind", ()), tracer_eps=getattr(g, "tracer_eps", ()),
+                      tracer_sigma=getattr(g, "tracer_sigma", ()), tracer_mu=getattr(g, "tracer_mu", ()))
 
 
 def snap_abi_version() -> int:

@@ -27,8 +27,8 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
-SOURCES = ["snap_api.hip", "snap_aux.hip", "stage_f64.hip", "stage_f32.hip", "adjoint_f64.hip",
-           "batch_f64.hip", "batch_f32.hip",
+SOURCES = ["snap_api.hip", "snap_aux.hip", "stage_f64.hip", "stage_f32.hip", "stage_mix_f64.hip",
+           "stage_mix_f32.hip", "adjoint_f64.hip", "batch_f64.hip", "batch_f32.hip",
            "adjoint_f32.hip"]
 
 

@@ -53,6 +53,23 @@ size_t padded_bytes(const snap_grid* g) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The mixture equation of state is in effect (with no tracers it is the dry gas).
+bool uses_mixture(const snap_grid* g) { return g->eos == SNAP_EOS_MIXTURE && g->ntracer > 0; }
+
+// Coefficients of the mixture relation (App. B): a_t = 1/eps_t - 1 for a
+// vapour, -1 for a condensate; b_t = sigma_t - 1; mu_t.
+Mixture mixture_of(const snap_grid* g) {
+  Mixture m;
+  memset(&m, 0, sizeof m);
+  if (!uses_mixture(g)) return m;
+  for (int t = 0; t < g->ntracer; ++t) {
+    m.a[t] = g->tracer_kind[t] == SNAP_TRACER_CONDENSATE ? -1.0 : 1.0 / g->tracer_eps[t] - 1.0;
+    m.b[t] = g->tracer_sigma[t] - 1.0;
+    m.mu[t] = g->tracer_mu[t];
+  }
+  return m;
+}
+
 int check_grid(const snap_grid* g) {
   if (!g) return fail(SNAP_E_INVALID, "grid pointer is NULL");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1)
@@ -82,6 +99,21 @@ int check_grid(const snap_grid* g) {
     return fail(SNAP_E_INVALID, "weno_eps must lie in [1e-30, 1e30]");
   if (!g->rhobar_cell || !g->pbar_cell || !g->rhobar_face || !g->pbar_face)
     return fail(SNAP_E_INVALID, "reference profile pointer is NULL");
+  if (g->eos != SNAP_EOS_PASSIVE && g->eos != SNAP_EOS_MIXTURE)
+    return fail(SNAP_E_INVALID, "eos must be SNAP_EOS_PASSIVE or SNAP_EOS_MIXTURE (got %d)", g->eos);
+  if (g->eos == SNAP_EOS_MIXTURE) {
+    for (int t = 0; t < g->ntracer; ++t) {
+      const int k = g->tracer_kind[t];
+      if (k != SNAP_TRACER_VAPOUR && k != SNAP_TRACER_CONDENSATE)
+        return fail(SNAP_E_INVALID, "tracer_kind[%d] must be vapour or condensate (got %d)", t, k);
+      if (k == SNAP_TRACER_VAPOUR && !finite_pos(g->tracer_eps[t]))
+        return fail(SNAP_E_INVALID, "tracer_eps[%d] must be finite and > 0", t);
+      if (!finite_pos(g->tracer_sigma[t]))
+        return fail(SNAP_E_INVALID, "tracer_sigma[%d] must be finite and > 0", t);
+      if (!isfinite(g->tracer_mu[t]))
+        return fail(SNAP_E_INVALID, "tracer_mu[%d] must be finite", t);
+    }
+  }
   const double total = (double)padded_cells(g) * nvar_of(g);
   if (total > 9.0e18 / 8.0) return fail(SNAP_E_INVALID, "state too large");
   return SNAP_OK;
@@ -121,6 +153,7 @@ StageArgs stage_args(const snap_grid* g) {
   a.pbar_c = g->pbar_cell;
   a.rbar_f = g->rhobar_face;
   a.pbar_f = g->pbar_face;
+  a.mix = mixture_of(g);
   return a;
 }
 
@@ -131,18 +164,21 @@ int resident_slots(const snap_grid* g) {
   static std::vector<std::vector<int>> cache;  // [device][key]
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  const int key = (g->dtype * 2 + (is3d(g) ? 1 : 0)) * 16 + g->ntracer;
+  const int key = ((g->dtype * 2 + (is3d(g) ? 1 : 0)) * 2 + (uses_mixture(g) ? 1 : 0)) * 16 +
+                  g->ntracer;
   std::lock_guard<std::mutex> lk(m);
   if ((int)cache.size() <= dev) cache.resize(dev + 1);
   auto& c = cache[dev];
-  if (c.empty()) c.assign(64, 0);
+  if (c.empty()) c.assign(128, 0);
   if (c[key] == 0) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    int per = g->dtype == SNAP_F64 ? occupancy_f64(g->ntracer, is3d(g))
-                                   : occupancy_f32(g->ntracer, is3d(g));
+    const bool mix = uses_mixture(g);
+    int per = g->dtype == SNAP_F64
+                  ? (mix ? occupancy_mix_f64(g->ntracer, is3d(g)) : occupancy_f64(g->ntracer, is3d(g)))
+                  : (mix ? occupancy_mix_f32(g->ntracer, is3d(g)) : occupancy_f32(g->ntracer, is3d(g)));
     if (per <= 0) per = 1;
     c[key] = cus * per;
   }
@@ -221,8 +257,12 @@ int run_stage(const snap_grid* g, StageArgs a, hipStream_t st) {
     const int r = timing_mark(st);
     if (r) return r;
   }
-  const int r = g->dtype == SNAP_F64 ? launch_stage_f64(g->ntracer, is3d(g), a, nb, st)
-                                     : launch_stage_f32(g->ntracer, is3d(g), a, nb, st);
+  const bool mix = uses_mixture(g), d3 = is3d(g);
+  const int r = g->dtype == SNAP_F64
+                    ? (mix ? launch_stage_mix_f64(g->ntracer, d3, a, nb, st)
+                           : launch_stage_f64(g->ntracer, d3, a, nb, st))
+                    : (mix ? launch_stage_mix_f32(g->ntracer, d3, a, nb, st)
+                           : launch_stage_f32(g->ntracer, d3, a, nb, st));
   if (r != 0) return device_fail("stage kernel launch");
   if (timed) return timing_mark(st);
   return SNAP_OK;
@@ -329,6 +369,9 @@ int check_batch(const snap_grid* gs, int n) {
       return fail(SNAP_E_UNSUPPORTED, "member %d is 3-D: the batched step takes 2-D members", m);
     if (gs[m].dtype != gs[0].dtype || gs[m].ntracer != gs[0].ntracer)
       return fail(SNAP_E_INVALID, "member %d differs in dtype or ntracer from member 0", m);
+    if (uses_mixture(&gs[m]))
+      return fail(SNAP_E_UNSUPPORTED,
+                  "member %d uses the mixture equation of state: the batched step takes passive tracers", m);
   }
   return SNAP_OK;
 }
@@ -497,6 +540,8 @@ int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_b
   if (!q || !rhs_bar || !q_bar || !work)
     return fail(SNAP_E_INVALID, "q, rhs_bar, q_bar or work is NULL");
   if (q_bar == q || q_bar == rhs_bar) return fail(SNAP_E_INVALID, "q_bar must not alias q or rhs_bar");
+  if (uses_mixture(g))
+    return fail(SNAP_E_UNSUPPORTED, "the adjoint takes passive tracers (eos = SNAP_EOS_PASSIVE)");
   const hipStream_t st = (hipStream_t)stream;
   if ((r = fill(g, q, st))) return r;
   if ((r = run_adj_rhs(g, q, rhs_bar, q_bar, 0, 0.0, 1.0, work, st))) return r;
@@ -509,6 +554,8 @@ int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar,
   if (r) return r;
   if (!q_n || !q_bar || !work) return fail(SNAP_E_INVALID, "q_n, q_bar or work is NULL");
   if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
+  if (uses_mixture(g))
+    return fail(SNAP_E_UNSUPPORTED, "the adjoint takes passive tracers (eos = SNAP_EOS_PASSIVE)");
   const hipStream_t st = (hipStream_t)stream;
   char* b = static_cast<char*>(work);
   void* q1 = b;
@@ -665,6 +712,9 @@ int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_
   a.dx = g->dx;
   a.dy = g->dy;
   a.dz = g->dz;
+  a.ntracer = g->ntracer;
+  a.mix = uses_mixture(g) ? 1 : 0;
+  a.m = mixture_of(g);
   unsigned long long* dmax = static_cast<unsigned long long*>(work);
   if (launch_cfl(g->dtype, q, a, dmax, st)) return device_fail("cfl kernel launch");
   unsigned long long bits = 0;

@@ -111,8 +111,28 @@ __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
       const double inv = 1.0 / rho;
       const double u = mx * inv, v = my * inv, w = mz * inv;
       const double K = 0.5 * ((mx * u + my * v) + mz * w);
-      const double p = a.gm1 * (E - K);
-      const double cs = sqrt(a.gamma * p / rho);
+      double p, gam;
+      if (a.mix) {
+        // mixture equation of state: p and the parcel's effective gamma
+        double A = 0.0, num = 1.0, den = 1.0;
+#pragma unroll
+        for (int t = 0; t < MAX_TRACERS; ++t) {
+          if (t < a.ntracer) {   // constant indices: the argument stays out of scratch
+            const double rt = q[o + (5 + t) * a.sv];
+            const double qt = rt * inv;
+            A = t == 0 ? a.m.mu[0] * rt : A + a.m.mu[t] * rt;
+            num = num + a.m.a[t] * qt;
+            den = den + a.m.b[t] * qt;
+          }
+        }
+        const double ratio = num / den;
+        p = (a.gm1 * ratio) * ((E - K) - A);
+        gam = 1.0 + a.gm1 * ratio;
+      } else {
+        p = a.gm1 * (E - K);
+        gam = a.gamma;
+      }
+      const double cs = sqrt(gam * p / rho);
       s = (fabs(u) + cs) / a.dx;
       if (a.d3) s = s + (fabs(v) + cs) / a.dy;
       s = s + (fabs(w) + cs) / a.dz;

@@ -46,6 +46,54 @@ __device__ __forceinline__ void cons_to_prim(const double (&c)[NV], double rbar,
 }
 
 // ---------------------------------------------------------------------------
+// Mixture equation of state (Sec. 2, eqs. energy and eos; App. B, eq. p2 and
+// the effective adiabatic index). Per tracer t: a_t = 1/eps_t - 1 for a vapour
+// of molar-mass ratio eps_t, -1 for a condensate (mass without partial
+// pressure); b_t = sigma_t - 1 with sigma_t its heat capacity over c_v of the
+// dry gas; mu_t its chemical potential per unit mass. With q_t = rho_t / rho:
+//   p = (gamma_d - 1) (1 + sum a_t q_t) / (1 + sum b_t q_t) (E - K - A),
+//   A = sum mu_t rho_t, and gamma - 1 of the parcel is the factor before (E - K - A).
+// ---------------------------------------------------------------------------
+constexpr int MAX_TRACERS = 8;
+
+struct Mixture {
+  double a[MAX_TRACERS], b[MAX_TRACERS], mu[MAX_TRACERS];
+};
+
+// cons_to_prim with the mixture equation of state, in the fixed order
+//   A = (mu_1 rho_1 + mu_2 rho_2) + ...; num = (1 + a_1 q_1) + ...; den alike;
+//   p = ((gamma_d - 1)(num / den)) ((E - K) - A)
+// (double precision, no contraction, as cons_to_prim).
+template <int NV>
+__device__ __forceinline__ void cons_to_prim_mix(const double (&c)[NV], double rbar, double pbar,
+                                                 double gm1, const Mixture& m, double (&x)[NV]) {
+#pragma clang fp contract(off)
+  constexpr int NT = NV - 5;
+  static_assert(NT >= 1 && NT <= MAX_TRACERS, "the mixture needs tracers");
+  const double inv = 1.0 / c[0];
+  const double u = c[1] * inv;
+  const double v = c[2] * inv;
+  const double w = c[3] * inv;
+  const double K = 0.5 * ((c[1] * u + c[2] * v) + c[3] * w);
+#pragma unroll
+  for (int t = 5; t < NV; ++t) x[t] = c[t] * inv;
+  double A = m.mu[0] * c[5];
+  double num = 1.0, den = 1.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t > 0) A = A + m.mu[t] * c[5 + t];
+    num = num + m.a[t] * x[5 + t];
+    den = den + m.b[t] * x[5 + t];
+  }
+  const double p = (gm1 * (num / den)) * ((c[4] - K) - A);
+  x[0] = c[0] - rbar;
+  x[1] = u;
+  x[2] = v;
+  x[3] = w;
+  x[4] = p - pbar;
+}
+
+// ---------------------------------------------------------------------------
 // Reciprocal and square root for the stencil arithmetic.
 // Double precision: the hardware estimate (v_rcp_f64 / v_rsq_f64) refined by
 // two Newton-Raphson steps, e <- 1 - d r, r <- r + r e for the reciprocal and
@@ -190,6 +238,61 @@ __device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV],
 #pragma unroll
   for (int t = 5; t < NV; ++t) f[t] = mflux * (left ? xl[t] : xr[t]);
   f[nrm] += pstar;
+}
+
+// LMARS flux with the mixture equation of state: each side's effective
+// gamma - 1 = gm1 n / d with n = 1 + sum a_t q_t, d = 1 + sum b_t q_t of its
+// face mass fractions, so c^2 = (d + gm1 n) p / (d rho); the advected energy
+// is p d / (gm1 n) + rho |u|^2 / 2 + rho sum mu_t q_t of the upwind side.
+template <typename T, int NV>
+__device__ __forceinline__ void lmars_flux_mix(const T (&xl)[NV], const T (&xr)[NV], int nrm,
+                                               T rref, T pref, T gm1, const Mixture& m,
+                                               T (&f)[NV]) {
+  constexpr int NT = NV - 5;
+  const T rl = rref + xl[0], rr = rref + xr[0];
+  const T pl = pref + xl[4], pr = pref + xr[4];
+  // normal velocities by selects: a runtime index would put the face states
+  // in scratch memory
+  const T unl = nrm == 1 ? xl[1] : (nrm == 2 ? xl[2] : xl[3]);
+  const T unr = nrm == 1 ? xr[1] : (nrm == 2 ? xr[2] : xr[3]);
+  T nl = T(1), dl = T(1), ml = T(0), nr = T(1), dr = T(1), mr = T(0);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const T at = static_cast<T>(m.a[t]), bt = static_cast<T>(m.b[t]), mt = static_cast<T>(m.mu[t]);
+    nl += at * xl[5 + t];
+    dl += bt * xl[5 + t];
+    ml += mt * xl[5 + t];
+    nr += at * xr[5 + t];
+    dr += bt * xr[5 + t];
+    mr += mt * xr[5 + t];
+  }
+  const T gnl = gm1 * nl, gnr = gm1 * nr;
+  const T cl = sqrt_fast((dl + gnl) * pl * rcp_fast(dl * rl));
+  const T cr = sqrt_fast((dr + gnr) * pr * rcp_fast(dr * rr));
+  const T rc = (T(0.5) * (rl + rr)) * (T(0.5) * (cl + cr));
+  const T pstar = T(0.5) * (xl[4] + xr[4]) - T(0.5) * rc * (unr - unl);
+  const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) * (T(0.5) * rcp_fast(rc));
+  const bool left = ustar > T(0);
+  const T rs = left ? rl : rr;
+  const T ps = left ? pl : pr;
+  const T us = left ? xl[1] : xr[1];
+  const T vs = left ? xl[2] : xr[2];
+  const T ws = left ? xl[3] : xr[3];
+  const T ds = left ? dl : dr;
+  const T gs = left ? gnl : gnr;
+  const T ms = left ? ml : mr;
+  const T E = ps * ds * rcp_fast(gs) + rs * (T(0.5) * (us * us + vs * vs + ws * ws) + ms);
+  const T mflux = ustar * rs;
+  f[0] = mflux;
+  f[1] = mflux * us;
+  f[2] = mflux * vs;
+  f[3] = mflux * ws;
+  f[4] = ustar * (E + ps);
+#pragma unroll
+  for (int t = 5; t < NV; ++t) f[t] = mflux * (left ? xl[t] : xr[t]);
+  f[1] += nrm == 1 ? pstar : T(0);
+  f[2] += nrm == 2 ? pstar : T(0);
+  f[3] += nrm == 3 ? pstar : T(0);
 }
 
 // Block index -> logical tile with consecutive logical tiles on one XCD.

@@ -26,6 +26,8 @@ struct CflArgs {
   int nx, ny, nz, gy, d3;
   long long sy, sz, sv;
   double gamma, gm1, dx, dy, dz;
+  int ntracer, mix;   // mix: the mixture equation of state with coefficients m
+  Mixture m;
 };
 
 struct SumArgs {
@@ -41,6 +43,8 @@ TileShape tile_f64(int nv);
 TileShape tile_f32(int nv);
 int occupancy_f64(int ntracer, bool d3);
 int occupancy_f32(int ntracer, bool d3);
+int occupancy_mix_f64(int ntracer, bool d3);
+int occupancy_mix_f32(int ntracer, bool d3);
 
 struct AdjArgs;
 
@@ -61,6 +65,8 @@ int launch_adj_combine_f32(void* out, const void* x, const void* y, const void* 
                            double cb, double cc, long long n, hipStream_t st);
 int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+int launch_stage_mix_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+int launch_stage_mix_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st);
 int launch_fill_ghosts_batched(int dtype, const GhostDesc* d, int n, long long max_ghosts,
                                hipStream_t st);

@@ -52,6 +52,7 @@ struct StageArgs {
   const double* pbar_c;
   const double* rbar_f;  // nz + 1
   const double* pbar_f;
+  Mixture mix;           // mixture equation of state (kernels instantiated with MIX)
 };
 
 template <typename T>
@@ -61,6 +62,30 @@ __device__ __forceinline__ double to_d(T v) {
 
 // Load the NV conserved values of padded element offset `off` and convert them
 // to primitives with the level references (rb, pb).
+// Conserved -> primitive with the kernel's equation of state: passive tracers,
+// or the mixture (MIX) with coefficients mx.
+template <int NV, bool MIX>
+__device__ __forceinline__ void cons_to_prim_eos(const double (&c)[NV], double rb, double pb,
+                                                 double gm1, const Mixture& mx, double (&x)[NV]) {
+  if constexpr (MIX)
+    cons_to_prim_mix<NV>(c, rb, pb, gm1, mx, x);
+  else
+    cons_to_prim<NV>(c, rb, pb, gm1, x);
+}
+
+template <typename T, int NV, bool MIX = false>
+__device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off, long long sv,
+                                          double rb, double pb, double gm1, const Mixture& mx,
+                                          T (&x)[NV]) {
+  double c[NV], xd[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
+  cons_to_prim_eos<NV, MIX>(c, rb, pb, gm1, mx, xd);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+}
+
+// passive tracers
 template <typename T, int NV>
 __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off, long long sv,
                                           double rb, double pb, double gm1, T (&x)[NV]) {
@@ -70,6 +95,17 @@ __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off
   cons_to_prim<NV>(c, rb, pb, gm1, xd);
 #pragma unroll
   for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+}
+
+// LMARS flux with the kernel's equation of state.
+template <typename T, int NV, bool MIX>
+__device__ __forceinline__ void lmars_flux_eos(const T (&xl)[NV], const T (&xr)[NV], int nrm,
+                                               T rref, T pref, T gamma, T inv_gm1, T gm1,
+                                               const Mixture& mx, T (&f)[NV]) {
+  if constexpr (MIX)
+    lmars_flux_mix<T, NV>(xl, xr, nrm, rref, pref, gm1, mx, f);
+  else
+    lmars_flux<T, NV>(xl, xr, nrm, rref, pref, gamma, inv_gm1, f);
 }
 
 // Output of one interior cell: either R itself or the stage combination.
@@ -211,9 +247,10 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
 // Phase L: LMARS at every face of the tile, by the item that holds its right
 // state. x faces use the reference of their row (xref); second-axis faces use
 // sref(face index).
-template <typename T, int NV, int TX, int TY, typename XRef, typename SRef>
+template <typename T, int NV, int TX, int TY, bool MIX, typename XRef, typename SRef>
 __device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int h, int snrm,
-                                            T gamma, T inv_gm1, XRef xref, SRef sref,
+                                            T gamma, T inv_gm1, T gm1, const Mixture& mx,
+                                            XRef xref, SRef sref,
                                             const T (&QP)[PlaneItems<TX, TY>::RREG][NV]) {
   using I = PlaneItems<TX, TY>;
 #pragma unroll
@@ -233,7 +270,7 @@ __device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int 
         xref(jj, rr, pr);
       else
         sref(jj, rr, pr);
-      lmars_flux<T, NV>(xl, xr, xa ? 1 : snrm, rr, pr, gamma, inv_gm1, f);
+      lmars_flux_eos<T, NV, MIX>(xl, xr, xa ? 1 : snrm, rr, pr, gamma, inv_gm1, gm1, mx, f);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (xa)
@@ -276,18 +313,18 @@ __device__ __forceinline__ void load_cons(const T* __restrict__ q, long long off
   for (int v = 0; v < NV; ++v) c[v] = q[off + v * sv];
 }
 
-template <typename T, int NV>
+template <typename T, int NV, bool MIX>
 __device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], double rb, double pb, double gm1,
-                                               T (&x)[NV]) {
+                                               const Mixture& mx, T (&x)[NV]) {
   double cd[NV], xd[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) cd[v] = static_cast<double>(c[v]);
-  cons_to_prim<NV>(cd, rb, pb, gm1, xd);
+  cons_to_prim_eos<NV, MIX>(cd, rb, pb, gm1, mx, xd);
 #pragma unroll
   for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
 }
 
-template <typename T, int NT, int TX, int TY>
+template <typename T, int NT, int TX, int TY, bool MIX = false>
 __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(StageArgs a) {
   constexpr int NV = 5 + NT;
   using I = PlaneItems<TX, TY>;
@@ -309,7 +346,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   const int w = min(TX, a.nx - i0), h = min(TY, a.ny - j0);
   const bool act = ti < w && tj < h;
   const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
-  const T inv_gm1 = static_cast<T>(a.inv_gm1);
+  const T inv_gm1 = static_cast<T>(a.inv_gm1), gm1t = static_cast<T>(a.gm1);
   const T dxi = static_cast<T>(a.dxi), dyi = static_cast<T>(a.dyi), dzi = static_cast<T>(a.dzi);
   const bool linear = a.linear != 0;
   const bool combine = a.rhs_mode == 0;
@@ -347,7 +384,8 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int k = k0 - 3 + l;
-      load_prim<T, NV>(qs, col + lev(k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, W[l]);
+      load_prim<T, NV, MIX>(qs, col + lev(k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1,
+                            a.mix, W[l]);
     }
   }
   // prefetched raw conserved values: halo cells of the next level to be
@@ -380,7 +418,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
       for (int r = 0; r < HR; ++r) {
         if (hok[r]) {
           T x[NV];
-          cons_to_prim_t<T, NV>(hc[r], rbs, pbs, a.gm1, x);
+          cons_to_prim_t<T, NV, MIX>(hc[r], rbs, pbs, a.gm1, a.mix, x);
 #pragma unroll
           for (int v = 0; v < NV; ++v) S.P[v][hjj[r] + 3][hii[r] + 3] = x[v];
           if (s + 1 < k1) load_cons<T, NV>(qs, hoff[r] + lev(s + 1), a.sv, hc[r]);
@@ -396,13 +434,15 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
         r = rbT;
         p = pbT;
       };
-      phase_lmars<T, NV, TX, TY>(S, w, h, 2, gamma, inv_gm1, levref, levref, QP);
+      phase_lmars<T, NV, TX, TY, MIX>(S, w, h, 2, gamma, inv_gm1, gm1t, a.mix, levref, levref,
+                                      QP);
       __syncthreads();
     }
     // ---- vertical direction, own column: face s+1/2 (z-face index s+1) -------
     T dfz[NV];
     if (act) {
-      cons_to_prim_t<T, NV>(wc, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG], a.gm1, W[4]);
+      cons_to_prim_t<T, NV, MIX>(wc, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG], a.gm1, a.mix,
+                                 W[4]);
       T qmn[NV], qpn[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -411,8 +451,9 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
       }
       if (s >= k0 - 1) {
         T fz[NV];
-        lmars_flux<T, NV>(qmc, qpn, 3, static_cast<T>(a.rbar_f[s + 1]),
-                          static_cast<T>(a.pbar_f[s + 1]), gamma, inv_gm1, fz);
+        lmars_flux_eos<T, NV, MIX>(qmc, qpn, 3, static_cast<T>(a.rbar_f[s + 1]),
+                                   static_cast<T>(a.pbar_f[s + 1]), gamma, inv_gm1, gm1t, a.mix,
+                                   fz);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           dfz[v] = fz[v] - fzc[v];
@@ -462,7 +503,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 // 2-D (x-z) tile: TX x TZ tile number L of the plane, z is the second in-plane
 // axis. Shared by the single-domain kernel and the batched (ensemble) kernel.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int TX, int TZ>
+template <typename T, int NT, int TX, int TZ, bool MIX = false>
 __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
                                              Plane<T, 5 + NT, TX, TZ>& S) {
   constexpr int NV = 5 + NT;
@@ -477,7 +518,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
   const int w = min(TX, a.nx - i0), h = min(TZ, a.nz - k0);
   const bool act = ti < w && tk < h;
   const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
-  const T inv_gm1 = static_cast<T>(a.inv_gm1);
+  const T inv_gm1 = static_cast<T>(a.inv_gm1), gm1t = static_cast<T>(a.gm1);
   const T dxi = static_cast<T>(a.dxi), dzi = static_cast<T>(a.dzi);
   const bool linear = a.linear != 0;
 
@@ -487,7 +528,8 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
   if (act) {
     const int k = k0 + tk;
     T x[NV];
-    load_prim<T, NV>(qs, poff(i0 + ti, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, x);
+    load_prim<T, NV, MIX>(qs, poff(i0 + ti, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1,
+                          a.mix, x);
 #pragma unroll
     for (int v = 0; v < NV; ++v) S.P[v][tk + 3][ti + 3] = x[v];
   }
@@ -496,7 +538,8 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
     if (halo_item<TX, TZ>(it, w, h, ii, kk)) {
       const int k = k0 + kk;
       T x[NV];
-      load_prim<T, NV>(qs, poff(i0 + ii, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, x);
+      load_prim<T, NV, MIX>(qs, poff(i0 + ii, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1,
+                            a.mix, x);
 #pragma unroll
       for (int v = 0; v < NV; ++v) S.P[v][kk + 3][ii + 3] = x[v];
     }
@@ -513,7 +556,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
     r = static_cast<T>(a.rbar_f[k0 + fk]);
     p = static_cast<T>(a.pbar_f[k0 + fk]);
   };
-  phase_lmars<T, NV, TX, TZ>(S, w, h, 3, gamma, inv_gm1, xref, zref, QP);
+  phase_lmars<T, NV, TX, TZ, MIX>(S, w, h, 3, gamma, inv_gm1, gm1t, a.mix, xref, zref, QP);
   __syncthreads();
   if (act) {
     T R[NV];
@@ -532,10 +575,10 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
   }
 }
 
-template <typename T, int NT, int TX, int TZ>
+template <typename T, int NT, int TX, int TZ, bool MIX = false>
 __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
   __shared__ Plane<T, 5 + NT, TX, TZ> S;
-  stage2d_tile<T, NT, TX, TZ>(a, xcd_logical_block(blockIdx.x, gridDim.x), S);
+  stage2d_tile<T, NT, TX, TZ, MIX>(a, xcd_logical_block(blockIdx.x, gridDim.x), S);
 }
 
 // Ensemble of 2-D domains in one persistent launch: work item w is tile

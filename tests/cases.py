@@ -27,6 +27,16 @@ SPECS = [
     ("3d_small_2x3x4", dict(nx=2, ny=3, nz=4, nt=0, bc=(1, 1, 1), seed=26)),
 ]
 
+# Cases with the mixture equation of state: ``species`` picks tracers of
+# workloads.condensable_species (0, 1 = vapours; 2, 3 = their clouds).
+MIX_SPECS = [
+    ("mix_3d_25x19x22_nt4", dict(nx=25, ny=19, nz=22, nt=4, bc=(0, 0, 1), seed=31, species=(0, 1, 2, 3))),
+    ("mix_2d_33x27_nt2", dict(nx=33, ny=1, nz=27, nt=2, bc=(0, 0, 1), seed=32, species=(0, 2))),
+    ("mix_3d_walls_14x11x13_nt1", dict(nx=14, ny=11, nz=13, nt=1, bc=(1, 1, 1), seed=33, species=(1,))),
+    ("mix_3d_periodic_12x10x14_nt3", dict(nx=12, ny=10, nz=14, nt=3, bc=(0, 0, 0), seed=34, grav=0.0,
+                                          species=(2, 0, 3))),
+]
+
 
 @dataclasses.dataclass
 class Case:
@@ -55,6 +65,10 @@ def build_case(name: str, spec) -> Case:
         grid.dy = 1.0
     grid.ntracer = spec["nt"]
     grid.weno_linear = bool(spec.get("linear", False))
+    if "species" in spec:
+        base = wl.DryIsentropic()
+        table = wl.condensable_species(base.cp - base.rd, wl.RGAS / base.rd)
+        grid = wl.with_mixture(grid, [table[i] for i in spec["species"]])
     q = wl.random_smooth_state(grid, spec["seed"])
     return Case(name, grid, q, 0.2)
 
@@ -64,3 +78,4 @@ def all_cases():
 
 
 CASE_NAMES = [n for n, _ in SPECS]
+MIX_NAMES = [n for n, _ in MIX_SPECS]

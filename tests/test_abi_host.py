@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == 1
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 2
 
 
 def good_grid(**kw):
@@ -53,10 +53,17 @@ def good_grid(**kw):
     c.dx, c.dy, c.dz = 100.0, 100.0, 50.0
     c.gamma, c.grav, c.weno_eps = 1.4, 9.81, 1e-6
     c.rhobar_cell = c.pbar_cell = c.rhobar_face = c.pbar_face = FAKE
+    # a vapour and a condensate (read only with eos = SNAP_EOS_MIXTURE)
+    kw = {"tracer_kind": (snap.SNAP_TRACER_VAPOUR, snap.SNAP_TRACER_CONDENSATE),
+          "tracer_eps": (7.8, 0.0), "tracer_sigma": (0.16, 0.48), "tracer_mu": (0.0, -3.1e6), **kw}
     for k, v in kw.items():
         if k == "bc":
             for d in range(3):
                 c.bc[d] = v[d]
+        elif k.startswith("tracer_"):
+            arr = getattr(c, k)
+            for t, x in enumerate(v):
+                arr[t] = x
         else:
             setattr(c, k, v)
     return c
@@ -69,6 +76,10 @@ BAD_GRIDS = [
     dict(gamma=1.0), dict(gamma=math.nan), dict(grav=-1.0), dict(grav=math.inf),
     dict(weno_eps=0.0), dict(weno_eps=-1e-6), dict(rhobar_cell=None), dict(pbar_face=None),
     dict(nx=1 << 25),
+    dict(eos=2), dict(eos=-1),
+    dict(eos=1, tracer_kind=(2, 1)), dict(eos=1, tracer_eps=(0.0, 0.0)), dict(eos=1, tracer_eps=(math.inf, 0.0)),
+    dict(eos=1, tracer_sigma=(0.16, 0.0)), dict(eos=1, tracer_sigma=(math.nan, 0.48)),
+    dict(eos=1, tracer_mu=(math.nan, 0.0)), dict(eos=1, tracer_mu=(0.0, -math.inf)),
 ]
 
 
@@ -200,3 +211,26 @@ def test_batched_workspace_layout():
     total = lib.snap_batched_workspace_bytes(arr, 2)
     states = sum(2 * (((g.nx + 6) * (g.nz + 6) * (5 + g.ntracer) * 8 + 255) // 256 * 256) for g in gs)
     assert states < total <= states + 4 * 256 + 8 * 1024
+
+
+def test_mixture_fields_and_unsupported_entry_points():
+    """The tracer fields are read only under SNAP_EOS_MIXTURE; a condensate's
+    molar-mass ratio is ignored; the adjoint and batched entry points refuse
+    the mixture."""
+    lib = snap.lib()
+    # passive: garbage tracer fields are not validated
+    g = ctypes.byref(good_grid(tracer_kind=(7, 9), tracer_sigma=(-1.0, math.nan)))
+    assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) > 0
+    # mixture with no tracers: the dry gas, fields not read
+    g = ctypes.byref(good_grid(eos=1, ntracer=0, tracer_kind=(7, 9)))
+    assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) > 0
+    # a condensate's eps is not read
+    g = ctypes.byref(good_grid(eos=1, tracer_eps=(7.8, math.nan)))
+    assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) > 0
+    P = ctypes.c_void_p(FAKE)
+    Q2, Q3 = ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE)
+    assert lib.snap_rhs_adjoint(g, P, Q2, Q3, P, None) == snap.SNAP_E_UNSUPPORTED
+    assert lib.snap_rk3_step_adjoint(g, P, 0.1, Q2, Q3, None) == snap.SNAP_E_UNSUPPORTED
+    arr = (snap.SnapGridC * 2)(good_grid(ny=1, eos=1), good_grid(ny=1, eos=1))
+    assert lib.snap_batched_workspace_bytes(arr, 2) == 0
+    assert b"mixture" in lib.snap_last_error()

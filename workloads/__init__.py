@@ -368,6 +368,29 @@ def jovian_3d(nx=512, ny=512, nz=256, dxy=5.5e3, lz=400e3, seed_q=2, seed_theta=
     return grid, q
 
 
+def condensable_species(cvd: float, mu_dry: float):
+    """Water and ammonia vapours and their clouds, as mixture-equation-of-state
+    tracers of a gas with c_v = ``cvd`` (J/kg/K) and molar mass ``mu_dry``
+    (kg/mol): (kind, molar-mass ratio, heat capacity over cvd, chemical
+    potential). Vapour potentials are zero; a cloud's is -(L^r + (c_l - c_p,v) T^r)
+    (Sec. 2, eq. muij) with textbook latent heats at the triple points."""
+    return (
+        (TRACER_VAPOUR, 18.015e-3 / mu_dry, 1385.0 / cvd, 0.0),
+        (TRACER_VAPOUR, 17.031e-3 / mu_dry, 1572.0 / cvd, 0.0),
+        (TRACER_CONDENSATE, 1.0, 4184.0 / cvd, -(2.501e6 + (4184.0 - 1847.0) * 273.16)),
+        (TRACER_CONDENSATE, 1.0, 4700.0 / cvd, -(1.371e6 + (4700.0 - 2060.0) * 195.4)),
+    )
+
+
+def with_mixture(grid: Grid, species) -> Grid:
+    """The grid with the mixture equation of state and these tracers."""
+    return grid.copy(eos=EOS_MIXTURE, ntracer=len(species),
+                     tracer_kind=tuple(int(s[0]) for s in species),
+                     tracer_eps=tuple(float(s[1]) for s in species),
+                     tracer_sigma=tuple(float(s[2]) for s in species),
+                     tracer_mu=tuple(float(s[3]) for s in species))
+
+
 ENSEMBLE_SIZES = ((128, 128), (256, 128), (384, 192), (512, 256))
 
 
