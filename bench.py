@@ -50,7 +50,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (FMA = 2 flops)
 FP32_PEAK_TFLOPS = 157.3    # MI355X vector FP32 (counts packed FP32, which this build does not emit)
 
 
-def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int) -> int:
+def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int, mixture: bool = False) -> int:
     """Floating-point operations of one right-hand side + stage update of one cell.
 
     Counted from the method's formulas (+, -, *, /, sqrt = 1 flop each, a fused
@@ -58,10 +58,16 @@ def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int) -> int:
     movement: conserved -> primitive 14 + NT; WENO5 per variable and direction
     (both faces of the cell, shared smoothness indicators) 78; LMARS per face
     37 + NT; divergence 3 per variable and direction; gravity 4; Runge-Kutta
-    combination 4 per variable averaged over the three stages.
+    combination 4 per variable averaged over the three stages. The mixture
+    equation of state adds 6 NT + 2 to conserved -> primitive (chemical
+    energy, the two weighted sums, their ratio) and 12 NT + 10 per face (the
+    sums of both sides, their effective gamma and internal energy).
     """
     nv = 5 + ntracer
-    return (14 + ntracer) + ndir * nv * 78 + ndir * (37 + ntracer) + ndir * 3 * nv + 4 + 4 * nv
+    n = (14 + ntracer) + ndir * nv * 78 + ndir * (37 + ntracer) + ndir * 3 * nv + 4 + 4 * nv
+    if mixture and ntracer > 0:
+        n += 6 * ntracer + 2 + ndir * (12 * ntracer + 10)
+    return n
 
 
 # sources the stage kernel and its launch (tiling, z-chunks) are built from
@@ -166,14 +172,15 @@ def run_gpu(dtype, steps: int, warmup: int):
     return res
 
 
-def run_jovian(steps: int, warmup: int):
-    """3-D Jovian-like column 512x512x256, FP32, 4 tracer densities (vapours and clouds)."""
+def run_jovian(steps: int, warmup: int, mixture: bool = False):
+    """3-D Jovian-like column 512x512x256, FP32, 4 tracer densities (vapours and
+    clouds); passive, or under the mixture equation of state."""
     import torch
 
     import paper_1901_02955_amd as snap
     import workloads as wl
 
-    grid, q = wl.jovian_3d()
+    grid, q = wl.jovian_3d(mixture=mixture)
     dg = snap.device_grid(grid, dtype=torch.float32)
     qd = torch.as_tensor(q).float().cuda().contiguous()
     del q
@@ -194,10 +201,12 @@ def run_jovian(steps: int, warmup: int):
     snap.snap_stage_timing_enable(False)
     cells = grid.nx * grid.ny * grid.nz
     avg = ms / 1e3 / max(n, 1)
-    flops = algorithmic_flops_per_cell_stage(4, 3) * cells
+    flops = algorithmic_flops_per_cell_stage(4, 3, mixture) * cells
     byts = 8.0 / 3.0 * 9 * 4 * cells
+    eos = ("mixture equation of state (water and ammonia vapours and clouds)" if mixture
+           else "passive tracers")
     out = {"workload": "3-D Jovian-like column 512x512x256 (5.5 km x 5.5 km x 1.5625 km), FP32, "
-                       "5 conserved + 4 tracer densities, CFL 0.9",
+                       f"5 conserved + 4 tracer densities, {eos}, CFL 0.9",
            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
            "steps": steps, "stage_kernel_avg_ms": avg * 1e3,
            "alu_frac": flops / avg / 1e12 / FP32_PEAK_TFLOPS,
@@ -446,6 +455,9 @@ def main():
         out["f32_error_vs_f64"] = run_fp32_error()
     if not args.only_headline:
         out["jovian"] = run_jovian(50, 3)
+        out["jovian_mixture"] = run_jovian(50, 3, mixture=True)
+        out["jovian_mixture"]["cost_vs_passive"] = (out["jovian"]["value"]
+                                                    / out["jovian_mixture"]["value"])
         out["ensemble"] = run_ensemble(20)
         out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:

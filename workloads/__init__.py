@@ -339,12 +339,16 @@ def jovian_base() -> AdiabatIsothermal:
 
 
 def jovian_3d(nx=512, ny=512, nz=256, dxy=5.5e3, lz=400e3, seed_q=2, seed_theta=3,
-              condense_p=(7e5, 0.7e5), noise=0.1, nlev=10):
-    """3-D Jovian-like column: H2-He gas, two vapours and two (zero) clouds."""
+              condense_p=(7e5, 0.7e5), noise=0.1, nlev=10, mixture=False):
+    """3-D Jovian-like column: H2-He gas, two vapours and two (zero) clouds,
+    passive or (``mixture``) under the mixture equation of state with the
+    water / ammonia table of ``condensable_species``."""
     base = jovian_base()
     gamma = base.cp / (base.cp - base.rd)
     grid = Grid(nx=nx, ny=ny, nz=nz, dx=dxy, dy=dxy, dz=lz / nz, gamma=gamma,
                 grav=base.grav, ntracer=4, bc=(BC_PERIODIC, BC_PERIODIC, BC_REFLECT))
+    if mixture:
+        grid = with_mixture(grid, condensable_species(base.cp - base.rd, JOVIAN_MU))
     rc, pc, rf, pf = reference_profiles(base, nz, grid.dz, base.grav, BC_REFLECT)
     grid.rhobar_cell, grid.pbar_cell, grid.rhobar_face, grid.pbar_face = rc, pc, rf, pf
     rho, p = rest_fields(grid)
