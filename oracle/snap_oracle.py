@@ -448,6 +448,97 @@ def conservation_sums(q, grid) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Microphysics: Kessler scheme integrated by backward Euler (Sec. 3, App. D)
+# ---------------------------------------------------------------------------
+
+def temperature(q, grid, rd: float) -> torch.Tensor:
+    """Temperature of every cell of a padded state under the mixture equation
+    of state: p = R_d T (rho_d + sum over vapours rho_i / eps_i) (Sec. 2, eq. eos)."""
+    q = _t(q)
+    p = cons_to_prim(q, grid.copy(rhobar_cell=np.zeros(1), pbar_cell=np.zeros(1)))["p"]
+    rho_d = q[0] - sum(q[5 + t] for t in range(grid.ntracer))
+    gas = rho_d
+    for t in range(grid.ntracer):
+        if grid.tracer_kind[t] == 0:
+            gas = gas + q[5 + t] / grid.tracer_eps[t]
+    return p / (rd * gas)
+
+
+def saturation_vapour_pressure(T, sp) -> torch.Tensor:
+    """p* = p_ref exp[beta (1 - 1/t) - delta ln t], t = T / t_ref (App. D)."""
+    t = T / sp.t_ref
+    return sp.p_ref * torch.exp(sp.beta * (1.0 - 1.0 / t) - sp.delta * torch.log(t))
+
+
+def kessler_rates(qv, qc, qp, qs, sp, saturated):
+    """Reaction rates of vapour, cloud and precipitation (Sec. 3, eqs. qi .. qi2)
+    in the regime ``saturated`` (q_v > q*) or not:
+      saturated:   condensation k1 (q_v - q*);
+      unsaturated: evaporation k4 q_p (q* - q_v);
+      always:      autoconversion k2 q_c and accretion k3 q_c q_p.
+    """
+    cond = torch.where(saturated, sp.k1 * (qv - qs), torch.zeros_like(qv))
+    evap = torch.where(saturated, torch.zeros_like(qv), sp.k4 * qp * (qs - qv))
+    conv = sp.k2 * qc + sp.k3 * qc * qp
+    return torch.stack([-cond + evap, cond - conv, -evap + conv], dim=-1)
+
+
+def kessler_jacobian(qv, qc, qp, qs, sp, saturated):
+    """d(rates) / d(q_v, q_c, q_p) in the regime ``saturated`` (Sec. 3). The
+    unsaturated matrix includes the derivative of evaporation with respect to
+    q_p, k4 (q* - q_v), which the printed matrix leaves out; the fixed point of
+    the iteration, the backward-Euler solution, does not depend on it."""
+    z = torch.zeros_like(qv)
+    a = sp.k2 + sp.k3 * qp          # d(conversion)/d q_c
+    b = sp.k3 * qc                  # d(conversion)/d q_p
+    ev = sp.k4 * (qs - qv)
+    rows = [
+        [torch.where(saturated, z - sp.k1, -sp.k4 * qp), z, torch.where(saturated, z, ev)],
+        [torch.where(saturated, z + sp.k1, z), -a, -b],
+        [torch.where(saturated, z, sp.k4 * qp), a, torch.where(saturated, b, b - ev)],
+    ]
+    return torch.stack([torch.stack(r, dim=-1) for r in rows], dim=-2)
+
+
+def kessler_solve(qv0, qc0, qp0, qs, sp, dt: float, iters: int = 60):
+    """Backward-Euler step X = X^n + dt Phi(X) for X = (q_v, q_c, q_p), by the
+    iteration of Sec. 3 (eq. x_n+1): X^{m} = X^{m-1} + (I/dt - J)^{-1}
+    [Phi(X^{m-1}) - (X^{m-1} - X^n)/dt], started at X^n. The regime is that
+    of X^n: backward Euler keeps q_v on the side of q* it starts on."""
+    sat = qv0 > qs
+    X0 = torch.stack([qv0, qc0, qp0], dim=-1)
+    X = X0.clone()
+    eye = torch.eye(3, dtype=F64)
+    for _ in range(iters):
+        r = kessler_rates(X[..., 0], X[..., 1], X[..., 2], qs, sp, sat) - (X - X0) / dt
+        J = kessler_jacobian(X[..., 0], X[..., 1], X[..., 2], qs, sp, sat)
+        X = X + torch.linalg.solve(eye / dt - J, r.unsqueeze(-1)).squeeze(-1)
+    return X[..., 0], X[..., 1], X[..., 2]
+
+
+def kessler_step(q, grid, dt: float, kessler) -> torch.Tensor:
+    """Padded state after one Kessler microphysics step of length dt.
+
+    Per cell: T from the mixture state, the saturation mixing ratio
+    q* = p*(T) eps / (R_d T rho) of each condensable, the backward-Euler
+    step of its (vapour, cloud, precipitation) mixing ratios with q* held at
+    its value of the step's start, and the new tracer densities rho q. Total
+    density, momentum and total energy are unchanged (Sec. 3: rho_d and rho e
+    are conserved by phase changes; the temperature follows from them).
+    """
+    q = _t(q).clone()
+    qi = _interior(q, grid)
+    T = _interior(temperature(q, grid, kessler.rd).unsqueeze(0), grid)[0]
+    rho = qi[0]
+    for sp in kessler.species:
+        v, c, pr = 5 + sp.vapour, 5 + sp.cloud, 5 + sp.precip
+        qs = saturation_vapour_pressure(T, sp) * sp.eps / (kessler.rd * T) / rho
+        qv, qc, qp = kessler_solve(qi[v] / rho, qi[c] / rho, qi[pr] / rho, qs, sp, dt)
+        qi[v], qi[c], qi[pr] = rho * qv, rho * qc, rho * qp
+    return q
+
+
+# ---------------------------------------------------------------------------
 # Discrete adjoint (torch autograd through the oracle)
 # ---------------------------------------------------------------------------
 

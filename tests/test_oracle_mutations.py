@@ -161,3 +161,61 @@ def test_chemical_energy_dropped_at_faces_breaks_advection_pin(monkeypatch):
     monkeypatch.setattr(O, "lmars_flux", bad)
     with pytest.raises(AssertionError):
         TM.test_chemical_energy_is_advected_with_its_tracer()
+
+
+# --- Kessler microphysics ---------------------------------------------------
+
+def _kessler_pins():
+    from tests import test_oracle_kessler as TK
+    return TK
+
+
+def test_evaporation_sign_breaks_closed_form_pin(monkeypatch):
+    TK = _kessler_pins()
+    orig = O.kessler_rates
+
+    def bad(qv, qc, qp, qs, sp, saturated):
+        r = orig(qv, qc, qp, qs, sp, saturated)
+        evap = torch.where(saturated, torch.zeros_like(qv), sp.k4 * qp * (qs - qv))
+        return r + torch.stack([-2 * evap, torch.zeros_like(qv), 2 * evap], dim=-1)   # evaporation reversed
+    monkeypatch.setattr(O, "kessler_rates", bad)
+    with pytest.raises(AssertionError):
+        TK.test_evaporation_alone_is_the_smaller_quadratic_root()
+
+
+def test_accretion_lost_from_precipitation_breaks_conservation(monkeypatch):
+    TK = _kessler_pins()
+    orig = O.kessler_rates
+
+    def bad(qv, qc, qp, qs, sp, saturated):
+        r = orig(qv, qc, qp, qs, sp, saturated)
+        acc = sp.k3 * qc * qp
+        return r - torch.stack([torch.zeros_like(qv), torch.zeros_like(qv), acc], dim=-1)
+    monkeypatch.setattr(O, "kessler_rates", bad)
+    with pytest.raises(AssertionError):
+        TK.test_all_processes_conserve_and_satisfy_backward_euler()
+
+
+def test_wrong_kirchhoff_term_breaks_clausius_clapeyron_pin(monkeypatch):
+    TK = _kessler_pins()
+
+    def bad(T, sp):
+        t = T / sp.t_ref
+        return sp.p_ref * torch.exp(sp.beta * (1.0 - 1.0 / t) + sp.delta * torch.log(t))
+    monkeypatch.setattr(O, "saturation_vapour_pressure", bad)
+    with pytest.raises(AssertionError):
+        TK.test_saturation_vapour_pressure_solves_clausius_clapeyron()
+
+
+def test_vapour_molar_mass_ignored_breaks_latent_heating_pin(monkeypatch):
+    TK = _kessler_pins()
+
+    def bad(q, grid, rd):
+        q = O._t(q)
+        p = O.cons_to_prim(q, grid.copy(rhobar_cell=np.zeros(1), pbar_cell=np.zeros(1)))["p"]
+        rho_d = q[0] - sum(q[5 + t] for t in range(grid.ntracer))
+        gas = rho_d + sum(q[5 + t] for t in range(grid.ntracer) if grid.tracer_kind[t] == 0)
+        return p / (rd * gas)                   # R_v taken equal to R_d
+    monkeypatch.setattr(O, "temperature", bad)
+    with pytest.raises(AssertionError):
+        TK.test_constant_volume_phase_change_heats_as_the_paper_states()

@@ -395,6 +395,47 @@ def with_mixture(grid: Grid, species) -> Grid:
                      tracer_mu=tuple(float(s[3]) for s in species))
 
 
+@dataclasses.dataclass
+class KesslerSpecies:
+    """One condensable of the Kessler scheme (Sec. 3), as parameters.
+
+    vapour, cloud, precip: tracer indices of its vapour, cloud and
+    precipitation (mixture equation of state: one vapour, two condensates);
+    k1 condensation (1/s), k2 autoconversion (1/s), k3 accretion and k4
+    evaporation (1/s per unit mixing ratio); saturation vapour pressure over
+    the cloud p* = p_ref exp[beta (1 - 1/t) - delta ln t] with t = T / t_ref
+    (App. D); eps: molar mass over that of the dry gas.
+    """
+    vapour: int
+    cloud: int
+    precip: int
+    k1: float
+    k2: float
+    k3: float
+    k4: float
+    p_ref: float
+    t_ref: float
+    beta: float
+    delta: float
+    eps: float
+
+
+@dataclasses.dataclass
+class Kessler:
+    """Kessler microphysics of a grid: its condensables, the dry gas constant,
+    and the stopping rule of the Newton iteration (step size below
+    ``tol`` times the species' total mixing ratio, at most ``max_iter``)."""
+    species: Tuple[KesslerSpecies, ...]
+    rd: float
+    max_iter: int = 30
+    tol: float = 1e-14
+
+
+def clausius_clapeyron(latent_ref: float, dc: float, r_vap: float, t_ref: float):
+    """(beta, delta) of App. D from the latent heat at t_ref, c_cond - c_p,vap and R_vap."""
+    return (latent_ref + dc * t_ref) / (r_vap * t_ref), dc / r_vap
+
+
 ENSEMBLE_SIZES = ((128, 128), (256, 128), (384, 192), (512, 256))
 
 
