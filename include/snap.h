@@ -274,6 +274,61 @@ int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const doub
                           int variant, int nblocks, void* work, void* stream);
 
 /*
+ * Kessler microphysics (Sec. 3), operator-split after a time step.
+ *
+ * Per condensable species: the mass mixing ratios X = (q_v, q_c, q_p) of its
+ * vapour, cloud and precipitation evolve by
+ *   dq_v/dt = -k1 (q_v - q*)+ + k4 q_p (q* - q_v)+
+ *   dq_c/dt =  k1 (q_v - q*)+ - k3 q_c q_p - k2 q_c
+ *   dq_p/dt = -k4 q_p (q* - q_v)+ + k3 q_c q_p + k2 q_c      (x+ = max(x, 0)),
+ * integrated over dt by backward Euler, X = X^n + dt Phi(X), with the Newton
+ * iteration of Sec. 3 (eq. x_n+1) started at X^n: rates and Jacobian of the
+ * regime of X^n (saturated if q_v > q*; backward Euler keeps q_v on that
+ * side of q*); the unsaturated Jacobian includes d/dq_p of the evaporation
+ * term, which the printed matrix leaves out (the fixed point does not depend
+ * on it). The iteration stops when the largest Newton step is at most
+ * tol (q_v + q_c + q_p)^n, or after max_iter steps. It can land on the
+ * unphysical root of the accretion quadratic when dt k3 (q_c - q_p) > 1.
+ * q* = p*(T) eps / (R_d T rho), with eps the vapour's tracer_eps, the
+ * saturation vapour pressure over the cloud p* = p_ref exp[beta (1 - 1/t) -
+ * delta ln t], t = T / t_ref (App. D, integrated Clausius-Clapeyron), and the
+ * temperature of the mixture T = p / (R_d (rho_d + sum_vapours rho_i / eps_i))
+ * (Sec. 2, eq. eos), both taken at the start and held through the step.
+ * Afterwards rho_t = rho q_t for the three tracers; total density, momentum
+ * and total energy are unchanged (the temperature follows from them through
+ * the chemical potentials). The arithmetic is double precision whatever the
+ * storage type.
+ *
+ * g      grid with eos = SNAP_EOS_MIXTURE: vapour tracers of kind
+ *        SNAP_TRACER_VAPOUR, cloud and precipitation of kind SNAP_TRACER_CONDENSATE.
+ * q      padded state, interior updated in place (ghost layers untouched).
+ * dt     finite > 0.
+ * k      HOST parameters; nspecies in 1 .. SNAP_KESSLER_MAX_SPECIES, tracer
+ *        indices in [0, ntracer) and all distinct; k1..k4 finite >= 0; p_ref,
+ *        t_ref, rd finite > 0; beta, delta finite; max_iter in 1 .. 100; tol
+ *        finite >= 0.
+ * Returns SNAP_E_INVALID for any other input; no workspace is needed.
+ */
+#define SNAP_KESSLER_MAX_SPECIES (SNAP_MAX_TRACERS / 3)
+
+typedef struct snap_kessler_species {
+  int32_t vapour, cloud, precip; /* tracer indices */
+  double k1, k2, k3, k4;         /* condensation, autoconversion (1/s); accretion, evaporation (1/s per unit q) */
+  double p_ref, t_ref;           /* saturation vapour pressure (Pa) at t_ref (K) */
+  double beta, delta;            /* (L^r + dc t_ref) / (R_v t_ref) and dc / R_v, dc = c_cloud - c_p,vapour */
+} snap_kessler_species;
+
+typedef struct snap_kessler {
+  int32_t nspecies;
+  snap_kessler_species species[SNAP_KESSLER_MAX_SPECIES];
+  double rd;        /* gas constant of the dry gas, J/kg/K */
+  int32_t max_iter; /* Newton steps at most */
+  double tol;       /* stop at a step of tol x the species' total mixing ratio */
+} snap_kessler;
+
+int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler* k, void* stream);
+
+/*
  * Benchmark instrumentation of the fused stage kernel (the kernel that
  * evaluates the right-hand side and applies one Runge-Kutta stage).
  * snap_stage_timing_enable(1) discards earlier records and brackets every later

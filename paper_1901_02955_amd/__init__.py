@@ -27,6 +27,7 @@ __all__ = [
     "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
     "SNAP_EOS_PASSIVE", "SNAP_EOS_MIXTURE", "SNAP_TRACER_VAPOUR", "SNAP_TRACER_CONDENSATE",
+    "snap_kessler_step", "kessler_params",
 ]
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -88,6 +89,28 @@ class SnapGridC(ctypes.Structure):
     ]
 
 
+SNAP_KESSLER_MAX_SPECIES = SNAP_MAX_TRACERS // 3
+
+
+class SnapKesslerSpeciesC(ctypes.Structure):
+    """Mirror of ``snap_kessler_species`` in include/snap.h."""
+    _fields_ = [
+        ("vapour", ctypes.c_int32), ("cloud", ctypes.c_int32), ("precip", ctypes.c_int32),
+        ("k1", ctypes.c_double), ("k2", ctypes.c_double), ("k3", ctypes.c_double),
+        ("k4", ctypes.c_double), ("p_ref", ctypes.c_double), ("t_ref", ctypes.c_double),
+        ("beta", ctypes.c_double), ("delta", ctypes.c_double),
+    ]
+
+
+class SnapKesslerC(ctypes.Structure):
+    """Mirror of ``snap_kessler`` in include/snap.h."""
+    _fields_ = [
+        ("nspecies", ctypes.c_int32),
+        ("species", SnapKesslerSpeciesC * SNAP_KESSLER_MAX_SPECIES),
+        ("rd", ctypes.c_double), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+    ]
+
+
 _P = ctypes.c_void_p
 _GP = ctypes.POINTER(SnapGridC)
 _SIGNATURES = {
@@ -108,6 +131,7 @@ _SIGNATURES = {
     "snap_rk3_step_batched": (ctypes.c_int, [_GP, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
                                              ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                              ctypes.c_int, _P, _P]),
+    "snap_kessler_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, ctypes.POINTER(SnapKesslerC), _P]),
     "snap_stage_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "snap_stage_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),
@@ -367,3 +391,29 @@ def snap_stage_timing_read():
     n = ctypes.c_int64(0)
     _check(lib().snap_stage_timing_read(ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def kessler_params(k) -> SnapKesslerC:
+    """``snap_kessler`` from any object with ``species`` (each with vapour, cloud,
+    precip, k1..k4, p_ref, t_ref, beta, delta), ``rd``, ``max_iter`` and ``tol``."""
+    c = SnapKesslerC()
+    if len(k.species) > SNAP_KESSLER_MAX_SPECIES:
+        raise ValueError(f"at most {SNAP_KESSLER_MAX_SPECIES} species")
+    c.nspecies = len(k.species)
+    for i, sp in enumerate(k.species):
+        d = c.species[i]
+        d.vapour, d.cloud, d.precip = int(sp.vapour), int(sp.cloud), int(sp.precip)
+        d.k1, d.k2, d.k3, d.k4 = float(sp.k1), float(sp.k2), float(sp.k3), float(sp.k4)
+        d.p_ref, d.t_ref = float(sp.p_ref), float(sp.t_ref)
+        d.beta, d.delta = float(sp.beta), float(sp.delta)
+    c.rd, c.max_iter, c.tol = float(k.rd), int(k.max_iter), float(k.tol)
+    return c
+
+
+def snap_kessler_step(grid: DeviceGrid, q: torch.Tensor, dt: float, kessler, stream=None) -> None:
+    """Kessler microphysics step of length dt on the interior of q (in place)."""
+    grid._check_state(q)
+    params = kessler if isinstance(kessler, SnapKesslerC) else kessler_params(kessler)
+    _check(lib().snap_kessler_step(grid.ptr(), ctypes.c_void_p(q.data_ptr()), ctypes.c_double(dt),
+                                   ctypes.byref(params), _stream(stream)))
+

@@ -689,6 +689,83 @@ int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const doub
   return ok();
 }
 
+int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler* k,
+                      void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !k) return fail(SNAP_E_INVALID, "q or k is NULL");
+  if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
+  if (!uses_mixture(g))
+    return fail(SNAP_E_INVALID, "the microphysics needs eos = SNAP_EOS_MIXTURE and tracers");
+  if (k->nspecies < 1 || k->nspecies > SNAP_KESSLER_MAX_SPECIES)
+    return fail(SNAP_E_INVALID, "nspecies must lie in [1, %d]", SNAP_KESSLER_MAX_SPECIES);
+  if (!finite_pos(k->rd)) return fail(SNAP_E_INVALID, "rd must be finite and > 0");
+  if (k->max_iter < 1 || k->max_iter > 100) return fail(SNAP_E_INVALID, "max_iter must lie in [1, 100]");
+  if (!isfinite(k->tol) || k->tol < 0.0) return fail(SNAP_E_INVALID, "tol must be finite and >= 0");
+  KesslerArgs a;
+  memset(&a, 0, sizeof a);
+  bool used[SNAP_MAX_TRACERS] = {false};
+  for (int sidx = 0; sidx < k->nspecies; ++sidx) {
+    const snap_kessler_species& sp = k->species[sidx];
+    const int idx[3] = {sp.vapour, sp.cloud, sp.precip};
+    for (int m = 0; m < 3; ++m) {
+      if (idx[m] < 0 || idx[m] >= g->ntracer)
+        return fail(SNAP_E_INVALID, "species %d: tracer index %d outside [0, %d)", sidx, idx[m], g->ntracer);
+      if (used[idx[m]]) return fail(SNAP_E_INVALID, "species %d: tracer %d used twice", sidx, idx[m]);
+      used[idx[m]] = true;
+      const int want = m == 0 ? SNAP_TRACER_VAPOUR : SNAP_TRACER_CONDENSATE;
+      if (g->tracer_kind[idx[m]] != want)
+        return fail(SNAP_E_INVALID, "species %d: tracer %d must be a %s", sidx, idx[m],
+                    m == 0 ? "vapour" : "condensate");
+    }
+    const double kk[4] = {sp.k1, sp.k2, sp.k3, sp.k4};
+    for (int m = 0; m < 4; ++m)
+      if (!isfinite(kk[m]) || kk[m] < 0.0)
+        return fail(SNAP_E_INVALID, "species %d: k%d must be finite and >= 0", sidx, m + 1);
+    if (!finite_pos(sp.p_ref) || !finite_pos(sp.t_ref))
+      return fail(SNAP_E_INVALID, "species %d: p_ref and t_ref must be finite and > 0", sidx);
+    if (!isfinite(sp.beta) || !isfinite(sp.delta))
+      return fail(SNAP_E_INVALID, "species %d: beta and delta must be finite", sidx);
+    KesslerSpec& d = a.s[sidx];
+    d.v = sp.vapour;
+    d.c = sp.cloud;
+    d.p = sp.precip;
+    d.k1 = sp.k1;
+    d.k2 = sp.k2;
+    d.k3 = sp.k3;
+    d.k4 = sp.k4;
+    d.p_ref = sp.p_ref;
+    d.t_ref = sp.t_ref;
+    d.beta = sp.beta;
+    d.delta = sp.delta;
+    d.eps = g->tracer_eps[sp.vapour];
+  }
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.nspecies = k->nspecies;
+  a.max_iter = k->max_iter;
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.dt = dt;
+  a.rd = k->rd;
+  a.tol = k->tol;
+  a.gm1 = g->gamma - 1.0;
+  a.m = mixture_of(g);
+  for (int t = 0; t < g->ntracer; ++t) {
+    a.vap[t] = g->tracer_kind[t] == SNAP_TRACER_VAPOUR ? 1 : 0;
+    a.eps[t] = a.vap[t] ? g->tracer_eps[t] : 1.0;
+  }
+  if ((long long)g->ny * g->nz > 0x7fffffffLL) return fail(SNAP_E_INVALID, "ny nz too large");
+  if (launch_kessler(g->dtype, g->ntracer, q, a, (hipStream_t)stream))
+    return device_fail("microphysics kernel launch");
+  return ok();
+}
+
 int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_host,
                 void* stream) {
   int r = check_grid(g);

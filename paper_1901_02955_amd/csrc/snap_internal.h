@@ -30,6 +30,22 @@ struct CflArgs {
   Mixture m;
 };
 
+// Kessler microphysics (Sec. 3): one condensable species.
+struct KesslerSpec {
+  int v, c, p;   // tracer indices of vapour, cloud, precipitation
+  double k1, k2, k3, k4, p_ref, t_ref, beta, delta, eps;
+};
+
+struct KesslerArgs {
+  int nx, ny, nz, gy, nspecies, max_iter;
+  long long sy, sz, sv;
+  double dt, rd, tol, gm1;
+  Mixture m;                      // mixture coefficients of the pressure
+  int vap[MAX_TRACERS];           // 1: tracer t is a vapour
+  double eps[MAX_TRACERS];        // molar-mass ratios of the tracers
+  KesslerSpec s[MAX_TRACERS / 3];
+};
+
 struct SumArgs {
   int nx, ny, nz, gy, nvar;
   long long sy, sz, sv;
@@ -79,6 +95,7 @@ int launch_stage2d_batched(int dtype, int ntracer, int variant, const StageArgs*
                            const int* first, int n, int nblocks, hipStream_t st);
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st);
+int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st);
 int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double* out,
                 hipStream_t st);
 

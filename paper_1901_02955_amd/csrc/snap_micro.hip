@@ -1,0 +1,136 @@
+// Kessler microphysics (Sec. 3) integrated by backward Euler, one thread per
+// interior cell, double-precision arithmetic for either storage type.
+#include "snap_internal.h"
+
+namespace snap {
+
+namespace {
+
+// Value of tracer `idx` of c (a runtime index into a register array would put
+// the array in scratch memory; compare-and-select over constant indices instead).
+template <int NV>
+__device__ __forceinline__ double tracer(const double (&c)[NV], int idx) {
+  double r = 0.0;
+#pragma unroll
+  for (int t = 0; t < NV - 5; ++t) r = t == idx ? c[5 + t] : r;
+  return r;
+}
+
+template <int NV>
+__device__ __forceinline__ void set_tracer(double (&c)[NV], int idx, double val) {
+#pragma unroll
+  for (int t = 0; t < NV - 5; ++t) c[5 + t] = t == idx ? val : c[5 + t];
+}
+
+// Backward-Euler step of (q_v, q_c, q_p) by the Newton iteration of Sec. 3 in
+// the regime of the starting point (saturated: q_v > q*).
+__device__ __forceinline__ void kessler_solve(const KesslerSpec& sp, double qs, double dt,
+                                              int max_iter, double tol, double& xv, double& xc,
+                                              double& xp) {
+  const double x0v = xv, x0c = xc, x0p = xp;
+  const bool sat = x0v > qs;
+  const double lim = tol * (x0v + x0c + x0p);
+  const double idt = 1.0 / dt;
+  for (int it = 0; it < max_iter; ++it) {
+    // rates (Sec. 3, eqs. qi .. qi2) and the residual of X = X^n + dt Phi(X)
+    const double cond = sat ? sp.k1 * (xv - qs) : 0.0;
+    const double evap = sat ? 0.0 : sp.k4 * xp * (qs - xv);
+    const double conv = sp.k2 * xc + sp.k3 * xc * xp;
+    const double r0 = (-cond + evap) - (xv - x0v) / dt;
+    const double r1 = (cond - conv) - (xc - x0c) / dt;
+    const double r2 = (-evap + conv) - (xp - x0p) / dt;
+    // M = I/dt - dPhi/dX (row 0, column 1 is zero in both regimes)
+    const double A = sp.k2 + sp.k3 * xp, B = sp.k3 * xc, ev = sp.k4 * (qs - xv);
+    const double m00 = idt - (sat ? -sp.k1 : -sp.k4 * xp);
+    const double m02 = -(sat ? 0.0 : ev);
+    const double m10 = -(sat ? sp.k1 : 0.0), m11 = idt + A, m12 = B;
+    const double m20 = -(sat ? 0.0 : sp.k4 * xp), m21 = -A, m22 = idt - (sat ? B : B - ev);
+    // Cramer's rule
+    const double c00 = m11 * m22 - m12 * m21;
+    const double c10 = m10 * m22 - m12 * m20;
+    const double c20 = m10 * m21 - m11 * m20;
+    const double det = m00 * c00 + m02 * c20;
+    const double idet = 1.0 / det;
+    const double d0 = (r0 * c00 + m02 * (r1 * m21 - m11 * r2)) * idet;
+    const double d1 = (m00 * (r1 * m22 - m12 * r2) - r0 * c10 + m02 * (m10 * r2 - r1 * m20)) * idet;
+    const double d2 = (m00 * (m11 * r2 - r1 * m21) + r0 * c20) * idet;
+    xv += d0;
+    xc += d1;
+    xp += d2;
+    if (fmax(fabs(d0), fmax(fabs(d1), fabs(d2))) <= lim) break;
+  }
+}
+
+}  // namespace
+
+// grid: x over interior rows (nz ny), y over the interior row
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_kessler(T* __restrict__ q, KesslerArgs a) {
+  constexpr int NV = 5 + NT;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, k = row / a.ny;
+  const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+  double c[NV], x[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = static_cast<double>(q[o + v * a.sv]);
+  cons_to_prim_mix<NV>(c, 0.0, 0.0, a.gm1, a.m, x);   // x[4] = p
+  double temp;
+  {
+    // T = p / (R_d (rho_d + sum over vapours rho_i / eps_i)), rho_d = rho - sum rho_t
+#pragma clang fp contract(off)
+    double st = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) st = st + c[5 + t];
+    double gas = c[0] - st;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (a.vap[t]) gas = gas + c[5 + t] / a.eps[t];
+    temp = x[4] / (a.rd * gas);
+  }
+  const double rho = c[0];
+#pragma unroll
+  for (int s = 0; s < MAX_TRACERS / 3; ++s) {
+    if (s >= a.nspecies) break;
+    const KesslerSpec& sp = a.s[s];
+    // saturation mixing ratio over the cloud (App. D): p* eps / (R_d T) / rho
+    const double tt = temp / sp.t_ref;
+    const double pstar = sp.p_ref * exp(sp.beta * (1.0 - 1.0 / tt) - sp.delta * log(tt));
+    const double qs = pstar * sp.eps / (a.rd * temp) / rho;
+    double xv = tracer(c, sp.v) / rho, xc = tracer(c, sp.c) / rho, xp = tracer(c, sp.p) / rho;
+    kessler_solve(sp, qs, a.dt, a.max_iter, a.tol, xv, xc, xp);
+    set_tracer(c, sp.v, rho * xv);
+    set_tracer(c, sp.c, rho * xc);
+    set_tracer(c, sp.p, rho * xp);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) q[o + (5 + t) * a.sv] = static_cast<T>(c[5 + t]);
+}
+
+template <typename T>
+int launch_kessler_t(int ntracer, T* q, const KesslerArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)(a.ny * a.nz), (unsigned)((a.nx + 255) / 256));
+  switch (ntracer) {
+#define SNAP_KESSLER_CASE(N)                                                        \
+  case N:                                                                           \
+    hipLaunchKernelGGL((k_kessler<T, N>), grid, dim3(256), 0, st, q, a);            \
+    break;
+    SNAP_KESSLER_CASE(3)
+    SNAP_KESSLER_CASE(4)
+    SNAP_KESSLER_CASE(5)
+    SNAP_KESSLER_CASE(6)
+    SNAP_KESSLER_CASE(7)
+    SNAP_KESSLER_CASE(8)
+#undef SNAP_KESSLER_CASE
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st) {
+  return dtype == 0 ? launch_kessler_t<double>(ntracer, static_cast<double*>(q), a, st)
+                    : launch_kessler_t<float>(ntracer, static_cast<float*>(q), a, st);
+}
+
+}  // namespace snap

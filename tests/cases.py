@@ -79,3 +79,36 @@ def all_cases():
 
 CASE_NAMES = [n for n, _ in SPECS]
 MIX_NAMES = [n for n, _ in MIX_SPECS]
+
+
+# Cases of the Kessler microphysics: water and ammonia (vapour, cloud,
+# precipitation; workloads.kessler_tracers) on an isentropic 300 K base,
+# 10 km deep, so that water is saturated aloft and not below.
+KESSLER_SPECS = [
+    ("kessler_3d_21x13x16", dict(nx=21, ny=13, nz=16, seed=41)),
+    ("kessler_2d_37x24", dict(nx=37, ny=1, nz=24, seed=42)),
+    ("kessler_3d_ragged_9x7x5", dict(nx=9, ny=7, nz=5, seed=43)),
+]
+KESSLER_NAMES = [n for n, _ in KESSLER_SPECS]
+
+
+def build_kessler_case(name: str, spec):
+    """(grid, padded state, Kessler parameters, dt) of a microphysics case."""
+    nx, ny, nz = spec["nx"], spec["ny"], spec["nz"]
+    base = wl.DryIsentropic()
+    grid, _ = wl.dry_grid(nx, ny, nz, 250.0 * nx, 250.0 * ny, 10e3, bc=(0, 0, 1))
+    if ny == 1:
+        grid.dy = 1.0
+    table, kes = wl.kessler_tracers(base.cp - base.rd, wl.RGAS / base.rd, base.rd)
+    grid = wl.with_mixture(grid, table)
+    rng = np.random.default_rng(spec["seed"])
+    shp = (nz, ny, nx)
+    rho, p = wl.rest_fields(grid)
+    rho = rho * (1.0 + 0.01 * rng.standard_normal(shp))
+    u, v, w = (2.0 * rng.standard_normal(shp) for _ in range(3))
+    if ny == 1:
+        v = np.zeros(shp)
+    vap = [10.0 ** rng.uniform(-3.5, -1.5, shp) for _ in range(2)]
+    cond = [10.0 ** rng.uniform(-5.0, -3.0, shp) for _ in range(4)]
+    q = wl.state_from_primitives(grid, rho, u, v, w, p, vap + cond)
+    return Case(name, grid, q, 2.0), kes

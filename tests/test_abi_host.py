@@ -234,3 +234,56 @@ def test_mixture_fields_and_unsupported_entry_points():
     arr = (snap.SnapGridC * 2)(good_grid(ny=1, eos=1), good_grid(ny=1, eos=1))
     assert lib.snap_batched_workspace_bytes(arr, 2) == 0
     assert b"mixture" in lib.snap_last_error()
+
+
+def _kessler(**kw):
+    k = snap.SnapKesslerC()
+    k.nspecies, k.rd, k.max_iter, k.tol = 1, 287.0, 30, 1e-14
+    sp = k.species[0]
+    sp.vapour, sp.cloud, sp.precip = 0, 1, 2
+    sp.k1, sp.k2, sp.k3, sp.k4 = 0.3, 1e-3, 2.2, 0.5
+    sp.p_ref, sp.t_ref, sp.beta, sp.delta = 611.7, 273.16, 24.9, 5.06
+    for key, v in kw.items():
+        if hasattr(sp, key) and key not in ("rd",):
+            setattr(sp, key, v)
+        else:
+            setattr(k, key, v)
+    return k
+
+
+def _kessler_grid(**kw):
+    base = dict(eos=1, ntracer=3, tracer_kind=(0, 1, 1), tracer_eps=(0.62, 0.0, 0.0),
+                tracer_sigma=(1.9, 5.8, 5.8), tracer_mu=(0.0, -3.1e6, -3.1e6))
+    base.update(kw)
+    return good_grid(**base)
+
+
+BAD_KESSLER = [
+    dict(nspecies=0), dict(nspecies=3), dict(rd=0.0), dict(max_iter=0), dict(max_iter=101),
+    dict(tol=-1.0), dict(tol=math.nan), dict(vapour=3), dict(cloud=-1), dict(precip=0),
+    dict(vapour=1, cloud=0), dict(k1=-0.1), dict(k4=math.inf), dict(p_ref=0.0), dict(t_ref=-1.0),
+    dict(beta=math.nan), dict(delta=math.inf),
+]
+
+
+@pytest.mark.parametrize("kw", BAD_KESSLER, ids=[str(k) for k in BAD_KESSLER])
+def test_kessler_rejects_bad_parameters(kw):
+    lib = snap.lib()
+    g = ctypes.byref(_kessler_grid())
+    k = _kessler(**kw)
+    assert lib.snap_kessler_step(g, ctypes.c_void_p(FAKE), 1.0, ctypes.byref(k), None) == snap.SNAP_E_INVALID
+    assert lib.snap_last_error().decode()
+
+
+def test_kessler_needs_the_mixture_and_valid_scalars():
+    lib = snap.lib()
+    k = _kessler()
+    P = ctypes.c_void_p(FAKE)
+    passive = ctypes.byref(_kessler_grid(eos=0))
+    assert lib.snap_kessler_step(passive, P, 1.0, ctypes.byref(k), None) == snap.SNAP_E_INVALID
+    assert b"MIXTURE" in lib.snap_last_error()
+    g = ctypes.byref(_kessler_grid())
+    for dt in (0.0, -1.0, math.nan):
+        assert lib.snap_kessler_step(g, P, dt, ctypes.byref(k), None) == snap.SNAP_E_INVALID
+    assert lib.snap_kessler_step(g, None, 1.0, ctypes.byref(k), None) == snap.SNAP_E_INVALID
+    assert lib.snap_kessler_step(g, P, 1.0, None, None) == snap.SNAP_E_INVALID

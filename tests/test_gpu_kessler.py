@@ -1,0 +1,97 @@
+"""GPU parity of the Kessler microphysics step (Sec. 3; saturation vapour
+pressure of App. D) against the FP64 CPU oracle.
+
+Bars: the tracer densities within 1e-12 of the oracle relative to each
+field's largest magnitude in FP64 (both iterate to the same backward-Euler
+fixed point; the iteration stops at a step of 1e-14 of the species' total),
+1e-6 with FP32 storage (the output rounding); density, momentum and total
+energy untouched bit for bit; after two steps of dynamics plus microphysics
+within max(1e-12, 10 x the oracle's 1-ulp input sensitivity).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_02955_amd as snap
+from tests import cases as C
+from tests.test_gpu_parity import TOL64, assert_steps_close, field_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kcases():
+    return {n: C.build_kessler_case(n, s) for n, s in C.KESSLER_SPECS}
+
+
+@pytest.mark.parametrize("name", C.KESSLER_NAMES)
+def test_kessler_fp64(kcases, name):
+    c, kes = kcases[name]
+    print(f"[kessler] fp64 {name}", flush=True)
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    snap.snap_kessler_step(dg, qd, c.dt, kes)
+    got = c.grid.interior(qd.cpu().numpy())
+    ref = c.grid.interior(oracle.kessler_step(c.q, c.grid, c.dt, kes).numpy())
+    qi = c.grid.interior(c.q)
+    assert np.array_equal(got[:5], qi[:5])
+    errs = field_errors(got[5:], ref[5:])
+    moved = [float(np.max(np.abs(ref[5 + t] - qi[5 + t])) / np.max(np.abs(ref[5 + t])))
+             for t in range(6)]
+    print("   errors", ["%.2e" % e for e in errs], " change", ["%.1e" % m for m in moved], flush=True)
+    assert all(e <= TOL64 for e in errs), errs
+    assert max(moved) > 1e-3                      # the step does something
+
+
+@pytest.mark.parametrize("name", C.KESSLER_NAMES)
+def test_kessler_fp32(kcases, name):
+    c, kes = kcases[name]
+    print(f"[kessler] fp32 {name}", flush=True)
+    q32 = torch.as_tensor(c.q).float()
+    dg = snap.device_grid(c.grid, dtype=torch.float32)
+    qd = q32.cuda()
+    snap.snap_kessler_step(dg, qd, c.dt, kes)
+    got = c.grid.interior(qd.cpu().double().numpy())
+    ref = c.grid.interior(oracle.kessler_step(q32.double().numpy(), c.grid, c.dt, kes).numpy())
+    errs = field_errors(got[5:], ref[5:])
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-6 for e in errs), errs
+
+
+def test_dynamics_plus_microphysics_two_steps(kcases):
+    c, kes = kcases["kessler_3d_21x13x16"]
+    print("[kessler] rk3 + kessler, 2 steps", flush=True)
+    dt = 0.5 * oracle.cfl_dt(c.q, c.grid, 0.9)
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+
+    def oracle_run(q0):
+        q = torch.as_tensor(q0)
+        for _ in range(2):
+            q = oracle.kessler_step(oracle.rk3_step(q, c.grid, dt), c.grid, dt, kes)
+        return c.grid.interior(q.numpy())
+
+    for _ in range(2):
+        snap.snap_rk3_step(dg, qd, dt, work)
+        snap.snap_kessler_step(dg, qd, dt, kes)
+    ref = oracle_run(c.q)
+    rng = np.random.default_rng(0)
+    kappa = np.zeros(c.grid.nvar)
+    for _ in range(2):
+        qp = c.q.copy()
+        c.grid.interior(qp)[...] *= 1.0 + np.finfo(np.float64).eps * rng.choice([-1.0, 0.0, 1.0],
+                                                                                size=c.grid.interior_shape)
+        kappa = np.maximum(kappa, field_errors(oracle_run(qp), ref))
+    assert_steps_close(c.grid.interior(qd.cpu().numpy()), ref, kappa, "rk3 + kessler")
+
+
+def test_kessler_deterministic(kcases):
+    c, kes = kcases["kessler_3d_21x13x16"]
+    dg = snap.device_grid(c.grid)
+    a = torch.as_tensor(c.q).cuda()
+    b = a.clone()
+    snap.snap_kessler_step(dg, a, c.dt, kes)
+    snap.snap_kessler_step(dg, b, c.dt, kes)
+    assert torch.equal(a, b)

@@ -372,18 +372,50 @@ def jovian_3d(nx=512, ny=512, nz=256, dxy=5.5e3, lz=400e3, seed_q=2, seed_theta=
     return grid, q
 
 
+# Condensables: molar mass (kg/mol), c_v and c_p of the vapour, heat capacity
+# of the condensate (J/kg/K), latent heat (J/kg) and saturation vapour
+# pressure (Pa) at the reference (triple-point) temperature (K); textbook values.
+WATER = dict(molar=18.015e-3, cv_vap=1385.0, cp_vap=1847.0, c_cond=4184.0, latent=2.501e6,
+             t_ref=273.16, p_ref=611.7)
+AMMONIA = dict(molar=17.031e-3, cv_vap=1572.0, cp_vap=2060.0, c_cond=4700.0, latent=1.371e6,
+               t_ref=195.4, p_ref=6060.0)
+
+
+def _vapour(sp, cvd, mu_dry):
+    return (TRACER_VAPOUR, sp["molar"] / mu_dry, sp["cv_vap"] / cvd, 0.0)
+
+
+def _condensate(sp, cvd):
+    # chemical potential of the condensate: -(L^r + (c_cond - c_p,vap) T^r) (Sec. 2, eq. muij)
+    mu = -(sp["latent"] + (sp["c_cond"] - sp["cp_vap"]) * sp["t_ref"])
+    return (TRACER_CONDENSATE, 1.0, sp["c_cond"] / cvd, mu)
+
+
 def condensable_species(cvd: float, mu_dry: float):
     """Water and ammonia vapours and their clouds, as mixture-equation-of-state
     tracers of a gas with c_v = ``cvd`` (J/kg/K) and molar mass ``mu_dry``
     (kg/mol): (kind, molar-mass ratio, heat capacity over cvd, chemical
-    potential). Vapour potentials are zero; a cloud's is -(L^r + (c_l - c_p,v) T^r)
-    (Sec. 2, eq. muij) with textbook latent heats at the triple points."""
-    return (
-        (TRACER_VAPOUR, 18.015e-3 / mu_dry, 1385.0 / cvd, 0.0),
-        (TRACER_VAPOUR, 17.031e-3 / mu_dry, 1572.0 / cvd, 0.0),
-        (TRACER_CONDENSATE, 1.0, 4184.0 / cvd, -(2.501e6 + (4184.0 - 1847.0) * 273.16)),
-        (TRACER_CONDENSATE, 1.0, 4700.0 / cvd, -(1.371e6 + (4700.0 - 2060.0) * 195.4)),
-    )
+    potential). Vapour potentials are zero."""
+    return (_vapour(WATER, cvd, mu_dry), _vapour(AMMONIA, cvd, mu_dry),
+            _condensate(WATER, cvd), _condensate(AMMONIA, cvd))
+
+
+def kessler_tracers(cvd: float, mu_dry: float, rd: float, species=(WATER, AMMONIA),
+                    k=(0.3, 1e-3, 2.2, 0.5)):
+    """Tracer table [vapours, clouds, precipitations] of ``species`` and the
+    Kessler parameters (rate coefficients k = (k1, k2, k3, k4); saturation
+    vapour pressure from the species' latent heat and heat capacities)."""
+    n = len(species)
+    table = ([_vapour(sp, cvd, mu_dry) for sp in species] + [_condensate(sp, cvd) for sp in species]
+             + [_condensate(sp, cvd) for sp in species])
+    kes = []
+    for i, sp in enumerate(species):
+        beta, delta = clausius_clapeyron(sp["latent"], sp["c_cond"] - sp["cp_vap"],
+                                         RGAS / sp["molar"], sp["t_ref"])
+        kes.append(KesslerSpecies(vapour=i, cloud=n + i, precip=2 * n + i, k1=k[0], k2=k[1], k3=k[2],
+                                  k4=k[3], p_ref=sp["p_ref"], t_ref=sp["t_ref"], beta=beta,
+                                  delta=delta, eps=sp["molar"] / mu_dry))
+    return tuple(table), Kessler(species=tuple(kes), rd=rd)
 
 
 def with_mixture(grid: Grid, species) -> Grid:
