@@ -216,6 +216,58 @@ def run_jovian(steps: int, warmup: int, mixture: bool = False):
     return out
 
 
+def run_jovian_kessler(steps: int, warmup: int):
+    """The Jovian-like column with water and ammonia vapour, cloud and
+    precipitation (6 tracers) under the mixture equation of state, FP32: an
+    SSP-RK3 step followed by a Kessler microphysics step of the same dt."""
+    import torch
+
+    import paper_1901_02955_amd as snap
+    import workloads as wl
+
+    grid, q, kes = wl.jovian_kessler_3d()
+    dg = snap.device_grid(grid, dtype=torch.float32)
+    qd = torch.as_tensor(q).float().cuda().contiguous()
+    del q
+    params = snap.kessler_params(kes)
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+
+    def step():
+        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
+        snap.snap_rk3_step(dg, qd, dt, work)
+        snap.snap_kessler_step(dg, qd, dt, params)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    # the microphysics kernel alone, on the stream, over the same number of calls
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        snap.snap_kessler_step(dg, qd, 1e-9, params)
+    e1.record()
+    torch.cuda.synchronize()
+    micro_ms = e0.elapsed_time(e1) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = grid.nx * grid.ny * grid.nz
+    byts = (11 + 6) * 4 * cells          # reads every field, writes the six tracers
+    out = {"workload": "3-D Jovian-like column 512x512x256, FP32, water and ammonia vapour, cloud and "
+                       "precipitation (6 tracers), mixture equation of state, SSP-RK3 step + Kessler "
+                       "microphysics step, CFL 0.9",
+           "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
+           "steps": steps, "microphysics_ms": micro_ms,
+           "microphysics_hbm_frac": byts / (micro_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "microphysics_share": micro_ms / (el / steps * 1e3)}
+    del qd, work, cw
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_ensemble(steps: int):
     """64 uneven 2-D bubbles (FP32): one persistent launch per stage vs separate steps."""
     import torch
@@ -458,6 +510,7 @@ def main():
         out["jovian_mixture"] = run_jovian(50, 3, mixture=True)
         out["jovian_mixture"]["cost_vs_passive"] = (out["jovian"]["value"]
                                                     / out["jovian_mixture"]["value"])
+        out["jovian_kessler"] = run_jovian_kessler(20, 2)
         out["ensemble"] = run_ensemble(20)
         out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:

@@ -66,6 +66,9 @@ Mixture mixture_of(const snap_grid* g) {
     m.a[t] = g->tracer_kind[t] == SNAP_TRACER_CONDENSATE ? -1.0 : 1.0 / g->tracer_eps[t] - 1.0;
     m.b[t] = g->tracer_sigma[t] - 1.0;
     m.mu[t] = g->tracer_mu[t];
+    m.af[t] = (float)m.a[t];
+    m.bf[t] = (float)m.b[t];
+    m.muf[t] = (float)m.mu[t];
   }
   return m;
 }

@@ -58,7 +58,23 @@ constexpr int MAX_TRACERS = 8;
 
 struct Mixture {
   double a[MAX_TRACERS], b[MAX_TRACERS], mu[MAX_TRACERS];
+  // single-precision copies for the FP32 face arithmetic: used straight from
+  // scalar registers, where converted doubles would take vector registers
+  float af[MAX_TRACERS], bf[MAX_TRACERS], muf[MAX_TRACERS];
 };
+
+template <typename T>
+__device__ __forceinline__ void mixture_coef(const Mixture& m, int t, T& a, T& b, T& mu) {
+  if constexpr (sizeof(T) == 4) {
+    a = m.af[t];
+    b = m.bf[t];
+    mu = m.muf[t];
+  } else {
+    a = m.a[t];
+    b = m.b[t];
+    mu = m.mu[t];
+  }
+}
 
 // cons_to_prim with the mixture equation of state, in the fixed order
 //   A = (mu_1 rho_1 + mu_2 rho_2) + ...; num = (1 + a_1 q_1) + ...; den alike;
@@ -258,7 +274,8 @@ __device__ __forceinline__ void lmars_flux_mix(const T (&xl)[NV], const T (&xr)[
   T nl = T(1), dl = T(1), ml = T(0), nr = T(1), dr = T(1), mr = T(0);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const T at = static_cast<T>(m.a[t]), bt = static_cast<T>(m.b[t]), mt = static_cast<T>(m.mu[t]);
+    T at, bt, mt;
+    mixture_coef<T>(m, t, at, bt, mt);
     nl += at * xl[5 + t];
     dl += bt * xl[5 + t];
     ml += mt * xl[5 + t];

@@ -330,6 +330,11 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   using I = PlaneItems<TX, TY>;
   constexpr int NHALO = 6 * (TX + TY);
   constexpr int HR = (NHALO + I::NTHR - 1) / I::NTHR;   // halo items per thread
+  // Load the next level's halo, window and stage-combination values a level
+  // ahead only where the extra 4 NV live values still leave room for two
+  // waves per SIMD (256 registers); with more variables each value is loaded
+  // where it is used.
+  constexpr bool PF = sizeof(T) == 4 ? NV <= 11 : NV <= 5;
   __shared__ Plane<T, NV, TX, TY> S;
   const T* __restrict__ qs = static_cast<const T*>(a.qs);
 
@@ -391,20 +396,28 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   // prefetched raw conserved values: halo cells of the next level to be
   // planed, the window's next level, and this level's own Qs / Qn
   T hc[HR][NV];
+  if constexpr (PF) {
 #pragma unroll
-  for (int r = 0; r < HR; ++r)
-    if (hok[r]) load_cons<T, NV>(qs, hoff[r] + lev(k0), a.sv, hc[r]);
+    for (int r = 0; r < HR; ++r)
+      if (hok[r]) load_cons<T, NV>(qs, hoff[r] + lev(k0), a.sv, hc[r]);
+  }
+  // this level's own Qs (and Qn): the stage combination and the gravity work
+  auto load_own = [&](int s, T (&qsc)[NV], T (&qnc)[NV]) {
+    if (combine) {
+      load_cons<T, NV>(qs, col + lev(s), a.sv, qsc);
+      if (use_qn) load_cons<T, NV>(qn, col + lev(s), a.sv, qnc);
+    } else {
+      qsc[3] = qs[col + lev(s) + 3 * a.sv];
+    }
+  };
 
   T QP[I::RREG][NV];
   for (int s = k0 - 2; s < k1; ++s) {
     T wc[NV], qsc[NV], qnc[NV];
-    if (act) {
-      load_cons<T, NV>(qs, col + lev(s + 3), a.sv, wc);
-      if (s >= k0 && combine) {
-        load_cons<T, NV>(qs, col + lev(s), a.sv, qsc);
-        if (use_qn) load_cons<T, NV>(qn, col + lev(s), a.sv, qnc);
-      } else if (s >= k0) {
-        qsc[3] = qs[col + lev(s) + 3 * a.sv];
+    if constexpr (PF) {
+      if (act) {
+        load_cons<T, NV>(qs, col + lev(s + 3), a.sv, wc);
+        if (s >= k0) load_own(s, qsc, qnc);
       }
     }
     if (s >= k0) {
@@ -418,10 +431,13 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
       for (int r = 0; r < HR; ++r) {
         if (hok[r]) {
           T x[NV];
+          if constexpr (!PF) load_cons<T, NV>(qs, hoff[r] + lev(s), a.sv, hc[r]);
           cons_to_prim_t<T, NV, MIX>(hc[r], rbs, pbs, a.gm1, a.mix, x);
 #pragma unroll
           for (int v = 0; v < NV; ++v) S.P[v][hjj[r] + 3][hii[r] + 3] = x[v];
-          if (s + 1 < k1) load_cons<T, NV>(qs, hoff[r] + lev(s + 1), a.sv, hc[r]);
+          if constexpr (PF) {
+            if (s + 1 < k1) load_cons<T, NV>(qs, hoff[r] + lev(s + 1), a.sv, hc[r]);
+          }
         }
       }
       __syncthreads();
@@ -441,6 +457,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
     // ---- vertical direction, own column: face s+1/2 (z-face index s+1) -------
     T dfz[NV];
     if (act) {
+      if constexpr (!PF) load_cons<T, NV>(qs, col + lev(s + 3), a.sv, wc);
       cons_to_prim_t<T, NV, MIX>(wc, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG], a.gm1, a.mix,
                                  W[4]);
       T qmn[NV], qpn[NV];
@@ -465,6 +482,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
     }
     // ---- (D) divergence, gravity, output -------------------------------------
     if (s >= k0 && act) {
+      if constexpr (!PF) load_own(s, qsc, qnc);
       T R[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {

@@ -468,6 +468,28 @@ def clausius_clapeyron(latent_ref: float, dc: float, r_vap: float, t_ref: float)
     return (latent_ref + dc * t_ref) / (r_vap * t_ref), dc / r_vap
 
 
+def jovian_kessler_3d(nx=512, ny=512, nz=256, seed_q=2, seed_theta=3, **kw):
+    """The Jovian-like column with water and ammonia vapour, cloud and
+    precipitation under the mixture equation of state, and the Kessler
+    parameters of the two species: (grid, state, Kessler)."""
+    base = jovian_base()
+    grid, q = jovian_3d(nx=nx, ny=ny, nz=nz, seed_q=seed_q, seed_theta=seed_theta, **kw)
+    table, kes = kessler_tracers(base.cp - base.rd, JOVIAN_MU, base.rd)
+    g6 = with_mixture(grid, table)
+    rho = grid.interior(q)[0]
+    p = rest_fields(grid)[1]
+    shp = rho.shape
+    zc = cell_centres(nz, grid.dz)[:, None, None]
+    rng = np.random.default_rng(seed_q + 100)
+    vap = []
+    for pc_ in (7e5, 0.7e5):   # up to 20 km above the condensation level: supersaturated there
+        qv = 10.0 ** rng.uniform(-3.0, -0.9, size=shp)
+        vap.append(np.where(zc < base.z_of_pressure(pc_) + 20e3, qv, 0.0))
+    seeds = [10.0 ** rng.uniform(-6.0, -4.0, size=shp) for _ in range(4)]
+    q6 = state_from_primitives(g6, rho, 0.0, 0.0, 0.0, p, vap + seeds)
+    return g6, q6, kes
+
+
 ENSEMBLE_SIZES = ((128, 128), (256, 128), (384, 192), (512, 256))
 
 
