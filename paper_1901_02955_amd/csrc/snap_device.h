@@ -63,16 +63,18 @@ struct Mixture {
   float af[MAX_TRACERS], bf[MAX_TRACERS], muf[MAX_TRACERS];
 };
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void mixture_coef(const Mixture& m, int t, T& a, T& b, T& mu) {
-  if constexpr (sizeof(T) == 4) {
+  // with few tracers the converted coefficients fit in vector registers
+  // (and are hoisted out of the level loop); with more, the scalar copies
+  if constexpr (sizeof(T) == 4 && NT >= 5) {
     a = m.af[t];
     b = m.bf[t];
     mu = m.muf[t];
   } else {
-    a = m.a[t];
-    b = m.b[t];
-    mu = m.mu[t];
+    a = static_cast<T>(m.a[t]);
+    b = static_cast<T>(m.b[t]);
+    mu = static_cast<T>(m.mu[t]);
   }
 }
 
@@ -275,7 +277,7 @@ __device__ __forceinline__ void lmars_flux_mix(const T (&xl)[NV], const T (&xr)[
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     T at, bt, mt;
-    mixture_coef<T>(m, t, at, bt, mt);
+    mixture_coef<T, NT>(m, t, at, bt, mt);
     nl += at * xl[5 + t];
     dl += bt * xl[5 + t];
     ml += mt * xl[5 + t];
