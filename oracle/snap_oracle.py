@@ -366,7 +366,50 @@ def rhs_filled(qf: torch.Tensor, grid) -> torch.Tensor:
     isl = (slice(G, G + grid.nz), slice(_gy(grid), _gy(grid) + grid.ny), slice(G, G + grid.nx))
     R[3] = R[3] - grid.grav * prim["rp"][isl]
     R[4] = R[4] - grid.grav * qf[3][isl]
+    if any(getattr(grid, "tracer_wt", ()) or ()):
+        _add_sedimentation(qf, grid, prim, R, isl)
     return torch.stack(R)
+
+
+def _add_sedimentation(qf, grid, prim, R, isl):
+    """Sedimentation of condensates (Sec. 2, eqs. d3, the momentum equations
+    and the total-energy equation): condensate t with signed vertical velocity
+    w_t relative to the air carries, through every z face, the mass flux
+    m = w_t rho_t (into rho_t and the total density), the momentum m (u, v, w)
+    and the energy m e_t with e_t = c_t T + |u|^2 / 2 + mu_t; its weight does
+    the work -g rho_t w_t on the air (energy source).
+
+    Readings: the face value is that of the cell the condensate comes from
+    (first-order upwind in the direction of w_t); a reflecting z boundary lets
+    no condensate in and lets it out (precipitation leaves through the ground).
+    """
+    gy = _gy(grid)
+    cols = (slice(None), slice(gy, gy + grid.ny), slice(G, G + grid.nx))
+    T = temperature(qf, grid, grid.rd)[cols]
+    rho = qf[0][cols]
+    u, v, w = prim["u"][cols], prim["v"][cols], prim["w"][cols]
+    kin = 0.5 * (u * u + v * v + w * w)
+    cvd = grid.rd / (grid.gamma - 1.0)
+    nz = grid.nz
+    closed = grid.bc[2] == BC_REFLECT
+    for t, wt in enumerate(grid.tracer_wt):
+        if wt == 0.0:
+            continue
+        rt = qf[5 + t][cols]
+        e_t = grid.tracer_sigma[t] * cvd * T + kin + grid.tracer_mu[t]
+        # face f (0 .. nz) lies between padded levels G + f - 1 and G + f
+        src = slice(G, G + nz + 1) if wt < 0 else slice(G - 1, G + nz)
+        m = wt * rt[src]
+        per_var = {0: m, 1: m * u[src], 2: m * v[src], 3: m * w[src], 4: m * e_t[src], 5 + t: m}
+        for var, F in per_var.items():
+            F = F.clone()
+            if closed:          # no inflow through a wall
+                if wt < 0:
+                    F[nz] = 0.0
+                else:
+                    F[0] = 0.0
+            R[var] = R[var] - (F[1:] - F[:-1]) / grid.dz
+        R[4] = R[4] - grid.grav * wt * qf[5 + t][isl]
 
 
 def rhs(q, grid) -> torch.Tensor:

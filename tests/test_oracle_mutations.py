@@ -219,3 +219,59 @@ def test_vapour_molar_mass_ignored_breaks_latent_heating_pin(monkeypatch):
     monkeypatch.setattr(O, "temperature", bad)
     with pytest.raises(AssertionError):
         TK.test_constant_volume_phase_change_heats_as_the_paper_states()
+
+
+# --- sedimentation ------------------------------------------------------------
+
+def _sediment_pins():
+    from tests import test_oracle_sediment as TS
+    return TS
+
+
+def test_open_lid_breaks_ground_budget(monkeypatch):
+    TS = _sediment_pins()
+
+    def bad(qf, grid, prim, R, isl):   # the lid lets condensate in from the mirrored ghost
+        return orig(qf, grid.copy(bc=(grid.bc[0], grid.bc[1], 0)), prim, R, isl)
+    orig = O._add_sedimentation
+    monkeypatch.setattr(O, "_add_sedimentation", bad)
+    with pytest.raises(AssertionError):
+        TS.test_wall_column_loses_rain_only_through_the_ground()
+
+
+def test_heating_sign_breaks_uniform_pin(monkeypatch):
+    TS = _sediment_pins()
+    orig = O._add_sedimentation
+
+    def bad(qf, grid, prim, R, isl):
+        orig(qf, grid, prim, R, isl)
+        for t, wt in enumerate(grid.tracer_wt):
+            R[4] = R[4] + 2.0 * grid.grav * wt * qf[5 + t][isl]
+    monkeypatch.setattr(O, "_add_sedimentation", bad)
+    with pytest.raises(AssertionError):
+        TS.test_uniform_state_only_heats()
+
+
+def test_chemical_energy_not_carried_breaks_ground_budget(monkeypatch):
+    TS = _sediment_pins()
+    orig = O._add_sedimentation
+    monkeypatch.setattr(O, "_add_sedimentation",
+                        lambda qf, grid, prim, R, isl: orig(qf, grid.copy(tracer_mu=(0.0,) * grid.ntracer),
+                                                            prim, R, isl))
+    with pytest.raises(AssertionError):
+        TS.test_wall_column_loses_rain_only_through_the_ground()
+
+
+def test_downwind_flux_breaks_falling_pin(monkeypatch):
+    TS = _sediment_pins()
+    orig = O._add_sedimentation
+
+    def bad(qf, grid, prim, R, isl):   # flip the upwind side by flipping the velocity sign twice
+        g2 = grid.copy(tracer_wt=tuple(-w for w in grid.tracer_wt))
+        R2 = [r.clone() for r in R]
+        orig(qf, g2, prim, R2, isl)
+        for m in range(len(R)):
+            R[m] = R[m] - (R2[m] - R[m])    # = sedimentation with the opposite upwind side, same sign
+    monkeypatch.setattr(O, "_add_sedimentation", bad)
+    with pytest.raises(AssertionError):
+        TS.test_rain_falls_into_the_cell_below()

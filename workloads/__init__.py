@@ -70,6 +70,11 @@ class Grid:
     tracer_eps: Tuple[float, ...] = ()
     tracer_sigma: Tuple[float, ...] = ()
     tracer_mu: Tuple[float, ...] = ()
+    # Sedimentation (mixture only): signed vertical velocity (m/s) of each
+    # condensate relative to the air (negative: falling), and the dry gas
+    # constant R_d (J/kg/K) that gives the temperature of the carried energy.
+    tracer_wt: Tuple[float, ...] = ()
+    rd: float = 0.0
 
     @property
     def nvar(self) -> int:
