@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 2
+#define SNAP_ABI_VERSION 3
 
 /* return codes */
 #define SNAP_OK 0
@@ -122,9 +122,24 @@ extern "C" {
  * tracer_mu      chemical potential per unit mass, J/kg, finite (0 for gases
  *                whose potentials are set to zero; for a condensate
  *                mu_i - (L^r + (c_ij - c_p,i) T^r), Sec. 2, eq. muij).
+ * tracer_wt      sedimentation (Sec. 2, eq. d3, the momentum and total-energy
+ *                equations): signed vertical velocity (m/s) of condensate t
+ *                relative to the air, negative when it falls; 0 for no fall
+ *                (and for every vapour). Through every z face a falling
+ *                condensate carries the mass flux m = w_t rho_t (into rho_t and
+ *                the total density), the momentum m (u, v, w) and the energy
+ *                m (c_t T + |u|^2 / 2 + mu_t), c_t = tracer_sigma[t] rd /
+ *                (gamma - 1), T = p / (rd rho (1 + sum a_s q_s)); the face value
+ *                is that of the cell the condensate comes from (first-order
+ *                upwind; the paper gives no discretisation); a reflecting z
+ *                boundary lets no condensate in and lets it out (precipitation
+ *                leaves through the ground). Its weight heats the air by
+ *                -g rho_t w_t. The CFL step does not include |w_t|.
+ * rd             gas constant of the dry gas (J/kg/K), finite > 0 when any
+ *                tracer_wt is nonzero; not read otherwise.
  *                The tracer fields are read only under SNAP_EOS_MIXTURE with
- *                ntracer > 0; there the adjoint and batched entry points return
- *                SNAP_E_UNSUPPORTED.
+ *                ntracer > 0 (a nonzero tracer_wt needs the mixture); there the
+ *                adjoint and batched entry points return SNAP_E_UNSUPPORTED.
  *
  * Density and pressure are reconstructed as perturbations rho - rhobar and
  * p - pbar of the level (the vertical perturbation pressure of Sec. 4.1); face
@@ -152,6 +167,8 @@ typedef struct snap_grid {
   double tracer_eps[SNAP_MAX_TRACERS];
   double tracer_sigma[SNAP_MAX_TRACERS];
   double tracer_mu[SNAP_MAX_TRACERS];
+  double tracer_wt[SNAP_MAX_TRACERS];
+  double rd;
 } snap_grid;
 
 /* Thread-local message of the last failed call of this thread ("" if none). */

@@ -45,7 +45,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 2
+SNAP_ABI_VERSION = 3
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_TRACER_VAPOUR = 0
@@ -86,6 +86,7 @@ class SnapGridC(ctypes.Structure):
         ("tracer_eps", ctypes.c_double * SNAP_MAX_TRACERS),
         ("tracer_sigma", ctypes.c_double * SNAP_MAX_TRACERS),
         ("tracer_mu", ctypes.c_double * SNAP_MAX_TRACERS),
+        ("tracer_wt", ctypes.c_double * SNAP_MAX_TRACERS), ("rd", ctypes.c_double),
     ]
 
 
@@ -179,7 +180,7 @@ class DeviceGrid:
     Built from plain values; ``device_grid`` builds one from any object with
     the same attribute names (nx, ny, nz, dx, dy, dz, gamma, grav, ntracer, bc,
     weno_eps, weno_linear, rhobar_cell, pbar_cell, rhobar_face, pbar_face and,
-    optionally, eos, tracer_kind, tracer_eps, tracer_sigma, tracer_mu).
+    optionally, eos, tracer_kind, tracer_eps, tracer_sigma, tracer_mu, tracer_wt, rd).
     """
 
     def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
@@ -188,7 +189,8 @@ class DeviceGrid:
                  rhobar_face, pbar_face, dtype: torch.dtype = torch.float64,
                  device: Optional[torch.device] = None, eos: int = SNAP_EOS_PASSIVE,
                  tracer_kind: Sequence[int] = (), tracer_eps: Sequence[float] = (),
-                 tracer_sigma: Sequence[float] = (), tracer_mu: Sequence[float] = ()):
+                 tracer_sigma: Sequence[float] = (), tracer_mu: Sequence[float] = (),
+                 tracer_wt: Sequence[float] = (), rd: float = 0.0):
         if dtype not in (torch.float64, torch.float32):
             raise ValueError("dtype must be torch.float64 or torch.float32")
         device = torch.device(device or "cuda")
@@ -216,6 +218,9 @@ class DeviceGrid:
                 raise ValueError(f"at most {SNAP_MAX_TRACERS} tracers")
             c.tracer_kind[t], c.tracer_eps[t] = int(k), float(e)
             c.tracer_sigma[t], c.tracer_mu[t] = float(sg), float(mu)
+        for t, wt in enumerate(tracer_wt):
+            c.tracer_wt[t] = float(wt)
+        c.rd = float(rd)
         self.eos = int(eos)
         self.c = c
 
@@ -254,7 +259,8 @@ def device_grid(g, dtype: torch.dtype = torch.float64, device=None) -> DeviceGri
                       g.pbar_face, dtype=dtype, device=device,
                       eos=getattr(g, "eos", SNAP_EOS_PASSIVE),
                       tracer_kind=getattr(g, "tracer_kind", ()), tracer_eps=getattr(g, "tracer_eps", ()),
-                      tracer_sigma=getattr(g, "tracer_sigma", ()), tracer_mu=getattr(g, "tracer_mu", ()))
+                      tracer_sigma=getattr(g, "tracer_sigma", ()), tracer_mu=getattr(g, "tracer_mu", ()),
+                      tracer_wt=getattr(g, "tracer_wt", ()), rd=getattr(g, "rd", 0.0))
 
 
 def snap_abi_version() -> int:

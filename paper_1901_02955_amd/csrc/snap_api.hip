@@ -73,6 +73,32 @@ Mixture mixture_of(const snap_grid* g) {
   return m;
 }
 
+// Any condensate falls (read only under the mixture).
+bool uses_sediment(const snap_grid* g) {
+  if (!uses_mixture(g)) return false;
+  for (int t = 0; t < g->ntracer; ++t)
+    if (g->tracer_wt[t] != 0.0) return true;
+  return false;
+}
+
+Sediment sediment_of(const snap_grid* g) {
+  Sediment d;
+  memset(&d, 0, sizeof d);
+  if (!uses_sediment(g)) return d;
+  d.on = 1;
+  d.closed_z = g->bc[2] == SNAP_BC_REFLECT ? 1 : 0;
+  d.rd = g->rd;
+  d.rdf = (float)g->rd;
+  const double cvd = g->rd / (g->gamma - 1.0);
+  for (int t = 0; t < g->ntracer; ++t) {
+    d.wt[t] = g->tracer_wt[t];
+    d.ct[t] = g->tracer_sigma[t] * cvd;
+    d.wtf[t] = (float)d.wt[t];
+    d.ctf[t] = (float)d.ct[t];
+  }
+  return d;
+}
+
 int check_grid(const snap_grid* g) {
   if (!g) return fail(SNAP_E_INVALID, "grid pointer is NULL");
   if (g->nx < 1 || g->ny < 1 || g->nz < 1)
@@ -115,7 +141,13 @@ int check_grid(const snap_grid* g) {
         return fail(SNAP_E_INVALID, "tracer_sigma[%d] must be finite and > 0", t);
       if (!isfinite(g->tracer_mu[t]))
         return fail(SNAP_E_INVALID, "tracer_mu[%d] must be finite", t);
+      if (!isfinite(g->tracer_wt[t]))
+        return fail(SNAP_E_INVALID, "tracer_wt[%d] must be finite", t);
+      if (g->tracer_wt[t] != 0.0 && k != SNAP_TRACER_CONDENSATE)
+        return fail(SNAP_E_INVALID, "tracer_wt[%d]: only condensates fall", t);
     }
+    if (uses_sediment(g) && !finite_pos(g->rd))
+      return fail(SNAP_E_INVALID, "rd must be finite and > 0 when a condensate falls");
   }
   const double total = (double)padded_cells(g) * nvar_of(g);
   if (total > 9.0e18 / 8.0) return fail(SNAP_E_INVALID, "state too large");
@@ -157,6 +189,7 @@ StageArgs stage_args(const snap_grid* g) {
   a.rbar_f = g->rhobar_face;
   a.pbar_f = g->pbar_face;
   a.mix = mixture_of(g);
+  a.sed = sediment_of(g);
   return a;
 }
 
@@ -267,7 +300,13 @@ int run_stage(const snap_grid* g, StageArgs a, hipStream_t st) {
                     : (mix ? launch_stage_mix_f32(g->ntracer, d3, a, nb, st)
                            : launch_stage_f32(g->ntracer, d3, a, nb, st));
   if (r != 0) return device_fail("stage kernel launch");
-  if (timed) return timing_mark(st);
+  if (timed) {
+    const int t = timing_mark(st);
+    if (t) return t;
+  }
+  // sedimentation: its part of the right-hand side added to the stage output
+  if (a.sed.on && launch_sediment(g->dtype, g->ntracer, a, st))
+    return device_fail("sedimentation kernel launch");
   return SNAP_OK;
 }
 

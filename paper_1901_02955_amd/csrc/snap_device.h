@@ -78,6 +78,16 @@ __device__ __forceinline__ void mixture_coef(const Mixture& m, int t, T& a, T& b
   }
 }
 
+// Sedimentation of condensates (Sec. 2, eq. d3, the momentum and total-energy
+// equations): per tracer its signed vertical velocity wt relative to the air
+// (0: does not fall) and heat capacity ct; rd the dry gas constant; closed_z:
+// the z axis has walls (no condensate enters through them).
+struct Sediment {
+  int on, closed_z;
+  double wt[MAX_TRACERS], ct[MAX_TRACERS], rd;
+  float wtf[MAX_TRACERS], ctf[MAX_TRACERS], rdf;
+};
+
 // cons_to_prim with the mixture equation of state, in the fixed order
 //   A = (mu_1 rho_1 + mu_2 rho_2) + ...; num = (1 + a_1 q_1) + ...; den alike;
 //   p = ((gamma_d - 1)(num / den)) ((E - K) - A)
@@ -312,6 +322,77 @@ __device__ __forceinline__ void lmars_flux_mix(const T (&xl)[NV], const T (&xr)[
   f[1] += nrm == 1 ? pstar : T(0);
   f[2] += nrm == 2 ? pstar : T(0);
   f[3] += nrm == 3 ? pstar : T(0);
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void sediment_coef(const Sediment& sd, int t, T& wt, T& ct) {
+  if constexpr (sizeof(T) == 4 && NT >= 5) {
+    wt = sd.wtf[t];
+    ct = sd.ctf[t];
+  } else {
+    wt = static_cast<T>(sd.wt[t]);
+    ct = static_cast<T>(sd.ct[t]);
+  }
+}
+
+// Sedimentation through the two z faces of one cell, and the heating of its
+// air, subtracted from / added to its right-hand side R. xb, x0, xa: primitive
+// vectors (rho', u, v, w, p', q) of the cells below, the cell, and above,
+// with their level references (rb, pb), (r0, p0), (ra, pa). A falling
+// condensate (wt < 0) crosses the upper face with the values of the cell
+// above and the lower face with this cell's; a rising one the reverse. No
+// condensate comes in through a wall (wall_below / wall_above).
+template <typename T, int NV>
+__device__ __forceinline__ void sediment_cell(const T (&xb)[NV], const T (&x0)[NV],
+                                              const T (&xa)[NV], T rb, T pb, T r0, T p0, T ra,
+                                              T pa, bool wall_below, bool wall_above,
+                                              const Mixture& mx, const Sediment& sd, T dzi,
+                                              T grav, T (&R)[NV]) {
+  constexpr int NT = NV - 5;
+  const T rd = sizeof(T) == 4 ? static_cast<T>(sd.rdf) : static_cast<T>(sd.rd);
+  // density, temperature p / (R_d rho (1 + sum a_s q_s)) and kinetic energy per mass
+  auto cell = [&](const T (&x)[NV], T rref, T pref, T& rho, T& temp, T& kin) {
+    rho = rref + x[0];
+    T num = T(1);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      T a, b, mu;
+      mixture_coef<T, NT>(mx, t, a, b, mu);
+      num += a * x[5 + t];
+    }
+    temp = (pref + x[4]) * rcp_fast(rd * rho * num);
+    kin = T(0.5) * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+  };
+  T rhob, tb, kb, rho0, t0, k0, rhoa, ta, ka;
+  cell(xb, rb, pb, rhob, tb, kb);
+  cell(x0, r0, p0, rho0, t0, k0);
+  cell(xa, ra, pa, rhoa, ta, ka);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    T wt, ct;
+    sediment_coef<T, NT>(sd, t, wt, ct);
+    if (wt == T(0)) continue;
+    T a, b, mu;
+    mixture_coef<T, NT>(mx, t, a, b, mu);
+    const bool fall = wt < T(0);
+    const T own = rho0 * x0[5 + t];
+    // upper face: from above if falling
+    const T m_up = (fall && wall_above) ? T(0) : wt * (fall ? rhoa * xa[5 + t] : own);
+    const T u_up = fall ? xa[1] : x0[1], v_up = fall ? xa[2] : x0[2], w_up = fall ? xa[3] : x0[3];
+    const T e_up = ct * (fall ? ta : t0) + (fall ? ka : k0) + mu;
+    // lower face: from this cell if falling
+    const T m_lo = (!fall && wall_below) ? T(0) : wt * (fall ? own : rhob * xb[5 + t]);
+    const T u_lo = fall ? x0[1] : xb[1], v_lo = fall ? x0[2] : xb[2], w_lo = fall ? x0[3] : xb[3];
+    const T e_lo = ct * (fall ? t0 : tb) + (fall ? k0 : kb) + mu;
+    const T dm = (m_up - m_lo) * dzi;
+    R[0] -= dm;
+    R[5 + t] -= dm;
+    R[1] -= (m_up * u_up - m_lo * u_lo) * dzi;
+    R[2] -= (m_up * v_up - m_lo * v_lo) * dzi;
+    R[3] -= (m_up * w_up - m_lo * w_lo) * dzi;
+    R[4] -= (m_up * e_up - m_lo * e_lo) * dzi;
+    R[4] -= grav * wt * own;   // frictional heating by the falling condensate
+  }
 }
 
 // Block index -> logical tile with consecutive logical tiles on one XCD.

@@ -96,6 +96,7 @@ int launch_stage2d_batched(int dtype, int ntracer, int variant, const StageArgs*
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st);
 int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st);
+int launch_sediment(int dtype, int ntracer, const StageArgs& a, hipStream_t st);
 int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double* out,
                 hipStream_t st);
 

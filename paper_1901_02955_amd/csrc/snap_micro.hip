@@ -108,6 +108,77 @@ __global__ void __launch_bounds__(256) k_kessler(T* __restrict__ q, KesslerArgs 
   for (int t = 0; t < NT; ++t) q[o + (5 + t) * a.sv] = static_cast<T>(c[5 + t]);
 }
 
+// Sedimentation part of the right-hand side of one interior cell (from the
+// stage input Qs, ghosts filled), added to the stage output: R_sed itself in
+// right-hand-side mode, cb dt R_sed after the stage combination (which is
+// linear in R). grid: x over interior rows (nz ny), y over the interior row.
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_sediment(StageArgs a) {
+  constexpr int NV = 5 + NT;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, k = row / a.ny;
+  const T* __restrict__ qs = static_cast<const T*>(a.qs);
+  const long long po = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+  T x[3][NV];   // primitives of levels k-1, k, k+1
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    double c[NV], xd[NV];
+    const long long o = po + (long long)(l - 1) * a.sz;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) c[v] = static_cast<double>(qs[o + v * a.sv]);
+    cons_to_prim_mix<NV>(c, a.rbar_c[k + l - 1 + NG], a.pbar_c[k + l - 1 + NG], a.gm1, a.mix, xd);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[l][v] = static_cast<T>(xd[v]);
+  }
+  T R[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) R[v] = T(0);
+  const bool wall_lo = a.sed.closed_z && k == 0, wall_up = a.sed.closed_z && k == a.nz - 1;
+  auto ref = [&](const double* r, int l) { return static_cast<T>(r[k + l - 1 + NG]); };
+  sediment_cell<T, NV>(x[0], x[1], x[2], ref(a.rbar_c, 0), ref(a.pbar_c, 0), ref(a.rbar_c, 1),
+                       ref(a.pbar_c, 1), ref(a.rbar_c, 2), ref(a.pbar_c, 2), wall_lo, wall_up, a.mix,
+                       a.sed, static_cast<T>(a.dzi), static_cast<T>(a.grav), R);
+  T* __restrict__ out = static_cast<T*>(a.out);
+  if (a.rhs_mode) {
+    const long long ro = (long long)k * a.rz + (long long)j * a.ry + i;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[ro + v * a.rv] += R[v];
+  } else {
+    const T f = static_cast<T>(a.cb * a.dt);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[po + v * a.sv] += f * R[v];
+  }
+}
+
+template <typename T>
+int launch_sediment_t(int ntracer, const StageArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)(a.ny * a.nz), (unsigned)((a.nx + 255) / 256));
+  switch (ntracer) {
+#define SNAP_SEDIMENT_CASE(N)                                                       \
+  case N:                                                                           \
+    hipLaunchKernelGGL((k_sediment<T, N>), grid, dim3(256), 0, st, a);              \
+    break;
+    SNAP_SEDIMENT_CASE(1)
+    SNAP_SEDIMENT_CASE(2)
+    SNAP_SEDIMENT_CASE(3)
+    SNAP_SEDIMENT_CASE(4)
+    SNAP_SEDIMENT_CASE(5)
+    SNAP_SEDIMENT_CASE(6)
+    SNAP_SEDIMENT_CASE(7)
+    SNAP_SEDIMENT_CASE(8)
+#undef SNAP_SEDIMENT_CASE
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_sediment(int dtype, int ntracer, const StageArgs& a, hipStream_t st) {
+  return dtype == 0 ? launch_sediment_t<double>(ntracer, a, st)
+                    : launch_sediment_t<float>(ntracer, a, st);
+}
+
 template <typename T>
 int launch_kessler_t(int ntracer, T* q, const KesslerArgs& a, hipStream_t st) {
   const dim3 grid((unsigned)(a.ny * a.nz), (unsigned)((a.nx + 255) / 256));

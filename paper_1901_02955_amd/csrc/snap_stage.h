@@ -53,6 +53,7 @@ struct StageArgs {
   const double* rbar_f;  // nz + 1
   const double* pbar_f;
   Mixture mix;           // mixture equation of state (kernels instantiated with MIX)
+  Sediment sed;          // sedimentation (a kernel of its own, when sed.on)
 };
 
 template <typename T>

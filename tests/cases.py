@@ -112,3 +112,25 @@ def build_kessler_case(name: str, spec):
     cond = [10.0 ** rng.uniform(-5.0, -3.0, shp) for _ in range(4)]
     q = wl.state_from_primitives(grid, rho, u, v, w, p, vap + cond)
     return Case(name, grid, q, 2.0), kes
+
+
+# Cases with falling precipitation (sedimentation): the Kessler cases with the
+# water and ammonia rain falling at 6 and 4 m/s, with walls or periodic in z.
+SED_SPECS = [
+    ("sed_3d_walls_21x13x16", dict(nx=21, ny=13, nz=16, seed=51, bc=(0, 0, 1))),
+    ("sed_3d_periodic_z_12x9x14", dict(nx=12, ny=9, nz=14, seed=52, bc=(0, 0, 0))),
+    ("sed_2d_walls_29x20", dict(nx=29, ny=1, nz=20, seed=53, bc=(1, 0, 1))),
+]
+SED_NAMES = [n for n, _ in SED_SPECS]
+
+
+def build_sediment_case(name: str, spec) -> Case:
+    c, _ = build_kessler_case(name, spec)
+    base = wl.DryIsentropic()
+    g = c.grid
+    if tuple(spec["bc"]) != tuple(g.bc):
+        g2, _ = wl.dry_grid(g.nx, g.ny, g.nz, g.dx * g.nx, g.dy * g.ny, g.dz * g.nz, bc=spec["bc"])
+        g = g.copy(bc=tuple(spec["bc"]), rhobar_cell=g2.rhobar_cell, pbar_cell=g2.pbar_cell,
+                   rhobar_face=g2.rhobar_face, pbar_face=g2.pbar_face)
+    g = g.copy(tracer_wt=(0.0, 0.0, 0.0, 0.0, -6.0, -4.0), rd=base.rd)
+    return Case(name, g, c.q, 0.2)

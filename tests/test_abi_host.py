@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 2
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 3
 
 
 def good_grid(**kw):
@@ -80,6 +80,8 @@ BAD_GRIDS = [
     dict(eos=1, tracer_kind=(2, 1)), dict(eos=1, tracer_eps=(0.0, 0.0)), dict(eos=1, tracer_eps=(math.inf, 0.0)),
     dict(eos=1, tracer_sigma=(0.16, 0.0)), dict(eos=1, tracer_sigma=(math.nan, 0.48)),
     dict(eos=1, tracer_mu=(math.nan, 0.0)), dict(eos=1, tracer_mu=(0.0, -math.inf)),
+    dict(eos=1, tracer_wt=(0.0, math.nan)), dict(eos=1, tracer_wt=(-5.0, 0.0)),   # a vapour cannot fall
+    dict(eos=1, tracer_wt=(0.0, -5.0), rd=0.0), dict(eos=1, tracer_wt=(0.0, -5.0), rd=math.inf),
 ]
 
 
@@ -227,6 +229,10 @@ def test_mixture_fields_and_unsupported_entry_points():
     # a condensate's eps is not read
     g = ctypes.byref(good_grid(eos=1, tracer_eps=(7.8, math.nan)))
     assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) > 0
+    # rd is read only when a condensate falls
+    assert lib.snap_workspace_bytes(ctypes.byref(good_grid(eos=1, rd=math.nan)), snap.SNAP_OP_RK3) > 0
+    assert lib.snap_workspace_bytes(ctypes.byref(good_grid(eos=1, rd=287.0, tracer_wt=(0.0, -6.0))),
+                                    snap.SNAP_OP_RK3) > 0
     P = ctypes.c_void_p(FAKE)
     Q2, Q3 = ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE)
     assert lib.snap_rhs_adjoint(g, P, Q2, Q3, P, None) == snap.SNAP_E_UNSUPPORTED
