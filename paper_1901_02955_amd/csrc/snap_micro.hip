@@ -108,57 +108,76 @@ __global__ void __launch_bounds__(256) k_kessler(T* __restrict__ q, KesslerArgs 
   for (int t = 0; t < NT; ++t) q[o + (5 + t) * a.sv] = static_cast<T>(c[5 + t]);
 }
 
-// Sedimentation part of the right-hand side of one interior cell (from the
-// stage input Qs, ghosts filled), added to the stage output: R_sed itself in
-// right-hand-side mode, cb dt R_sed after the stage combination (which is
-// linear in R). grid: x over interior rows (nz ny), y over the interior row.
+// Sedimentation part of the right-hand side (from the stage input Qs, ghosts
+// filled), added to the stage output: R_sed itself in right-hand-side mode,
+// cb dt R_sed after the stage combination (which is linear in R). One thread
+// walks a chunk of SED_CHUNK levels of one column with the primitives of the
+// levels below, at and above the cell in registers, so that every level is
+// converted once. grid: x over (row j, chunk), y over blocks of the row.
+constexpr int SED_CHUNK = 16;
+
 template <typename T, int NT>
-__global__ void __launch_bounds__(256) k_sediment(StageArgs a) {
+__global__ void __launch_bounds__(256) k_sediment(StageArgs a, int nchunk) {
   constexpr int NV = 5 + NT;
   const int i = blockIdx.y * 256 + threadIdx.x;
   if (i >= a.nx) return;
-  const int row = blockIdx.x;
-  const int j = row % a.ny, k = row / a.ny;
+  const int j = blockIdx.x / nchunk, kc = blockIdx.x % nchunk;
+  const int k0 = kc * SED_CHUNK, k1 = min(k0 + SED_CHUNK, a.nz);
   const T* __restrict__ qs = static_cast<const T*>(a.qs);
-  const long long po = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
-  T x[3][NV];   // primitives of levels k-1, k, k+1
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
+  const long long col = (long long)(j + a.gy) * a.sy + (i + NG);
+  auto prim = [&](int k, T (&x)[NV]) {   // primitives of level k (ghost levels allowed)
     double c[NV], xd[NV];
-    const long long o = po + (long long)(l - 1) * a.sz;
+    const long long o = col + (long long)(k + NG) * a.sz;
 #pragma unroll
     for (int v = 0; v < NV; ++v) c[v] = static_cast<double>(qs[o + v * a.sv]);
-    cons_to_prim_mix<NV>(c, a.rbar_c[k + l - 1 + NG], a.pbar_c[k + l - 1 + NG], a.gm1, a.mix, xd);
+    cons_to_prim_mix<NV>(c, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, a.mix, xd);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) x[l][v] = static_cast<T>(xd[v]);
-  }
-  T R[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) R[v] = T(0);
-  const bool wall_lo = a.sed.closed_z && k == 0, wall_up = a.sed.closed_z && k == a.nz - 1;
-  auto ref = [&](const double* r, int l) { return static_cast<T>(r[k + l - 1 + NG]); };
-  sediment_cell<T, NV>(x[0], x[1], x[2], ref(a.rbar_c, 0), ref(a.pbar_c, 0), ref(a.rbar_c, 1),
-                       ref(a.pbar_c, 1), ref(a.rbar_c, 2), ref(a.pbar_c, 2), wall_lo, wall_up, a.mix,
-                       a.sed, static_cast<T>(a.dzi), static_cast<T>(a.grav), R);
+    for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+  };
+  auto ref = [&](const double* r, int k) { return static_cast<T>(r[k + NG]); };
+  // only the five dynamic fields and the falling tracers change (a uniform test)
+  auto moves = [&](int v) { return v < 5 || a.sed.wt[v - 5] != 0.0; };
+  T xb[NV], x0[NV], xa[NV];
+  prim(k0 - 1, xb);
+  prim(k0, x0);
   T* __restrict__ out = static_cast<T*>(a.out);
-  if (a.rhs_mode) {
-    const long long ro = (long long)k * a.rz + (long long)j * a.ry + i;
+  const T f = static_cast<T>(a.cb * a.dt);
+  for (int k = k0; k < k1; ++k) {
+    prim(k + 1, xa);
+    T R[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[ro + v * a.rv] += R[v];
-  } else {
-    const T f = static_cast<T>(a.cb * a.dt);
+    for (int v = 0; v < NV; ++v) R[v] = T(0);
+    const bool wall_lo = a.sed.closed_z && k == 0, wall_up = a.sed.closed_z && k == a.nz - 1;
+    sediment_cell<T, NV>(xb, x0, xa, ref(a.rbar_c, k - 1), ref(a.pbar_c, k - 1), ref(a.rbar_c, k),
+                         ref(a.pbar_c, k), ref(a.rbar_c, k + 1), ref(a.pbar_c, k + 1), wall_lo,
+                         wall_up, a.mix, a.sed, static_cast<T>(a.dzi), static_cast<T>(a.grav), R);
+    if (a.rhs_mode) {
+      const long long ro = (long long)k * a.rz + (long long)j * a.ry + i;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[po + v * a.sv] += f * R[v];
+      for (int v = 0; v < NV; ++v)
+        if (moves(v)) out[ro + v * a.rv] += R[v];
+    } else {
+      const long long po = col + (long long)(k + NG) * a.sz;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (moves(v)) out[po + v * a.sv] += f * R[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xb[v] = x0[v];
+      x0[v] = xa[v];
+    }
   }
 }
 
 template <typename T>
 int launch_sediment_t(int ntracer, const StageArgs& a, hipStream_t st) {
-  const dim3 grid((unsigned)(a.ny * a.nz), (unsigned)((a.nx + 255) / 256));
+  const int nchunk = (a.nz + SED_CHUNK - 1) / SED_CHUNK;
+  const dim3 grid((unsigned)(a.ny * nchunk), (unsigned)((a.nx + 255) / 256));
   switch (ntracer) {
 #define SNAP_SEDIMENT_CASE(N)                                                       \
   case N:                                                                           \
-    hipLaunchKernelGGL((k_sediment<T, N>), grid, dim3(256), 0, st, a);              \
+    hipLaunchKernelGGL((k_sediment<T, N>), grid, dim3(256), 0, st, a, nchunk);      \
     break;
     SNAP_SEDIMENT_CASE(1)
     SNAP_SEDIMENT_CASE(2)

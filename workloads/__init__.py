@@ -473,10 +473,11 @@ def clausius_clapeyron(latent_ref: float, dc: float, r_vap: float, t_ref: float)
     return (latent_ref + dc * t_ref) / (r_vap * t_ref), dc / r_vap
 
 
-def jovian_kessler_3d(nx=512, ny=512, nz=256, seed_q=2, seed_theta=3, **kw):
+def jovian_kessler_3d(nx=512, ny=512, nz=256, seed_q=2, seed_theta=3, sediment=False, **kw):
     """The Jovian-like column with water and ammonia vapour, cloud and
     precipitation under the mixture equation of state, and the Kessler
-    parameters of the two species: (grid, state, Kessler)."""
+    parameters of the two species: (grid, state, Kessler); ``sediment``: the
+    precipitation falls."""
     base = jovian_base()
     grid, q = jovian_3d(nx=nx, ny=ny, nz=nz, seed_q=seed_q, seed_theta=seed_theta, **kw)
     table, kes = kessler_tracers(base.cp - base.rd, JOVIAN_MU, base.rd)
@@ -491,6 +492,8 @@ def jovian_kessler_3d(nx=512, ny=512, nz=256, seed_q=2, seed_theta=3, **kw):
         qv = 10.0 ** rng.uniform(-3.0, -0.9, size=shp)
         vap.append(np.where(zc < base.z_of_pressure(pc_) + 20e3, qv, 0.0))
     seeds = [10.0 ** rng.uniform(-6.0, -4.0, size=shp) for _ in range(4)]
+    if sediment:   # water and ammonia rain fall at 8 and 5 m/s
+        g6 = g6.copy(tracer_wt=(0.0, 0.0, 0.0, 0.0, -8.0, -5.0), rd=base.rd)
     q6 = state_from_primitives(g6, rho, 0.0, 0.0, 0.0, p, vap + seeds)
     return g6, q6, kes
 
