@@ -315,6 +315,75 @@ def lmars_flux(L: dict, R: dict, normal: int, gamma: float, ntracer: int, thermo
     return flux, pstar, ustar
 
 
+def _conserved_and_flux(S, normal, gamma):
+    """Conserved vector U and Euler flux F along ``normal`` of a face state, the
+    normal momentum flux with the perturbation pressure (as in LMARS)."""
+    vel = [S["u"], S["v"], S["w"]]
+    un = vel[normal]
+    E = prim_to_cons_energy(S["rho"], S["u"], S["v"], S["w"], S["p"], gamma)
+    U = [S["rho"]] + [S["rho"] * vm for vm in vel] + [E] + [S["rho"] * qt for qt in S["q"]]
+    F = [S["rho"] * un] + [S["rho"] * vel[m] * un + (S["pp"] if m == normal else 0.0)
+                            for m in range(3)]
+    F += [(E + S["p"]) * un] + [S["rho"] * qt * un for qt in S["q"]]
+    return U, F
+
+
+def hllc_star(S, Sk, Ss, normal, gamma):
+    """Star-region conserved state next to side S (HLLC: the HLL average with the
+    contact restored; Toro, Riemann Solvers and Numerical Methods for Fluid
+    Dynamics, ch. 10): with un the side's normal velocity and Sk its outer wave
+    speed, U* = rho (Sk - un)/(Sk - S*) (1, S* on the normal and the side's
+    tangential velocities, E/rho + (S* - un)(S* + p / (rho (Sk - un))), q)."""
+    vel = [S["u"], S["v"], S["w"]]
+    un = vel[normal]
+    E = prim_to_cons_energy(S["rho"], S["u"], S["v"], S["w"], S["p"], gamma)
+    fac = S["rho"] * (Sk - un) / (Sk - Ss)
+    mom = [fac * (Ss if m == normal else vel[m]) for m in range(3)]
+    e = fac * (E / S["rho"] + (Ss - un) * (Ss + S["p"] / (S["rho"] * (Sk - un))))
+    return [fac] + mom + [e] + [fac * qt for qt in S["q"]]
+
+
+def hllc_wave_speeds(L, R, normal, gamma):
+    """Outer wave speeds (Davis): S_L = min(u_L - c_L, u_R - c_R),
+    S_R = max(u_L + c_L, u_R + c_R); contact speed
+    S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R))
+         / (rho_L (S_L - u_L) - rho_R (S_R - u_R))."""
+    vel = ("u", "v", "w")
+    uL, uR = L[vel[normal]], R[vel[normal]]
+    cL = torch.sqrt(gamma * L["p"] / L["rho"])
+    cR = torch.sqrt(gamma * R["p"] / R["rho"])
+    SL = torch.minimum(uL - cL, uR - cR)
+    SR = torch.maximum(uL + cL, uR + cR)
+    num = R["p"] - L["p"] + L["rho"] * uL * (SL - uL) - R["rho"] * uR * (SR - uR)
+    den = L["rho"] * (SL - uL) - R["rho"] * (SR - uR)
+    return SL, SR, num / den
+
+
+def hllc_flux(L: dict, R: dict, normal: int, gamma: float, ntracer: int):
+    """HLLC numerical flux at a face (the alternative Riemann solver the paper
+    compares LMARS with, Sec. 5): F_L if 0 <= S_L; F_L + S_L (U*_L - U_L) if
+    S_L < 0 <= S*; F_R + S_R (U*_R - U_R) if S* < 0 < S_R; F_R if S_R <= 0.
+    Face states as for ``lmars_flux``; full pressure and density set the wave
+    speeds and star states, and the normal momentum flux carries the
+    perturbation pressure (the full flux minus the face reference pressure,
+    exact in every branch since the star terms carry no pressure offset).
+    Returns (flux, perturbation pressure of the star region, S*)."""
+    SL, SR, Ss = hllc_wave_speeds(L, R, normal, gamma)
+    UL, FL = _conserved_and_flux(L, normal, gamma)
+    UR, FR = _conserved_and_flux(R, normal, gamma)
+    sL = hllc_star(L, SL, Ss, normal, gamma)
+    sR = hllc_star(R, SR, Ss, normal, gamma)
+    flux = []
+    for m in range(len(UL)):
+        fl_star = FL[m] + SL * (sL[m] - UL[m])
+        fr_star = FR[m] + SR * (sR[m] - UR[m])
+        flux.append(torch.where(SL >= 0, FL[m], torch.where(Ss >= 0, fl_star,
+                                                            torch.where(SR > 0, fr_star, FR[m]))))
+    vel = ("u", "v", "w")
+    pstar = L["pp"] + L["rho"] * (SL - L[vel[normal]]) * (Ss - L[vel[normal]])
+    return flux, pstar, Ss
+
+
 # ---------------------------------------------------------------------------
 # Right-hand side (Sec. 4, eq. forward)
 # ---------------------------------------------------------------------------
@@ -356,8 +425,11 @@ def rhs_filled(qf: torch.Tensor, grid) -> torch.Tensor:
                  "w": rec[3][side], "pp": rec[4][side], "p": pref + rec[4][side],
                  "q": [r[side] for r in rec[5:]]}
             states.append(S)
-        flux, _, _ = lmars_flux(states[0], states[1], comp, grid.gamma, grid.ntracer,
-                                mixture_coefficients(grid))
+        if getattr(grid, "riemann", 0) == 1:
+            flux, _, _ = hllc_flux(states[0], states[1], comp, grid.gamma, grid.ntracer)
+        else:
+            flux, _, _ = lmars_flux(states[0], states[1], comp, grid.gamma, grid.ntracer,
+                                    mixture_coefficients(grid))
         for m in range(nvar):
             F = flux[m]
             dF = F.narrow(arr_axis, 1, n) - F.narrow(arr_axis, 0, n)

@@ -275,3 +275,52 @@ def test_downwind_flux_breaks_falling_pin(monkeypatch):
     monkeypatch.setattr(O, "_add_sedimentation", bad)
     with pytest.raises(AssertionError):
         TS.test_rain_falls_into_the_cell_below()
+
+
+# --- HLLC ----------------------------------------------------------------------
+
+def _hllc_pins():
+    from tests import test_oracle_hllc as TH
+    return TH
+
+
+def test_contact_speed_pressure_sign_breaks_exact_star_pin(monkeypatch):
+    TH = _hllc_pins()
+    orig = O.hllc_wave_speeds
+
+    def bad(L, R, normal, gamma):
+        SL, SR, Ss = orig(L, R, normal, gamma)
+        den = L["rho"] * (SL - L["u"]) - R["rho"] * (SR - R["u"])
+        return SL, SR, Ss - 2.0 * (R["p"] - L["p"]) / den          # p_L - p_R in the numerator
+    monkeypatch.setattr(O, "hllc_wave_speeds", bad)
+    with pytest.raises(AssertionError):
+        TH.test_star_state_matches_exact_riemann_to_second_order()
+
+
+def test_star_energy_without_pressure_work_breaks_fan_conservation(monkeypatch):
+    TH = _hllc_pins()
+    orig = O.hllc_star
+
+    def bad(S, Sk, Ss, normal, gamma):
+        U = orig(S, Sk, Ss, normal, gamma)
+        vel = [S["u"], S["v"], S["w"]]
+        fac = S["rho"] * (Sk - vel[normal]) / (Sk - Ss)
+        U[4] = U[4] - fac * (Ss - vel[normal]) * S["p"] / (S["rho"] * (Sk - vel[normal]))
+        return U
+    monkeypatch.setattr(O, "hllc_star", bad)
+    with pytest.raises(AssertionError):
+        TH.test_star_states_conserve_across_the_fan()
+
+
+def test_star_momentum_with_side_velocity_breaks_fan_conservation(monkeypatch):
+    TH = _hllc_pins()
+    orig = O.hllc_star
+
+    def bad(S, Sk, Ss, normal, gamma):
+        U = orig(S, Sk, Ss, normal, gamma)
+        vel = [S["u"], S["v"], S["w"]]
+        U[1 + normal] = U[0] * vel[normal]          # normal momentum of the side, not S*
+        return U
+    monkeypatch.setattr(O, "hllc_star", bad)
+    with pytest.raises(AssertionError):
+        TH.test_star_states_conserve_across_the_fan()

@@ -30,6 +30,8 @@ BC_PERIODIC = 0
 BC_REFLECT = 1
 MAX_TRACERS = 8
 RGAS = 8.314462618         # J / (mol K)
+RIEMANN_LMARS = 0
+RIEMANN_HLLC = 1
 EOS_PASSIVE = 0            # tracers do not enter the equation of state
 EOS_MIXTURE = 1            # ideal-gas mixture with condensates (Sec. 2, App. B)
 TRACER_VAPOUR = 0
@@ -75,6 +77,8 @@ class Grid:
     # constant R_d (J/kg/K) that gives the temperature of the carried energy.
     tracer_wt: Tuple[float, ...] = ()
     rd: float = 0.0
+    # Riemann solver at the faces: RIEMANN_LMARS (Sec. 4.1) or RIEMANN_HLLC
+    riemann: int = 0
 
     @property
     def nvar(self) -> int:
