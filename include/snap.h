@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 3
+#define SNAP_ABI_VERSION 4
 
 /* return codes */
 #define SNAP_OK 0
@@ -64,6 +64,10 @@ extern "C" {
 
 #define SNAP_NG 3
 #define SNAP_MAX_TRACERS 8
+
+/* Riemann solver at the faces */
+#define SNAP_RIEMANN_LMARS 0 /* Sec. 4.1 (what a zero-initialised struct selects) */
+#define SNAP_RIEMANN_HLLC 1  /* HLLC with Davis wave speeds (passive tracers only) */
 
 /* equation of state */
 #define SNAP_EOS_PASSIVE 0 /* tracers do not enter the pressure */
@@ -137,6 +141,14 @@ extern "C" {
  *                -g rho_t w_t. The CFL step does not include |w_t|.
  * rd             gas constant of the dry gas (J/kg/K), finite > 0 when any
  *                tracer_wt is nonzero; not read otherwise.
+ * riemann        SNAP_RIEMANN_LMARS or SNAP_RIEMANN_HLLC, the flux at every face.
+ *                HLLC: Davis outer wave speeds, contact speed S*, star states
+ *                U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S* / tangential
+ *                velocities, E_K/rho_K + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K))),
+ *                q_K), with full face density and pressure; the normal momentum
+ *                flux carries the perturbation pressure as under LMARS. HLLC
+ *                takes eos = SNAP_EOS_PASSIVE; the adjoint and batched entry
+ *                points return SNAP_E_UNSUPPORTED for it.
  *                The tracer fields are read only under SNAP_EOS_MIXTURE with
  *                ntracer > 0 (a nonzero tracer_wt needs the mixture); there the
  *                adjoint and batched entry points return SNAP_E_UNSUPPORTED.
@@ -169,6 +181,7 @@ typedef struct snap_grid {
   double tracer_mu[SNAP_MAX_TRACERS];
   double tracer_wt[SNAP_MAX_TRACERS];
   double rd;
+  int32_t riemann;
 } snap_grid;
 
 /* Thread-local message of the last failed call of this thread ("" if none). */

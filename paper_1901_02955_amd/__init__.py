@@ -27,6 +27,7 @@ __all__ = [
     "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
     "SNAP_EOS_PASSIVE", "SNAP_EOS_MIXTURE", "SNAP_TRACER_VAPOUR", "SNAP_TRACER_CONDENSATE",
+    "SNAP_RIEMANN_LMARS", "SNAP_RIEMANN_HLLC",
     "snap_kessler_step", "kessler_params",
 ]
 
@@ -45,9 +46,11 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 3
+SNAP_ABI_VERSION = 4
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
+SNAP_RIEMANN_LMARS = 0
+SNAP_RIEMANN_HLLC = 1
 SNAP_TRACER_VAPOUR = 0
 SNAP_TRACER_CONDENSATE = 1
 SNAP_OP_RHS = 0
@@ -87,6 +90,7 @@ class SnapGridC(ctypes.Structure):
         ("tracer_sigma", ctypes.c_double * SNAP_MAX_TRACERS),
         ("tracer_mu", ctypes.c_double * SNAP_MAX_TRACERS),
         ("tracer_wt", ctypes.c_double * SNAP_MAX_TRACERS), ("rd", ctypes.c_double),
+        ("riemann", ctypes.c_int32),
     ]
 
 
@@ -180,7 +184,7 @@ class DeviceGrid:
     Built from plain values; ``device_grid`` builds one from any object with
     the same attribute names (nx, ny, nz, dx, dy, dz, gamma, grav, ntracer, bc,
     weno_eps, weno_linear, rhobar_cell, pbar_cell, rhobar_face, pbar_face and,
-    optionally, eos, tracer_kind, tracer_eps, tracer_sigma, tracer_mu, tracer_wt, rd).
+    optionally, eos, tracer_kind, tracer_eps, tracer_sigma, tracer_mu, tracer_wt, rd, riemann).
     """
 
     def __init__(self, nx: int, ny: int, nz: int, dx: float, dy: float, dz: float,
@@ -190,7 +194,8 @@ class DeviceGrid:
                  device: Optional[torch.device] = None, eos: int = SNAP_EOS_PASSIVE,
                  tracer_kind: Sequence[int] = (), tracer_eps: Sequence[float] = (),
                  tracer_sigma: Sequence[float] = (), tracer_mu: Sequence[float] = (),
-                 tracer_wt: Sequence[float] = (), rd: float = 0.0):
+                 tracer_wt: Sequence[float] = (), rd: float = 0.0,
+                 riemann: int = SNAP_RIEMANN_LMARS):
         if dtype not in (torch.float64, torch.float32):
             raise ValueError("dtype must be torch.float64 or torch.float32")
         device = torch.device(device or "cuda")
@@ -221,6 +226,7 @@ class DeviceGrid:
         for t, wt in enumerate(tracer_wt):
             c.tracer_wt[t] = float(wt)
         c.rd = float(rd)
+        c.riemann = int(riemann)
         self.eos = int(eos)
         self.c = c
 
@@ -260,7 +266,8 @@ def device_grid(g, dtype: torch.dtype = torch.float64, device=None) -> DeviceGri
                       eos=getattr(g, "eos", SNAP_EOS_PASSIVE),
                       tracer_kind=getattr(g, "tracer_kind", ()), tracer_eps=getattr(g, "tracer_eps", ()),
                       tracer_sigma=getattr(g, "tracer_sigma", ()), tracer_mu=getattr(g, "tracer_mu", ()),
-                      tracer_wt=getattr(g, "tracer_wt", ()), rd=getattr(g, "rd", 0.0))
+                      tracer_wt=getattr(g, "tracer_wt", ()), rd=getattr(g, "rd", 0.0),
+                      riemann=getattr(g, "riemann", SNAP_RIEMANN_LMARS))
 
 
 def snap_abi_version() -> int:

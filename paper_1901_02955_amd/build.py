@@ -28,7 +28,7 @@ HIPCC_FLAGS = [
 ]
 
 SOURCES = ["snap_api.hip", "snap_aux.hip", "stage_f64.hip", "stage_f32.hip", "stage_mix_f64.hip",
-           "stage_mix_f32.hip", "adjoint_f64.hip", "batch_f64.hip", "batch_f32.hip",
+           "stage_mix_f32.hip", "stage_hllc_f64.hip", "stage_hllc_f32.hip", "adjoint_f64.hip", "batch_f64.hip", "batch_f32.hip",
            "adjoint_f32.hip", "snap_micro.hip"]
 
 

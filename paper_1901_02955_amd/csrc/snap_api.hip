@@ -128,6 +128,9 @@ int check_grid(const snap_grid* g) {
     return fail(SNAP_E_INVALID, "weno_eps must lie in [1e-30, 1e30]");
   if (!g->rhobar_cell || !g->pbar_cell || !g->rhobar_face || !g->pbar_face)
     return fail(SNAP_E_INVALID, "reference profile pointer is NULL");
+  if (g->riemann != SNAP_RIEMANN_LMARS && g->riemann != SNAP_RIEMANN_HLLC)
+    return fail(SNAP_E_INVALID, "riemann must be SNAP_RIEMANN_LMARS or SNAP_RIEMANN_HLLC (got %d)",
+                g->riemann);
   if (g->eos != SNAP_EOS_PASSIVE && g->eos != SNAP_EOS_MIXTURE)
     return fail(SNAP_E_INVALID, "eos must be SNAP_EOS_PASSIVE or SNAP_EOS_MIXTURE (got %d)", g->eos);
   if (g->eos == SNAP_EOS_MIXTURE) {
@@ -149,6 +152,8 @@ int check_grid(const snap_grid* g) {
     if (uses_sediment(g) && !finite_pos(g->rd))
       return fail(SNAP_E_INVALID, "rd must be finite and > 0 when a condensate falls");
   }
+  if (g->riemann == SNAP_RIEMANN_HLLC && uses_mixture(g))
+    return fail(SNAP_E_UNSUPPORTED, "HLLC takes passive tracers (eos = SNAP_EOS_PASSIVE)");
   const double total = (double)padded_cells(g) * nvar_of(g);
   if (total > 9.0e18 / 8.0) return fail(SNAP_E_INVALID, "state too large");
   return SNAP_OK;
@@ -200,21 +205,23 @@ int resident_slots(const snap_grid* g) {
   static std::vector<std::vector<int>> cache;  // [device][key]
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  const int key = ((g->dtype * 2 + (is3d(g) ? 1 : 0)) * 2 + (uses_mixture(g) ? 1 : 0)) * 16 +
-                  g->ntracer;
+  const int kind = uses_mixture(g) ? 1 : (g->riemann == SNAP_RIEMANN_HLLC ? 2 : 0);
+  const int key = ((g->dtype * 2 + (is3d(g) ? 1 : 0)) * 3 + kind) * 16 + g->ntracer;
   std::lock_guard<std::mutex> lk(m);
   if ((int)cache.size() <= dev) cache.resize(dev + 1);
   auto& c = cache[dev];
-  if (c.empty()) c.assign(128, 0);
+  if (c.empty()) c.assign(192, 0);
   if (c[key] == 0) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    const bool mix = uses_mixture(g);
+    const bool d3 = is3d(g);
     int per = g->dtype == SNAP_F64
-                  ? (mix ? occupancy_mix_f64(g->ntracer, is3d(g)) : occupancy_f64(g->ntracer, is3d(g)))
-                  : (mix ? occupancy_mix_f32(g->ntracer, is3d(g)) : occupancy_f32(g->ntracer, is3d(g)));
+                  ? (kind == 1 ? occupancy_mix_f64(g->ntracer, d3)
+                               : kind == 2 ? occupancy_hllc_f64(g->ntracer, d3) : occupancy_f64(g->ntracer, d3))
+                  : (kind == 1 ? occupancy_mix_f32(g->ntracer, d3)
+                               : kind == 2 ? occupancy_hllc_f32(g->ntracer, d3) : occupancy_f32(g->ntracer, d3));
     if (per <= 0) per = 1;
     c[key] = cus * per;
   }
@@ -293,12 +300,14 @@ int run_stage(const snap_grid* g, StageArgs a, hipStream_t st) {
     const int r = timing_mark(st);
     if (r) return r;
   }
-  const bool mix = uses_mixture(g), d3 = is3d(g);
+  const bool mix = uses_mixture(g), hllc = g->riemann == SNAP_RIEMANN_HLLC, d3 = is3d(g);
   const int r = g->dtype == SNAP_F64
                     ? (mix ? launch_stage_mix_f64(g->ntracer, d3, a, nb, st)
-                           : launch_stage_f64(g->ntracer, d3, a, nb, st))
+                           : hllc ? launch_stage_hllc_f64(g->ntracer, d3, a, nb, st)
+                                  : launch_stage_f64(g->ntracer, d3, a, nb, st))
                     : (mix ? launch_stage_mix_f32(g->ntracer, d3, a, nb, st)
-                           : launch_stage_f32(g->ntracer, d3, a, nb, st));
+                           : hllc ? launch_stage_hllc_f32(g->ntracer, d3, a, nb, st)
+                                  : launch_stage_f32(g->ntracer, d3, a, nb, st));
   if (r != 0) return device_fail("stage kernel launch");
   if (timed) {
     const int t = timing_mark(st);
@@ -414,6 +423,8 @@ int check_batch(const snap_grid* gs, int n) {
     if (uses_mixture(&gs[m]))
       return fail(SNAP_E_UNSUPPORTED,
                   "member %d uses the mixture equation of state: the batched step takes passive tracers", m);
+    if (gs[m].riemann != SNAP_RIEMANN_LMARS)
+      return fail(SNAP_E_UNSUPPORTED, "member %d: the batched step takes the LMARS flux", m);
   }
   return SNAP_OK;
 }
@@ -584,6 +595,8 @@ int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_b
   if (q_bar == q || q_bar == rhs_bar) return fail(SNAP_E_INVALID, "q_bar must not alias q or rhs_bar");
   if (uses_mixture(g))
     return fail(SNAP_E_UNSUPPORTED, "the adjoint takes passive tracers (eos = SNAP_EOS_PASSIVE)");
+  if (g->riemann != SNAP_RIEMANN_LMARS)
+    return fail(SNAP_E_UNSUPPORTED, "the adjoint takes the LMARS flux");
   const hipStream_t st = (hipStream_t)stream;
   if ((r = fill(g, q, st))) return r;
   if ((r = run_adj_rhs(g, q, rhs_bar, q_bar, 0, 0.0, 1.0, work, st))) return r;
@@ -598,6 +611,8 @@ int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar,
   if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
   if (uses_mixture(g))
     return fail(SNAP_E_UNSUPPORTED, "the adjoint takes passive tracers (eos = SNAP_EOS_PASSIVE)");
+  if (g->riemann != SNAP_RIEMANN_LMARS)
+    return fail(SNAP_E_UNSUPPORTED, "the adjoint takes the LMARS flux");
   const hipStream_t st = (hipStream_t)stream;
   char* b = static_cast<char*>(work);
   void* q1 = b;

@@ -268,6 +268,58 @@ __device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV],
   f[nrm] += pstar;
 }
 
+// HLLC flux at one face (the Riemann solver the paper compares LMARS with):
+// Davis outer wave speeds S_L = min(u_L - c_L, u_R - c_R), S_R = max(u_L + c_L,
+// u_R + c_R); contact speed S* = (p_R - p_L + d_L u_L - d_R u_R) / (d_L - d_R)
+// with d_K = rho_K (S_K - u_K); flux F_L if 0 <= S_L, F_L + S_L (U*_L - U_L) if
+// S_L < 0 <= S*, F_R + S_R (U*_R - U_R) if S* < 0 < S_R, F_R if S_R <= 0, where
+// U*_K = d_K / (S_K - S*) (1, S* on the normal and the side's tangential
+// velocities, E_K/rho_K + (S* - u_K)(S* + p_K / d_K), q_K). Face states and
+// references as for lmars_flux; the normal momentum flux carries the
+// perturbation pressure (the full flux minus the face reference pressure).
+template <typename T, int NV>
+__device__ __forceinline__ void hllc_flux(const T (&xl)[NV], const T (&xr)[NV], int nrm, T rref,
+                                          T pref, T gamma, T inv_gm1, T (&f)[NV]) {
+  const T rl = rref + xl[0], rr = rref + xr[0];
+  const T pl = pref + xl[4], pr = pref + xr[4];
+  const T unl = nrm == 1 ? xl[1] : (nrm == 2 ? xl[2] : xl[3]);
+  const T unr = nrm == 1 ? xr[1] : (nrm == 2 ? xr[2] : xr[3]);
+  const T cl = sqrt_fast(gamma * pl * rcp_fast(rl));
+  const T cr = sqrt_fast(gamma * pr * rcp_fast(rr));
+  const T SL = fmin(unl - cl, unr - cr), SR = fmax(unl + cl, unr + cr);
+  const T dl = rl * (SL - unl), dr = rr * (SR - unr);
+  const T Ss = (pr - pl + dl * unl - dr * unr) * rcp_fast(dl - dr);
+  // the side whose flux (plain or star) is taken, and whether in the star region
+  const bool left = SL >= T(0) || Ss >= T(0);
+  const bool star = !(SL >= T(0)) && (left || SR > T(0));
+  const T rk = left ? rl : rr, pk = left ? pl : pr, ppk = left ? xl[4] : xr[4];
+  const T uk = left ? xl[1] : xr[1], vk = left ? xl[2] : xr[2], wk = left ? xl[3] : xr[3];
+  const T unk = left ? unl : unr, Sk = left ? SL : SR, dk = left ? dl : dr;
+  const T E = pk * inv_gm1 + T(0.5) * rk * (uk * uk + vk * vk + wk * wk);
+  const T mass = rk * unk;
+  f[0] = mass;
+  f[1] = mass * uk + (nrm == 1 ? ppk : T(0));
+  f[2] = mass * vk + (nrm == 2 ? ppk : T(0));
+  f[3] = mass * wk + (nrm == 3 ? ppk : T(0));
+  f[4] = (E + pk) * unk;
+#pragma unroll
+  for (int t = 5; t < NV; ++t) f[t] = mass * (left ? xl[t] : xr[t]);
+  if (star) {
+    const T fac = dk * rcp_fast(Sk - Ss);
+    const T e_star = fac * (E * rcp_fast(rk) + (Ss - unk) * (Ss + pk * rcp_fast(dk)));
+    f[0] += Sk * (fac - rk);
+    f[1] += Sk * (fac * (nrm == 1 ? Ss : uk) - rk * uk);
+    f[2] += Sk * (fac * (nrm == 2 ? Ss : vk) - rk * vk);
+    f[3] += Sk * (fac * (nrm == 3 ? Ss : wk) - rk * wk);
+    f[4] += Sk * (e_star - E);
+#pragma unroll
+    for (int t = 5; t < NV; ++t) {
+      const T qk = left ? xl[t] : xr[t];
+      f[t] += Sk * (fac - rk) * qk;
+    }
+  }
+}
+
 // LMARS flux with the mixture equation of state: each side's effective
 // gamma - 1 = gm1 n / d with n = 1 + sum a_t q_t, d = 1 + sum b_t q_t of its
 // face mass fractions, so c^2 = (d + gm1 n) p / (d rho); the advected energy

@@ -61,6 +61,8 @@ int occupancy_f64(int ntracer, bool d3);
 int occupancy_f32(int ntracer, bool d3);
 int occupancy_mix_f64(int ntracer, bool d3);
 int occupancy_mix_f32(int ntracer, bool d3);
+int occupancy_hllc_f64(int ntracer, bool d3);
+int occupancy_hllc_f32(int ntracer, bool d3);
 
 struct AdjArgs;
 
@@ -83,6 +85,8 @@ int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t
 int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_mix_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_mix_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+int launch_stage_hllc_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+int launch_stage_hllc_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st);
 int launch_fill_ghosts_batched(int dtype, const GhostDesc* d, int n, long long max_ghosts,
                                hipStream_t st);

@@ -98,12 +98,16 @@ __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off
   for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
 }
 
-// LMARS flux with the kernel's equation of state.
-template <typename T, int NV, bool MIX>
-__device__ __forceinline__ void lmars_flux_eos(const T (&xl)[NV], const T (&xr)[NV], int nrm,
-                                               T rref, T pref, T gamma, T inv_gm1, T gm1,
-                                               const Mixture& mx, T (&f)[NV]) {
-  if constexpr (MIX)
+// Face flux of the kernel's Riemann solver (LMARS, or HLLC with passive
+// tracers) and equation of state.
+template <typename T, int NV, bool MIX, bool HLLC>
+__device__ __forceinline__ void riemann_flux(const T (&xl)[NV], const T (&xr)[NV], int nrm,
+                                             T rref, T pref, T gamma, T inv_gm1, T gm1,
+                                             const Mixture& mx, T (&f)[NV]) {
+  static_assert(!(MIX && HLLC), "HLLC takes passive tracers");
+  if constexpr (HLLC)
+    hllc_flux<T, NV>(xl, xr, nrm, rref, pref, gamma, inv_gm1, f);
+  else if constexpr (MIX)
     lmars_flux_mix<T, NV>(xl, xr, nrm, rref, pref, gm1, mx, f);
   else
     lmars_flux<T, NV>(xl, xr, nrm, rref, pref, gamma, inv_gm1, f);
@@ -248,7 +252,7 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
 // Phase L: LMARS at every face of the tile, by the item that holds its right
 // state. x faces use the reference of their row (xref); second-axis faces use
 // sref(face index).
-template <typename T, int NV, int TX, int TY, bool MIX, typename XRef, typename SRef>
+template <typename T, int NV, int TX, int TY, bool MIX, bool HLLC, typename XRef, typename SRef>
 __device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int h, int snrm,
                                             T gamma, T inv_gm1, T gm1, const Mixture& mx,
                                             XRef xref, SRef sref,
@@ -271,7 +275,7 @@ __device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int 
         xref(jj, rr, pr);
       else
         sref(jj, rr, pr);
-      lmars_flux_eos<T, NV, MIX>(xl, xr, xa ? 1 : snrm, rr, pr, gamma, inv_gm1, gm1, mx, f);
+      riemann_flux<T, NV, MIX, HLLC>(xl, xr, xa ? 1 : snrm, rr, pr, gamma, inv_gm1, gm1, mx, f);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (xa)
@@ -325,7 +329,7 @@ __device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], double rb, doub
   for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
 }
 
-template <typename T, int NT, int TX, int TY, bool MIX = false>
+template <typename T, int NT, int TX, int TY, bool MIX = false, bool HLLC = false>
 __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(StageArgs a) {
   constexpr int NV = 5 + NT;
   using I = PlaneItems<TX, TY>;
@@ -451,8 +455,8 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
         r = rbT;
         p = pbT;
       };
-      phase_lmars<T, NV, TX, TY, MIX>(S, w, h, 2, gamma, inv_gm1, gm1t, a.mix, levref, levref,
-                                      QP);
+      phase_lmars<T, NV, TX, TY, MIX, HLLC>(S, w, h, 2, gamma, inv_gm1, gm1t, a.mix, levref,
+                                            levref, QP);
       __syncthreads();
     }
     // ---- vertical direction, own column: face s+1/2 (z-face index s+1) -------
@@ -469,9 +473,9 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
       }
       if (s >= k0 - 1) {
         T fz[NV];
-        lmars_flux_eos<T, NV, MIX>(qmc, qpn, 3, static_cast<T>(a.rbar_f[s + 1]),
-                                   static_cast<T>(a.pbar_f[s + 1]), gamma, inv_gm1, gm1t, a.mix,
-                                   fz);
+        riemann_flux<T, NV, MIX, HLLC>(qmc, qpn, 3, static_cast<T>(a.rbar_f[s + 1]),
+                                       static_cast<T>(a.pbar_f[s + 1]), gamma, inv_gm1, gm1t,
+                                       a.mix, fz);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           dfz[v] = fz[v] - fzc[v];
@@ -522,7 +526,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 // 2-D (x-z) tile: TX x TZ tile number L of the plane, z is the second in-plane
 // axis. Shared by the single-domain kernel and the batched (ensemble) kernel.
 // ---------------------------------------------------------------------------
-template <typename T, int NT, int TX, int TZ, bool MIX = false>
+template <typename T, int NT, int TX, int TZ, bool MIX = false, bool HLLC = false>
 __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
                                              Plane<T, 5 + NT, TX, TZ>& S) {
   constexpr int NV = 5 + NT;
@@ -575,7 +579,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
     r = static_cast<T>(a.rbar_f[k0 + fk]);
     p = static_cast<T>(a.pbar_f[k0 + fk]);
   };
-  phase_lmars<T, NV, TX, TZ, MIX>(S, w, h, 3, gamma, inv_gm1, gm1t, a.mix, xref, zref, QP);
+  phase_lmars<T, NV, TX, TZ, MIX, HLLC>(S, w, h, 3, gamma, inv_gm1, gm1t, a.mix, xref, zref, QP);
   __syncthreads();
   if (act) {
     T R[NV];
@@ -594,10 +598,10 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
   }
 }
 
-template <typename T, int NT, int TX, int TZ, bool MIX = false>
+template <typename T, int NT, int TX, int TZ, bool MIX = false, bool HLLC = false>
 __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
   __shared__ Plane<T, 5 + NT, TX, TZ> S;
-  stage2d_tile<T, NT, TX, TZ, MIX>(a, xcd_logical_block(blockIdx.x, gridDim.x), S);
+  stage2d_tile<T, NT, TX, TZ, MIX, HLLC>(a, xcd_logical_block(blockIdx.x, gridDim.x), S);
 }
 
 // Ensemble of 2-D domains in one persistent launch: work item w is tile

@@ -25,58 +25,61 @@ struct TileFor {
 };
 
 // MIX: the mixture equation of state (instantiated for NT >= 1 only; with no
-// tracers the mixture is the dry gas).
-template <typename T, int NT, bool MIX>
+// tracers the mixture is the dry gas). HLLC: the HLLC Riemann solver (passive
+// tracers).
+template <typename T, int NT, bool MIX, bool HLLC = false>
 int launch_nt(bool d3, const StageArgs& a, int nblocks, hipStream_t st) {
   constexpr int TX = TileFor<T, NT>::TX, TY = TileFor<T, NT>::TY;
   constexpr bool M = MIX && NT > 0;
   if (d3)
-    hipLaunchKernelGGL((k_stage3d<T, NT, TX, TY, M>), dim3(nblocks), dim3(TX * TY), 0, st, a);
+    hipLaunchKernelGGL((k_stage3d<T, NT, TX, TY, M, HLLC>), dim3(nblocks), dim3(TX * TY), 0, st,
+                       a);
   else
-    hipLaunchKernelGGL((k_stage2d<T, NT, TX, TY, M>), dim3(nblocks), dim3(TX * TY), 0, st, a);
+    hipLaunchKernelGGL((k_stage2d<T, NT, TX, TY, M, HLLC>), dim3(nblocks), dim3(TX * TY), 0, st,
+                       a);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename T, int NT, bool MIX>
+template <typename T, int NT, bool MIX, bool HLLC = false>
 int occupancy_nt(bool d3) {
   constexpr int TX = TileFor<T, NT>::TX, TY = TileFor<T, NT>::TY;
   constexpr bool M = MIX && NT > 0;
   int n = 0;
-  const void* k = d3 ? reinterpret_cast<const void*>(&k_stage3d<T, NT, TX, TY, M>)
-                     : reinterpret_cast<const void*>(&k_stage2d<T, NT, TX, TY, M>);
+  const void* k = d3 ? reinterpret_cast<const void*>(&k_stage3d<T, NT, TX, TY, M, HLLC>)
+                     : reinterpret_cast<const void*>(&k_stage2d<T, NT, TX, TY, M, HLLC>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, TX * TY, 0) != hipSuccess) return 0;
   return n;
 }
 
 // Workgroups of the stage kernel that fit on one compute unit (0 if unknown).
-template <typename T, bool MIX>
+template <typename T, bool MIX, bool HLLC = false>
 int occupancy_t(int ntracer, bool d3) {
   switch (ntracer) {
-    case 0: return occupancy_nt<T, 0, MIX>(d3);
-    case 1: return occupancy_nt<T, 1, MIX>(d3);
-    case 2: return occupancy_nt<T, 2, MIX>(d3);
-    case 3: return occupancy_nt<T, 3, MIX>(d3);
-    case 4: return occupancy_nt<T, 4, MIX>(d3);
-    case 5: return occupancy_nt<T, 5, MIX>(d3);
-    case 6: return occupancy_nt<T, 6, MIX>(d3);
-    case 7: return occupancy_nt<T, 7, MIX>(d3);
-    case 8: return occupancy_nt<T, 8, MIX>(d3);
+    case 0: return occupancy_nt<T, 0, MIX, HLLC>(d3);
+    case 1: return occupancy_nt<T, 1, MIX, HLLC>(d3);
+    case 2: return occupancy_nt<T, 2, MIX, HLLC>(d3);
+    case 3: return occupancy_nt<T, 3, MIX, HLLC>(d3);
+    case 4: return occupancy_nt<T, 4, MIX, HLLC>(d3);
+    case 5: return occupancy_nt<T, 5, MIX, HLLC>(d3);
+    case 6: return occupancy_nt<T, 6, MIX, HLLC>(d3);
+    case 7: return occupancy_nt<T, 7, MIX, HLLC>(d3);
+    case 8: return occupancy_nt<T, 8, MIX, HLLC>(d3);
     default: return 0;
   }
 }
 
-template <typename T, bool MIX>
+template <typename T, bool MIX, bool HLLC = false>
 int launch_stage_t(int ntracer, bool d3, const StageArgs& a, int nblocks, hipStream_t st) {
   switch (ntracer) {
-    case 0: return launch_nt<T, 0, MIX>(d3, a, nblocks, st);
-    case 1: return launch_nt<T, 1, MIX>(d3, a, nblocks, st);
-    case 2: return launch_nt<T, 2, MIX>(d3, a, nblocks, st);
-    case 3: return launch_nt<T, 3, MIX>(d3, a, nblocks, st);
-    case 4: return launch_nt<T, 4, MIX>(d3, a, nblocks, st);
-    case 5: return launch_nt<T, 5, MIX>(d3, a, nblocks, st);
-    case 6: return launch_nt<T, 6, MIX>(d3, a, nblocks, st);
-    case 7: return launch_nt<T, 7, MIX>(d3, a, nblocks, st);
-    case 8: return launch_nt<T, 8, MIX>(d3, a, nblocks, st);
+    case 0: return launch_nt<T, 0, MIX, HLLC>(d3, a, nblocks, st);
+    case 1: return launch_nt<T, 1, MIX, HLLC>(d3, a, nblocks, st);
+    case 2: return launch_nt<T, 2, MIX, HLLC>(d3, a, nblocks, st);
+    case 3: return launch_nt<T, 3, MIX, HLLC>(d3, a, nblocks, st);
+    case 4: return launch_nt<T, 4, MIX, HLLC>(d3, a, nblocks, st);
+    case 5: return launch_nt<T, 5, MIX, HLLC>(d3, a, nblocks, st);
+    case 6: return launch_nt<T, 6, MIX, HLLC>(d3, a, nblocks, st);
+    case 7: return launch_nt<T, 7, MIX, HLLC>(d3, a, nblocks, st);
+    case 8: return launch_nt<T, 8, MIX, HLLC>(d3, a, nblocks, st);
     default: return -1;
   }
 }

@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 3
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 4
 
 
 def good_grid(**kw):
@@ -82,6 +82,7 @@ BAD_GRIDS = [
     dict(eos=1, tracer_mu=(math.nan, 0.0)), dict(eos=1, tracer_mu=(0.0, -math.inf)),
     dict(eos=1, tracer_wt=(0.0, math.nan)), dict(eos=1, tracer_wt=(-5.0, 0.0)),   # a vapour cannot fall
     dict(eos=1, tracer_wt=(0.0, -5.0), rd=0.0), dict(eos=1, tracer_wt=(0.0, -5.0), rd=math.inf),
+    dict(riemann=2), dict(riemann=-1),
 ]
 
 
@@ -293,3 +294,17 @@ def test_kessler_needs_the_mixture_and_valid_scalars():
         assert lib.snap_kessler_step(g, P, dt, ctypes.byref(k), None) == snap.SNAP_E_INVALID
     assert lib.snap_kessler_step(g, None, 1.0, ctypes.byref(k), None) == snap.SNAP_E_INVALID
     assert lib.snap_kessler_step(g, P, 1.0, None, None) == snap.SNAP_E_INVALID
+
+
+def test_hllc_refuses_the_mixture_and_is_refused_by_adjoint_and_batched():
+    lib = snap.lib()
+    P = ctypes.c_void_p(FAKE)
+    Q2, Q3 = ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE)
+    g = ctypes.byref(good_grid(riemann=1))
+    assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) > 0
+    assert lib.snap_rhs_adjoint(g, P, Q2, Q3, P, None) == snap.SNAP_E_UNSUPPORTED
+    assert lib.snap_rk3_step_adjoint(g, P, 0.1, Q2, Q3, None) == snap.SNAP_E_UNSUPPORTED
+    arr = (snap.SnapGridC * 2)(good_grid(ny=1, riemann=1), good_grid(ny=1, riemann=1))
+    assert lib.snap_batched_workspace_bytes(arr, 2) == 0
+    mixed = ctypes.byref(good_grid(riemann=1, eos=1))
+    assert lib.snap_rhs(mixed, P, Q2, None) == snap.SNAP_E_UNSUPPORTED

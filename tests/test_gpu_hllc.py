@@ -1,0 +1,95 @@
+"""GPU parity of the HLLC Riemann solver (the paper's alternative to LMARS)
+against the FP64 CPU oracle, on the passive parity cases: right-hand side
+within 1e-12 per field (FP64) and 1e-4 (FP32 form), three RK3 steps within
+the multi-step bar, and determinism.
+
+In the star region HLLC's fluxes are F + S (U* - U), differences of terms of
+size S U; for a state at rest (the bubble) the mass and energy right-hand
+sides are pure rounding of those terms, so the FP64 bar carries an absolute
+floor at that rounding: 1e-15 c_max max|U_m| / min(dx, dy, dz)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_02955_amd as snap
+import workloads as wl
+from tests import cases as C
+from tests.test_gpu_fp32 import RHS32_TOL
+from tests.test_gpu_parity import TOL64, assert_steps_close, field_errors, rounding_sensitivity
+
+pytestmark = pytest.mark.gpu
+
+HLLC_CASES = ["2d_bubble_64x64", "2d_smooth_37x29_nt3", "2d_reflect_21x19", "2d_thin_19x2",
+              "3d_smooth_35x21x19", "3d_tracers_20x18x24_nt4", "3d_linear_17x9x11",
+              "3d_periodic_z_12x10x14", "3d_small_2x3x4"]
+
+
+@pytest.fixture(scope="module")
+def hcases():
+    out = {}
+    for n in HLLC_CASES:
+        c = C.build_case(n, dict(C.SPECS)[n])
+        out[n] = C.Case(n, c.grid.copy(riemann=wl.RIEMANN_HLLC), c.q, c.dt)
+    return out
+
+
+@pytest.mark.parametrize("name", HLLC_CASES)
+def test_rhs_fp64_hllc(hcases, name):
+    c = hcases[name]
+    print(f"[hllc] rhs fp64 {name}", flush=True)
+    dg = snap.device_grid(c.grid)
+    rhs = torch.empty(dg.interior_shape, dtype=torch.float64, device="cuda")
+    snap.snap_rhs(dg, torch.as_tensor(c.q).cuda(), rhs)
+    got, ref = rhs.cpu().numpy(), oracle.rhs(c.q, c.grid).numpy()
+    qi = c.grid.interior(c.q)
+    cmax = float(np.max(np.sqrt(c.grid.gamma * 0.4 * qi[4] / qi[0]))) * 2.0   # generous c bound
+    dmin = min(c.grid.dx, c.grid.dz, c.grid.dy if c.grid.ny > 1 else c.grid.dx)
+    bad = []
+    for m in range(c.grid.nvar):
+        floor = 1e-15 * cmax * float(np.max(np.abs(qi[m]))) / dmin
+        err = float(np.max(np.abs(got[m] - ref[m])))
+        bar = TOL64 * float(np.max(np.abs(ref[m]))) + floor
+        print(f"   field {m}: error {err:.2e}  bar {bar:.2e}", flush=True)
+        if not err <= bar:
+            bad.append(m)
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("name", ["2d_bubble_64x64", "3d_smooth_35x21x19", "3d_tracers_20x18x24_nt4"])
+def test_rk3_fp64_hllc(hcases, name):
+    c = hcases[name]
+    print(f"[hllc] rk3 fp64 {name}", flush=True)
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    for _ in range(3):
+        snap.snap_rk3_step(dg, qd, c.dt, work)
+    ref, kappa = rounding_sensitivity(c.grid, c.q, c.dt, 3)
+    assert_steps_close(c.grid.interior(qd.cpu().numpy()), ref, kappa, f"hllc {name}")
+
+
+@pytest.mark.parametrize("name", ["2d_smooth_37x29_nt3", "3d_smooth_35x21x19", "3d_tracers_20x18x24_nt4"])
+def test_rhs_fp32_hllc(hcases, name):
+    c = hcases[name]
+    q32 = torch.as_tensor(c.q).float()
+    dg = snap.device_grid(c.grid, dtype=torch.float32)
+    rhs = torch.empty(dg.interior_shape, dtype=torch.float32, device="cuda")
+    snap.snap_rhs(dg, q32.cuda(), rhs)
+    errs = field_errors(rhs.cpu().double().numpy(), oracle.rhs(q32.double().numpy(), c.grid).numpy())
+    print(f"[hllc] fp32 {name}", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= RHS32_TOL for e in errs), errs
+
+
+def test_hllc_differs_from_lmars_and_is_deterministic(hcases):
+    c = hcases["3d_smooth_35x21x19"]
+    qd = torch.as_tensor(c.q).cuda()
+    dh = snap.device_grid(c.grid)
+    dl = snap.device_grid(c.grid.copy(riemann=wl.RIEMANN_LMARS))
+    rh = torch.empty(dh.interior_shape, dtype=torch.float64, device="cuda")
+    rh2, rl = torch.empty_like(rh), torch.empty_like(rh)
+    snap.snap_rhs(dh, qd, rh)
+    snap.snap_rhs(dh, qd, rh2)
+    snap.snap_rhs(dl, qd, rl)
+    assert torch.equal(rh, rh2)
+    assert float((rh[0] - rl[0]).abs().max()) > 1e-3 * float(rl[0].abs().max())
