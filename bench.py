@@ -50,7 +50,8 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X vector FP64 (FMA = 2 flops)
 FP32_PEAK_TFLOPS = 157.3    # MI355X vector FP32 (counts packed FP32, which this build does not emit)
 
 
-def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int, mixture: bool = False) -> int:
+def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int, mixture: bool = False,
+                                     hllc: bool = False) -> int:
     """Floating-point operations of one right-hand side + stage update of one cell.
 
     Counted from the method's formulas (+, -, *, /, sqrt = 1 flop each, a fused
@@ -61,10 +62,14 @@ def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int, mixture: bool = Fa
     combination 4 per variable averaged over the three stages. The mixture
     equation of state adds 6 NT + 2 to conserved -> primitive (chemical
     energy, the two weighted sums, their ratio) and 12 NT + 10 per face (the
-    sums of both sides, their effective gamma and internal energy).
+    sums of both sides, their effective gamma and internal energy). HLLC in
+    place of LMARS costs 66 + 3 NT per face: the two sound speeds and Davis
+    bounds 10, the contact speed 11, the upwind side's physical flux 14 + NT,
+    its star-state correction 31 + 2 NT.
     """
     nv = 5 + ntracer
-    n = (14 + ntracer) + ndir * nv * 78 + ndir * (37 + ntracer) + ndir * 3 * nv + 4 + 4 * nv
+    face = (66 + 3 * ntracer) if hllc else (37 + ntracer)
+    n = (14 + ntracer) + ndir * nv * 78 + ndir * face + ndir * 3 * nv + 4 + 4 * nv
     if mixture and ntracer > 0:
         n += 6 * ntracer + 2 + ndir * (12 * ntracer + 10)
     return n
@@ -110,13 +115,15 @@ def measured_traffic(dtype_name: str):
     return _profile_value(f"bytes_per_launch_{dtype_name}")
 
 
-def run_gpu(dtype, steps: int, warmup: int):
+def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     import torch
 
     import paper_1901_02955_amd as snap
     import workloads as wl
 
     grid, q, _ = wl.convection_3d(NX, NY, NZ)
+    if hllc:
+        grid = grid.copy(riemann=wl.RIEMANN_HLLC)
     dg = snap.device_grid(grid, dtype=dtype)
     qd = torch.as_tensor(q).to(dtype).cuda().contiguous()
     del q
@@ -140,13 +147,13 @@ def run_gpu(dtype, steps: int, warmup: int):
     esize = 8 if dtype == torch.float64 else 4
     nvar = dg.nvar
     bytes_per_launch = 8.0 / 3.0 * nvar * esize * cells
-    flops_per_launch = algorithmic_flops_per_cell_stage(dg.ntracer, 3) * cells
+    flops_per_launch = algorithmic_flops_per_cell_stage(dg.ntracer, 3, hllc=hllc) * cells
     avg_launch_s = stage_ms / 1e3 / max(launches, 1)
     gbs = bytes_per_launch / avg_launch_s / 1e9
     tflops = flops_per_launch / avg_launch_s / 1e12
     name = "f64" if dtype == torch.float64 else "f32"
     peak = FP64_PEAK_TFLOPS if name == "f64" else FP32_PEAK_TFLOPS
-    traffic = measured_traffic(name)
+    traffic = None if hllc else measured_traffic(name)
     res = {
         "value": cells * steps / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
@@ -164,7 +171,7 @@ def run_gpu(dtype, steps: int, warmup: int):
         },
         # VALU instructions issued / (256 CUs x one wave instruction per cycle x
         # active cycles), from the committed SQ_INSTS_VALU / GRBM_GUI_ACTIVE run
-        "valu_utilisation": _profile_value(f"valu_issue_util_{name}"),
+        "valu_utilisation": None if hllc else _profile_value(f"valu_issue_util_{name}"),
         "final_dt": dt,
     }
     del qd, work, cw
@@ -513,6 +520,13 @@ def main():
         out["jovian_mixture"]["cost_vs_passive"] = (out["jovian"]["value"]
                                                     / out["jovian_mixture"]["value"])
         out["jovian_kessler"] = run_jovian_kessler(20, 2)
+        out["hllc"] = {}
+        for name, dt_, ref in (("f64", torch.float64, f64), ("f32", torch.float32, out.get("variants", {}).get("f32"))):
+            h = run_gpu(dt_, 30, 3, hllc=True)
+            out["hllc"][name] = {"value": h["value"], "ms_per_step": h["ms_per_step"],
+                                 "stage_kernel_avg_ms": h["stage_kernel_avg_ms"],
+                                 "roofline": h["roofline"],
+                                 "cost_vs_lmars": (ref["value"] / h["value"]) if ref else None}
         out["ensemble"] = run_ensemble(20)
         out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:
