@@ -207,35 +207,64 @@ __device__ __forceinline__ bool plane_item(int it, int w, int h, bool& xaxis, in
 }
 
 // Phase R: WENO5 of every item cell; left states to LDS, right states kept.
+// An x item reads a row of the plane (stride 1), a second-axis item a column
+// (stride TX + 6), so one code path serves both. With RPF the five stencil
+// values of variable v + 1 are read from LDS before variable v is
+// reconstructed: the LDS latency then overlaps that reconstruction instead of
+// stalling the wave at the start of every variable. RPF is off where those
+// five live values would push the kernel past an occupancy step.
+template <typename T, int NV>
+constexpr bool reconstruct_prefetch() {
+  // single precision with 1 or 8 tracers: 167 -> 178 and 256 -> 257 registers
+  return !(sizeof(T) == 4 && (NV == 6 || NV == 13));
+}
+
 template <typename T, int NV, int TX, int TY>
 __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w, int h, T eps,
                                                   bool linear,
                                                   T (&QP)[PlaneItems<TX, TY>::RREG][NV]) {
   using I = PlaneItems<TX, TY>;
+  constexpr bool RPF = reconstruct_prefetch<T, NV>();
+  constexpr int PV = (TY + 6) * (TX + 6);   // plane stride between variables
+  constexpr int FXV = TY * (TX + 1), FYV = (TY + 1) * TX;
 #pragma unroll
   for (int r = 0; r < I::ROUNDS; ++r) {
     const int it = item_thread<I::NTHR>() + r * I::NTHR;
     bool xa;
     int ii, jj;
     if (it < I::NR && plane_item<TX, TY>(it, w, h, xa, ii, jj)) {
+      const int st = xa ? 1 : TX + 6;
+      const T* src = xa ? &S.P[0][jj + 3][ii + 1] : &S.P[0][jj + 1][ii + 3];
+      T* dst = xa ? &S.FX[0][jj][ii + 1] : &S.FY[0][jj + 1][ii];
+      const int dv = xa ? FXV : FYV;
+      const bool put = xa ? ii < w : jj < h;
       T qp[NV];
-      if (xa) {
+      T cur[5];
+      if constexpr (RPF) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const T* row = &S.P[v][jj + 3][ii + 1];
-          T qm;
-          weno5_cell<T>(row[0], row[1], row[2], row[3], row[4], eps, linear, qm, qp[v]);
-          if (ii < w) S.FX[v][jj][ii + 1] = qm;
-          SNAP_VAR_FENCE();
+        for (int m = 0; m < 5; ++m) cur[m] = src[m * st];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T nxt[5];
+        if constexpr (RPF) {
+          if (v + 1 < NV) {
+#pragma unroll
+            for (int m = 0; m < 5; ++m) nxt[m] = src[(v + 1) * PV + m * st];
+          }
+        } else {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) cur[m] = src[v * PV + m * st];
         }
-      } else {
+        T qm;
+        weno5_cell<T>(cur[0], cur[1], cur[2], cur[3], cur[4], eps, linear, qm, qp[v]);
+        if (put) dst[v * dv] = qm;
+        SNAP_VAR_FENCE();
+        if constexpr (RPF) {
+          if (v + 1 < NV) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          T qm;
-          weno5_cell<T>(S.P[v][jj + 1][ii + 3], S.P[v][jj + 2][ii + 3], S.P[v][jj + 3][ii + 3],
-                        S.P[v][jj + 4][ii + 3], S.P[v][jj + 5][ii + 3], eps, linear, qm, qp[v]);
-          if (jj < h) S.FY[v][jj + 1][ii] = qm;
-          SNAP_VAR_FENCE();
+            for (int m = 0; m < 5; ++m) cur[m] = nxt[m];
+          }
         }
       }
 #pragma unroll
