@@ -151,6 +151,26 @@ __device__ __forceinline__ double sqrt_fast(double y) {
 }
 __device__ __forceinline__ float sqrt_fast(float y) { return y * __builtin_amdgcn_rsqf(y); }
 
+// Sound speed sqrt(gp / rho) from gp = gamma p and the density, written as
+// gp / sqrt(gp rho) so no reciprocal of rho is needed. Double precision
+// refines the hardware reciprocal square root of y = gp rho by two
+// Goldschmidt steps, which carry g -> sqrt(y) and h -> 1 / (2 sqrt(y))
+// together; c = 2 gp h.
+__device__ __forceinline__ double sound_speed(double gp, double rho) {
+  const double y = gp * rho;
+  const double h0 = __builtin_amdgcn_rsq(y);
+  double g = y * h0, h = 0.5 * h0;
+  double e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  e = fma(-g, h, 0.5);
+  h = fma(h, e, h);
+  return (gp + gp) * h;
+}
+__device__ __forceinline__ float sound_speed(float gp, float rho) {
+  return gp * __builtin_amdgcn_rsqf(gp * rho);
+}
+
 // ---------------------------------------------------------------------------
 // Fifth-order WENO of one cell j from v_{j-2}, .., v_{j+2} = a, b, c, d, e.
 //
@@ -166,10 +186,13 @@ __device__ __forceinline__ float sqrt_fast(float y) { return y * __builtin_amdgc
 // fifth-order polynomial interpolant). Nonlinear weights:
 //   w_k = (d_k / s_k^2) / sum_m (d_m / s_m^2),  s_k = eps + beta_k,
 // evaluated as d_k t_k / sum_m d_m t_m with t_k the product of the other two
-// s_m^2. Double precision shares one reciprocal between both faces (s_k^8 is
-// far inside the exponent range for eps >= 1e-30 and beta < 1e30). Single
-// precision first scales the s_k by the power of two of their maximum, which
-// is exact and leaves the weights unchanged while keeping the products in range.
+// s_m^2. The weights depend only on the ratios of the s_k, so the code uses
+// 4 s_k = 4 eps + (13/3) u_k^2 + v_k^2 (beta_k = (13/12) u_k^2 + (1/4) v_k^2):
+// two fused multiply-adds and a product per indicator. Double precision
+// shares one reciprocal between both faces (s_k^8 is far inside the exponent
+// range for eps >= 1e-30 and beta < 1e30). Single precision first scales the
+// s_k by the power of two of their maximum, which is exact and leaves the
+// weights unchanged while keeping the products in range.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool linear, T& qm,
@@ -188,13 +211,13 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool 
     qp = c + (T(0.1) * p0 + T(0.6) * p1 + T(0.3) * p2) * sixth;
     return;
   }
-  const T k13 = T(13) / T(12);
-  const T u0 = da - T(2) * db, v0 = da - T(4) * db;
+  const T k13 = T(13) / T(3), eps4 = T(4) * eps;
+  const T u0 = fma(T(-2), db, da), v0 = fma(T(-4), db, da);
   const T u1 = db + dd, v1 = db - dd;
-  const T u2 = de - T(2) * dd, v2 = de - T(4) * dd;
-  T s0 = eps + (k13 * u0 * u0 + T(0.25) * v0 * v0);
-  T s1 = eps + (k13 * u1 * u1 + T(0.25) * v1 * v1);
-  T s2 = eps + (k13 * u2 * u2 + T(0.25) * v2 * v2);
+  const T u2 = fma(T(-2), dd, de), v2 = fma(T(-4), dd, de);
+  T s0 = fma(v0, v0, fma(k13 * u0, u0, eps4));
+  T s1 = fma(v1, v1, fma(k13 * u1, u1, eps4));
+  T s2 = fma(v2, v2, fma(k13 * u2, u2, eps4));
   if constexpr (sizeof(T) == 4) {
     const float mx = fmaxf(fmaxf(s0, s1), s2);
     const float sc = __builtin_amdgcn_ldexpf(1.0f, -__builtin_amdgcn_frexp_expf(mx));
@@ -245,9 +268,9 @@ __device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV],
   const T rl = rref + xl[0], rr = rref + xr[0];
   const T pl = pref + xl[4], pr = pref + xr[4];
   const T unl = xl[nrm], unr = xr[nrm];
-  const T cl = sqrt_fast(gamma * pl * rcp_fast(rl));
-  const T cr = sqrt_fast(gamma * pr * rcp_fast(rr));
-  const T rc = (T(0.5) * (rl + rr)) * (T(0.5) * (cl + cr));
+  const T cl = sound_speed(gamma * pl, rl);
+  const T cr = sound_speed(gamma * pr, rr);
+  const T rc = T(0.25) * ((rl + rr) * (cl + cr));
   const T pstar = T(0.5) * (xl[4] + xr[4]) - T(0.5) * rc * (unr - unl);
   const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) * (T(0.5) * rcp_fast(rc));
   const bool left = ustar > T(0);
@@ -284,8 +307,8 @@ __device__ __forceinline__ void hllc_flux(const T (&xl)[NV], const T (&xr)[NV], 
   const T pl = pref + xl[4], pr = pref + xr[4];
   const T unl = nrm == 1 ? xl[1] : (nrm == 2 ? xl[2] : xl[3]);
   const T unr = nrm == 1 ? xr[1] : (nrm == 2 ? xr[2] : xr[3]);
-  const T cl = sqrt_fast(gamma * pl * rcp_fast(rl));
-  const T cr = sqrt_fast(gamma * pr * rcp_fast(rr));
+  const T cl = sound_speed(gamma * pl, rl);
+  const T cr = sound_speed(gamma * pr, rr);
   const T SL = fmin(unl - cl, unr - cr), SR = fmax(unl + cl, unr + cr);
   const T dl = rl * (SL - unl), dr = rr * (SR - unr);
   const T Ss = (pr - pl + dl * unl - dr * unr) * rcp_fast(dl - dr);
@@ -348,9 +371,9 @@ __device__ __forceinline__ void lmars_flux_mix(const T (&xl)[NV], const T (&xr)[
     mr += mt * xr[5 + t];
   }
   const T gnl = gm1 * nl, gnr = gm1 * nr;
-  const T cl = sqrt_fast((dl + gnl) * pl * rcp_fast(dl * rl));
-  const T cr = sqrt_fast((dr + gnr) * pr * rcp_fast(dr * rr));
-  const T rc = (T(0.5) * (rl + rr)) * (T(0.5) * (cl + cr));
+  const T cl = sound_speed((dl + gnl) * pl, dl * rl);
+  const T cr = sound_speed((dr + gnr) * pr, dr * rr);
+  const T rc = T(0.25) * ((rl + rr) * (cl + cr));
   const T pstar = T(0.5) * (xl[4] + xr[4]) - T(0.5) * rc * (unr - unl);
   const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) * (T(0.5) * rcp_fast(rc));
   const bool left = ustar > T(0);
