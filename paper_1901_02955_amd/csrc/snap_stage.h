@@ -280,9 +280,12 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
 
 // Phase L: LMARS at every face of the tile, by the item that holds its right
 // state. x faces use the reference of their row (xref); second-axis faces use
-// sref(face index).
-template <typename T, int NV, int TX, int TY, bool MIX, bool HLLC, typename XRef, typename SRef>
-__device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int h, int snrm,
+// sref(face index). SNRM is the index of the second axis's velocity; the flux
+// is called in two branches, each with a constant normal, so that picking the
+// normal velocity and adding p* need no selects over the velocity components.
+template <typename T, int NV, int TX, int TY, int SNRM, bool MIX, bool HLLC, typename XRef,
+          typename SRef>
+__device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int h,
                                             T gamma, T inv_gm1, T gm1, const Mixture& mx,
                                             XRef xref, SRef sref,
                                             const T (&QP)[PlaneItems<TX, TY>::RREG][NV]) {
@@ -300,11 +303,13 @@ __device__ __forceinline__ void phase_lmars(Plane<T, NV, TX, TY>& S, int w, int 
         xl[v] = xa ? S.FX[v][jj][ii] : S.FY[v][jj][ii];
       }
       T rr, pr;
-      if (xa)
+      if (xa) {
         xref(jj, rr, pr);
-      else
+        riemann_flux<T, NV, MIX, HLLC>(xl, xr, 1, rr, pr, gamma, inv_gm1, gm1, mx, f);
+      } else {
         sref(jj, rr, pr);
-      riemann_flux<T, NV, MIX, HLLC>(xl, xr, xa ? 1 : snrm, rr, pr, gamma, inv_gm1, gm1, mx, f);
+        riemann_flux<T, NV, MIX, HLLC>(xl, xr, SNRM, rr, pr, gamma, inv_gm1, gm1, mx, f);
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (xa)
@@ -484,7 +489,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
         r = rbT;
         p = pbT;
       };
-      phase_lmars<T, NV, TX, TY, MIX, HLLC>(S, w, h, 2, gamma, inv_gm1, gm1t, a.mix, levref,
+      phase_lmars<T, NV, TX, TY, 2, MIX, HLLC>(S, w, h, gamma, inv_gm1, gm1t, a.mix, levref,
                                             levref, QP);
       __syncthreads();
     }
@@ -608,7 +613,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
     r = static_cast<T>(a.rbar_f[k0 + fk]);
     p = static_cast<T>(a.pbar_f[k0 + fk]);
   };
-  phase_lmars<T, NV, TX, TZ, MIX, HLLC>(S, w, h, 3, gamma, inv_gm1, gm1t, a.mix, xref, zref, QP);
+  phase_lmars<T, NV, TX, TZ, 3, MIX, HLLC>(S, w, h, gamma, inv_gm1, gm1t, a.mix, xref, zref, QP);
   __syncthreads();
   if (act) {
     T R[NV];
