@@ -74,9 +74,10 @@ __device__ __forceinline__ long long padded_off(const AdjArgs& a, int i, int j, 
 // weno5_cell). weno5_lin returns both face values and keeps the forward
 // quantities the linearisation needs; weno5_rev maps the cotangents gm of qm
 // and gp of qp back to the five inputs a..e.
-// The smoothness sums s_k = eps + beta_k are scaled by a common power of two
-// (exact; the normalised weights do not depend on it) so that the products
-// of squared sums below stay in range in single precision.
+// As in weno5_cell the smoothness sums are formed as 4 s_k = 4 eps + (13/3)
+// u_k^2 + v_k^2 (the normalised weights depend only on their ratios), and
+// they are scaled by a common power of two (exact) so that the products of
+// squared sums below stay in range in single precision.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct WenoLin {
@@ -97,13 +98,13 @@ __device__ __forceinline__ void weno5_lin(T a, T b, T c, T d, T e, T eps, bool l
     qp = c + (T(0.1) * p0 + T(0.6) * p1 + T(0.3) * p2) * sixth;
     return;
   }
-  const T k13 = T(13) / T(12);
-  const T u0 = da - T(2) * db, v0 = da - T(4) * db;
+  const T k13 = T(13) / T(3), eps4 = T(4) * eps;
+  const T u0 = fma(T(-2), db, da), v0 = fma(T(-4), db, da);
   const T u1 = db + dd, v1 = db - dd;
-  const T u2 = de - T(2) * dd, v2 = de - T(4) * dd;
-  T s0 = eps + (k13 * u0 * u0 + T(0.25) * v0 * v0);
-  T s1 = eps + (k13 * u1 * u1 + T(0.25) * v1 * v1);
-  T s2 = eps + (k13 * u2 * u2 + T(0.25) * v2 * v2);
+  const T u2 = fma(T(-2), dd, de), v2 = fma(T(-4), dd, de);
+  T s0 = fma(v0, v0, fma(k13 * u0, u0, eps4));
+  T s1 = fma(v1, v1, fma(k13 * u1, u1, eps4));
+  T s2 = fma(v2, v2, fma(k13 * u2, u2, eps4));
   T sc;
   if constexpr (sizeof(T) == 4) {
     const float mx = fmaxf(fmaxf(s0, s1), s2);
@@ -173,19 +174,19 @@ __device__ __forceinline__ void weno5_rev(T a, T b, T c, T d, T e, bool linear,
     const T qb0 = tb1 * q2 + tb2 * q1;
     const T qb1 = tb0 * q2 + tb2 * q0;
     const T qb2 = tb0 * q1 + tb1 * q0;
-    // cotangent of beta_k (that of the unscaled s_k): sc * 2 s'_k * qb_k,
-    // times d beta / d u = 2 (13/12) u and d beta / d v = v / 2
+    // cotangent of the unscaled 4 s_k: sc * 2 s'_k * qb_k (s'_k the scaled
+    // sum kept by the forward), times d(4 s)/du = (26/3) u and d(4 s)/dv = 2 v
     const T two_sc = T(2) * L.sc;
     const T bb0 = two_sc * L.s0 * qb0;
     const T bb1 = two_sc * L.s1 * qb1;
     const T bb2 = two_sc * L.s2 * qb2;
-    const T k136 = T(13) / T(6);
-    ub0 = k136 * (da - T(2) * db) * bb0;
-    vb0 = T(0.5) * (da - T(4) * db) * bb0;
-    ub1 = k136 * (db + dd) * bb1;
-    vb1 = T(0.5) * (db - dd) * bb1;
-    ub2 = k136 * (de - T(2) * dd) * bb2;
-    vb2 = T(0.5) * (de - T(4) * dd) * bb2;
+    const T k263 = T(26) / T(3);
+    ub0 = k263 * fma(T(-2), db, da) * bb0;
+    vb0 = T(2) * fma(T(-4), db, da) * bb0;
+    ub1 = k263 * (db + dd) * bb1;
+    vb1 = T(2) * (db - dd) * bb1;
+    ub2 = k263 * fma(T(-2), dd, de) * bb2;
+    vb2 = T(2) * fma(T(-4), dd, de) * bb2;
   }
   const T dab = T(2) * mb0 - pb2 + ub0 + vb0;
   const T dbb = -T(7) * mb0 - mb1 + T(2) * pb1 + T(5) * pb2 - T(2) * ub0 - T(4) * vb0 + ub1 + vb1;
@@ -211,8 +212,8 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
   const T rl = rref + xl[0], rr = rref + xr[0];
   const T pl = pref + xl[4], pr = pref + xr[4];
   const T unl = xl[nrm], unr = xr[nrm];
-  const T irl = rcp_fast(rl), irr = rcp_fast(rr);
-  const T cl = sqrt_fast(gamma * pl * irl), cr = sqrt_fast(gamma * pr * irr);
+  T hl, hr;   // 1 / sqrt(gamma p rho) of each side
+  const T cl = sound_speed_h(gamma * pl, rl, hl), cr = sound_speed_h(gamma * pr, rr, hr);
   const T ra = T(0.5) * (rl + rr), ca = T(0.5) * (cl + cr);
   const T rc = ra * ca;
   const T hh = T(0.5) * rcp_fast(rc);
@@ -282,12 +283,13 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
   const T rab = rcb * ca, cab = rcb * ra;
   T rlb = T(0.5) * rab, rrb = T(0.5) * rab;
   const T clb = T(0.5) * cab, crb = T(0.5) * cab;
-  // c = sqrt(gamma p / rho): dc/dp = c / (2p) = gamma / (2 rho c), dc/drho = -c / (2 rho)
-  const T hcl = T(0.5) * clb * irl, hcr = T(0.5) * crb * irr;
-  xlb[4] += hcl * gamma * rcp_fast(cl);
-  rlb += -hcl * cl;
-  xrb[4] += hcr * gamma * rcp_fast(cr);
-  rrb += -hcr * cr;
+  // c = gamma p h with h = 1 / sqrt(gamma p rho) = 1 / (rho c):
+  // dc/dp = gamma / (2 rho c) = gamma h / 2, dc/drho = -c / (2 rho) = -c^2 h / 2
+  const T hcl = T(0.5) * clb * hl, hcr = T(0.5) * crb * hr;
+  xlb[4] += hcl * gamma;
+  rlb += -hcl * cl * cl;
+  xrb[4] += hcr * gamma;
+  rrb += -hcr * cr * cr;
   xlb[0] += rlb;
   xrb[0] += rrb;
 }

@@ -152,23 +152,30 @@ __device__ __forceinline__ double sqrt_fast(double y) {
 __device__ __forceinline__ float sqrt_fast(float y) { return y * __builtin_amdgcn_rsqf(y); }
 
 // Sound speed sqrt(gp / rho) from gp = gamma p and the density, written as
-// gp / sqrt(gp rho) so no reciprocal of rho is needed. Double precision
-// refines the hardware reciprocal square root of y = gp rho by two
-// Goldschmidt steps, which carry g -> sqrt(y) and h -> 1 / (2 sqrt(y))
-// together; c = 2 gp h.
-__device__ __forceinline__ double sound_speed(double gp, double rho) {
+// gp h with h = 1 / sqrt(gp rho) (which is also 1 / (rho c)), so no
+// reciprocal of rho is needed. Double precision refines the hardware
+// reciprocal square root of y = gp rho by two Goldschmidt steps, which carry
+// g -> sqrt(y) and k -> 1 / (2 sqrt(y)) together; h = 2 k.
+__device__ __forceinline__ double sound_speed_h(double gp, double rho, double& h) {
   const double y = gp * rho;
   const double h0 = __builtin_amdgcn_rsq(y);
-  double g = y * h0, h = 0.5 * h0;
-  double e = fma(-g, h, 0.5);
+  double g = y * h0, k = 0.5 * h0;
+  double e = fma(-g, k, 0.5);
   g = fma(g, e, g);
-  h = fma(h, e, h);
-  e = fma(-g, h, 0.5);
-  h = fma(h, e, h);
-  return (gp + gp) * h;
+  k = fma(k, e, k);
+  e = fma(-g, k, 0.5);
+  k = fma(k, e, k);
+  h = k + k;
+  return gp * h;
 }
-__device__ __forceinline__ float sound_speed(float gp, float rho) {
-  return gp * __builtin_amdgcn_rsqf(gp * rho);
+__device__ __forceinline__ float sound_speed_h(float gp, float rho, float& h) {
+  h = __builtin_amdgcn_rsqf(gp * rho);
+  return gp * h;
+}
+template <typename T>
+__device__ __forceinline__ T sound_speed(T gp, T rho) {
+  T h;
+  return sound_speed_h(gp, rho, h);
 }
 
 // ---------------------------------------------------------------------------
