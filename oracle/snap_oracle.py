@@ -654,6 +654,87 @@ def kessler_step(q, grid, dt: float, kessler) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------------------
+# Saturation adjustment (App. D): phase equilibrium at constant volume
+# ---------------------------------------------------------------------------
+
+def vapour_gas_constant(grid, sp, rd: float) -> float:
+    """R_v = R_d / eps_v (eps_v: the vapour's molar mass over the dry gas's)."""
+    return rd / grid.tracer_eps[sp.vapour]
+
+
+def temperature_from_energy(qi, grid, rd: float, ek) -> torch.Tensor:
+    """T = (E - K - sum_t mu_t rho_t) / (c_vd (rho_d + sum_t sigma_t rho_t))
+    of interior fields qi, given ek = E - K (Sec. 2, eqs. energy and eos)."""
+    nt = grid.ntracer
+    cvd = rd / (grid.gamma - 1.0)
+    a = sum(grid.tracer_mu[t] * qi[5 + t] for t in range(nt))
+    c = qi[0] - sum(qi[5 + t] for t in range(nt)) + sum(grid.tracer_sigma[t] * qi[5 + t]
+                                                        for t in range(nt))
+    return (ek - a) / (cvd * c)
+
+
+def transfer_bounds(rho_v, rho_c):
+    """Limits of the mass moved from vapour to cloud: all cloud evaporated
+    (-rho_c) to all vapour condensed (rho_v)."""
+    return -rho_c, rho_v.clone()
+
+
+def saturation_adjust(q, grid, adjust, sweeps: int = 40, bisections: int = 90) -> torch.Tensor:
+    """Padded state after saturation adjustment: every vapour brought to phase
+    equilibrium with its cloud at constant volume and constant total energy
+    (App. D; Sec. 2, eqs. energy and eos for the temperature).
+
+    Plain definition, per cell and vapour / cloud pair: the mass x moved from
+    vapour to cloud (negative: cloud evaporated), -rho_c <= x <= rho_v, such
+    that the vapour's partial pressure equals the saturation vapour pressure
+    at the resulting temperature,
+        (rho_v - x) (R_d / eps_v) T(x) = p*(T(x)),
+    where T follows from the conserved energy and the new composition,
+        T = (E - K - sum_t mu_t rho_t) / (c_vd (rho_d + sum_t sigma_t rho_t));
+    if the vapour stays below saturation even with all cloud evaporated,
+    x = -rho_c. The residual decreases with x (the vapour pressure falls and
+    the latent heat raises p*), so each pair's equation is solved by
+    bisection; the pairs interact through the temperature and are swept in
+    turn until no transfer changes. Density, momentum and total energy are
+    unchanged.
+    """
+    q = _t(q).clone()
+    qi = _interior(q, grid)
+    ek = qi[4] - 0.5 * (qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]) / qi[0]
+    for _ in range(sweeps):
+        moved = 0.0
+        for sp in adjust.species:
+            v, c = 5 + sp.vapour, 5 + sp.cloud
+            rv0, rc0 = qi[v].clone(), qi[c].clone()
+            r_vap = vapour_gas_constant(grid, sp, adjust.rd)
+
+            def resid(x):
+                qi[v] = rv0 - x
+                qi[c] = rc0 + x
+                T = temperature_from_energy(qi, grid, adjust.rd, ek)
+                return (rv0 - x) * r_vap * T - saturation_vapour_pressure(T, sp)
+
+            lo, hi = transfer_bounds(rv0, rc0)
+            f_lo = resid(lo)
+            a, b = lo.clone(), hi.clone()
+            for _ in range(bisections):
+                mid = 0.5 * (a + b)
+                above = resid(mid) > 0.0
+                a = torch.where(above, mid, a)
+                b = torch.where(above, b, mid)
+            x = torch.where(f_lo <= 0.0, lo, 0.5 * (a + b))
+            qi[v] = rv0 - x
+            qi[c] = rc0 + x
+            tot = rv0 + rc0
+            rel = torch.where(tot > 0, x.abs() / torch.where(tot > 0, tot, torch.ones_like(tot)),
+                              torch.zeros_like(tot))
+            moved = max(moved, float(rel.max()))
+        if moved <= 1e-15:
+            break
+    return q
+
+
+# ---------------------------------------------------------------------------
 # Discrete adjoint (torch autograd through the oracle)
 # ---------------------------------------------------------------------------
 

@@ -324,3 +324,40 @@ def test_star_momentum_with_side_velocity_breaks_fan_conservation(monkeypatch):
     monkeypatch.setattr(O, "hllc_star", bad)
     with pytest.raises(AssertionError):
         TH.test_star_states_conserve_across_the_fan()
+
+
+# --- saturation adjustment ---------------------------------------------------
+
+def _satadj_pins():
+    from tests import test_oracle_satadj as TS
+    return TS
+
+
+def test_vapour_with_the_dry_gas_constant_breaks_equilibrium_pin(monkeypatch):
+    TS = _satadj_pins()
+    monkeypatch.setattr(O, "vapour_gas_constant", lambda grid, sp, rd: rd)
+    with pytest.raises(AssertionError):
+        TS.test_result_is_in_phase_equilibrium()
+
+
+def test_temperature_without_latent_heat_breaks_paper_iteration_pin(monkeypatch):
+    TS = _satadj_pins()
+    orig = O.temperature_from_energy
+    frozen = {}
+
+    def held(qi, grid, rd, ek):
+        key = id(ek)
+        if key not in frozen:
+            frozen[key] = orig(qi, grid, rd, ek)   # the temperature before any transfer
+        return frozen[key]
+    monkeypatch.setattr(O, "temperature_from_energy", held)
+    with pytest.raises(AssertionError):
+        TS.test_paper_iteration_reaches_the_oracles_equilibrium()
+
+
+def test_cloud_that_cannot_evaporate_breaks_equilibrium_pin(monkeypatch):
+    TS = _satadj_pins()
+    monkeypatch.setattr(O, "transfer_bounds", lambda rv, rc: (torch.zeros_like(rc), rv.clone()))
+    with pytest.raises(AssertionError):
+        TS.test_result_is_in_phase_equilibrium()
+

@@ -472,6 +472,44 @@ class Kessler:
     tol: float = 1e-14
 
 
+@dataclasses.dataclass(frozen=True)
+class SatAdjSpecies:
+    """One vapour / cloud pair of the saturation adjustment (App. D): tracer
+    indices of the vapour and of its cloud, and the saturation vapour pressure
+    over the cloud p* = p_ref exp[beta (1 - 1/t) - delta ln t], t = T / t_ref."""
+    vapour: int
+    cloud: int
+    p_ref: float
+    t_ref: float
+    beta: float
+    delta: float
+
+
+@dataclasses.dataclass(frozen=True)
+class SatAdjust:
+    """Saturation adjustment of a grid: its vapour / cloud pairs, the dry gas
+    constant, and the stopping rule (a transfer below ``tol`` times the pair's
+    total density, at most ``max_iter`` sweeps over the pairs)."""
+    species: Tuple[SatAdjSpecies, ...]
+    rd: float
+    max_iter: int = 20
+    tol: float = 1e-14
+
+
+def saturation_tracers(cvd: float, mu_dry: float, rd: float, species=(WATER, AMMONIA)):
+    """Tracer table [vapours, clouds] of ``species`` and their saturation
+    adjustment parameters."""
+    n = len(species)
+    table = [_vapour(sp, cvd, mu_dry) for sp in species] + [_condensate(sp, cvd) for sp in species]
+    pairs = []
+    for i, sp in enumerate(species):
+        beta, delta = clausius_clapeyron(sp["latent"], sp["c_cond"] - sp["cp_vap"],
+                                         RGAS / sp["molar"], sp["t_ref"])
+        pairs.append(SatAdjSpecies(vapour=i, cloud=n + i, p_ref=sp["p_ref"], t_ref=sp["t_ref"],
+                                   beta=beta, delta=delta))
+    return tuple(table), SatAdjust(species=tuple(pairs), rd=rd)
+
+
 def clausius_clapeyron(latent_ref: float, dc: float, r_vap: float, t_ref: float):
     """(beta, delta) of App. D from the latent heat at t_ref, c_cond - c_p,vap and R_vap."""
     return (latent_ref + dc * t_ref) / (r_vap * t_ref), dc / r_vap
@@ -500,6 +538,29 @@ def jovian_kessler_3d(nx=512, ny=512, nz=256, seed_q=2, seed_theta=3, sediment=F
         g6 = g6.copy(tracer_wt=(0.0, 0.0, 0.0, 0.0, -8.0, -5.0), rd=base.rd)
     q6 = state_from_primitives(g6, rho, 0.0, 0.0, 0.0, p, vap + seeds)
     return g6, q6, kes
+
+
+def jovian_satadj_3d(nx=512, ny=512, nz=256, seed_q=2, seed_theta=3, **kw):
+    """The Jovian-like column with water and ammonia vapour and cloud under
+    the mixture equation of state (4 tracers), vapour supersaturated up to
+    20 km above each condensation level and clouds seeded, and the saturation
+    adjustment parameters of the two species: (grid, state, SatAdjust)."""
+    base = jovian_base()
+    grid, q = jovian_3d(nx=nx, ny=ny, nz=nz, seed_q=seed_q, seed_theta=seed_theta, **kw)
+    table, adj = saturation_tracers(base.cp - base.rd, JOVIAN_MU, base.rd)
+    g4 = with_mixture(grid, table)
+    rho = grid.interior(q)[0]
+    p = rest_fields(grid)[1]
+    shp = rho.shape
+    zc = cell_centres(nz, grid.dz)[:, None, None]
+    rng = np.random.default_rng(seed_q + 200)
+    vap = []
+    for pc_ in (7e5, 0.7e5):
+        qv = 10.0 ** rng.uniform(-3.0, -0.9, size=shp)
+        vap.append(np.where(zc < base.z_of_pressure(pc_) + 20e3, qv, 0.0))
+    clouds = [10.0 ** rng.uniform(-6.0, -4.0, size=shp) for _ in range(2)]
+    q4 = state_from_primitives(g4, rho, 0.0, 0.0, 0.0, p, vap + clouds)
+    return g4, q4, adj
 
 
 ENSEMBLE_SIZES = ((128, 128), (256, 128), (384, 192), (512, 256))
