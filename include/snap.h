@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 4
+#define SNAP_ABI_VERSION 5
 
 /* return codes */
 #define SNAP_OK 0
@@ -357,6 +357,57 @@ typedef struct snap_kessler {
 } snap_kessler;
 
 int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler* k, void* stream);
+
+/*
+ * Saturation adjustment (App. D), the alternative to the Kessler scheme for
+ * instantaneous condensation: every vapour is brought to phase equilibrium
+ * with its cloud at constant volume and constant total energy.
+ *
+ * Per cell and vapour / cloud pair the mass x moved from vapour to cloud
+ * (negative: cloud evaporated), -rho_c <= x <= rho_v, solves
+ *   (rho_v - x) R_v T(x) = p*(T(x)),  R_v = rd / eps_v,
+ * with the saturation vapour pressure over the cloud p* = p_ref exp[beta (1 -
+ * 1/t) - delta ln t], t = T / t_ref (App. D), and the temperature of the
+ * adjusted composition from the conserved energy (Sec. 2, eqs. energy and eos):
+ *   T = (E - K - sum_t mu_t rho_t) / (c_vd (rho_d + sum_t sigma_t rho_t)),
+ *   c_vd = rd / (gamma - 1);
+ * if the vapour stays below saturation with all cloud evaporated, x = -rho_c.
+ * The pairs interact through T: each sweep takes, pair by pair, one Newton
+ * step on the residual above with the latent heating in its derivative
+ * (dT/dx = L_v / (c_vd (rho_d + sum sigma rho)), L_v the latent heat at
+ * constant volume), clipped to the limits; the sweeps stop when no step
+ * exceeds tol times its pair's total density, or after max_iter sweeps. The
+ * paper's own update (eq. dxf with the isochoric alpha) is a Newton-like step
+ * on the same condition in molar mixing ratios with an approximate
+ * derivative; both have the same fixed point. Total density, momentum and
+ * total energy are unchanged; the arithmetic is double precision whatever
+ * the storage type.
+ *
+ * g      grid with eos = SNAP_EOS_MIXTURE: vapours of kind SNAP_TRACER_VAPOUR,
+ *        clouds of kind SNAP_TRACER_CONDENSATE.
+ * q      padded state, interior updated in place (ghost layers untouched).
+ * s      HOST parameters; nspecies in 1 .. SNAP_SATADJ_MAX_SPECIES, tracer
+ *        indices in [0, ntracer) and all distinct; p_ref, t_ref, rd finite
+ *        > 0; beta, delta finite; max_iter in 1 .. 100; tol finite >= 0.
+ * Returns SNAP_E_INVALID for any other input; no workspace is needed.
+ */
+#define SNAP_SATADJ_MAX_SPECIES (SNAP_MAX_TRACERS / 2)
+
+typedef struct snap_satadj_species {
+  int32_t vapour, cloud;  /* tracer indices */
+  double p_ref, t_ref;    /* saturation vapour pressure (Pa) at t_ref (K) */
+  double beta, delta;     /* (L^r + dc t_ref) / (R_v t_ref) and dc / R_v, dc = c_cloud - c_p,vapour */
+} snap_satadj_species;
+
+typedef struct snap_satadj {
+  int32_t nspecies;
+  snap_satadj_species species[SNAP_SATADJ_MAX_SPECIES];
+  double rd;        /* gas constant of the dry gas, J/kg/K */
+  int32_t max_iter; /* sweeps over the pairs at most */
+  double tol;       /* stop when no step exceeds tol x its pair's total density */
+} snap_satadj;
+
+int snap_saturation_adjust(const snap_grid* g, void* q, const snap_satadj* s, void* stream);
 
 /*
  * Benchmark instrumentation of the fused stage kernel (the kernel that

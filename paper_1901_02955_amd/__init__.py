@@ -28,7 +28,7 @@ __all__ = [
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
     "SNAP_EOS_PASSIVE", "SNAP_EOS_MIXTURE", "SNAP_TRACER_VAPOUR", "SNAP_TRACER_CONDENSATE",
     "SNAP_RIEMANN_LMARS", "SNAP_RIEMANN_HLLC",
-    "snap_kessler_step", "kessler_params",
+    "snap_kessler_step", "kessler_params", "snap_saturation_adjust", "satadj_params",
 ]
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -46,7 +46,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 4
+SNAP_ABI_VERSION = 5
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
@@ -116,6 +116,27 @@ class SnapKesslerC(ctypes.Structure):
     ]
 
 
+SNAP_SATADJ_MAX_SPECIES = SNAP_MAX_TRACERS // 2
+
+
+class SnapSatAdjSpeciesC(ctypes.Structure):
+    """Mirror of ``snap_satadj_species`` in include/snap.h."""
+    _fields_ = [
+        ("vapour", ctypes.c_int32), ("cloud", ctypes.c_int32),
+        ("p_ref", ctypes.c_double), ("t_ref", ctypes.c_double),
+        ("beta", ctypes.c_double), ("delta", ctypes.c_double),
+    ]
+
+
+class SnapSatAdjC(ctypes.Structure):
+    """Mirror of ``snap_satadj`` in include/snap.h."""
+    _fields_ = [
+        ("nspecies", ctypes.c_int32),
+        ("species", SnapSatAdjSpeciesC * SNAP_SATADJ_MAX_SPECIES),
+        ("rd", ctypes.c_double), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+    ]
+
+
 _P = ctypes.c_void_p
 _GP = ctypes.POINTER(SnapGridC)
 _SIGNATURES = {
@@ -137,6 +158,7 @@ _SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                              ctypes.c_int, _P, _P]),
     "snap_kessler_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, ctypes.POINTER(SnapKesslerC), _P]),
+    "snap_saturation_adjust": (ctypes.c_int, [_GP, _P, ctypes.POINTER(SnapSatAdjC), _P]),
     "snap_stage_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "snap_stage_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),
@@ -430,3 +452,26 @@ def snap_kessler_step(grid: DeviceGrid, q: torch.Tensor, dt: float, kessler, str
     _check(lib().snap_kessler_step(grid.ptr(), ctypes.c_void_p(q.data_ptr()), ctypes.c_double(dt),
                                    ctypes.byref(params), _stream(stream)))
 
+
+def satadj_params(adj) -> SnapSatAdjC:
+    """``snap_satadj`` from any object with ``species`` (each with vapour, cloud,
+    p_ref, t_ref, beta, delta), ``rd``, ``max_iter`` and ``tol``."""
+    c = SnapSatAdjC()
+    if len(adj.species) > SNAP_SATADJ_MAX_SPECIES:
+        raise ValueError(f"at most {SNAP_SATADJ_MAX_SPECIES} species")
+    c.nspecies = len(adj.species)
+    for i, sp in enumerate(adj.species):
+        d = c.species[i]
+        d.vapour, d.cloud = int(sp.vapour), int(sp.cloud)
+        d.p_ref, d.t_ref = float(sp.p_ref), float(sp.t_ref)
+        d.beta, d.delta = float(sp.beta), float(sp.delta)
+    c.rd, c.max_iter, c.tol = float(adj.rd), int(adj.max_iter), float(adj.tol)
+    return c
+
+
+def snap_saturation_adjust(grid: DeviceGrid, q: torch.Tensor, adjust, stream=None) -> None:
+    """Saturation adjustment of the interior of q (in place)."""
+    grid._check_state(q)
+    params = adjust if isinstance(adjust, SnapSatAdjC) else satadj_params(adjust)
+    _check(lib().snap_saturation_adjust(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
+                                        ctypes.byref(params), _stream(stream)))

@@ -823,6 +823,69 @@ int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler
   return ok();
 }
 
+int snap_saturation_adjust(const snap_grid* g, void* q, const snap_satadj* sa, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !sa) return fail(SNAP_E_INVALID, "q or s is NULL");
+  if (!uses_mixture(g))
+    return fail(SNAP_E_INVALID, "the adjustment needs eos = SNAP_EOS_MIXTURE and tracers");
+  if (sa->nspecies < 1 || sa->nspecies > SNAP_SATADJ_MAX_SPECIES)
+    return fail(SNAP_E_INVALID, "nspecies must lie in [1, %d]", SNAP_SATADJ_MAX_SPECIES);
+  if (!finite_pos(sa->rd)) return fail(SNAP_E_INVALID, "rd must be finite and > 0");
+  if (sa->max_iter < 1 || sa->max_iter > 100) return fail(SNAP_E_INVALID, "max_iter must lie in [1, 100]");
+  if (!isfinite(sa->tol) || sa->tol < 0.0) return fail(SNAP_E_INVALID, "tol must be finite and >= 0");
+  SatAdjArgs a;
+  memset(&a, 0, sizeof a);
+  bool used[SNAP_MAX_TRACERS] = {false};
+  for (int sidx = 0; sidx < sa->nspecies; ++sidx) {
+    const snap_satadj_species& sp = sa->species[sidx];
+    const int idx[2] = {sp.vapour, sp.cloud};
+    for (int m = 0; m < 2; ++m) {
+      if (idx[m] < 0 || idx[m] >= g->ntracer)
+        return fail(SNAP_E_INVALID, "species %d: tracer index %d outside [0, %d)", sidx, idx[m], g->ntracer);
+      if (used[idx[m]]) return fail(SNAP_E_INVALID, "species %d: tracer %d used twice", sidx, idx[m]);
+      used[idx[m]] = true;
+      const int want = m == 0 ? SNAP_TRACER_VAPOUR : SNAP_TRACER_CONDENSATE;
+      if (g->tracer_kind[idx[m]] != want)
+        return fail(SNAP_E_INVALID, "species %d: tracer %d must be a %s", sidx, idx[m],
+                    m == 0 ? "vapour" : "condensate");
+    }
+    if (!finite_pos(sp.p_ref) || !finite_pos(sp.t_ref))
+      return fail(SNAP_E_INVALID, "species %d: p_ref and t_ref must be finite and > 0", sidx);
+    if (!isfinite(sp.beta) || !isfinite(sp.delta))
+      return fail(SNAP_E_INVALID, "species %d: beta and delta must be finite", sidx);
+    SatAdjSpec& d = a.s[sidx];
+    d.v = sp.vapour;
+    d.c = sp.cloud;
+    d.p_ref = sp.p_ref;
+    d.t_ref = sp.t_ref;
+    d.beta = sp.beta;
+    d.delta = sp.delta;
+    d.rv = sa->rd / g->tracer_eps[sp.vapour];
+  }
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.nspecies = sa->nspecies;
+  a.max_iter = sa->max_iter;
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.tol = sa->tol;
+  a.cvd = sa->rd / (g->gamma - 1.0);
+  for (int t = 0; t < g->ntracer; ++t) {
+    a.sigma[t] = g->tracer_sigma[t];
+    a.mu[t] = g->tracer_mu[t];
+  }
+  if ((long long)g->ny * g->nz > 0x7fffffffLL) return fail(SNAP_E_INVALID, "ny nz too large");
+  if (launch_satadj(g->dtype, g->ntracer, q, a, (hipStream_t)stream))
+    return device_fail("saturation adjustment kernel launch");
+  return ok();
+}
+
 int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_host,
                 void* stream) {
   int r = check_grid(g);

@@ -46,6 +46,20 @@ struct KesslerArgs {
   KesslerSpec s[MAX_TRACERS / 3];
 };
 
+struct SatAdjSpec {
+  int v, c;                            // tracer indices of vapour and cloud
+  double p_ref, t_ref, beta, delta, rv;   // rv = R_d / eps of the vapour
+};
+
+struct SatAdjArgs {
+  int nx, ny, nz, gy, nspecies, max_iter;
+  long long sy, sz, sv;
+  double tol, cvd;                     // c_vd = R_d / (gamma - 1)
+  double sigma[MAX_TRACERS];           // heat capacities over c_vd
+  double mu[MAX_TRACERS];              // chemical potentials (J/kg)
+  SatAdjSpec s[MAX_TRACERS / 2];
+};
+
 struct SumArgs {
   int nx, ny, nz, gy, nvar;
   long long sy, sz, sv;
@@ -100,6 +114,7 @@ int launch_stage2d_batched(int dtype, int ntracer, int variant, const StageArgs*
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st);
 int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st);
+int launch_satadj(int dtype, int ntracer, void* q, const SatAdjArgs& a, hipStream_t st);
 int launch_sediment(int dtype, int ntracer, const StageArgs& a, hipStream_t st);
 int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double* out,
                 hipStream_t st);

@@ -22,6 +22,15 @@ __device__ __forceinline__ void set_tracer(double (&c)[NV], int idx, double val)
   for (int t = 0; t < NV - 5; ++t) c[5 + t] = t == idx ? val : c[5 + t];
 }
 
+// Entry `idx` of a per-tracer parameter table in the kernel arguments, by
+// compare-and-select (a runtime index would copy the argument struct to scratch).
+__device__ __forceinline__ double tracer_of(const double (&tab)[MAX_TRACERS], int idx) {
+  double r = 0.0;
+#pragma unroll
+  for (int t = 0; t < MAX_TRACERS; ++t) r = t == idx ? tab[t] : r;
+  return r;
+}
+
 // Backward-Euler step of (q_v, q_c, q_p) by the Newton iteration of Sec. 3 in
 // the regime of the starting point (saturated: q_v > q*).
 __device__ __forceinline__ void kessler_solve(const KesslerSpec& sp, double qs, double dt,
@@ -103,6 +112,69 @@ __global__ void __launch_bounds__(256) k_kessler(T* __restrict__ q, KesslerArgs 
     set_tracer(c, sp.v, rho * xv);
     set_tracer(c, sp.c, rho * xc);
     set_tracer(c, sp.p, rho * xp);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) q[o + (5 + t) * a.sv] = static_cast<T>(c[5 + t]);
+}
+
+// Saturation adjustment (App. D): each vapour / cloud pair brought to phase
+// equilibrium at constant volume and energy, one thread per interior cell,
+// double-precision arithmetic. The energy available as heat, E - K - sum mu
+// rho, and the heat capacity c_vd (rho_d + sum sigma rho) are carried as
+// running sums and updated with every transfer; T is their ratio.
+// grid: x over interior rows (nz ny), y over the interior row
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_satadj(T* __restrict__ q, SatAdjArgs a) {
+  constexpr int NV = 5 + NT;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, k = row / a.ny;
+  const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+  double c[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = static_cast<double>(q[o + v * a.sv]);
+  const double rho = c[0];
+  const double heat0 = c[4] - 0.5 * (c[1] * c[1] + c[2] * c[2] + c[3] * c[3]) / rho;
+  double chem = 0.0, cap = rho;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    chem += a.mu[t] * c[5 + t];
+    cap += (a.sigma[t] - 1.0) * c[5 + t];
+  }
+  cap *= a.cvd;
+  for (int it = 0; it < a.max_iter; ++it) {
+    double moved = 0.0;
+#pragma unroll
+    for (int s = 0; s < MAX_TRACERS / 2; ++s) {
+      if (s >= a.nspecies) break;
+      const SatAdjSpec& sp = a.s[s];
+      double rv = tracer(c, sp.v), rc = tracer(c, sp.c);
+      const double tot = rv + rc;
+      if (!(tot > 0.0)) continue;
+      const double temp = (heat0 - chem) / cap;
+      const double tt = temp / sp.t_ref;
+      const double lam = sp.beta / tt - sp.delta;          // d ln p* / d ln T
+      const double pstar = sp.p_ref * exp(sp.beta * (1.0 - 1.0 / tt) - sp.delta * log(tt));
+      const double f = rv * sp.rv * temp - pstar;          // > 0: supersaturated
+      if (rc <= 0.0 && f <= 0.0) continue;                  // no cloud and below saturation
+      // latent heating per unit mass condensed: dT/dx = -(dmu + T dcap) / cap
+      const double dmu = tracer_of(a.mu, sp.c) - tracer_of(a.mu, sp.v);
+      const double dcap = a.cvd * (tracer_of(a.sigma, sp.c) - tracer_of(a.sigma, sp.v));
+      const double dTdx = -(dmu + temp * dcap) / cap;
+      double fp = -sp.rv * temp + rv * sp.rv * dTdx - pstar * lam / temp * dTdx;
+      if (!(fp < 0.0)) fp = -sp.rv * temp;                 // keep the step downhill
+      double x = -f / fp;
+      x = fmin(fmax(x, -rc), rv);
+      rv -= x;
+      rc += x;
+      chem += x * dmu;
+      cap += x * dcap;
+      set_tracer(c, sp.v, rv);
+      set_tracer(c, sp.c, rc);
+      moved = fmax(moved, fabs(x) / tot);
+    }
+    if (moved <= a.tol) break;
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) q[o + (5 + t) * a.sv] = static_cast<T>(c[5 + t]);
@@ -221,6 +293,32 @@ int launch_kessler_t(int ntracer, T* q, const KesslerArgs& a, hipStream_t st) {
 int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st) {
   return dtype == 0 ? launch_kessler_t<double>(ntracer, static_cast<double*>(q), a, st)
                     : launch_kessler_t<float>(ntracer, static_cast<float*>(q), a, st);
+}
+
+template <typename T>
+int launch_satadj_t(int ntracer, T* q, const SatAdjArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)(a.ny * a.nz), (unsigned)((a.nx + 255) / 256));
+  switch (ntracer) {
+#define SNAP_SATADJ_CASE(N)                                                         \
+  case N:                                                                           \
+    hipLaunchKernelGGL((k_satadj<T, N>), grid, dim3(256), 0, st, q, a);             \
+    break;
+    SNAP_SATADJ_CASE(2)
+    SNAP_SATADJ_CASE(3)
+    SNAP_SATADJ_CASE(4)
+    SNAP_SATADJ_CASE(5)
+    SNAP_SATADJ_CASE(6)
+    SNAP_SATADJ_CASE(7)
+    SNAP_SATADJ_CASE(8)
+#undef SNAP_SATADJ_CASE
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_satadj(int dtype, int ntracer, void* q, const SatAdjArgs& a, hipStream_t st) {
+  return dtype == 0 ? launch_satadj_t<double>(ntracer, static_cast<double*>(q), a, st)
+                    : launch_satadj_t<float>(ntracer, static_cast<float*>(q), a, st);
 }
 
 }  // namespace snap

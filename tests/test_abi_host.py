@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 4
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 5
 
 
 def good_grid(**kw):
@@ -294,6 +294,49 @@ def test_kessler_needs_the_mixture_and_valid_scalars():
         assert lib.snap_kessler_step(g, P, dt, ctypes.byref(k), None) == snap.SNAP_E_INVALID
     assert lib.snap_kessler_step(g, None, 1.0, ctypes.byref(k), None) == snap.SNAP_E_INVALID
     assert lib.snap_kessler_step(g, P, 1.0, None, None) == snap.SNAP_E_INVALID
+
+
+def _satadj(**kw):
+    a = snap.SnapSatAdjC()
+    a.nspecies, a.rd, a.max_iter, a.tol = 1, 287.0, 20, 1e-14
+    sp = a.species[0]
+    sp.vapour, sp.cloud = 0, 1
+    sp.p_ref, sp.t_ref, sp.beta, sp.delta = 611.7, 273.16, 24.9, 5.06
+    for key, v in kw.items():
+        if hasattr(sp, key) and key not in ("rd",):
+            setattr(sp, key, v)
+        else:
+            setattr(a, key, v)
+    return a
+
+
+BAD_SATADJ = [
+    dict(nspecies=0), dict(nspecies=5), dict(rd=0.0), dict(rd=math.nan), dict(max_iter=0),
+    dict(max_iter=101), dict(tol=-1.0), dict(tol=math.inf), dict(vapour=3), dict(cloud=-1),
+    dict(vapour=1, cloud=0), dict(cloud=0), dict(p_ref=0.0), dict(t_ref=-1.0),
+    dict(beta=math.nan), dict(delta=math.inf),
+]
+
+
+@pytest.mark.parametrize("kw", BAD_SATADJ, ids=[str(k) for k in BAD_SATADJ])
+def test_saturation_adjust_rejects_bad_parameters(kw):
+    lib = snap.lib()
+    g = ctypes.byref(_kessler_grid())
+    a = _satadj(**kw)
+    assert lib.snap_saturation_adjust(g, ctypes.c_void_p(FAKE), ctypes.byref(a), None) == snap.SNAP_E_INVALID
+    assert lib.snap_last_error().decode()
+
+
+def test_saturation_adjust_needs_the_mixture():
+    lib = snap.lib()
+    a = _satadj()
+    P = ctypes.c_void_p(FAKE)
+    passive = ctypes.byref(_kessler_grid(eos=0))
+    assert lib.snap_saturation_adjust(passive, P, ctypes.byref(a), None) == snap.SNAP_E_INVALID
+    assert b"MIXTURE" in lib.snap_last_error()
+    g = ctypes.byref(_kessler_grid())
+    assert lib.snap_saturation_adjust(g, None, ctypes.byref(a), None) == snap.SNAP_E_INVALID
+    assert lib.snap_saturation_adjust(g, P, None, None) == snap.SNAP_E_INVALID
 
 
 def test_hllc_refuses_the_mixture_and_is_refused_by_adjoint_and_batched():

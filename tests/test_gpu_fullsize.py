@@ -340,3 +340,37 @@ def test_rhs_fullsize_bubble_member(size, dtype):
             continue
         print(f"   field {m}: error / max|ref| {err / scale:.2e}", flush=True)
         assert err <= tol * scale, (m, err / scale)
+
+
+def test_saturation_adjust_fullsize_fp32():
+    """The saturation adjustment on the benchmark's own 512 x 512 x 256 state
+    (water and ammonia vapour supersaturated aloft, clouds seeded) against the
+    oracle on sampled blocks; the other fields are left bit for bit."""
+    grid, q, adj = wl.jovian_satadj_3d()
+    print(f"[fullsize] saturation adjustment {grid.nx}x{grid.ny}x{grid.nz} nvar {grid.nvar} fp32",
+          flush=True)
+    qt = torch.as_tensor(q).float()
+    dg = snap.device_grid(grid, dtype=torch.float32)
+    qd = qt.cuda()
+    snap.snap_saturation_adjust(dg, qd, adj)
+    got, ref, orig = [], [], []
+    for (i0, j0, k0) in sample_blocks(grid):
+        blk = padded_block(qt.double(), i0, j0, k0, B)
+        r = oracle.saturation_adjust(blk, sub_grid(grid, k0, B), adj)
+        ref.append(r[:, G:G + B, G:G + B, G:G + B].reshape(grid.nvar, -1).numpy())
+        sl = (slice(None), slice(k0 + G, k0 + G + B), slice(j0 + G, j0 + G + B),
+              slice(i0 + G, i0 + G + B))
+        got.append(qd[sl].double().cpu().reshape(grid.nvar, -1).numpy())
+        orig.append(qt[sl].double().reshape(grid.nvar, -1).numpy())
+    del qd
+    torch.cuda.empty_cache()
+    ref, got, orig = (np.concatenate(x, axis=1) for x in (ref, got, orig))
+    assert np.array_equal(got[:5], orig[:5])
+    for m in range(5, grid.nvar):
+        scale = float(np.max(np.abs(ref[m])))
+        err = float(np.max(np.abs(got[m] - ref[m])))
+        moved = float(np.max(np.abs(ref[m] - orig[m])))
+        print(f"   tracer {m - 5}: error / max|ref| {err / scale:.2e}, change {moved / scale:.1e}",
+              flush=True)
+        assert err <= 1e-6 * scale, (m, err / scale)
+

@@ -1,0 +1,106 @@
+"""GPU parity of the saturation adjustment (App. D) against the FP64 oracle.
+
+The kernel takes Newton steps on the equilibrium condition of each vapour /
+cloud pair; the oracle bisects it. Both reach the same state: tracer
+densities within 1e-12 of each field's largest magnitude in FP64 and 1e-6
+with FP32 storage (the output rounding); density, momentum and total energy
+untouched bit for bit. The GPU result is also checked directly against the
+equilibrium condition, against a second adjustment (nothing moves) and for
+determinism.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_02955_amd as snap
+import workloads as wl
+from tests.test_gpu_parity import TOL64, field_errors
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "column_3d_6x5x48": dict(nx=6, ny=5, nz=48, seed_q=5),
+    "column_3d_9x7x64": dict(nx=9, ny=7, nz=64, seed_q=8),
+    "slab_2d_40x1x36": dict(nx=40, ny=1, nz=36, seed_q=6),
+}
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return {n: wl.jovian_satadj_3d(**kw) for n, kw in CASES.items()}
+
+
+def run_gpu(g, q, adj, dtype):
+    dg = snap.device_grid(g, dtype=dtype)
+    qd = torch.as_tensor(q).to(dtype).cuda()
+    snap.snap_saturation_adjust(dg, qd, adj)
+    return qd
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_satadj_fp64(cases, name):
+    g, q, adj = cases[name]
+    print(f"[satadj] fp64 {name}", flush=True)
+    got = g.interior(run_gpu(g, q, adj, torch.float64).cpu().numpy())
+    ref = g.interior(oracle.saturation_adjust(q, g, adj).numpy())
+    qi = g.interior(q)
+    assert np.array_equal(got[:5], qi[:5])
+    errs = field_errors(got[5:], ref[5:])
+    moved = [float(np.max(np.abs(ref[5 + t] - qi[5 + t])) / np.max(np.abs(ref[5 + t])))
+             for t in range(g.ntracer)]
+    print("   errors", ["%.2e" % e for e in errs], " change", ["%.1e" % m for m in moved], flush=True)
+    assert all(e <= TOL64 for e in errs), errs
+    assert max(moved) > 1e-3
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_satadj_fp32(cases, name):
+    g, q, adj = cases[name]
+    print(f"[satadj] fp32 {name}", flush=True)
+    q32 = torch.as_tensor(q).float()
+    got = g.interior(run_gpu(g, q32.double().numpy(), adj, torch.float32).cpu().double().numpy())
+    ref = g.interior(oracle.saturation_adjust(q32.double().numpy(), g, adj).numpy())
+    errs = field_errors(got[5:], ref[5:])
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-6 for e in errs), errs
+
+
+def test_satadj_gpu_result_is_in_equilibrium(cases):
+    g, q, adj = cases["column_3d_9x7x64"]
+    out = g.interior(run_gpu(g, q, adj, torch.float64).cpu().numpy())
+    rho = out[0]
+    kin = 0.5 * (out[1] ** 2 + out[2] ** 2 + out[3] ** 2) / rho
+    chem = sum(g.tracer_mu[t] * out[5 + t] for t in range(g.ntracer))
+    cvd = adj.rd / (g.gamma - 1.0)
+    heat = cvd * (rho - sum(out[5 + t] for t in range(g.ntracer))
+                  + sum(g.tracer_sigma[t] * out[5 + t] for t in range(g.ntracer)))
+    T = (out[4] - kin - chem) / heat
+    for sp in adj.species:
+        t = T / sp.t_ref
+        ps = sp.p_ref * np.exp(sp.beta * (1.0 - 1.0 / t) - sp.delta * np.log(t))
+        pv = out[5 + sp.vapour] * adj.rd / g.tracer_eps[sp.vapour] * T
+        cloudy = out[5 + sp.cloud] > 0
+        print(f"[satadj] pair {sp.vapour}: cloudy {cloudy.mean():.2f}, "
+              f"max |pv - p*| / p* {np.max(np.abs(pv[cloudy] - ps[cloudy]) / ps[cloudy]):.1e}",
+              flush=True)
+        assert cloudy.any() and (~cloudy).any()
+        assert np.max(np.abs(pv[cloudy] - ps[cloudy]) / ps[cloudy]) < 1e-11
+        assert np.all(pv[~cloudy] <= ps[~cloudy] * (1 + 1e-11))
+
+
+def test_satadj_twice_moves_nothing_and_is_deterministic(cases):
+    g, q, adj = cases["column_3d_6x5x48"]
+    dg = snap.device_grid(g)
+    a = torch.as_tensor(q).cuda()
+    b = a.clone()
+    snap.snap_saturation_adjust(dg, a, adj)
+    snap.snap_saturation_adjust(dg, b, adj)
+    assert torch.equal(a, b)
+    once = g.interior(a.cpu().numpy()).copy()
+    snap.snap_saturation_adjust(dg, a, adj)
+    twice = g.interior(a.cpu().numpy())
+    for sp in adj.species:
+        tot = once[5 + sp.vapour] + once[5 + sp.cloud]
+        d = np.abs(twice[5 + sp.cloud] - once[5 + sp.cloud]) / np.where(tot > 0, tot, 1.0)
+        assert float(d.max()) < 1e-13
