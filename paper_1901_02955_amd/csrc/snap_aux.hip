@@ -19,37 +19,41 @@ __device__ __forceinline__ int ghost_src(int idx, int n, int bc, bool& flip) {
 // regions: z ghost levels (all y, x), y ghost rows of interior levels (all x),
 // x ghost columns of interior rows. Threads start at `first` and stride by
 // `stride` over the enumeration.
-template <typename T>
+// The enumeration index has type I: 32-bit unsigned whenever the ghost cells
+// of the grid number fewer than 2^31 (its divisions are then far cheaper),
+// 64-bit otherwise.
+template <typename T, typename I>
 __device__ __forceinline__ void fill_ghosts_range(T* __restrict__ q, const GhostArgs& a,
-                                                  long long first, long long stride) {
-  const long long nzr = 6LL * a.nyp * a.nxp;
-  const long long nyr = a.d3 ? (long long)a.nz * 6 * a.nxp : 0;
-  const long long nxr = (long long)a.nz * a.ny * 6;
-  const long long total = nzr + nyr + nxr;
-  for (long long g = first; g < total; g += stride) {
+                                                  I first, I stride) {
+  const I nxp = (I)a.nxp, nyp = (I)a.nyp;
+  const I nzr = (I)6 * nyp * nxp;
+  const I nyr = a.d3 ? (I)a.nz * 6 * nxp : (I)0;
+  const I nxr = (I)a.nz * (I)a.ny * 6;
+  const I total = nzr + nyr + nxr;
+  for (I g = first; g < total; g += stride) {
     int i, j, k;
     if (g < nzr) {
-      const int ip = g % a.nxp;
-      const long long r = g / a.nxp;
-      const int jp = r % a.nyp;
-      const int kg = r / a.nyp;
+      const int ip = (int)(g % nxp);
+      const I r = g / nxp;
+      const int jp = (int)(r % nyp);
+      const int kg = (int)(r / nyp);
       i = ip - NG;
       j = jp - a.gy;
       k = kg < 3 ? kg - 3 : a.nz + kg - 3;
     } else if (g < nzr + nyr) {
-      const long long h = g - nzr;
-      const int ip = h % a.nxp;
-      const long long r = h / a.nxp;
-      const int jg = r % 6;
-      k = r / 6;
+      const I h = g - nzr;
+      const int ip = (int)(h % nxp);
+      const I r = h / nxp;
+      const int jg = (int)(r % 6);
+      k = (int)(r / 6);
       i = ip - NG;
       j = jg < 3 ? jg - 3 : a.ny + jg - 3;
     } else {
-      const long long h = g - nzr - nyr;
-      const int ig = h % 6;
-      const long long r = h / 6;
-      j = r % a.ny;
-      k = r / a.ny;
+      const I h = g - nzr - nyr;
+      const int ig = (int)(h % 6);
+      const I r = h / 6;
+      j = (int)(r % (I)a.ny);
+      k = (int)(r / (I)a.ny);
       i = ig < 3 ? ig - 3 : a.nx + ig - 3;
     }
     bool fx, fy = false, fz;
@@ -58,27 +62,49 @@ __device__ __forceinline__ void fill_ghosts_range(T* __restrict__ q, const Ghost
     const int sk = ghost_src(k, a.nz, a.bcz, fz);
     const long long dst = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
     const long long src = (long long)(sk + NG) * a.sz + (long long)(sj + a.gy) * a.sy + (si + NG);
-    for (int v = 0; v < a.nvar; ++v) {
-      T x = q[src + v * a.sv];
-      if ((v == 1 && fx) || (v == 2 && fy) || (v == 3 && fz)) x = -x;
-      q[dst + v * a.sv] = x;
+    // all loads first, then all stores: the ghost cell is never its own
+    // source, but through one pointer the compiler cannot know that, and
+    // interleaved load / store pairs would wait on memory once per variable
+    T x[5 + MAX_TRACERS];
+#pragma unroll
+    for (int v = 0; v < 5 + MAX_TRACERS; ++v)
+      if (v < a.nvar) x[v] = q[src + v * a.sv];
+#pragma unroll
+    for (int v = 0; v < 5 + MAX_TRACERS; ++v) {
+      if (v < a.nvar) {
+        const T y = (v == 1 && fx) || (v == 2 && fy) || (v == 3 && fz) ? -x[v] : x[v];
+        q[dst + v * a.sv] = y;
+      }
     }
   }
 }
 
+// Ghost cells of a grid (6 layers per axis, z layers over the whole padded
+// plane), and whether their count fits the 32-bit enumeration.
+__host__ __device__ inline long long ghost_count(const GhostArgs& a) {
+  return 6LL * a.nyp * a.nxp + (a.d3 ? (long long)a.nz * 6 * a.nxp : 0) + (long long)a.nz * a.ny * 6;
+}
+
+template <typename T>
+__device__ __forceinline__ void fill_ghosts_all(T* __restrict__ q, const GhostArgs& a) {
+  const long long first = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  if (ghost_count(a) + stride < 0x7fffffffLL)
+    fill_ghosts_range<T, unsigned>(q, a, (unsigned)first, (unsigned)stride);
+  else
+    fill_ghosts_range<T, long long>(q, a, first, stride);
+}
+
 template <typename T>
 __global__ void k_fill_ghosts(T* __restrict__ q, GhostArgs a) {
-  fill_ghosts_range<T>(q, a, blockIdx.x * (long long)blockDim.x + threadIdx.x,
-                       (long long)gridDim.x * blockDim.x);
+  fill_ghosts_all<T>(q, a);
 }
 
 // All members of an ensemble: member blockIdx.y.
 template <typename T>
 __global__ void k_fill_ghosts_batched(const GhostDesc* __restrict__ d) {
   const GhostDesc g = d[blockIdx.y];
-  fill_ghosts_range<T>(static_cast<T*>(g.q), g.a,
-                       blockIdx.x * (long long)blockDim.x + threadIdx.x,
-                       (long long)gridDim.x * blockDim.x);
+  fill_ghosts_all<T>(static_cast<T*>(g.q), g.a);
 }
 
 // ---------------------------------------------------------------------------
@@ -92,17 +118,18 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ULL;
 }
 
+// One block per interior row (k, j) at a time, its threads along x: the
+// row's offset is formed once, and no per-cell division is needed.
 template <typename T>
 __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
                                              unsigned long long* __restrict__ out) {
   unsigned long long b = 0ULL;  // bit pattern of the running maximum
-  const long long n = (long long)a.nx * a.ny * a.nz;
-  for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
-    const int i = c % a.nx;
-    const long long r = c / a.nx;
-    const int j = r % a.ny;
-    const int k = r / a.ny;
-    const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+  const long long rows = (long long)a.ny * a.nz;
+  for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+   const int j = (int)(row % a.ny), k = (int)(row / a.ny);
+   const long long base = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + NG;
+   for (int i = threadIdx.x; i < a.nx; i += 256) {
+    const long long o = base + i;
     double s;
     {
 #pragma clang fp contract(off)
@@ -140,6 +167,7 @@ __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
     }
     const unsigned long long sb = (unsigned long long)__double_as_longlong(s);
     b = sb > b ? sb : b;
+   }
   }
   // wave reduction of the unsigned bit patterns
   for (int off = 32; off > 0; off >>= 1) {
@@ -202,8 +230,7 @@ __global__ void k_sums_final(const double* __restrict__ part, int nblk, int nvar
 // launchers
 // ---------------------------------------------------------------------------
 int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st) {
-  const long long total = 6LL * a.nyp * a.nxp + (a.d3 ? (long long)a.nz * 6 * a.nxp : 0) +
-                          (long long)a.nz * a.ny * 6;
+  const long long total = ghost_count(a);
   long long nb = (total + 255) / 256;
   if (nb > 65536) nb = 65536;
   if (nb < 1) nb = 1;
@@ -231,9 +258,9 @@ int launch_fill_ghosts_batched(int dtype, const GhostDesc* d, int n, long long m
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, out, 1);
-  const long long n = (long long)a.nx * a.ny * a.nz;
-  long long nb = (n + 255) / 256;
+  long long nb = (long long)a.ny * a.nz;   // rows
   if (nb > CFL_BLOCKS) nb = CFL_BLOCKS;
+  if (nb < 1) nb = 1;
   if (dtype == 0)
     hipLaunchKernelGGL(k_cfl<double>, dim3((unsigned)nb), dim3(256), 0, st,
                        static_cast<const double*>(q), a, out);

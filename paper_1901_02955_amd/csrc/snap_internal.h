@@ -7,7 +7,7 @@
 
 namespace snap {
 
-constexpr int CFL_BLOCKS = 1024;
+constexpr int CFL_BLOCKS = 2048;
 constexpr int SUM_BLOCKS = 512;
 
 struct GhostArgs {
