@@ -361,6 +361,7 @@ struct LineTile {
   };
   T XL[NV][LN][NF];   // cotangent of the left state at face f
   T XR[NV][LN][NF];   // cotangent of the right state at face f
+  T WL[NV][LN][TL + 10];   // primitives of cells -5 .. TL+4 (relative), the stencils of (A) and (C)
   long long pbase[LN];  // padded offset of position 0 of each line
   long long rbase[LN];  // interior offset of position 0 of each line
   int lev[LN];          // level (z index) of each line (x and y lines)
@@ -482,17 +483,27 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
   const bool line_a = threadIdx.x < LN * Tile::NA && L0 + la < g.nlines;
   const int ja = c0 - 3 + pa;
   const bool cell_a = line_a && ja >= -1 && ja <= g.nd;
-  const long long pca = cell_a ? S.pbase[la] + ja * g.sd : 0;
   WenoLin<T> lin[NV];
-  // the stencils of every variable are loaded before any arithmetic, so that
-  // all NV x 5 loads are in flight together
+  // the primitives of the tile's lines, cells c0-5 .. c0+TL+4 (those outside
+  // the padded range -3 .. nd+2 are never read), staged in LDS once: the
+  // stencils of (A) and (C) are read from there
+  for (int it = threadIdx.x; it < LN * (TL + 10); it += NTHR) {
+    int l, m;
+    decode(it, TL + 10, l, m);
+    const int jg = c0 - 5 + m;
+    if (L0 + l < g.nlines && jg >= -3 && jg <= g.nd + 2) {
+      const long long pc = S.pbase[l] + jg * g.sd;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) S.WL[v][l][m] = W[pc + v * a.sv];
+    }
+  }
+  __syncthreads();
+  // cell ja = c0-3+pa uses cells ja-2 .. ja+2, positions pa .. pa+4 of WL
   auto load_stencils = [&](T (&st)[NV][5]) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T* w = W + v * a.sv + pca;
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int o = 0; o < 5; ++o) st[v][o] = w[(o - 2) * g.sd];
-    }
+      for (int o = 0; o < 5; ++o) st[v][o] = S.WL[v][la][pa + o];
   };
   if (cell_a) {
     T st[NV][5];
