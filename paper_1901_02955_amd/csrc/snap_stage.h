@@ -34,6 +34,10 @@
 
 namespace snap {
 
+#ifndef SNAP_MAX_PASSES
+#define SNAP_MAX_PASSES 8
+#endif
+
 struct StageArgs {
   const void* qs;   // padded state whose right-hand side is taken (ghosts filled)
   const void* qn;   // padded Q^n for the stage combination (may alias out); unused if ca == 0
@@ -45,6 +49,14 @@ struct StageArgs {
   long long sy, sz, sv;    // padded strides (elements)
   long long ry, rz, rv;    // interior (rhs) strides
   int tiles_x, tiles_y, nchunk, tz;
+  // 3-D only. pass_map = 0: block -> (tile, chunk) through the XCD-aware
+  // order, chunk kc covering levels kc*tz .. min(kc*tz + tz, nz) - 1.
+  // pass_map = 1 (a launch of exactly one workgroup per compute unit per
+  // chunk, all co-resident): chunk kc = blockIdx / tiles, i.e. the dispatch
+  // pass, covering levels kb[kc] .. kb[kc+1] - 1; consecutive blocks of a
+  // pass go to different XCDs, and the tiles one XCD receives are adjacent.
+  int pass_map;
+  int kb[SNAP_MAX_PASSES + 1];
   double dxi, dyi, dzi;    // 1 / spacing
   double gamma, gm1, inv_gm1, grav, eps;
   int linear;
@@ -379,14 +391,26 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 
   const int tid = threadIdx.x;
   const int ti = tid % TX, tj = tid / TX;
-  const int L = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tx = L % a.tiles_x;
-  const int rr_ = L / a.tiles_x;
-  const int ty = rr_ % a.tiles_y;
-  const int kc = rr_ / a.tiles_y;
+  int tx, ty, k0, k1;
+  if (a.pass_map) {
+    const int tiles = a.tiles_x * a.tiles_y;
+    const int kc = blockIdx.x / tiles;
+    const int r = blockIdx.x - kc * tiles;
+    const int t = (r % 8) * (tiles / 8) + r / 8;
+    tx = t % a.tiles_x;
+    ty = t / a.tiles_x;
+    k0 = a.kb[kc];
+    k1 = a.kb[kc + 1];
+  } else {
+    const int L = xcd_logical_block(blockIdx.x, gridDim.x);
+    tx = L % a.tiles_x;
+    const int rr_ = L / a.tiles_x;
+    ty = rr_ % a.tiles_y;
+    const int kc = rr_ / a.tiles_y;
+    k0 = kc * a.tz;
+    k1 = min(k0 + a.tz, a.nz);
+  }
   const int i0 = tx * TX, j0 = ty * TY;
-  const int k0 = kc * a.tz;
-  const int k1 = min(k0 + a.tz, a.nz);
   const int w = min(TX, a.nx - i0), h = min(TY, a.ny - j0);
   const bool act = ti < w && tj < h;
   const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
