@@ -127,20 +127,22 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     dg = snap.device_grid(grid, dtype=dtype)
     qd = torch.as_tensor(q).to(dtype).cuda().contiguous()
     del q
-    work = snap.workspace(dg, snap.SNAP_OP_RK3)
-    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+    # each step takes dt = CFL / (maximum signal speed of Q^n) on the device
+    # (snap_rk3_step_cfl: the reduction, then the three stages reading dt from
+    # device memory), so steps queue back to back without a host round trip
+    work = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
+    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
-        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
-        snap.snap_rk3_step(dg, qd, dt, work)
+        snap.snap_rk3_step_cfl(dg, qd, CFL, work, dt_dev)
     torch.cuda.synchronize()
     snap.snap_stage_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
-        snap.snap_rk3_step(dg, qd, dt, work)
+        snap.snap_rk3_step_cfl(dg, qd, CFL, work, dt_dev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    dt = float(dt_dev.item())
     stage_ms, launches = snap.snap_stage_timing_read()
     snap.snap_stage_timing_enable(False)
     cells = NX * NY * NZ
@@ -174,7 +176,7 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
         "valu_utilisation": None if hllc else _profile_value(f"valu_issue_util_{name}"),
         "final_dt": dt,
     }
-    del qd, work, cw
+    del qd, work, dt_dev
     torch.cuda.empty_cache()
     return res
 
@@ -191,17 +193,14 @@ def run_jovian(steps: int, warmup: int, mixture: bool = False):
     dg = snap.device_grid(grid, dtype=torch.float32)
     qd = torch.as_tensor(q).float().cuda().contiguous()
     del q
-    work = snap.workspace(dg, snap.SNAP_OP_RK3)
-    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+    work = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
     for _ in range(warmup):
-        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
-        snap.snap_rk3_step(dg, qd, dt, work)
+        snap.snap_rk3_step_cfl(dg, qd, CFL, work)
     torch.cuda.synchronize()
     snap.snap_stage_timing_enable(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
-        snap.snap_rk3_step(dg, qd, dt, work)
+        snap.snap_rk3_step_cfl(dg, qd, CFL, work)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms, n = snap.snap_stage_timing_read()
@@ -218,7 +217,7 @@ def run_jovian(steps: int, warmup: int, mixture: bool = False):
            "steps": steps, "stage_kernel_avg_ms": avg * 1e3,
            "alu_frac": flops / avg / 1e12 / FP32_PEAK_TFLOPS,
            "hbm_frac_algorithmic": byts / avg / 1e9 / HBM_PEAK_GBS}
-    del qd, work, cw
+    del qd, work
     torch.cuda.empty_cache()
     return out
 
@@ -291,8 +290,7 @@ def run_jovian_satadj(steps: int, warmup: int):
     qd = torch.as_tensor(q).float().cuda().contiguous()
     del q
     params = snap.satadj_params(adj)
-    work = snap.workspace(dg, snap.SNAP_OP_RK3)
-    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+    work = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
     # the adjustment alone, each call on a fresh copy of the initial state
     # (supersaturated aloft, clouds seeded): a second call on an adjusted
     # state would stop after one sweep
@@ -312,8 +310,7 @@ def run_jovian_satadj(steps: int, warmup: int):
     del q0
 
     def step():
-        dt = snap.snap_cfl_dt(dg, qd, CFL, cw)
-        snap.snap_rk3_step(dg, qd, dt, work)
+        snap.snap_rk3_step_cfl(dg, qd, CFL, work)
         snap.snap_saturation_adjust(dg, qd, params)
 
     for _ in range(warmup):
@@ -333,7 +330,7 @@ def run_jovian_satadj(steps: int, warmup: int):
            "steps": steps, "adjustment_ms": adj_ms,
            "adjustment_hbm_frac": byts / (adj_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
            "adjustment_share": adj_ms / (el / steps * 1e3)}
-    del qd, work, cw
+    del qd, work
     torch.cuda.empty_cache()
     return out
 
@@ -558,7 +555,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "3-D dry convection 256x256x128 (20x20x10 km), FP64, 5 conserved vars, "
-                        "periodic x/y, rigid lids, CFL 0.9 (dt per step), WENO5+LMARS, SSP-RK3",
+                        "periodic x/y, rigid lids, CFL 0.9 (dt per step, formed on the device), WENO5+LMARS, SSP-RK3",
             "nx": NX, "ny": NY, "nz": NZ, "nvar": 5, "cfl": CFL,
         },
         "roofline": f64["roofline"],

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 5
+#define SNAP_ABI_VERSION 6
 
 /* return codes */
 #define SNAP_OK 0
@@ -84,6 +84,7 @@ extern "C" {
 #define SNAP_OP_SUMS 3
 #define SNAP_OP_RHS_ADJ 4
 #define SNAP_OP_RK3_ADJ 5
+#define SNAP_OP_RK3_CFL 6
 
 /*
  * Grid, physical constants and hydrostatic reference profiles.
@@ -193,7 +194,8 @@ int snap_abi_version(void);
 /*
  * Bytes of device workspace `work` needed by operation `op` (SNAP_OP_*) on grid
  * g; 0 if none is needed. Returns 0 and sets the last error for an invalid grid.
- * SNAP_OP_RK3 and SNAP_OP_RHS_ADJ need two padded state arrays, SNAP_OP_RK3_ADJ
+ * SNAP_OP_RK3 and SNAP_OP_RHS_ADJ need two padded state arrays, SNAP_OP_RK3_CFL
+ * the same plus 256 bytes, SNAP_OP_RK3_ADJ
  * four padded plus two interior arrays, SNAP_OP_CFL and SNAP_OP_SUMS a few
  * hundred kilobytes of reduction partials.
  */
@@ -271,6 +273,24 @@ int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar,
  * work  device workspace of snap_workspace_bytes(g, SNAP_OP_CFL) bytes.
  */
 int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_host, void* stream);
+
+/*
+ * snap_cfl_dt followed by snap_rk3_step, with dt kept on the device: the
+ * maximum signal speed of Q^n is reduced into `work`, and each stage kernel
+ * forms dt = cfl / (that maximum) itself, the same double division the host
+ * makes in snap_cfl_dt, so the step equals snap_rk3_step with that dt bit for
+ * bit. The host neither waits for nor needs dt: steps can be queued back to
+ * back (and captured in a graph, no memset being recorded).
+ * q       padded state, as in snap_rk3_step.
+ * cfl     host value, finite and > 0.
+ * work    device workspace of snap_workspace_bytes(g, SNAP_OP_RK3_CFL) bytes.
+ * dt_dev  DEVICE pointer receiving the step's dt (one double), or NULL.
+ * Argument errors are reported as by snap_rk3_step. A state that snap_cfl_dt
+ * would reject (non-finite or non-positive density or pressure) cannot be
+ * reported from the device: its dt and the new state are then not finite.
+ */
+int snap_rk3_step_cfl(const snap_grid* g, void* q, double cfl, void* work, double* dt_dev,
+                      void* stream);
 
 /*
  * Sums over interior cells of every conserved field, accumulated in double

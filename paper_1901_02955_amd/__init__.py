@@ -21,7 +21,8 @@ __all__ = [
     "snap_fill_ghosts", "snap_rhs", "snap_rk3_step", "snap_cfl_dt",
     "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
     "snap_stage_timing_enable", "snap_stage_timing_read", "snap_rhs_adjoint",
-    "snap_rk3_step_adjoint", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ",
+    "snap_rk3_step_adjoint", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ", "snap_rk3_step_cfl",
+    "SNAP_OP_RK3_CFL",
     "snap_batched_workspace_bytes", "snap_batched_tile_variant", "snap_rk3_step_batched",
     "batched_workspace",
     "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
@@ -46,7 +47,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 5
+SNAP_ABI_VERSION = 6
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
@@ -59,6 +60,7 @@ SNAP_OP_CFL = 2
 SNAP_OP_SUMS = 3
 SNAP_OP_RHS_ADJ = 4
 SNAP_OP_RK3_ADJ = 5
+SNAP_OP_RK3_CFL = 6
 
 _ERROR_NAMES = {
     SNAP_E_INVALID: "SNAP_E_INVALID", SNAP_E_UNSUPPORTED: "SNAP_E_UNSUPPORTED",
@@ -146,6 +148,7 @@ _SIGNATURES = {
     "snap_fill_ghosts": (ctypes.c_int, [_GP, _P, _P]),
     "snap_rhs": (ctypes.c_int, [_GP, _P, _P, _P]),
     "snap_rk3_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P]),
+    "snap_rk3_step_cfl": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P, _P]),
     "snap_cfl_dt": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_rhs_adjoint": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P]),
@@ -329,6 +332,24 @@ def snap_rk3_step(grid: DeviceGrid, q: torch.Tensor, dt: float, work: torch.Tens
         raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3)")
     _check(lib().snap_rk3_step(grid.ptr(), ctypes.c_void_p(q.data_ptr()), ctypes.c_double(dt),
                                ctypes.c_void_p(work.data_ptr()), _stream(stream)))
+
+
+def snap_rk3_step_cfl(grid: DeviceGrid, q: torch.Tensor, cfl: float, work: torch.Tensor,
+                      dt_out: torch.Tensor | None = None, stream=None) -> None:
+    """One SSP-RK3 step with dt = cfl / (maximum signal speed of q) formed on
+    the device; dt_out (a float64 device tensor of at least one element), if
+    given, receives the step's dt."""
+    grid._check_state(q)
+    if work.numel() < snap_workspace_bytes(grid, SNAP_OP_RK3_CFL):
+        raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3_CFL)")
+    dptr = None
+    if dt_out is not None:
+        if dt_out.dtype != torch.float64 or not dt_out.is_cuda or dt_out.numel() < 1:
+            raise ValueError("dt_out must be a float64 device tensor with at least one element")
+        dptr = ctypes.c_void_p(dt_out.data_ptr())
+    _check(lib().snap_rk3_step_cfl(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
+                                   ctypes.c_double(cfl), ctypes.c_void_p(work.data_ptr()),
+                                   dptr, _stream(stream)))
 
 
 def snap_cfl_dt(grid: DeviceGrid, q: torch.Tensor, cfl: float, work: torch.Tensor,

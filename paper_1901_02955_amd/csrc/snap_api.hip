@@ -195,6 +195,9 @@ StageArgs stage_args(const snap_grid* g) {
   a.pbar_f = g->pbar_face;
   a.mix = mixture_of(g);
   a.sed = sediment_of(g);
+  a.ghost = (g->bc[0] == SNAP_BC_REFLECT ? GF_RX : 0) |
+            (is3d(g) && g->bc[1] == SNAP_BC_REFLECT ? GF_RY : 0) |
+            (g->bc[2] == SNAP_BC_REFLECT ? GF_RZ : 0);   // GF_ON is set by the caller
   return a;
 }
 
@@ -553,6 +556,7 @@ size_t snap_workspace_bytes(const snap_grid* g, int op) {
   switch (op) {
     case SNAP_OP_RHS: return 0;
     case SNAP_OP_RK3: return 2 * align256(padded_bytes(g));
+    case SNAP_OP_RK3_CFL: return 2 * align256(padded_bytes(g)) + 256;
     case SNAP_OP_CFL: return 256;
     case SNAP_OP_SUMS:
       return align256((size_t)SUM_BLOCKS * nvar_of(g) * sizeof(double)) +
@@ -613,29 +617,40 @@ int snap_rhs(const snap_grid* g, void* q, void* rhs, void* stream) {
   return ok();
 }
 
-int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stream) {
-  int r = check_grid(g);
-  if (r) return r;
-  if (!q) return fail(SNAP_E_INVALID, "q is NULL");
-  if (!work) return fail(SNAP_E_INVALID, "work is NULL");
-  if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
-  const hipStream_t st = (hipStream_t)stream;
-  char* w = static_cast<char*>(work);
+}  // extern "C"
+
+namespace {
+
+// The three stages of one SSP-RK3 step (Sec. 4.3) on validated arguments.
+// dt is taken from the host (smax == nullptr) or, on the device, as
+// cfl / *smax; dt_out (device, optional) receives the dt of the first stage.
+int rk3_stages(const snap_grid* g, void* q, double dt, const unsigned long long* smax,
+               double cfl, double* dt_out, char* w, hipStream_t st) {
+  int r;
   void* q1 = w;
   void* q2 = w + align256(padded_bytes(g));
   StageArgs a = stage_args(g);
   a.dt = dt;
+  a.smax = smax;
+  a.cfl = cfl;
   a.rhs_mode = 0;
+  // The 3-D stage kernels without tracers read the ghost cells they need at
+  // their sources, so their input needs no fill; the sedimentation kernel
+  // still reads z ghosts.
+  if (is3d(g) && !a.sed.on && ghosts_in_place(g->ntracer)) a.ghost |= GF_ON;
+  auto prepare = [&](void* x) { return (a.ghost & GF_ON) ? SNAP_OK : fill(g, x, st); };
   // Q1 = Q + dt R(Q)
-  if ((r = fill(g, q, st))) return r;
+  if ((r = prepare(q))) return r;
   a.qs = q;
   a.qn = nullptr;
   a.out = q1;
   a.ca = 0.0;
   a.cb = 1.0;
+  a.dt_out = dt_out;
   if ((r = run_stage(g, a, st))) return r;
+  a.dt_out = nullptr;
   // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1))
-  if ((r = fill(g, q1, st))) return r;
+  if ((r = prepare(q1))) return r;
   a.qs = q1;
   a.qn = q;
   a.out = q2;
@@ -643,7 +658,7 @@ int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stre
   a.cb = 0.25;
   if ((r = run_stage(g, a, st))) return r;
   // Q <- 1/3 Q + 2/3 (Q2 + dt R(Q2)), in place (each cell reads only its own Q)
-  if ((r = fill(g, q2, st))) return r;
+  if ((r = prepare(q2))) return r;
   a.qs = q2;
   a.qn = q;
   a.out = q;
@@ -651,6 +666,59 @@ int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stre
   a.cb = 2.0 / 3.0;
   if ((r = run_stage(g, a, st))) return r;
   return ok();
+}
+
+// Arguments of the maximum-signal-speed reduction (snap_cfl_dt).
+CflArgs cfl_args(const snap_grid* g) {
+  CflArgs a;
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.d3 = d3;
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.gamma = g->gamma;
+  a.gm1 = g->gamma - 1.0;
+  a.dx = g->dx;
+  a.dy = g->dy;
+  a.dz = g->dz;
+  a.ntracer = g->ntracer;
+  a.mix = uses_mixture(g) ? 1 : 0;
+  a.m = mixture_of(g);
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q) return fail(SNAP_E_INVALID, "q is NULL");
+  if (!work) return fail(SNAP_E_INVALID, "work is NULL");
+  if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
+  return rk3_stages(g, q, dt, nullptr, 0.0, nullptr, static_cast<char*>(work),
+                    (hipStream_t)stream);
+}
+
+int snap_rk3_step_cfl(const snap_grid* g, void* q, double cfl, void* work, double* dt_dev,
+                      void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q) return fail(SNAP_E_INVALID, "q is NULL");
+  if (!work) return fail(SNAP_E_INVALID, "work is NULL");
+  if (!finite_pos(cfl)) return fail(SNAP_E_INVALID, "cfl must be finite and > 0");
+  const hipStream_t st = (hipStream_t)stream;
+  char* w = static_cast<char*>(work);
+  unsigned long long* smax =
+      reinterpret_cast<unsigned long long*>(w + 2 * align256(padded_bytes(g)));
+  if (launch_cfl(g->dtype, q, cfl_args(g), smax, st)) return device_fail("cfl kernel launch");
+  return rk3_stages(g, q, 0.0, smax, cfl, dt_dev, w, st);
 }
 
 int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_bar, void* work,
@@ -960,25 +1028,7 @@ int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_
   if (!q || !work || !dt_host) return fail(SNAP_E_INVALID, "q, work or dt_host is NULL");
   if (!finite_pos(cfl)) return fail(SNAP_E_INVALID, "cfl must be finite and > 0");
   const hipStream_t st = (hipStream_t)stream;
-  CflArgs a;
-  const bool d3 = is3d(g);
-  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
-  a.nx = g->nx;
-  a.ny = g->ny;
-  a.nz = g->nz;
-  a.gy = d3 ? SNAP_NG : 0;
-  a.d3 = d3;
-  a.sy = nxp;
-  a.sz = nxp * nyp;
-  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
-  a.gamma = g->gamma;
-  a.gm1 = g->gamma - 1.0;
-  a.dx = g->dx;
-  a.dy = g->dy;
-  a.dz = g->dz;
-  a.ntracer = g->ntracer;
-  a.mix = uses_mixture(g) ? 1 : 0;
-  a.m = mixture_of(g);
+  const CflArgs a = cfl_args(g);
   unsigned long long* dmax = static_cast<unsigned long long*>(work);
   if (launch_cfl(g->dtype, q, a, dmax, st)) return device_fail("cfl kernel launch");
   unsigned long long bits = 0;

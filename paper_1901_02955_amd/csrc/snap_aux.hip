@@ -3,18 +3,6 @@
 
 namespace snap {
 
-// Source index along one axis for padded-coordinate index `idx` (interior
-// coordinates, ghosts outside [0, n)). Periodic: idx mod n. Reflecting: the
-// mirror image across the wall (clamped to the interior for n < 3).
-__device__ __forceinline__ int ghost_src(int idx, int n, int bc, bool& flip) {
-  flip = false;
-  if (idx >= 0 && idx < n) return idx;
-  if (bc == 0) return ((idx % n) + n) % n;
-  flip = true;
-  if (idx < 0) return min(-1 - idx, n - 1);
-  return max(2 * n - 1 - idx, 0);
-}
-
 // One thread per ghost cell; the ghost cells are enumerated as three disjoint
 // regions: z ghost levels (all y, x), y ghost rows of interior levels (all x),
 // x ghost columns of interior rows. Threads start at `first` and stride by

@@ -17,6 +17,20 @@ namespace snap {
 
 constexpr int NG = 3;
 
+// Source index along one axis of the cell a ghost cell copies, for index `idx`
+// in interior coordinates (ghosts outside [0, n)). Periodic (bc 0): idx mod n.
+// Reflecting: the mirror image across the wall (clamped to the interior for
+// n < 3), and `flip` is set: the momentum normal to that wall changes sign.
+// Shared by the ghost fill and the stage kernel that reads ghosts in place.
+__device__ __forceinline__ int ghost_src(int idx, int n, int bc, bool& flip) {
+  flip = false;
+  if (idx >= 0 && idx < n) return idx;
+  if (bc == 0) return ((idx % n) + n) % n;
+  flip = true;
+  if (idx < 0) return min(-1 - idx, n - 1);
+  return max(2 * n - 1 - idx, 0);
+}
+
 // ---------------------------------------------------------------------------
 // Conserved -> primitive (App. B). The arithmetic runs in double whatever the
 // storage type, and in one fixed order with no fused multiply-add, because the

@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) k_sediment(StageArgs a, int nchunk) {
   prim(k0 - 1, xb);
   prim(k0, x0);
   T* __restrict__ out = static_cast<T*>(a.out);
-  const T f = static_cast<T>(a.cb * a.dt);
+  const T f = static_cast<T>(a.cb * stage_dt(a));
   for (int k = k0; k < k1; ++k) {
     prim(k + 1, xa);
     T R[NV];

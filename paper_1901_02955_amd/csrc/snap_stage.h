@@ -66,7 +66,38 @@ struct StageArgs {
   const double* pbar_f;
   Mixture mix;           // mixture equation of state (kernels instantiated with MIX)
   Sediment sed;          // sedimentation (a kernel of its own, when sed.on)
+  // Time step from the device: when smax is set, dt = cfl / (the maximum
+  // signal speed whose IEEE bits smax holds, written by the reduction kernel
+  // earlier on the stream) and a.dt is unused. When dt_out is set, block 0
+  // stores the dt it used there.
+  const unsigned long long* smax;
+  double cfl;
+  double* dt_out;
+  // 3-D only. GF_ON: the kernel reads each ghost cell it needs (the x / y
+  // halo of its tile, the window levels below 0 and above nz - 1) from the
+  // interior cell the ghost fill copies (ghost_src, momentum normal to a
+  // reflecting wall negated), so no fill has to precede it; GF_RX / GF_RY /
+  // GF_RZ: that axis reflects (else it is periodic).
+  int ghost;
 };
+enum : int { GF_ON = 1, GF_RX = 2, GF_RY = 4, GF_RZ = 8 };
+
+// The 3-D stage kernels that can read ghosts in place (GF_ON): those without
+// tracers. With tracers the extra per-level scalar work pushed some instances
+// past an occupancy step, and they keep the fill.
+constexpr bool ghosts_in_place(int ntracer) { return ntracer == 0; }
+
+// The stage's time step (uniform over the launch).
+__device__ __forceinline__ double stage_dt(const StageArgs& a) {
+  if (a.smax == nullptr) return a.dt;
+  return a.cfl / __longlong_as_double(static_cast<long long>(*a.smax));
+}
+
+// Block 0 records the time step of the launch where the caller asked for it.
+__device__ __forceinline__ void store_stage_dt(const StageArgs& a, double dt) {
+  if (a.dt_out != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    *a.dt_out = dt;
+}
 
 template <typename T>
 __device__ __forceinline__ double to_d(T v) {
@@ -135,7 +166,7 @@ __device__ __forceinline__ void write_cell(const StageArgs& a, const T* __restri
     for (int v = 0; v < NV; ++v) o[roff + v * a.rv] = R[v];
     return;
   }
-  const T dt = static_cast<T>(a.dt), ca = static_cast<T>(a.ca), cb = static_cast<T>(a.cb);
+  const T dt = static_cast<T>(stage_dt(a)), ca = static_cast<T>(a.ca), cb = static_cast<T>(a.cb);
   T* o = static_cast<T*>(a.out);
   const T* qn = static_cast<const T*>(a.qn);
   if (a.ca != 0.0) {
@@ -378,6 +409,7 @@ __device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], double rb, doub
 template <typename T, int NT, int TX, int TY, bool MIX = false, bool HLLC = false>
 __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(StageArgs a) {
   constexpr int NV = 5 + NT;
+  constexpr bool GF = ghosts_in_place(NT);
   using I = PlaneItems<TX, TY>;
   constexpr int NHALO = 6 * (TX + TY);
   constexpr int HR = (NHALO + I::NTHR - 1) / I::NTHR;   // halo items per thread
@@ -417,6 +449,10 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   const T inv_gm1 = static_cast<T>(a.inv_gm1), gm1t = static_cast<T>(a.gm1);
   const T dxi = static_cast<T>(a.dxi), dyi = static_cast<T>(a.dyi), dzi = static_cast<T>(a.dzi);
   const bool linear = a.linear != 0;
+  // read before any store: the stores of the level loop could alias *a.smax,
+  // and a load inside the loop would be repeated at every level
+  const double dtd = stage_dt(a);
+  store_stage_dt(a, dtd);
   const bool combine = a.rhs_mode == 0;
   const bool use_qn = combine && a.ca != 0.0;
   const T* qn = static_cast<const T*>(a.qn);
@@ -428,7 +464,10 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   const int ic = i0 + (act ? ti : 0), jc = j0 + (act ? tj : 0);
   const long long col = poff(ic, jc, 0) - (long long)NG * a.sz;   // offset of level -3
 
-  // halo items of this thread (fixed across levels) and their column offsets
+  // halo items of this thread (fixed across levels) and their column offsets;
+  // with ghost_free a halo cell beyond the domain is read at the interior cell
+  // the fill would copy (its momentum normal to a reflecting wall is negated
+  // where it is planed)
   int hii[HR], hjj[HR];
   bool hok[HR];
   long long hoff[HR];
@@ -436,9 +475,23 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   for (int r = 0; r < HR; ++r) {
     const int it = item_thread<I::NTHR>() + r * I::NTHR;
     hok[r] = it < NHALO && halo_item<TX, TY>(it, w, h, hii[r], hjj[r]);
-    hoff[r] = hok[r] ? poff(i0 + hii[r], j0 + hjj[r], 0) - (long long)NG * a.sz : 0;
+    int gi = i0 + hii[r], gj = j0 + hjj[r];
+    if (GF && (a.ghost & GF_ON) && hok[r]) {
+      bool fx, fy;
+      gi = ghost_src(gi, a.nx, (a.ghost & GF_RX) ? 1 : 0, fx);
+      gj = ghost_src(gj, a.ny, (a.ghost & GF_RY) ? 1 : 0, fy);
+    }
+    hoff[r] = hok[r] ? poff(gi, gj, 0) - (long long)NG * a.sz : 0;
   }
   auto lev = [&](int k) -> long long { return (long long)(k + NG) * a.sz; };
+  // level read for window level k (uniform): k itself, or with GF_ON the
+  // level a z ghost copies; zf: rho w changes sign (mirror at a z wall)
+  auto zsrc = [&](int k, bool& zf) -> int {
+    zf = false;
+    if (GF && (a.ghost & GF_ON) && (k < 0 || k >= a.nz))
+      return ghost_src(k, a.nz, (a.ghost & GF_RZ) ? 1 : 0, zf);
+    return k;
+  };
 
   T W[5][NV];     // primitives of levels s-1 .. s+3 (own column)
   T qmc[NV];      // left state at the vertical face above the current level
@@ -452,8 +505,11 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int k = k0 - 3 + l;
-      load_prim<T, NV, MIX>(qs, col + lev(k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1,
-                            a.mix, W[l]);
+      bool zf;
+      T c[NV];
+      load_cons<T, NV>(qs, col + lev(zsrc(k, zf)), a.sv, c);
+      if (zf) c[3] = -c[3];
+      cons_to_prim_t<T, NV, MIX>(c, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, a.mix, W[l]);
     }
   }
   // prefetched raw conserved values: halo cells of the next level to be
@@ -477,9 +533,11 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   T QP[I::RREG][NV];
   for (int s = k0 - 2; s < k1; ++s) {
     T wc[NV], qsc[NV], qnc[NV];
+    bool wzf;
+    const int wsrc = zsrc(s + 3, wzf);
     if constexpr (PF) {
       if (act) {
-        load_cons<T, NV>(qs, col + lev(s + 3), a.sv, wc);
+        load_cons<T, NV>(qs, col + lev(wsrc), a.sv, wc);
         if (s >= k0) load_own(s, qsc, qnc);
       }
     }
@@ -495,6 +553,11 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
         if (hok[r]) {
           T x[NV];
           if constexpr (!PF) load_cons<T, NV>(qs, hoff[r] + lev(s), a.sv, hc[r]);
+          if (GF && (a.ghost & GF_ON) && (a.ghost & (GF_RX | GF_RY))) {
+            const int gi = i0 + hii[r], gj = j0 + hjj[r];
+            if ((a.ghost & GF_RX) && (gi < 0 || gi >= a.nx)) hc[r][1] = -hc[r][1];
+            if ((a.ghost & GF_RY) && (gj < 0 || gj >= a.ny)) hc[r][2] = -hc[r][2];
+          }
           cons_to_prim_t<T, NV, MIX>(hc[r], rbs, pbs, a.gm1, a.mix, x);
 #pragma unroll
           for (int v = 0; v < NV; ++v) S.P[v][hjj[r] + 3][hii[r] + 3] = x[v];
@@ -520,7 +583,8 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
     // ---- vertical direction, own column: face s+1/2 (z-face index s+1) -------
     T dfz[NV];
     if (act) {
-      if constexpr (!PF) load_cons<T, NV>(qs, col + lev(s + 3), a.sv, wc);
+      if constexpr (!PF) load_cons<T, NV>(qs, col + lev(wsrc), a.sv, wc);
+      if (wzf) wc[3] = -wc[3];
       cons_to_prim_t<T, NV, MIX>(wc, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG], a.gm1, a.mix,
                                  W[4]);
       T qmn[NV], qpn[NV];
@@ -563,7 +627,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[ro + v * a.rv] = R[v];
       } else {
-        const T dt = static_cast<T>(a.dt), ca = static_cast<T>(a.ca), cb = static_cast<T>(a.cb);
+        const T dt = static_cast<T>(dtd), ca = static_cast<T>(a.ca), cb = static_cast<T>(a.cb);
         T* o = static_cast<T*>(a.out);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -659,6 +723,7 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
 template <typename T, int NT, int TX, int TZ, bool MIX = false, bool HLLC = false>
 __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
   __shared__ Plane<T, 5 + NT, TX, TZ> S;
+  store_stage_dt(a, stage_dt(a));
   stage2d_tile<T, NT, TX, TZ, MIX, HLLC>(a, xcd_logical_block(blockIdx.x, gridDim.x), S);
 }
 

@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 5
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 6
 
 
 def good_grid(**kw):
@@ -97,6 +97,7 @@ def test_invalid_grid_rejected_by_every_entry_point(kw):
         lambda: lib.snap_fill_ghosts(g, P, None),
         lambda: lib.snap_rhs(g, P, ctypes.c_void_p(FAKE * 2), None),
         lambda: lib.snap_rk3_step(g, P, 0.1, P, None),
+        lambda: lib.snap_rk3_step_cfl(g, P, 0.9, P, None, None),
         lambda: lib.snap_cfl_dt(g, P, 0.9, P, ctypes.byref(d), None),
         lambda: lib.snap_conservation_sums(g, P, P, sums, None),
         lambda: lib.snap_rhs_adjoint(g, P, ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE), P, None),
@@ -130,6 +131,10 @@ def test_invalid_buffers_and_scalars():
         assert lib.snap_rk3_step(g, P, dt, P, None) == snap.SNAP_E_INVALID
     assert lib.snap_rk3_step(g, P, 0.1, None, None) == snap.SNAP_E_INVALID
     assert lib.snap_rk3_step(g, None, 0.1, P, None) == snap.SNAP_E_INVALID
+    for cfl in (0.0, -0.5, math.nan, math.inf):
+        assert lib.snap_rk3_step_cfl(g, P, cfl, P, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_cfl(g, P, 0.9, None, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_cfl(g, None, 0.9, P, None, None) == snap.SNAP_E_INVALID
     for cfl in (0.0, -0.5, math.nan):
         assert lib.snap_cfl_dt(g, P, cfl, P, ctypes.byref(d), None) == snap.SNAP_E_INVALID
     assert lib.snap_cfl_dt(g, P, 0.9, None, ctypes.byref(d), None) == snap.SNAP_E_INVALID
@@ -161,6 +166,7 @@ def test_workspace_sizes():
         padded = (c.nx + 6) * (c.ny + 6) * (c.nz + 6) * (5 + c.ntracer) * es
         a256 = (padded + 255) // 256 * 256
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) == 2 * a256
+        assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3_CFL) == 2 * a256 + 256
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RHS) == 0
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_CFL) >= 8
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_SUMS) >= 8 * (5 + c.ntracer)

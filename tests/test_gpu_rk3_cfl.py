@@ -1,0 +1,70 @@
+"""snap_rk3_step_cfl against snap_cfl_dt followed by snap_rk3_step.
+
+The device-side step forms dt = cfl / (maximum signal speed) in each stage
+kernel with the same double division the host makes, so the two paths must
+agree bit for bit, and the dt it reports must equal the host's. Cases: a
+ragged 3-D dry grid (double), a 2-D bubble (both element types), the Jovian
+column under the mixture equation of state (single), the same with falling
+precipitation (the sedimentation kernel reads the device dt too), and the
+full 256 x 256 x 128 convection grid (the launch whose chunks are sized per
+dispatch pass), three steps each.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1901_02955_amd as snap
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+CFL = 0.9
+
+
+def cases():
+    g3, _ = wl.dry_grid(37, 23, 19, 7400.0, 4600.0, 2850.0)
+    yield "dry_3d_37x23x19_f64", g3, wl.random_smooth_state(g3, 31), torch.float64
+    gb, qb = wl.bubble_2d(96, 48)
+    yield "bubble_2d_96x48_f64", gb, qb, torch.float64
+    yield "bubble_2d_96x48_f32", gb, qb, torch.float32
+    gj, qj = wl.jovian_3d(nx=24, ny=20, nz=40, mixture=True)
+    yield "jovian_mixture_24x20x40_f32", gj, qj, torch.float32
+    gk, qk, _ = wl.jovian_kessler_3d(nx=20, ny=18, nz=48, sediment=True)
+    yield "jovian_sediment_20x18x48_f32", gk, qk, torch.float32
+    gc, qc, _ = wl.convection_3d(256, 256, 128)
+    yield "convection_256x256x128_f64", gc, qc, torch.float64
+
+
+@pytest.mark.parametrize("case", list(cases()), ids=lambda c: c[0])
+def test_device_dt_step_equals_host_dt_step(case):
+    name, grid, q, dtype = case
+    print(f"[rk3-cfl] {name}", flush=True)
+    dg = snap.device_grid(grid, dtype=dtype)
+    q0 = torch.as_tensor(q).to(dtype).cuda()
+    host, dev = q0.clone(), q0.clone()
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+    wcfl = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
+    dt_dev = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    for step in range(3):
+        dt = snap.snap_cfl_dt(dg, host, CFL, cw)
+        snap.snap_rk3_step(dg, host, dt, work)
+        snap.snap_rk3_step_cfl(dg, dev, CFL, wcfl, dt_dev)
+        torch.cuda.synchronize()
+        got = float(dt_dev.item())
+        assert got == dt, (step, got, dt)
+        ih = grid.interior(host.cpu().numpy())
+        idv = grid.interior(dev.cpu().numpy())
+        assert np.array_equal(ih, idv), f"step {step}: device-dt step differs"
+    assert np.isfinite(idv).all()
+
+
+def test_device_dt_step_without_dt_output():
+    grid, q = wl.bubble_2d(64, 32)
+    dg = snap.device_grid(grid)
+    a = torch.as_tensor(q).cuda()
+    b = a.clone()
+    w = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
+    snap.snap_rk3_step_cfl(dg, a, CFL, w)
+    snap.snap_rk3_step_cfl(dg, b, CFL, w, torch.zeros(1, dtype=torch.float64, device="cuda"))
+    assert np.array_equal(grid.interior(a.cpu().numpy()), grid.interior(b.cpu().numpy()))
