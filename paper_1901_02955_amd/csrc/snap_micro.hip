@@ -191,6 +191,7 @@ constexpr int SED_CHUNK = 16;
 template <typename T, int NT>
 __global__ void __launch_bounds__(256) k_sediment(StageArgs a, int nchunk) {
   constexpr int NV = 5 + NT;
+  const double fd = a.cb * stage_dt(a);
   const int i = blockIdx.y * 256 + threadIdx.x;
   if (i >= a.nx) return;
   const int j = blockIdx.x / nchunk, kc = blockIdx.x % nchunk;
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(256) k_sediment(StageArgs a, int nchunk) {
   prim(k0 - 1, xb);
   prim(k0, x0);
   T* __restrict__ out = static_cast<T*>(a.out);
-  const T f = static_cast<T>(a.cb * stage_dt(a));
+  const T f = static_cast<T>(fd);
   for (int k = k0; k < k1; ++k) {
     prim(k + 1, xa);
     T R[NV];

@@ -25,6 +25,11 @@ SPECS = [
     ("3d_nt8_10x12x9", dict(nx=10, ny=12, nz=9, nt=8, bc=(0, 0, 1), seed=24)),
     ("3d_periodic_z_12x10x14", dict(nx=12, ny=10, nz=14, nt=2, bc=(0, 0, 0), seed=25, grav=0.0)),
     ("3d_small_2x3x4", dict(nx=2, ny=3, nz=4, nt=0, bc=(1, 1, 1), seed=26)),
+    # no tracers: the stage kernel reads ghost cells in place (periodic z, an x
+    # wall with periodic y, and a periodic domain narrower than the ghost width)
+    ("3d_periodic_all_13x11x10", dict(nx=13, ny=11, nz=10, nt=0, bc=(0, 0, 0), seed=27, grav=0.0)),
+    ("3d_xwall_19x17x12", dict(nx=19, ny=17, nz=12, nt=0, bc=(1, 0, 1), seed=28)),
+    ("3d_tiny_periodic_2x2x5", dict(nx=2, ny=2, nz=5, nt=0, bc=(0, 0, 0), seed=29, grav=0.0)),
 ]
 
 # Cases with the mixture equation of state: ``species`` picks tracers of
