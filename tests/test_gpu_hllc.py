@@ -22,7 +22,8 @@ pytestmark = pytest.mark.gpu
 
 HLLC_CASES = ["2d_bubble_64x64", "2d_smooth_37x29_nt3", "2d_reflect_21x19", "2d_thin_19x2",
               "3d_smooth_35x21x19", "3d_tracers_20x18x24_nt4", "3d_linear_17x9x11",
-              "3d_periodic_z_12x10x14", "3d_small_2x3x4"]
+              "3d_periodic_z_12x10x14", "3d_small_2x3x4", "3d_xwall_19x17x12",
+              "3d_periodic_all_13x11x10"]
 
 
 @pytest.fixture(scope="module")
