@@ -255,7 +255,7 @@ bool pass_weights(const snap_grid* g, int passes, double* w) {
     for (int p = 0; p < passes && *c; ++p) {
       char* end = nullptr;
       const double v = strtod(c, &end);
-      if (end == c || !(v > 0.0)) return false;
+      if (end == c || !(v > 0.0 && v < 1e30)) return false;   // also rejects inf and nan
       w[p] = v;
       c = *end == ',' ? end + 1 : end;
     }
