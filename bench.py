@@ -128,21 +128,21 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     qd = torch.as_tensor(q).to(dtype).cuda().contiguous()
     del q
     # each step takes dt = CFL / (maximum signal speed of Q^n) on the device
-    # (snap_rk3_step_cfl: the reduction, then the three stages reading dt from
-    # device memory), so steps queue back to back without a host round trip
+    # (snap_rk3_steps_cfl: the stages read dt from device memory, and in double
+    # precision the last stage of a step reduces the next step's signal speed),
+    # so the steps run back to back without a host round trip
     work = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
-    dt_dev = torch.zeros(1, dtype=torch.float64, device="cuda")
-    for _ in range(warmup):
-        snap.snap_rk3_step_cfl(dg, qd, CFL, work, dt_dev)
+    dt_dev = torch.zeros(max(steps, warmup, 1), dtype=torch.float64, device="cuda")
+    if warmup > 0:
+        snap.snap_rk3_steps_cfl(dg, qd, CFL, warmup, work, dt_dev)
     torch.cuda.synchronize()
     snap.snap_stage_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        snap.snap_rk3_step_cfl(dg, qd, CFL, work, dt_dev)
+    snap.snap_rk3_steps_cfl(dg, qd, CFL, steps, work, dt_dev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    dt = float(dt_dev.item())
+    dt = float(dt_dev[steps - 1].item())
     stage_ms, launches = snap.snap_stage_timing_read()
     snap.snap_stage_timing_enable(False)
     cells = NX * NY * NZ

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 6
+#define SNAP_ABI_VERSION 7
 
 /* return codes */
 #define SNAP_OK 0
@@ -291,6 +291,20 @@ int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_
  */
 int snap_rk3_step_cfl(const snap_grid* g, void* q, double cfl, void* work, double* dt_dev,
                       void* stream);
+
+/*
+ * nsteps calls of snap_rk3_step_cfl in one: the same steps, bit for bit, each
+ * taking dt = cfl / (maximum signal speed of its Q^n). For 3-D double-precision
+ * grids without tracers (or sedimentation) the last stage of each step also
+ * reduces the signal speed of the state it writes, so the next step needs no
+ * separate reduction pass over Q^n.
+ * nsteps  >= 1.
+ * work    device workspace of snap_workspace_bytes(g, SNAP_OP_RK3_CFL) bytes.
+ * dt_dev  DEVICE pointer receiving the nsteps time steps (doubles), or NULL.
+ * Errors as for snap_rk3_step_cfl, and SNAP_E_INVALID for nsteps < 1.
+ */
+int snap_rk3_steps_cfl(const snap_grid* g, void* q, double cfl, int nsteps, void* work,
+                       double* dt_dev, void* stream);
 
 /*
  * Sums over interior cells of every conserved field, accumulated in double

@@ -22,6 +22,7 @@ __all__ = [
     "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
     "snap_stage_timing_enable", "snap_stage_timing_read", "snap_rhs_adjoint",
     "snap_rk3_step_adjoint", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ", "snap_rk3_step_cfl",
+    "snap_rk3_steps_cfl",
     "SNAP_OP_RK3_CFL",
     "snap_batched_workspace_bytes", "snap_batched_tile_variant", "snap_rk3_step_batched",
     "batched_workspace",
@@ -47,7 +48,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 6
+SNAP_ABI_VERSION = 7
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
@@ -149,6 +150,7 @@ _SIGNATURES = {
     "snap_rhs": (ctypes.c_int, [_GP, _P, _P, _P]),
     "snap_rk3_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P]),
     "snap_rk3_step_cfl": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P, _P]),
+    "snap_rk3_steps_cfl": (ctypes.c_int, [_GP, _P, ctypes.c_double, ctypes.c_int, _P, _P, _P]),
     "snap_cfl_dt": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_rhs_adjoint": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P]),
@@ -350,6 +352,25 @@ def snap_rk3_step_cfl(grid: DeviceGrid, q: torch.Tensor, cfl: float, work: torch
     _check(lib().snap_rk3_step_cfl(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
                                    ctypes.c_double(cfl), ctypes.c_void_p(work.data_ptr()),
                                    dptr, _stream(stream)))
+
+
+def snap_rk3_steps_cfl(grid: DeviceGrid, q: torch.Tensor, cfl: float, nsteps: int,
+                       work: torch.Tensor, dt_out: torch.Tensor | None = None,
+                       stream=None) -> None:
+    """nsteps SSP-RK3 steps, each with dt = cfl / (maximum signal speed of its
+    state) formed on the device; dt_out (a float64 device tensor of at least
+    nsteps elements), if given, receives the time steps."""
+    grid._check_state(q)
+    if work.numel() < snap_workspace_bytes(grid, SNAP_OP_RK3_CFL):
+        raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3_CFL)")
+    dptr = None
+    if dt_out is not None:
+        if dt_out.dtype != torch.float64 or not dt_out.is_cuda or dt_out.numel() < nsteps:
+            raise ValueError("dt_out must be a float64 device tensor with at least nsteps elements")
+        dptr = ctypes.c_void_p(dt_out.data_ptr())
+    _check(lib().snap_rk3_steps_cfl(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
+                                    ctypes.c_double(cfl), ctypes.c_int(nsteps),
+                                    ctypes.c_void_p(work.data_ptr()), dptr, _stream(stream)))
 
 
 def snap_cfl_dt(grid: DeviceGrid, q: torch.Tensor, cfl: float, work: torch.Tensor,

@@ -621,11 +621,38 @@ int snap_rhs(const snap_grid* g, void* q, void* rhs, void* stream) {
 
 namespace {
 
+// Arguments of the maximum-signal-speed reduction (snap_cfl_dt).
+CflArgs cfl_args(const snap_grid* g) {
+  CflArgs a;
+  const bool d3 = is3d(g);
+  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.gy = d3 ? SNAP_NG : 0;
+  a.d3 = d3;
+  a.sy = nxp;
+  a.sz = nxp * nyp;
+  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.gamma = g->gamma;
+  a.gm1 = g->gamma - 1.0;
+  a.dxi = 1.0 / g->dx;
+  a.dyi = 1.0 / g->dy;
+  a.dzi = 1.0 / g->dz;
+  a.ntracer = g->ntracer;
+  a.mix = uses_mixture(g) ? 1 : 0;
+  a.m = mixture_of(g);
+  return a;
+}
+
 // The three stages of one SSP-RK3 step (Sec. 4.3) on validated arguments.
 // dt is taken from the host (smax == nullptr) or, on the device, as
 // cfl / *smax; dt_out (device, optional) receives the dt of the first stage.
+// smax_next (only where fused_speed_ok): the first stage clears it and the
+// last reduces the new state's maximum signal speed into it.
 int rk3_stages(const snap_grid* g, void* q, double dt, const unsigned long long* smax,
-               double cfl, double* dt_out, char* w, hipStream_t st) {
+               double cfl, double* dt_out, char* w, hipStream_t st,
+               unsigned long long* smax_next = nullptr) {
   int r;
   void* q1 = w;
   void* q2 = w + align256(padded_bytes(g));
@@ -647,8 +674,10 @@ int rk3_stages(const snap_grid* g, void* q, double dt, const unsigned long long*
   a.ca = 0.0;
   a.cb = 1.0;
   a.dt_out = dt_out;
+  a.smax_zero = smax_next;
   if ((r = run_stage(g, a, st))) return r;
   a.dt_out = nullptr;
+  a.smax_zero = nullptr;
   // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1))
   if ((r = prepare(q1))) return r;
   a.qs = q1;
@@ -664,33 +693,43 @@ int rk3_stages(const snap_grid* g, void* q, double dt, const unsigned long long*
   a.out = q;
   a.ca = 1.0 / 3.0;
   a.cb = 2.0 / 3.0;
+  a.smax_out = smax_next;
   if ((r = run_stage(g, a, st))) return r;
   return ok();
 }
 
-// Arguments of the maximum-signal-speed reduction (snap_cfl_dt).
-CflArgs cfl_args(const snap_grid* g) {
-  CflArgs a;
-  const bool d3 = is3d(g);
-  const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
-  a.nx = g->nx;
-  a.ny = g->ny;
-  a.nz = g->nz;
-  a.gy = d3 ? SNAP_NG : 0;
-  a.d3 = d3;
-  a.sy = nxp;
-  a.sz = nxp * nyp;
-  a.sv = a.sz * (g->nz + 2 * SNAP_NG);
-  a.gamma = g->gamma;
-  a.gm1 = g->gamma - 1.0;
-  a.dx = g->dx;
-  a.dy = g->dy;
-  a.dz = g->dz;
-  a.ntracer = g->ntracer;
-  a.mix = uses_mixture(g) ? 1 : 0;
-  a.m = mixture_of(g);
-  return a;
+// Grids whose last stage can reduce the next step's signal speed itself
+// (fused_speed in the kernels: double precision, no tracers, 3-D, ghosts read
+// in place, i.e. no sedimentation).
+bool fused_speed_ok(const snap_grid* g) {
+  return is3d(g) && g->dtype == SNAP_F64 && ghosts_in_place(g->ntracer) && !sediment_of(g).on;
 }
+
+// nsteps SSP-RK3 steps with the time step formed on the device. The maximum
+// signal speed of Q^n lives in one of two slots after the RK3 workspace: the
+// first comes from the reduction kernel; each later one from the previous
+// step's last stage where the kernels can fuse it, else from the kernel.
+int rk3_steps_cfl(const snap_grid* g, void* q, double cfl, int nsteps, void* work,
+                  double* dt_dev, hipStream_t st) {
+  char* w = static_cast<char*>(work);
+  unsigned long long* slot =
+      reinterpret_cast<unsigned long long*>(w + 2 * align256(padded_bytes(g)));
+  const bool fused = fused_speed_ok(g);
+  const CflArgs ca = cfl_args(g);
+  if (launch_cfl(g->dtype, q, ca, slot, st)) return device_fail("cfl kernel launch");
+  for (int n = 0; n < nsteps; ++n) {
+    unsigned long long* cur = slot + (n & 1);
+    unsigned long long* nxt = slot + ((n + 1) & 1);
+    const bool more = n + 1 < nsteps;
+    const int r = rk3_stages(g, q, 0.0, cur, cfl, dt_dev ? dt_dev + n : nullptr, w, st,
+                             fused && more ? nxt : nullptr);
+    if (r) return r;
+    if (more && !fused && launch_cfl(g->dtype, q, ca, nxt, st))
+      return device_fail("cfl kernel launch");
+  }
+  return ok();
+}
+
 
 }  // namespace
 
@@ -713,12 +752,18 @@ int snap_rk3_step_cfl(const snap_grid* g, void* q, double cfl, void* work, doubl
   if (!q) return fail(SNAP_E_INVALID, "q is NULL");
   if (!work) return fail(SNAP_E_INVALID, "work is NULL");
   if (!finite_pos(cfl)) return fail(SNAP_E_INVALID, "cfl must be finite and > 0");
-  const hipStream_t st = (hipStream_t)stream;
-  char* w = static_cast<char*>(work);
-  unsigned long long* smax =
-      reinterpret_cast<unsigned long long*>(w + 2 * align256(padded_bytes(g)));
-  if (launch_cfl(g->dtype, q, cfl_args(g), smax, st)) return device_fail("cfl kernel launch");
-  return rk3_stages(g, q, 0.0, smax, cfl, dt_dev, w, st);
+  return rk3_steps_cfl(g, q, cfl, 1, work, dt_dev, (hipStream_t)stream);
+}
+
+int snap_rk3_steps_cfl(const snap_grid* g, void* q, double cfl, int nsteps, void* work,
+                       double* dt_dev, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q) return fail(SNAP_E_INVALID, "q is NULL");
+  if (!work) return fail(SNAP_E_INVALID, "work is NULL");
+  if (!finite_pos(cfl)) return fail(SNAP_E_INVALID, "cfl must be finite and > 0");
+  if (nsteps < 1) return fail(SNAP_E_INVALID, "nsteps must be >= 1");
+  return rk3_steps_cfl(g, q, cfl, nsteps, work, dt_dev, (hipStream_t)stream);
 }
 
 int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_bar, void* work,

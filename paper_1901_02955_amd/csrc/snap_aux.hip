@@ -96,7 +96,8 @@ __global__ void k_fill_ghosts_batched(const GhostDesc* __restrict__ d) {
 }
 
 // ---------------------------------------------------------------------------
-// CFL: per-cell signal speed sum_d (|u_d| + c) / dx_d in double precision,
+// CFL: per-cell signal speed sum_d (|u_d| + c) / dx_d in double precision
+// (each term multiplied by the reciprocal spacing 1 / dx_d),
 // written with the same operation order as the conserved -> primitive
 // conversion, reduced to its maximum. A cell with rho <= 0 or p <= 0 (or NaN)
 // contributes NaN, whose bit pattern exceeds every finite double and +inf when
@@ -148,9 +149,9 @@ __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
         gam = a.gamma;
       }
       const double cs = sqrt(gam * p / rho);
-      s = (fabs(u) + cs) / a.dx;
-      if (a.d3) s = s + (fabs(v) + cs) / a.dy;
-      s = s + (fabs(w) + cs) / a.dz;
+      s = (fabs(u) + cs) * a.dxi;
+      if (a.d3) s = s + (fabs(v) + cs) * a.dyi;
+      s = s + (fabs(w) + cs) * a.dzi;
       if (!(rho > 0.0) || !(p > 0.0)) s = __builtin_nan("");
     }
     const unsigned long long sb = (unsigned long long)__double_as_longlong(s);

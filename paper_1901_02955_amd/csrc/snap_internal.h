@@ -25,7 +25,7 @@ struct GhostDesc {
 struct CflArgs {
   int nx, ny, nz, gy, d3;
   long long sy, sz, sv;
-  double gamma, gm1, dx, dy, dz;
+  double gamma, gm1, dxi, dyi, dzi;   // dxi = 1 / dx (x, y, z)
   int ntracer, mix;   // mix: the mixture equation of state with coefficients m
   Mixture m;
 };

@@ -79,6 +79,14 @@ struct StageArgs {
   // reflecting wall negated), so no fill has to precede it; GF_RX / GF_RY /
   // GF_RZ: that axis reflects (else it is periodic).
   int ghost;
+  // Next step's time step (double-precision kernels that read ghosts in place):
+  // with smax_out set, the kernel also reduces the maximum signal speed of its
+  // output (the quantity and the arithmetic of the CFL reduction kernel, so the
+  // dt formed from it is the same) into *smax_out with atomicMax; with
+  // smax_zero set, block 0 clears *smax_zero (a slot that a later launch of
+  // the step fills).
+  unsigned long long* smax_out;
+  unsigned long long* smax_zero;
 };
 enum : int { GF_ON = 1, GF_RX = 2, GF_RY = 4, GF_RZ = 8 };
 
@@ -86,6 +94,11 @@ enum : int { GF_ON = 1, GF_RX = 2, GF_RY = 4, GF_RZ = 8 };
 // tracers. With tracers the extra per-level scalar work pushed some instances
 // past an occupancy step, and they keep the fill.
 constexpr bool ghosts_in_place(int ntracer) { return ntracer == 0; }
+
+// Kernels that can reduce the signal speed of their output (smax_out).
+template <typename T, int NT>
+constexpr bool fused_speed() { return sizeof(T) == 8 && ghosts_in_place(NT); }
+
 
 // The stage's time step (uniform over the launch).
 __device__ __forceinline__ double stage_dt(const StageArgs& a) {
@@ -453,6 +466,11 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   // and a load inside the loop would be repeated at every level
   const double dtd = stage_dt(a);
   store_stage_dt(a, dtd);
+  constexpr bool FS = fused_speed<T, NT>();
+  if constexpr (FS) {
+    if (a.smax_zero != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.smax_zero = 0ULL;
+  }
+  unsigned long long smx = 0ULL;   // running maximum (IEEE bits) of the output's signal speed
   const bool combine = a.rhs_mode == 0;
   const bool use_qn = combine && a.ca != 0.0;
   const T* qn = static_cast<const T*>(a.qn);
@@ -629,10 +647,31 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
       } else {
         const T dt = static_cast<T>(dtd), ca = static_cast<T>(a.ca), cb = static_cast<T>(a.cb);
         T* o = static_cast<T*>(a.out);
+        T ov[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           const T t = qsc[v] + dt * R[v];
-          o[po + v * a.sv] = use_qn ? ca * qnc[v] + cb * t : cb * t;
+          ov[v] = use_qn ? ca * qnc[v] + cb * t : cb * t;
+          o[po + v * a.sv] = ov[v];
+        }
+        if constexpr (FS) {
+          if (a.smax_out != nullptr) {
+            // sum_d (|u_d| + c) / dx_d of the new state (times 1 / dx_d), in the CFL kernel's
+            // order and operations (no contraction)
+#pragma clang fp contract(off)
+            const double rho = ov[0], mx = ov[1], my = ov[2], mz = ov[3], E = ov[4];
+            const double inv = 1.0 / rho;
+            const double u = mx * inv, v = my * inv, w = mz * inv;
+            const double K = 0.5 * ((mx * u + my * v) + mz * w);
+            const double p = a.gm1 * (E - K);
+            const double cs = sqrt(a.gamma * p / rho);
+            double sp = (fabs(u) + cs) * a.dxi;
+            sp = sp + (fabs(v) + cs) * a.dyi;
+            sp = sp + (fabs(w) + cs) * a.dzi;
+            if (!(rho > 0.0) || !(p > 0.0)) sp = __builtin_nan("");
+            const unsigned long long sb = (unsigned long long)__double_as_longlong(sp);
+            smx = sb > smx ? sb : smx;
+          }
         }
       }
     }
@@ -641,6 +680,15 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
     for (int l = 0; l < 4; ++l)
 #pragma unroll
       for (int v = 0; v < NV; ++v) W[l][v] = W[l + 1][v];
+  }
+  if constexpr (FS) {
+    if (a.smax_out != nullptr) {
+      for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o2 = __shfl_xor(smx, off, 64);
+        smx = o2 > smx ? o2 : smx;
+      }
+      if ((threadIdx.x & 63) == 0) atomicMax(a.smax_out, smx);
+    }
   }
 }
 

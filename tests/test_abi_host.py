@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 6
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 7
 
 
 def good_grid(**kw):
@@ -98,6 +98,7 @@ def test_invalid_grid_rejected_by_every_entry_point(kw):
         lambda: lib.snap_rhs(g, P, ctypes.c_void_p(FAKE * 2), None),
         lambda: lib.snap_rk3_step(g, P, 0.1, P, None),
         lambda: lib.snap_rk3_step_cfl(g, P, 0.9, P, None, None),
+        lambda: lib.snap_rk3_steps_cfl(g, P, 0.9, 3, P, None, None),
         lambda: lib.snap_cfl_dt(g, P, 0.9, P, ctypes.byref(d), None),
         lambda: lib.snap_conservation_sums(g, P, P, sums, None),
         lambda: lib.snap_rhs_adjoint(g, P, ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE), P, None),
@@ -135,6 +136,10 @@ def test_invalid_buffers_and_scalars():
         assert lib.snap_rk3_step_cfl(g, P, cfl, P, None, None) == snap.SNAP_E_INVALID
     assert lib.snap_rk3_step_cfl(g, P, 0.9, None, None, None) == snap.SNAP_E_INVALID
     assert lib.snap_rk3_step_cfl(g, None, 0.9, P, None, None) == snap.SNAP_E_INVALID
+    for n in (0, -2):
+        assert lib.snap_rk3_steps_cfl(g, P, 0.9, n, P, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_steps_cfl(g, P, math.nan, 2, P, None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_steps_cfl(g, P, 0.9, 2, None, None, None) == snap.SNAP_E_INVALID
     for cfl in (0.0, -0.5, math.nan):
         assert lib.snap_cfl_dt(g, P, cfl, P, ctypes.byref(d), None) == snap.SNAP_E_INVALID
     assert lib.snap_cfl_dt(g, P, 0.9, None, ctypes.byref(d), None) == snap.SNAP_E_INVALID

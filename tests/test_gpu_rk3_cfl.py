@@ -68,3 +68,27 @@ def test_device_dt_step_without_dt_output():
     snap.snap_rk3_step_cfl(dg, a, CFL, w)
     snap.snap_rk3_step_cfl(dg, b, CFL, w, torch.zeros(1, dtype=torch.float64, device="cuda"))
     assert np.array_equal(grid.interior(a.cpu().numpy()), grid.interior(b.cpu().numpy()))
+
+
+@pytest.mark.parametrize("case", list(cases()), ids=lambda c: c[0])
+def test_multi_step_call_equals_single_steps(case):
+    """snap_rk3_steps_cfl: four steps in one call; on 3-D double-precision grids
+    without tracers each step's last stage reduces the next step's signal
+    speed itself, and every dt and state must still equal the host's."""
+    name, grid, q, dtype = case
+    print(f"[rk3-cfl] steps {name}", flush=True)
+    dg = snap.device_grid(grid, dtype=dtype)
+    q0 = torch.as_tensor(q).to(dtype).cuda()
+    host, dev = q0.clone(), q0.clone()
+    work = snap.workspace(dg, snap.SNAP_OP_RK3)
+    cw = snap.workspace(dg, snap.SNAP_OP_CFL)
+    n = 4
+    dts = []
+    for _ in range(n):
+        dts.append(snap.snap_cfl_dt(dg, host, CFL, cw))
+        snap.snap_rk3_step(dg, host, dts[-1], work)
+    dt_dev = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    snap.snap_rk3_steps_cfl(dg, dev, CFL, n, snap.workspace(dg, snap.SNAP_OP_RK3_CFL), dt_dev)
+    torch.cuda.synchronize()
+    assert dt_dev.cpu().tolist() == dts
+    assert np.array_equal(grid.interior(host.cpu().numpy()), grid.interior(dev.cpu().numpy()))
