@@ -294,8 +294,8 @@ int snap_rk3_step_cfl(const snap_grid* g, void* q, double cfl, void* work, doubl
 
 /*
  * nsteps calls of snap_rk3_step_cfl in one: the same steps, bit for bit, each
- * taking dt = cfl / (maximum signal speed of its Q^n). For 3-D double-precision
- * grids without tracers (or sedimentation) the last stage of each step also
+ * taking dt = cfl / (maximum signal speed of its Q^n). For 3-D grids without
+ * tracers (or sedimentation) the last stage of each step also
  * reduces the signal speed of the state it writes, so the next step needs no
  * separate reduction pass over Q^n.
  * nsteps  >= 1.

@@ -699,10 +699,10 @@ int rk3_stages(const snap_grid* g, void* q, double dt, const unsigned long long*
 }
 
 // Grids whose last stage can reduce the next step's signal speed itself
-// (fused_speed in the kernels: double precision, no tracers, 3-D, ghosts read
-// in place, i.e. no sedimentation).
+// (fused_speed in the kernels: no tracers, 3-D, ghosts read in place, i.e. no
+// sedimentation).
 bool fused_speed_ok(const snap_grid* g) {
-  return is3d(g) && g->dtype == SNAP_F64 && ghosts_in_place(g->ntracer) && !sediment_of(g).on;
+  return is3d(g) && ghosts_in_place(g->ntracer) && !sediment_of(g).on;
 }
 
 // nsteps SSP-RK3 steps with the time step formed on the device. The maximum

@@ -79,7 +79,7 @@ struct StageArgs {
   // reflecting wall negated), so no fill has to precede it; GF_RX / GF_RY /
   // GF_RZ: that axis reflects (else it is periodic).
   int ghost;
-  // Next step's time step (double-precision kernels that read ghosts in place):
+  // Next step's time step (kernels that read ghosts in place):
   // with smax_out set, the kernel also reduces the maximum signal speed of its
   // output (the quantity and the arithmetic of the CFL reduction kernel, so the
   // dt formed from it is the same) into *smax_out with atomicMax; with
@@ -97,7 +97,7 @@ constexpr bool ghosts_in_place(int ntracer) { return ntracer == 0; }
 
 // Kernels that can reduce the signal speed of their output (smax_out).
 template <typename T, int NT>
-constexpr bool fused_speed() { return sizeof(T) == 8 && ghosts_in_place(NT); }
+constexpr bool fused_speed() { return ghosts_in_place(NT); }
 
 
 // The stage's time step (uniform over the launch).
@@ -470,7 +470,10 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   if constexpr (FS) {
     if (a.smax_zero != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *a.smax_zero = 0ULL;
   }
-  unsigned long long smx = 0ULL;   // running maximum (IEEE bits) of the output's signal speed
+  // running maximum (IEEE bits) of the output's signal speed: one LDS slot per
+  // thread, which keeps it out of the registers the level loop needs
+  __shared__ unsigned long long smx_lds[FS ? TX * TY : 1];
+  if constexpr (FS) smx_lds[tid] = 0ULL;
   const bool combine = a.rhs_mode == 0;
   const bool use_qn = combine && a.ca != 0.0;
   const T* qn = static_cast<const T*>(a.qn);
@@ -670,7 +673,8 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
             sp = sp + (fabs(w) + cs) * a.dzi;
             if (!(rho > 0.0) || !(p > 0.0)) sp = __builtin_nan("");
             const unsigned long long sb = (unsigned long long)__double_as_longlong(sp);
-            smx = sb > smx ? sb : smx;
+            const unsigned long long cur = smx_lds[tid];
+            smx_lds[tid] = sb > cur ? sb : cur;
           }
         }
       }
@@ -683,6 +687,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   }
   if constexpr (FS) {
     if (a.smax_out != nullptr) {
+      unsigned long long smx = smx_lds[tid];
       for (int off = 32; off > 0; off >>= 1) {
         const unsigned long long o2 = __shfl_xor(smx, off, 64);
         smx = o2 > smx ? o2 : smx;

@@ -24,6 +24,7 @@ CFL = 0.9
 def cases():
     g3, _ = wl.dry_grid(37, 23, 19, 7400.0, 4600.0, 2850.0)
     yield "dry_3d_37x23x19_f64", g3, wl.random_smooth_state(g3, 31), torch.float64
+    yield "dry_3d_37x23x19_f32", g3, wl.random_smooth_state(g3, 31), torch.float32
     gb, qb = wl.bubble_2d(96, 48)
     yield "bubble_2d_96x48_f64", gb, qb, torch.float64
     yield "bubble_2d_96x48_f32", gb, qb, torch.float32
@@ -33,6 +34,7 @@ def cases():
     yield "jovian_sediment_20x18x48_f32", gk, qk, torch.float32
     gc, qc, _ = wl.convection_3d(256, 256, 128)
     yield "convection_256x256x128_f64", gc, qc, torch.float64
+    yield "convection_256x256x128_f32", gc, qc, torch.float32
 
 
 @pytest.mark.parametrize("case", list(cases()), ids=lambda c: c[0])
@@ -72,9 +74,9 @@ def test_device_dt_step_without_dt_output():
 
 @pytest.mark.parametrize("case", list(cases()), ids=lambda c: c[0])
 def test_multi_step_call_equals_single_steps(case):
-    """snap_rk3_steps_cfl: four steps in one call; on 3-D double-precision grids
-    without tracers each step's last stage reduces the next step's signal
-    speed itself, and every dt and state must still equal the host's."""
+    """snap_rk3_steps_cfl: four steps in one call; on 3-D grids without
+    tracers each step's last stage reduces the next step's signal speed
+    itself, and every dt and state must still equal the host's."""
     name, grid, q, dtype = case
     print(f"[rk3-cfl] steps {name}", flush=True)
     dg = snap.device_grid(grid, dtype=dtype)
