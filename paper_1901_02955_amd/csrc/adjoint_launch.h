@@ -23,7 +23,8 @@ void adj_line_launch(const T* W, const T* r, const AdjArgs& a, int d, T* P, hipS
 }
 
 template <typename T, int NV>
-int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, hipStream_t st) {
+int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
+               int mode, double alpha, double beta, hipStream_t st) {
   const T* qs = static_cast<const T*>(q);
   const T* r = static_cast<const T*>(rb);
   T* W = static_cast<T*>(w.W);
@@ -36,17 +37,9 @@ int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb
   adj_line_launch<T, NV, true>(W, r, a, 0, P, st);
   if (a.d3) adj_line_launch<T, NV, false>(W, r, a, 1, P, st);
   adj_line_launch<T, NV, false>(W, r, a, 2, P, st);
-  // the conserved cotangent reuses W (dead after the line passes)
-  hipLaunchKernelGGL((k_adj_cons<T, NV>), pgrid, dim3(256), 0, st, qs, P, r, a, W);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-template <typename T, int NV>
-int adj_fold_nv(const AdjWork& w, const AdjArgs& a, void* out, int mode, double alpha,
-                double beta, hipStream_t st) {
   const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
-  hipLaunchKernelGGL((k_adj_fold<T, NV>), fgrid, dim3(256), 0, st,
-                     static_cast<const T*>(w.W), a, static_cast<T*>(out), mode, alpha, beta);
+  hipLaunchKernelGGL((k_adj_consfold<T, NV>), fgrid, dim3(256), 0, st, qs, P, r, a,
+                     static_cast<T*>(out), mode, alpha, beta);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -57,8 +50,7 @@ int adj_rhs_t(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb,
   switch (a.nvar) {
 #define SNAP_ADJ_CASE(NVV)                                                      \
   case NVV:                                                                     \
-    r = adj_rhs_nv<T, NVV>(w, a, q, rb, st);                                    \
-    if (r == 0) r = adj_fold_nv<T, NVV>(w, a, out, mode, alpha, beta, st);      \
+    r = adj_rhs_nv<T, NVV>(w, a, q, rb, out, mode, alpha, beta, st);           \
     break;
     SNAP_ADJ_CASE(5)
     SNAP_ADJ_CASE(6)

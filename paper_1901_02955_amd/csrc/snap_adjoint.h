@@ -11,11 +11,10 @@
 //                    cotangent F_bar = (r_bar[right cell] - r_bar[left cell]) / dx_d,
 //                    WENO5 reverse to the five stencil inputs, and a fixed-order
 //                    gather of those contributions into the primitive cotangent;
-//   k_adj_cons       per padded cell: gravity terms and the reverse of the
-//                    conserved -> primitive map (double precision);
-//   k_adj_fold       per interior cell: its own cotangent plus those of the
-//                    ghost cells that copy it (sign flipped on the reflected
-//                    normal momentum).
+//   k_adj_consfold   per interior cell: gravity terms and the reverse of the
+//                    conserved -> primitive map (double precision) for the
+//                    cell and for each ghost cell that copies it, summed
+//                    (sign flipped on the reflected normal momentum).
 #pragma once
 
 #include "snap_device.h"
@@ -617,62 +616,6 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
   }
 }
 
-// Per padded cell of the stencil region: gravity and the reverse of the
-// conserved -> primitive map. Writes the conserved cotangent Qb (padded).
-template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_adj_cons(const T* __restrict__ q,
-                                                  const T* __restrict__ P,
-                                                  const T* __restrict__ rb, AdjArgs a,
-                                                  T* __restrict__ Qb) {
-  // grid: x over padded rows, y over the padded row
-  const int nxp = a.nx + 2 * NG, nyp = a.d3 ? a.ny + 2 * NG : 1;
-  const int ip = blockIdx.y * 256 + threadIdx.x;
-  if (ip >= nxp) return;
-  const int row = blockIdx.x;
-  const int jp = row % nyp, kp = row / nyp;
-  const long long c = (long long)row * nxp + ip;
-  {
-    const int i = ip - NG, j = jp - a.gy, k = kp - NG;
-    const int gi = (i < 0 || i >= a.nx) + (j < 0 || j >= a.ny) + (k < 0 || k >= a.nz);
-    if (gi > 1) {   // corner ghosts are never read by the cross-shaped stencil
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Qb[c + v * a.sv] = T(0);
-      return;
-    }
-    double pb[NV], cv[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      pb[v] = static_cast<double>(P[c + v * a.sv]);
-      cv[v] = static_cast<double>(q[c + v * a.sv]);
-    }
-    double qe = 0.0;   // extra conserved cotangent of rho w from the energy source
-    if (gi == 0) {
-      const long long ro = (long long)k * a.rz + (long long)j * a.ry + i;
-      pb[0] += -a.grav * static_cast<double>(rb[ro + 3 * a.rv]);   // R_rhow -= g rho'
-      qe = -a.grav * static_cast<double>(rb[ro + 4 * a.rv]);       // R_E -= g rho w
-    }
-    const double inv = 1.0 / cv[0];
-    const double u = cv[1] * inv, v = cv[2] * inv, w = cv[3] * inv;
-    // p = (gamma - 1)(E - (m.m)/(2 rho)):  dp/drho = (gamma-1) |u|^2 / 2, dp/dm = -(gamma-1) u
-    double rhob = pb[0] - (u * pb[1] + v * pb[2] + w * pb[3]) * inv +
-                  a.gm1 * 0.5 * (u * u + v * v + w * w) * pb[4];
-    double out[NV];
-#pragma unroll
-    for (int t = 5; t < NV; ++t) {
-      const double qt = cv[t] * inv;
-      rhob -= qt * pb[t] * inv;
-      out[t] = pb[t] * inv;
-    }
-    out[0] = rhob;
-    out[1] = pb[1] * inv - a.gm1 * u * pb[4];
-    out[2] = pb[2] * inv - a.gm1 * v * pb[4];
-    out[3] = pb[3] * inv - a.gm1 * w * pb[4] + qe;
-    out[4] = a.gm1 * pb[4];
-#pragma unroll
-    for (int t = 0; t < NV; ++t) Qb[c + t * a.sv] = static_cast<T>(out[t]);
-  }
-}
-
 __device__ __forceinline__ int adj_ghost_src(int idx, int n, int bc) {
   if (idx >= 0 && idx < n) return idx;
   if (bc == 0) return ((idx % n) + n) % n;
@@ -680,54 +623,91 @@ __device__ __forceinline__ int adj_ghost_src(int idx, int n, int bc) {
   return max(2 * n - 1 - idx, 0);
 }
 
-// Per interior cell: own cotangent plus those of the ghost cells that copy it.
-// out: interior layout, overwritten (mode 0), added to (mode 1), or scaled
-// sum out = alpha * out + beta * result (mode 2).
+// Conserved cotangent of one cell of the stencil region (interior
+// coordinates; ghost cells lie outside the domain along one axis at most),
+// in double precision: gravity terms (interior cells only) and the reverse of
+// the conserved -> primitive map applied to the primitive cotangent P.
 template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_adj_fold(const T* __restrict__ Qb, AdjArgs a,
-                                                  T* __restrict__ out, int mode, double alpha,
-                                                  double beta) {
+__device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* __restrict__ P,
+                                              const T* __restrict__ rb, const AdjArgs& a, int i,
+                                              int j, int k, double (&out)[NV]) {
+  const long long c = padded_off(a, i, j, k);
+  double pb[NV], cv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    pb[v] = static_cast<double>(P[c + v * a.sv]);
+    cv[v] = static_cast<double>(q[c + v * a.sv]);
+  }
+  double qe = 0.0;   // extra conserved cotangent of rho w from the energy source
+  const bool inside = i >= 0 && i < a.nx && j >= 0 && j < a.ny && k >= 0 && k < a.nz;
+  if (inside) {
+    const long long ro = (long long)k * a.rz + (long long)j * a.ry + i;
+    pb[0] += -a.grav * static_cast<double>(rb[ro + 3 * a.rv]);   // R_rhow -= g rho'
+    qe = -a.grav * static_cast<double>(rb[ro + 4 * a.rv]);       // R_E -= g rho w
+  }
+  const double inv = 1.0 / cv[0];
+  const double u = cv[1] * inv, v = cv[2] * inv, w = cv[3] * inv;
+  // p = (gamma - 1)(E - (m.m)/(2 rho)):  dp/drho = (gamma-1) |u|^2 / 2, dp/dm = -(gamma-1) u
+  double rhob = pb[0] - (u * pb[1] + v * pb[2] + w * pb[3]) * inv +
+                a.gm1 * 0.5 * (u * u + v * v + w * w) * pb[4];
+#pragma unroll
+  for (int t = 5; t < NV; ++t) {
+    const double qt = cv[t] * inv;
+    rhob -= qt * pb[t] * inv;
+    out[t] = pb[t] * inv;
+  }
+  out[0] = rhob;
+  out[1] = pb[1] * inv - a.gm1 * u * pb[4];
+  out[2] = pb[2] * inv - a.gm1 * v * pb[4];
+  out[3] = pb[3] * inv - a.gm1 * w * pb[4] + qe;
+  out[4] = a.gm1 * pb[4];
+}
+
+// Per interior cell: its conserved cotangent plus those of the ghost cells
+// that copy it (fixed order: x, y, z; low then high; the reflected normal
+// momentum negated), computed in place from q and P, so no padded conserved
+// cotangent is written and read back. out: interior layout, overwritten
+// (mode 0), added to (mode 1), or out = alpha * out + beta * result (mode 2).
+template <typename T, int NV>
+__global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
+                                                      const T* __restrict__ P,
+                                                      const T* __restrict__ rb, AdjArgs a,
+                                                      T* __restrict__ out, int mode,
+                                                      double alpha, double beta) {
   // grid: x over interior rows, y over the interior row
   const int i = blockIdx.y * 256 + threadIdx.x;
   if (i >= a.nx) return;
   const int row = blockIdx.x;
   const int j = row % a.ny, k = row / a.ny;
   const long long c = (long long)row * a.nx + i;
-  {
-    double acc[NV];
-    const long long pc = padded_off(a, i, j, k);
+  double acc[NV];
+  adj_cons_cell<T, NV>(q, P, rb, a, i, j, k, acc);
+  for (int d = 0; d < 3; ++d) {
+    if (d == 1 && !a.d3) continue;
+    const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
+    const int me = d == 0 ? i : (d == 1 ? j : k);
+    if (me >= 3 && me < nd - 3) continue;   // no ghost cell copies a cell this deep
+    for (int m = 0; m < 6; ++m) {
+      const int gidx = m < 3 ? -1 - m : nd + (m - 3);
+      if (adj_ghost_src(gidx, nd, a.bc[d]) != me) continue;
+      int gc[3] = {i, j, k};
+      gc[d] = gidx;
+      double x[NV];
+      adj_cons_cell<T, NV>(q, P, rb, a, gc[0], gc[1], gc[2], x);
+      const bool flip = a.bc[d] == 1;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = static_cast<double>(Qb[pc + v * a.sv]);
-    // ghosts along each axis in the same line (fixed order: x, y, z; low then high)
-    for (int d = 0; d < 3; ++d) {
-      if (d == 1 && !a.d3) continue;
-      const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
-      const int me = d == 0 ? i : (d == 1 ? j : k);
-      if (me >= 3 && me < nd - 3) continue;   // no ghost cell copies a cell this deep
-      for (int m = 0; m < 6; ++m) {
-        const int gidx = m < 3 ? -1 - m : nd + (m - 3);
-        if (adj_ghost_src(gidx, nd, a.bc[d]) != me) continue;
-        int gc[3] = {i, j, k};
-        gc[d] = gidx;
-        const long long pg = padded_off(a, gc[0], gc[1], gc[2]);
-        const bool flip = a.bc[d] == 1;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const double x = static_cast<double>(Qb[pg + v * a.sv]);
-          acc[v] += (flip && v == 1 + d) ? -x : x;
-        }
-      }
+      for (int v = 0; v < NV; ++v) acc[v] += (flip && v == 1 + d) ? -x[v] : x[v];
     }
+  }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const long long o = c + v * a.rv;
-      if (mode == 0)
-        out[o] = static_cast<T>(acc[v]);
-      else if (mode == 1)
-        out[o] = static_cast<T>(static_cast<double>(out[o]) + acc[v]);
-      else
-        out[o] = static_cast<T>(alpha * static_cast<double>(out[o]) + beta * acc[v]);
-    }
+  for (int v = 0; v < NV; ++v) {
+    const long long o = c + v * a.rv;
+    if (mode == 0)
+      out[o] = static_cast<T>(acc[v]);
+    else if (mode == 1)
+      out[o] = static_cast<T>(static_cast<double>(out[o]) + acc[v]);
+    else
+      out[o] = static_cast<T>(alpha * static_cast<double>(out[o]) + beta * acc[v]);
   }
 }
 
