@@ -81,9 +81,11 @@ def algorithmic_flops_per_cell_stage(ntracer: int, ndir: int, mixture: bool = Fa
 CFL_FLOPS_PER_CELL = 23
 
 
-# sources the stage kernel and its launch (tiling, z-chunks) are built from
+# sources the stage kernel and its launch (tiling, z-chunks) are built from, with
+# build.py's flags
 STAGE_SOURCES = ("snap_device.h", "snap_stage.h", "snap_internal.h", "stage_launch.h",
-                 "stage_f64.hip", "stage_f32.hip", "snap_api.hip")
+                 "stage_dry_f64.hip", "stage_dry_f32.hip", "stage_f64.hip", "stage_f32.hip",
+                 "snap_api.hip")
 
 
 def stage_sources_digest() -> str:
@@ -94,6 +96,10 @@ def stage_sources_digest() -> str:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
+    # the compiler flags, which differ between the stage files
+    with open(os.path.join(ROOT, "paper_1901_02955_amd", "build.py"), "rb") as f:
+        h.update(b"build.py")
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -96,6 +96,13 @@ int launch_adj_combine_f64(void* out, const void* x, const void* y, const void* 
 int launch_adj_combine_f32(void* out, const void* x, const void* y, const void* z, double ca,
                            double cb, double cc, long long n, hipStream_t st);
 int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+// The stage kernels without tracers (LMARS, or HLLC with hllc = true) live in
+// translation units of their own, compiled with another instruction scheduling
+// strategy than the kernels with tracers (see build.py).
+int launch_stage_dry_f64(bool hllc, bool d3, const StageArgs& a, int nblocks, hipStream_t st);
+int launch_stage_dry_f32(bool hllc, bool d3, const StageArgs& a, int nblocks, hipStream_t st);
+int occupancy_dry_f64(bool hllc, bool d3);
+int occupancy_dry_f32(bool hllc, bool d3);
 int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_mix_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_mix_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);

@@ -1,6 +1,6 @@
 // Instantiation and dispatch of the stage kernels for one element type.
-// Included once by stage_f64.hip (T = double) and once by stage_f32.hip
-// (T = float) so that the two instantiation sets compile in parallel.
+// Included by the stage_*.hip files, one per element type and kernel family,
+// so that the instantiation sets compile in parallel.
 #pragma once
 
 #include "snap_internal.h"
@@ -51,11 +51,30 @@ int occupancy_nt(bool d3) {
   return n;
 }
 
+// Without tracers the mixture is the dry gas, and the kernels are the ones of
+// stage_dry_f64.hip / stage_dry_f32.hip, so that no other translation unit
+// instantiates them.
+template <typename T>
+int launch_dry(bool hllc, bool d3, const StageArgs& a, int nblocks, hipStream_t st) {
+  if constexpr (sizeof(T) == 8)
+    return launch_stage_dry_f64(hllc, d3, a, nblocks, st);
+  else
+    return launch_stage_dry_f32(hllc, d3, a, nblocks, st);
+}
+
+template <typename T>
+int occupancy_dry(bool hllc, bool d3) {
+  if constexpr (sizeof(T) == 8)
+    return occupancy_dry_f64(hllc, d3);
+  else
+    return occupancy_dry_f32(hllc, d3);
+}
+
 // Workgroups of the stage kernel that fit on one compute unit (0 if unknown).
 template <typename T, bool MIX, bool HLLC = false>
 int occupancy_t(int ntracer, bool d3) {
   switch (ntracer) {
-    case 0: return occupancy_nt<T, 0, MIX, HLLC>(d3);
+    case 0: return occupancy_dry<T>(HLLC, d3);
     case 1: return occupancy_nt<T, 1, MIX, HLLC>(d3);
     case 2: return occupancy_nt<T, 2, MIX, HLLC>(d3);
     case 3: return occupancy_nt<T, 3, MIX, HLLC>(d3);
@@ -71,7 +90,7 @@ int occupancy_t(int ntracer, bool d3) {
 template <typename T, bool MIX, bool HLLC = false>
 int launch_stage_t(int ntracer, bool d3, const StageArgs& a, int nblocks, hipStream_t st) {
   switch (ntracer) {
-    case 0: return launch_nt<T, 0, MIX, HLLC>(d3, a, nblocks, st);
+    case 0: return launch_dry<T>(HLLC, d3, a, nblocks, st);
     case 1: return launch_nt<T, 1, MIX, HLLC>(d3, a, nblocks, st);
     case 2: return launch_nt<T, 2, MIX, HLLC>(d3, a, nblocks, st);
     case 3: return launch_nt<T, 3, MIX, HLLC>(d3, a, nblocks, st);
