@@ -667,7 +667,8 @@ __device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* 
 // that copy it (fixed order: x, y, z; low then high; the reflected normal
 // momentum negated), computed in place from q and P, so no padded conserved
 // cotangent is written and read back. out: interior layout, overwritten
-// (mode 0), added to (mode 1), or out = alpha * out + beta * result (mode 2).
+// (mode 0), added to (mode 1), out = alpha * out + beta * result (mode 2), or
+// out = alpha * rb + beta * result (mode 3; out and rb distinct).
 template <typename T, int NV>
 __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
                                                       const T* __restrict__ P,
@@ -706,8 +707,10 @@ __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
       out[o] = static_cast<T>(acc[v]);
     else if (mode == 1)
       out[o] = static_cast<T>(static_cast<double>(out[o]) + acc[v]);
-    else
+    else if (mode == 2)
       out[o] = static_cast<T>(alpha * static_cast<double>(out[o]) + beta * acc[v]);
+    else
+      out[o] = static_cast<T>(alpha * static_cast<double>(rb[o]) + beta * acc[v]);
   }
 }
 

@@ -818,17 +818,15 @@ int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar,
   a.ca = 0.75;
   a.cb = 0.25;
   if ((r = run_stage(g, a, st))) return r;
+  // The ghost cells of Q and Q1 filled above still hold their copies: no
+  // kernel below writes Q or Q1.
   // Q3 = Q/3 + 2/3 (Q2 + dt R(Q2)):  B2 = 2/3 (Qb3 + dt J(Q2)^T Qb3)
-  if ((r = run_combine(g, b2, q_bar, nullptr, nullptr, 1.0, 0.0, 0.0, st))) return r;
   if ((r = fill(g, q2, st))) return r;
-  if ((r = run_adj_rhs(g, q2, q_bar, b2, 2, 2.0 / 3.0, 2.0 / 3.0 * dt, aw, st))) return r;
+  if ((r = run_adj_rhs(g, q2, q_bar, b2, 3, 2.0 / 3.0, 2.0 / 3.0 * dt, aw, st))) return r;
   // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1)):  B1 = 1/4 (B2 + dt J(Q1)^T B2)
-  if ((r = run_combine(g, b1, b2, nullptr, nullptr, 1.0, 0.0, 0.0, st))) return r;
-  if ((r = fill(g, q1, st))) return r;
-  if ((r = run_adj_rhs(g, q1, b2, b1, 2, 0.25, 0.25 * dt, aw, st))) return r;
+  if ((r = run_adj_rhs(g, q1, b2, b1, 3, 0.25, 0.25 * dt, aw, st))) return r;
   // Q1 = Q + dt R(Q):  Qb = Qb3/3 + 3/4 B2 + B1 + dt J(Q)^T B1
   if ((r = run_combine(g, q_bar, q_bar, b2, b1, 1.0 / 3.0, 0.75, 1.0, st))) return r;
-  if ((r = fill(g, q_n, st))) return r;
   if ((r = run_adj_rhs(g, q_n, b1, q_bar, 2, 1.0, dt, aw, st))) return r;
   return ok();
 }
