@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 7
+#define SNAP_ABI_VERSION 8
 
 /* return codes */
 #define SNAP_OK 0
@@ -227,7 +227,9 @@ int snap_rhs(const snap_grid* g, void* q, void* rhs, void* stream);
  *   Q <- 1/3 Q + 2/3 (Q2 + dt R(Q2)).
  * q     padded state: interior in = Q^n, interior out = Q^{n+1}; ghost layers on
  *       return are unspecified (snap_fill_ghosts refreshes them).
- * work  device workspace of snap_workspace_bytes(g, SNAP_OP_RK3) bytes.
+ * work  device workspace of snap_workspace_bytes(g, SNAP_OP_RK3) bytes; on
+ *       return it holds the stage states Q1 and Q2 (interiors; see
+ *       snap_rk3_step_adjoint_stages for the layout).
  */
 int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stream);
 
@@ -262,6 +264,24 @@ int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_b
  */
 int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar, void* work,
                           void* stream);
+
+/*
+ * snap_rk3_step_adjoint with the stage states kept from the forward step
+ * instead of recomputed (Sec. 4.3, the same reverse of the three stages):
+ * two stage kernels fewer per step, for callers that can hold the stage states
+ * of every step they walk back through (two padded states per step).
+ * stages  the workspace (SNAP_OP_RK3) of the snap_rk3_step call that advanced
+ *         Q^n with this dt: on return snap_rk3_step leaves Q1 in its first
+ *         padded block and Q2 in the block that starts at the first multiple
+ *         of 256 bytes past it. Their ghost cells are overwritten here, their
+ *         interiors read; the step must not have been followed by another
+ *         call that uses the same workspace.
+ * q_n, q_bar, work, errors: as for snap_rk3_step_adjoint (work of
+ *         snap_workspace_bytes(g, SNAP_OP_RK3_ADJ) bytes, of which the first
+ *         two padded blocks go unused); SNAP_E_INVALID if stages is NULL.
+ */
+int snap_rk3_step_adjoint_stages(const snap_grid* g, void* q_n, void* stages, double dt,
+                                 void* q_bar, void* work, void* stream);
 
 /*
  * Largest stable step dt = cfl / max over interior cells of

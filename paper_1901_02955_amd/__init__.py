@@ -21,7 +21,7 @@ __all__ = [
     "snap_fill_ghosts", "snap_rhs", "snap_rk3_step", "snap_cfl_dt",
     "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
     "snap_stage_timing_enable", "snap_stage_timing_read", "snap_rhs_adjoint",
-    "snap_rk3_step_adjoint", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ", "snap_rk3_step_cfl",
+    "snap_rk3_step_adjoint", "snap_rk3_step_adjoint_stages", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ", "snap_rk3_step_cfl",
     "snap_rk3_steps_cfl",
     "SNAP_OP_RK3_CFL",
     "snap_batched_workspace_bytes", "snap_batched_tile_variant", "snap_rk3_step_batched",
@@ -48,7 +48,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 7
+SNAP_ABI_VERSION = 8
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
@@ -155,6 +155,7 @@ _SIGNATURES = {
     "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_rhs_adjoint": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P]),
     "snap_rk3_step_adjoint": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P, _P]),
+    "snap_rk3_step_adjoint_stages": (ctypes.c_int, [_GP, _P, _P, ctypes.c_double, _P, _P, _P]),
     "snap_batched_workspace_bytes": (ctypes.c_size_t, [_GP, ctypes.c_int]),
     "snap_batched_tile_variant": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                  ctypes.POINTER(ctypes.c_int),
@@ -413,6 +414,23 @@ def snap_rk3_step_adjoint(grid: DeviceGrid, q_n: torch.Tensor, dt: float, q_bar:
     _check(lib().snap_rk3_step_adjoint(grid.ptr(), ctypes.c_void_p(q_n.data_ptr()),
                                        ctypes.c_double(dt), ctypes.c_void_p(q_bar.data_ptr()),
                                        ctypes.c_void_p(work.data_ptr()), _stream(stream)))
+
+
+def snap_rk3_step_adjoint_stages(grid: DeviceGrid, q_n: torch.Tensor, stages: torch.Tensor,
+                                 dt: float, q_bar: torch.Tensor, work: torch.Tensor,
+                                 stream=None) -> None:
+    """Adjoint of the step whose ``snap_rk3_step`` call used ``stages`` as its workspace."""
+    grid._check_state(q_n)
+    grid._check_state(q_bar, "q_bar", grid.interior_shape)
+    if stages.numel() < snap_workspace_bytes(grid, SNAP_OP_RK3):
+        raise ValueError("stages is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3)")
+    if work.numel() < snap_workspace_bytes(grid, SNAP_OP_RK3_ADJ):
+        raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3_ADJ)")
+    _check(lib().snap_rk3_step_adjoint_stages(grid.ptr(), ctypes.c_void_p(q_n.data_ptr()),
+                                              ctypes.c_void_p(stages.data_ptr()),
+                                              ctypes.c_double(dt),
+                                              ctypes.c_void_p(q_bar.data_ptr()),
+                                              ctypes.c_void_p(work.data_ptr()), _stream(stream)))
 
 
 def _grid_array(grids):

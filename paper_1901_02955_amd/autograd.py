@@ -6,7 +6,10 @@ through them with ``snap_rk3_step_adjoint`` (the discrete adjoint of the
 three-stage scheme of Sec. 4.3 with fixed dt). Memory is bounded by step
 checkpointing: the forward pass keeps the state every ``checkpoint_every``
 steps; the backward pass re-runs each segment from its checkpoint, keeping the
-segment's states, and then walks it in reverse.
+segment's states, and then walks it in reverse. With ``keep_stages`` (the
+default) the re-run also keeps every step's two stage states, so that the
+adjoint step does not recompute them (``snap_rk3_step_adjoint_stages``): a
+segment then holds three padded states per step instead of one.
 
 Only the interior of the state carries gradients: the library overwrites ghost
 layers from the interior on every call, so the gradient with respect to the
@@ -18,7 +21,7 @@ from __future__ import annotations
 import torch
 
 from . import (SNAP_NG, SNAP_OP_RK3, SNAP_OP_RK3_ADJ, DeviceGrid, snap_rk3_step,
-               snap_rk3_step_adjoint, workspace)
+               snap_rk3_step_adjoint, snap_rk3_step_adjoint_stages, workspace)
 
 
 def _interior(grid: DeviceGrid, q: torch.Tensor) -> torch.Tensor:
@@ -30,7 +33,7 @@ def _interior(grid: DeviceGrid, q: torch.Tensor) -> torch.Tensor:
 class _SnapRK3Run(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q0: torch.Tensor, grid: DeviceGrid, dt: float, nsteps: int,
-                checkpoint_every: int):
+                checkpoint_every: int, keep_stages: bool):
         work = workspace(grid, SNAP_OP_RK3)
         q = q0.detach().clone()
         checkpoints = []
@@ -39,6 +42,7 @@ class _SnapRK3Run(torch.autograd.Function):
                 checkpoints.append(q.clone())
             snap_rk3_step(grid, q, dt, work)
         ctx.grid, ctx.dt, ctx.nsteps, ctx.every = grid, dt, nsteps, checkpoint_every
+        ctx.keep_stages = keep_stages
         ctx.checkpoints = checkpoints
         return q
 
@@ -52,22 +56,41 @@ class _SnapRK3Run(torch.autograd.Function):
             start = seg * every
             stop = min(start + every, nsteps)
             states = [ctx.checkpoints[seg].clone()]
-            for _ in range(start, stop - 1):
-                nxt = states[-1].clone()
-                snap_rk3_step(grid, nxt, dt, work)
-                states.append(nxt)
-            for t in range(stop - start - 1, -1, -1):
-                snap_rk3_step_adjoint(grid, states[t], dt, qbar, awork)
+            if ctx.keep_stages:
+                # every step of the segment, the last included, for its stage states
+                stages = []
+                for t in range(start, stop):
+                    stages.append(workspace(grid, SNAP_OP_RK3))
+                    nxt = states[-1].clone()
+                    snap_rk3_step(grid, nxt, dt, stages[-1])
+                    if t < stop - 1:
+                        states.append(nxt)
+                for t in range(stop - start - 1, -1, -1):
+                    snap_rk3_step_adjoint_stages(grid, states[t], stages[t], dt, qbar, awork)
+                del stages
+            else:
+                for _ in range(start, stop - 1):
+                    nxt = states[-1].clone()
+                    snap_rk3_step(grid, nxt, dt, work)
+                    states.append(nxt)
+                for t in range(stop - start - 1, -1, -1):
+                    snap_rk3_step_adjoint(grid, states[t], dt, qbar, awork)
             del states
         grad_in = torch.zeros_like(grad_out)
         _interior(grid, grad_in).copy_(qbar)
         ctx.checkpoints = None
-        return grad_in, None, None, None, None
+        return grad_in, None, None, None, None, None
 
 
 def rk3_run(grid: DeviceGrid, q0: torch.Tensor, dt: float, nsteps: int,
-            checkpoint_every: int = 20) -> torch.Tensor:
-    """State after ``nsteps`` SSP-RK3 steps of fixed ``dt``; differentiable in q0's interior."""
+            checkpoint_every: int = 20, keep_stages: bool = True) -> torch.Tensor:
+    """State after ``nsteps`` SSP-RK3 steps of fixed ``dt``; differentiable in q0's interior.
+
+    keep_stages: keep the stage states of a segment's steps for the backward
+    pass (three padded states per step of a segment) instead of recomputing
+    them in every adjoint step (one per step).
+    """
     if nsteps < 1 or checkpoint_every < 1:
         raise ValueError("nsteps and checkpoint_every must be >= 1")
-    return _SnapRK3Run.apply(q0, grid, float(dt), int(nsteps), int(checkpoint_every))
+    return _SnapRK3Run.apply(q0, grid, float(dt), int(nsteps), int(checkpoint_every),
+                             bool(keep_stages))

@@ -783,8 +783,9 @@ int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_b
   return ok();
 }
 
-int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar, void* work,
-                          void* stream) {
+// Checks shared by both RK3 adjoint entry points.
+static int check_rk3_adjoint(const snap_grid* g, const void* q_n, double dt, const void* q_bar,
+                             const void* work) {
   int r = check_grid(g);
   if (r) return r;
   if (!q_n || !q_bar || !work) return fail(SNAP_E_INVALID, "q_n, q_bar or work is NULL");
@@ -793,6 +794,28 @@ int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar,
     return fail(SNAP_E_UNSUPPORTED, "the adjoint takes passive tracers (eos = SNAP_EOS_PASSIVE)");
   if (g->riemann != SNAP_RIEMANN_LMARS)
     return fail(SNAP_E_UNSUPPORTED, "the adjoint takes the LMARS flux");
+  return SNAP_OK;
+}
+
+// Reverse of the three stages, given Q, Q1 and Q2 with their ghost cells
+// filled (no kernel below writes them); b2, b1: interior scratch; aw: the
+// right-hand-side adjoint's workspace.
+static int rk3_adjoint_reverse(const snap_grid* g, void* q_n, void* q1, void* q2, double dt,
+                               void* q_bar, void* b2, void* b1, void* aw, hipStream_t st) {
+  int r;
+  // Q3 = Q/3 + 2/3 (Q2 + dt R(Q2)):  B2 = 2/3 (Qb3 + dt J(Q2)^T Qb3)
+  if ((r = run_adj_rhs(g, q2, q_bar, b2, 3, 2.0 / 3.0, 2.0 / 3.0 * dt, aw, st))) return r;
+  // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1)):  B1 = 1/4 (B2 + dt J(Q1)^T B2)
+  if ((r = run_adj_rhs(g, q1, b2, b1, 3, 0.25, 0.25 * dt, aw, st))) return r;
+  // Q1 = Q + dt R(Q):  Qb = Qb3/3 + 3/4 B2 + B1 + dt J(Q)^T B1
+  if ((r = run_combine(g, q_bar, q_bar, b2, b1, 1.0 / 3.0, 0.75, 1.0, st))) return r;
+  return run_adj_rhs(g, q_n, b1, q_bar, 2, 1.0, dt, aw, st);
+}
+
+int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar, void* work,
+                          void* stream) {
+  int r = check_rk3_adjoint(g, q_n, dt, q_bar, work);
+  if (r) return r;
   const hipStream_t st = (hipStream_t)stream;
   char* b = static_cast<char*>(work);
   void* q1 = b;
@@ -818,16 +841,28 @@ int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar,
   a.ca = 0.75;
   a.cb = 0.25;
   if ((r = run_stage(g, a, st))) return r;
-  // The ghost cells of Q and Q1 filled above still hold their copies: no
-  // kernel below writes Q or Q1.
-  // Q3 = Q/3 + 2/3 (Q2 + dt R(Q2)):  B2 = 2/3 (Qb3 + dt J(Q2)^T Qb3)
   if ((r = fill(g, q2, st))) return r;
-  if ((r = run_adj_rhs(g, q2, q_bar, b2, 3, 2.0 / 3.0, 2.0 / 3.0 * dt, aw, st))) return r;
-  // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1)):  B1 = 1/4 (B2 + dt J(Q1)^T B2)
-  if ((r = run_adj_rhs(g, q1, b2, b1, 3, 0.25, 0.25 * dt, aw, st))) return r;
-  // Q1 = Q + dt R(Q):  Qb = Qb3/3 + 3/4 B2 + B1 + dt J(Q)^T B1
-  if ((r = run_combine(g, q_bar, q_bar, b2, b1, 1.0 / 3.0, 0.75, 1.0, st))) return r;
-  if ((r = run_adj_rhs(g, q_n, b1, q_bar, 2, 1.0, dt, aw, st))) return r;
+  if ((r = rk3_adjoint_reverse(g, q_n, q1, q2, dt, q_bar, b2, b1, aw, st))) return r;
+  return ok();
+}
+
+int snap_rk3_step_adjoint_stages(const snap_grid* g, void* q_n, void* stages, double dt,
+                                 void* q_bar, void* work, void* stream) {
+  int r = check_rk3_adjoint(g, q_n, dt, q_bar, work);
+  if (r) return r;
+  if (!stages) return fail(SNAP_E_INVALID, "stages is NULL");
+  const hipStream_t st = (hipStream_t)stream;
+  // the stage states as snap_rk3_step leaves them in its workspace
+  void* q1 = stages;
+  void* q2 = static_cast<char*>(stages) + align256(padded_bytes(g));
+  char* b = static_cast<char*>(work);
+  void* b2 = b + 2 * align256(padded_bytes(g));
+  void* b1 = static_cast<char*>(b2) + align256(interior_bytes(g));
+  void* aw = static_cast<char*>(b1) + align256(interior_bytes(g));
+  if ((r = fill(g, q_n, st))) return r;
+  if ((r = fill(g, q1, st))) return r;
+  if ((r = fill(g, q2, st))) return r;
+  if ((r = rk3_adjoint_reverse(g, q_n, q1, q2, dt, q_bar, b2, b1, aw, st))) return r;
   return ok();
 }
 

@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 7
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 8
 
 
 def good_grid(**kw):
@@ -103,6 +103,8 @@ def test_invalid_grid_rejected_by_every_entry_point(kw):
         lambda: lib.snap_conservation_sums(g, P, P, sums, None),
         lambda: lib.snap_rhs_adjoint(g, P, ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE), P, None),
         lambda: lib.snap_rk3_step_adjoint(g, P, 0.1, ctypes.c_void_p(2 * FAKE), P, None),
+        lambda: lib.snap_rk3_step_adjoint_stages(g, P, ctypes.c_void_p(4 * FAKE), 0.1,
+                                                 ctypes.c_void_p(2 * FAKE), P, None),
     ]
     for call in calls:
         assert call() == snap.SNAP_E_INVALID
@@ -153,6 +155,13 @@ def test_invalid_buffers_and_scalars():
     for dt in (0.0, -1.0, math.nan):
         assert lib.snap_rk3_step_adjoint(g, P, dt, Q2, Q3, None) == snap.SNAP_E_INVALID
     assert lib.snap_rk3_step_adjoint(g, P, 0.1, None, Q3, None) == snap.SNAP_E_INVALID
+    Q4 = ctypes.c_void_p(4 * FAKE)
+    for dt in (0.0, -1.0, math.nan):
+        assert lib.snap_rk3_step_adjoint_stages(g, P, Q4, dt, Q2, Q3, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_adjoint_stages(g, P, None, 0.1, Q2, Q3, None) == snap.SNAP_E_INVALID
+    assert b"stages" in lib.snap_last_error()
+    assert lib.snap_rk3_step_adjoint_stages(g, P, Q4, 0.1, None, Q3, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_adjoint_stages(g, P, Q4, 0.1, Q2, None, None) == snap.SNAP_E_INVALID
 
 
 def test_two_d_ignores_y_spacing_and_bc():
@@ -249,6 +258,8 @@ def test_mixture_fields_and_unsupported_entry_points():
     Q2, Q3 = ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE)
     assert lib.snap_rhs_adjoint(g, P, Q2, Q3, P, None) == snap.SNAP_E_UNSUPPORTED
     assert lib.snap_rk3_step_adjoint(g, P, 0.1, Q2, Q3, None) == snap.SNAP_E_UNSUPPORTED
+    assert lib.snap_rk3_step_adjoint_stages(g, P, ctypes.c_void_p(4 * FAKE), 0.1, Q2, Q3,
+                                            None) == snap.SNAP_E_UNSUPPORTED
     arr = (snap.SnapGridC * 2)(good_grid(ny=1, eos=1), good_grid(ny=1, eos=1))
     assert lib.snap_batched_workspace_bytes(arr, 2) == 0
     assert b"mixture" in lib.snap_last_error()
@@ -358,6 +369,8 @@ def test_hllc_refuses_the_mixture_and_is_refused_by_adjoint_and_batched():
     assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) > 0
     assert lib.snap_rhs_adjoint(g, P, Q2, Q3, P, None) == snap.SNAP_E_UNSUPPORTED
     assert lib.snap_rk3_step_adjoint(g, P, 0.1, Q2, Q3, None) == snap.SNAP_E_UNSUPPORTED
+    assert lib.snap_rk3_step_adjoint_stages(g, P, ctypes.c_void_p(4 * FAKE), 0.1, Q2, Q3,
+                                            None) == snap.SNAP_E_UNSUPPORTED
     arr = (snap.SnapGridC * 2)(good_grid(ny=1, riemann=1), good_grid(ny=1, riemann=1))
     assert lib.snap_batched_workspace_bytes(arr, 2) == 0
     mixed = ctypes.byref(good_grid(riemann=1, eos=1))

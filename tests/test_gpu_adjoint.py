@@ -12,7 +12,11 @@ Bars (FP64):
   (relative agreement 1e-6, the truncation and rounding error of the quotient);
 * the adjoint is reproducible bit for bit;
 * the checkpointed multi-step autograd function matches step-by-step adjoints
-  and a finite-difference directional derivative of the loss.
+  and a finite-difference directional derivative of the loss;
+* snap_rk3_step_adjoint_stages, fed the stage states a forward snap_rk3_step
+  left in its workspace, gives the same bits as snap_rk3_step_adjoint, which
+  recomputes them (the same kernels on the same stage states), and rk3_run
+  gives the same gradient with and without kept stage states.
 States at rest are left out: there the interface velocity u* is rounding noise
 around zero, where LMARS switches its upwind side, so two correct evaluation
 orders may linearise on different sides of the switch.
@@ -72,6 +76,40 @@ def test_rk3_step_adjoint_fp64(name):
     errs = field_errors(qb.cpu().numpy(), ref)
     print("   errors", ["%.2e" % e for e in errs], flush=True)
     assert all(e <= TOL_ADJ for e in errs), errs
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", ["2d_smooth_37x29_nt3", "3d_smooth_35x21x19",
+                                  "3d_tracers_20x18x24_nt4", "3d_xwall_19x17x12",
+                                  "3d_tiny_periodic_2x2x5"])
+def test_rk3_step_adjoint_kept_stages(name, dtype):
+    c = case(name)
+    print(f"[adjoint] kept stages {name} {dtype}", flush=True)
+    dg = snap.device_grid(c.grid, dtype=dtype)
+    qn = torch.as_tensor(c.q).to(dtype).cuda()
+    qb0 = torch.as_tensor(wl.seeded_normal(c.grid.interior_shape, 102)).to(dtype).cuda()
+    stages = snap.workspace(dg, snap.SNAP_OP_RK3)
+    snap.snap_rk3_step(dg, qn.clone(), c.dt, stages)
+    aw = snap.workspace(dg, snap.SNAP_OP_RK3_ADJ)
+    qb_kept = qb0.clone()
+    snap.snap_rk3_step_adjoint_stages(dg, qn.clone(), stages, c.dt, qb_kept, aw)
+    qb_re = qb0.clone()
+    snap.snap_rk3_step_adjoint(dg, qn.clone(), c.dt, qb_re, aw)
+    assert torch.isfinite(qb_kept).all()
+    assert torch.equal(qb_kept, qb_re)
+
+
+def test_rk3_run_kept_stages_same_gradient():
+    c = case("3d_xwall_19x17x12")
+    print("[adjoint] rk3_run keep_stages on / off", flush=True)
+    dg = snap.device_grid(c.grid)
+    grads = []
+    for keep in (True, False):
+        q0 = torch.as_tensor(c.q).cuda().requires_grad_(True)
+        out = rk3_run(dg, q0, c.dt, 5, 2, keep_stages=keep)
+        _loss(c.grid, out).backward()
+        grads.append(q0.grad.detach().clone())
+    assert torch.equal(grads[0], grads[1])
 
 
 @pytest.mark.parametrize("name", ["2d_smooth_37x29_nt3", "3d_smooth_35x21x19"])
