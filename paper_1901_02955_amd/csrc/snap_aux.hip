@@ -108,8 +108,11 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 }
 
 // One block per interior row (k, j) at a time, its threads along x: the
-// row's offset is formed once, and no per-cell division is needed.
-template <typename T>
+// row's offset is formed once, and no per-cell division is needed. NT: the
+// tracer count under the mixture equation of state (0: the passive gas, whose
+// tracers the signal speed does not read); a compile-time count lets a
+// cell's tracer loads issue together with its five others.
+template <typename T, int NT>
 __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
                                              unsigned long long* __restrict__ out) {
   unsigned long long b = 0ULL;  // bit pattern of the running maximum
@@ -128,18 +131,16 @@ __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
       const double u = mx * inv, v = my * inv, w = mz * inv;
       const double K = 0.5 * ((mx * u + my * v) + mz * w);
       double p, gam;
-      if (a.mix) {
+      if constexpr (NT > 0) {
         // mixture equation of state: p and the parcel's effective gamma
         double A = 0.0, num = 1.0, den = 1.0;
 #pragma unroll
-        for (int t = 0; t < MAX_TRACERS; ++t) {
-          if (t < a.ntracer) {   // constant indices: the argument stays out of scratch
-            const double rt = q[o + (5 + t) * a.sv];
-            const double qt = rt * inv;
-            A = t == 0 ? a.m.mu[0] * rt : A + a.m.mu[t] * rt;
-            num = num + a.m.a[t] * qt;
-            den = den + a.m.b[t] * qt;
-          }
+        for (int t = 0; t < NT; ++t) {   // constant indices: the argument stays out of scratch
+          const double rt = q[o + (5 + t) * a.sv];
+          const double qt = rt * inv;
+          A = t == 0 ? a.m.mu[0] * rt : A + a.m.mu[t] * rt;
+          num = num + a.m.a[t] * qt;
+          den = den + a.m.b[t] * qt;
         }
         const double ratio = num / den;
         p = (a.gm1 * ratio) * ((E - K) - A);
@@ -250,12 +251,29 @@ int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* o
   long long nb = (long long)a.ny * a.nz;   // rows
   if (nb > CFL_BLOCKS) nb = CFL_BLOCKS;
   if (nb < 1) nb = 1;
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_cfl<double>, dim3((unsigned)nb), dim3(256), 0, st,
-                       static_cast<const double*>(q), a, out);
-  else
-    hipLaunchKernelGGL(k_cfl<float>, dim3((unsigned)nb), dim3(256), 0, st,
-                       static_cast<const float*>(q), a, out);
+  const int nt = a.mix ? a.ntracer : 0;
+  if (nt < 0 || nt > MAX_TRACERS) return -1;
+  switch (nt) {
+#define SNAP_CFL_CASE(N)                                                                  \
+  case N:                                                                                 \
+    if (dtype == 0)                                                                       \
+      hipLaunchKernelGGL((k_cfl<double, N>), dim3((unsigned)nb), dim3(256), 0, st,        \
+                         static_cast<const double*>(q), a, out);                          \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_cfl<float, N>), dim3((unsigned)nb), dim3(256), 0, st,         \
+                         static_cast<const float*>(q), a, out);                           \
+    break;
+    SNAP_CFL_CASE(0)
+    SNAP_CFL_CASE(1)
+    SNAP_CFL_CASE(2)
+    SNAP_CFL_CASE(3)
+    SNAP_CFL_CASE(4)
+    SNAP_CFL_CASE(5)
+    SNAP_CFL_CASE(6)
+    SNAP_CFL_CASE(7)
+    SNAP_CFL_CASE(8)
+#undef SNAP_CFL_CASE
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
