@@ -337,6 +337,101 @@ def convection_3d(nx=256, ny=256, nz=128, lx=20e3, ly=20e3, lz=10e3, noise=0.1, 
     return grid, q, dth
 
 
+def convection_flow_3d(nx=256, ny=256, nz=128, lx=20e3, ly=20e3, lz=10e3, noise=0.1, nlev=10,
+                       seed=1, flow_levels=16, seed_flow=37, p_amp=30.0):
+    """Base point of the gradient workload: the convection state plus a seeded
+    smooth flow in the top ``flow_levels`` levels.
+
+    Returns (grid, base, dtheta, vel): the theta perturbation (K, shape
+    (nz, ny, nx)) of ``convection_3d`` with the same seed, and a velocity
+    field (m/s, shape (3, nz, ny, nx)) that is zero below the top levels.
+    There each component is a sum of three horizontal Fourier modes with
+    seeded wave numbers (1 to 3 per axis), phases and weights, scaled by a
+    vertical envelope sin^2 that rises from about 0 at the lowest flow level
+    to 1 at the top: u = e (3 + 1.5 m_u), v = e (2 + 1 m_v) and w = e m_w,
+    with |m| <= 1. The horizontal components are then positive, so no x or y
+    interface velocity crosses zero where the upwind side of the Riemann flux
+    switches, and the flow is smooth, so that where the vertical one does the
+    two sides' states nearly agree and the switch leaves the map almost
+    differentiable. Without the flow the top levels are at rest for the whole
+    run (sound crosses about 60 levels in 200 steps) and a kinetic-energy loss
+    there is quadratic in round-off velocities.
+
+    Also returned: a smooth pressure perturbation dp (Pa, (nz, ny, nx)) of
+    amplitude ``p_amp`` everywhere, three seeded horizontal modes times
+    cos(pi kz z / lz) (kz in {1, 2}, so it mirrors smoothly at the lids).
+    Without it p - pbar is round-off, and any perturbation of the state moves
+    it across sqrt(weno_eps) (about 1e-3 Pa), the scale on which the
+    Jiang-Shu weights of p' bend; with it p' varies by Pa from cell to cell
+    and small perturbations stay in the weights' smooth regime. The state
+    follows from these by ``state_from_theta``.
+    """
+    grid, base = dry_grid(nx, ny, nz, lx, ly, lz)
+    rng = np.random.default_rng(seed)
+    dth = np.zeros((nz, ny, nx))
+    k = min(nlev, nz)
+    dth[:k] = rng.uniform(-noise, noise, size=(k, ny, nx))
+    vel = np.zeros((3, nz, ny, nx))
+    kf = min(flow_levels, nz)
+    fr = np.random.default_rng(seed_flow)
+    x = cell_centres(nx, 1.0 / nx)[None, :]
+    y = cell_centres(ny, 1.0 / ny)[:, None]
+
+    def modes():
+        m = np.zeros((ny, nx))
+        wts = fr.uniform(0.5, 1.0, size=3)
+        for a in wts:
+            kx, ky = fr.integers(1, 4, size=2)
+            ph = fr.uniform(0.0, 2.0 * np.pi)
+            m += a * np.sin(2.0 * np.pi * (kx * x + ky * y) + ph)
+        return m / wts.sum()
+
+    mu, mv, mw = modes(), modes(), modes()
+    lev = np.arange(kf, dtype=np.float64)
+    env = np.sin(0.5 * np.pi * (lev + 0.5) / kf) ** 2
+    for j, (c, a, m) in enumerate(((3.0, 1.5, mu), (2.0, 1.0, mv), (0.0, 1.0, mw))):
+        vel[j, nz - kf:] = env[:, None, None] * (c + a * m)[None]
+    zc = cell_centres(nz, 1.0 / nz)[:, None, None]
+    dp = np.zeros((nz, ny, nx))
+    pw = fr.uniform(0.5, 1.0, size=3)
+    for a in pw:
+        kz = fr.integers(1, 3)
+        dp += a * np.cos(np.pi * kz * zc) * modes()[None]
+    dp *= p_amp / pw.sum()
+    return grid, base, dth, vel, dp
+
+
+def state_from_theta(grid: Grid, base: DryIsentropic, dtheta, vel, dp=None):
+    """Padded conserved state (torch) from a theta perturbation and a velocity field.
+
+    The density is perturbed at constant pressure, rho = rhobar_k theta0 /
+    (theta0 + theta'), the pressure is the cell reference pbar_k plus ``dp``
+    (if given), and E = p / (gamma - 1) + rho |u|^2 / 2; ghost cells are zero.
+    ``dtheta`` (nz, ny, nx), ``vel`` (3, nz, ny, nx) and ``dp`` are torch
+    tensors of one dtype and device; the result has that dtype and device and
+    is differentiable in them (torch autograd), so that a gradient with
+    respect to the state's interior carries over to one with respect to
+    theta'.
+    """
+    import torch
+
+    dev, dt_ = dtheta.device, dtheta.dtype
+    nz = grid.nz
+    rc = torch.as_tensor(grid.rhobar_cell[G:G + nz], dtype=dt_, device=dev)[:, None, None]
+    pc = torch.as_tensor(grid.pbar_cell[G:G + nz], dtype=dt_, device=dev)[:, None, None]
+    rho = rc * base.theta0 / (base.theta0 + dtheta)
+    mom = rho * vel
+    p = pc if dp is None else pc + dp
+    e = p / (grid.gamma - 1.0) + 0.5 * rho * (vel * vel).sum(dim=0)
+    q = torch.zeros(grid.shape, dtype=dt_, device=dev)
+    gy = grid.gy
+    inner = q[:, G:G + nz, gy:gy + grid.ny, G:G + grid.nx]
+    inner[0] = rho
+    inner[1:4] = mom
+    inner[4] = e
+    return q
+
+
 JOVIAN_MU = 2.3e-3       # kg/mol
 JOVIAN_CP = 12400.0      # J/(kg K)
 JOVIAN_G = 24.79         # m/s^2
