@@ -161,9 +161,10 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     esize = 8 if dtype == torch.float64 else 4
     nvar = dg.nvar
     bytes_per_launch = 8.0 / 3.0 * nvar * esize * cells
-    # the last stage of every timed step but the call's last also reduces the
-    # next step's signal speed (3-D, no tracers): its flops count, per launch
-    fused_share = (steps - 1) / (3.0 * steps)
+    # the last stage of every timed step also reduces the signal speed of the
+    # state it writes (3-D, no tracers: the next step's time step, and the
+    # state check after the call's last step): its flops count, per launch
+    fused_share = 1.0 / 3.0
     flops_per_launch = (algorithmic_flops_per_cell_stage(dg.ntracer, 3, hllc=hllc)
                         + CFL_FLOPS_PER_CELL * fused_share) * cells
     avg_launch_s = stage_ms / 1e3 / max(launches, 1)

@@ -24,9 +24,11 @@
  * Field order: rho, rho*u, rho*v, rho*w, E, then ntracer tracer densities.
  * Element type: double for SNAP_F64, float for SNAP_F32.
  *
- * Ghost layers of q are library scratch: every call that reads q overwrites
- * them from the interior according to `bc`. Interior cells of q are read-only
- * except in the time-stepping calls.
+ * Ghost layers of q are library scratch: a call that reads q either fills them
+ * from the interior according to `bc` or reads each ghost value at the
+ * interior cell it copies (the 3-D time-stepping calls without tracers), and
+ * leaves them unspecified. Interior cells of q are read-only except in the
+ * time-stepping and microphysics calls.
  *
  * Calls are asynchronous on `stream` (a hipStream_t, NULL = default stream),
  * except snap_cfl_dt and snap_conservation_sums, which return host values and
@@ -45,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 8
+#define SNAP_ABI_VERSION 9
 
 /* return codes */
 #define SNAP_OK 0
@@ -195,7 +197,8 @@ int snap_abi_version(void);
  * Bytes of device workspace `work` needed by operation `op` (SNAP_OP_*) on grid
  * g; 0 if none is needed. Returns 0 and sets the last error for an invalid grid.
  * SNAP_OP_RK3 and SNAP_OP_RHS_ADJ need two padded state arrays, SNAP_OP_RK3_CFL
- * the same plus 256 bytes, SNAP_OP_RK3_ADJ
+ * the same plus 256 bytes (two signal-speed slots and the state flag read by
+ * snap_rk3_steps_status), SNAP_OP_RK3_ADJ
  * four padded plus two interior arrays, SNAP_OP_CFL and SNAP_OP_SUMS a few
  * hundred kilobytes of reduction partials.
  */
@@ -306,8 +309,9 @@ int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_
  * work    device workspace of snap_workspace_bytes(g, SNAP_OP_RK3_CFL) bytes.
  * dt_dev  DEVICE pointer receiving the step's dt (one double), or NULL.
  * Argument errors are reported as by snap_rk3_step. A state that snap_cfl_dt
- * would reject (non-finite or non-positive density or pressure) cannot be
- * reported from the device: its dt and the new state are then not finite.
+ * would reject (non-finite or non-positive density or pressure) gives a dt and
+ * new states that are not finite; the call does not wait to report it, but it
+ * leaves a flag in `work` that snap_rk3_steps_status turns into SNAP_E_STATE.
  */
 int snap_rk3_step_cfl(const snap_grid* g, void* q, double cfl, void* work, double* dt_dev,
                       void* stream);
@@ -325,6 +329,22 @@ int snap_rk3_step_cfl(const snap_grid* g, void* q, double cfl, void* work, doubl
  */
 int snap_rk3_steps_cfl(const snap_grid* g, void* q, double cfl, int nsteps, void* work,
                        double* dt_dev, void* stream);
+
+/*
+ * State check of the last snap_rk3_step_cfl / snap_rk3_steps_cfl call that
+ * used `work` (a SNAP_OP_RK3_CFL workspace of grid g): synchronises `stream`
+ * and returns SNAP_E_STATE if the state that any step of that call started
+ * from had a non-finite or non-positive density or pressure somewhere (the
+ * CFL reduction of that state, Sec. 4.3's time step being this library's
+ * reading, is then NaN, and so are its dt and every later state), else
+ * SNAP_OK. On 3-D grids without tracers (whose last stage reduces the signal
+ * speed of the state it writes) the state the call ends with is checked too;
+ * on other grids that state is checked by the next step or by snap_cfl_dt.
+ * The flag is cleared by each device-dt call, not by this one; reading it
+ * costs one 8-byte copy. The result is undefined for a workspace that no such
+ * call has used.
+ */
+int snap_rk3_steps_status(const snap_grid* g, void* work, void* stream);
 
 /*
  * Sums over interior cells of every conserved field, accumulated in double

@@ -22,7 +22,7 @@ __all__ = [
     "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
     "snap_stage_timing_enable", "snap_stage_timing_read", "snap_rhs_adjoint",
     "snap_rk3_step_adjoint", "snap_rk3_step_adjoint_stages", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ", "snap_rk3_step_cfl",
-    "snap_rk3_steps_cfl",
+    "snap_rk3_steps_cfl", "snap_rk3_steps_status",
     "SNAP_OP_RK3_CFL",
     "snap_batched_workspace_bytes", "snap_batched_tile_variant", "snap_rk3_step_batched",
     "batched_workspace",
@@ -48,7 +48,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 8
+SNAP_ABI_VERSION = 9
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
@@ -151,6 +151,7 @@ _SIGNATURES = {
     "snap_rk3_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P]),
     "snap_rk3_step_cfl": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P, _P]),
     "snap_rk3_steps_cfl": (ctypes.c_int, [_GP, _P, ctypes.c_double, ctypes.c_int, _P, _P, _P]),
+    "snap_rk3_steps_status": (ctypes.c_int, [_GP, _P, _P]),
     "snap_cfl_dt": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_rhs_adjoint": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P]),
@@ -372,6 +373,15 @@ def snap_rk3_steps_cfl(grid: DeviceGrid, q: torch.Tensor, cfl: float, nsteps: in
     _check(lib().snap_rk3_steps_cfl(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
                                     ctypes.c_double(cfl), ctypes.c_int(nsteps),
                                     ctypes.c_void_p(work.data_ptr()), dptr, _stream(stream)))
+
+
+def snap_rk3_steps_status(grid: DeviceGrid, work: torch.Tensor, stream=None) -> None:
+    """Raise SnapError(SNAP_E_STATE) if a step of the last device-dt call that
+    used ``work`` met a non-finite or non-positive density or pressure."""
+    if work.numel() < snap_workspace_bytes(grid, SNAP_OP_RK3_CFL):
+        raise ValueError("work is smaller than snap_workspace_bytes(grid, SNAP_OP_RK3_CFL)")
+    _check(lib().snap_rk3_steps_status(grid.ptr(), ctypes.c_void_p(work.data_ptr()),
+                                       _stream(stream)))
 
 
 def snap_cfl_dt(grid: DeviceGrid, q: torch.Tensor, cfl: float, work: torch.Tensor,

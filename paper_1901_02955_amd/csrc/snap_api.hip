@@ -652,7 +652,8 @@ CflArgs cfl_args(const snap_grid* g) {
 // last reduces the new state's maximum signal speed into it.
 int rk3_stages(const snap_grid* g, void* q, double dt, const unsigned long long* smax,
                double cfl, double* dt_out, char* w, hipStream_t st,
-               unsigned long long* smax_next = nullptr) {
+               unsigned long long* smax_next = nullptr,
+               unsigned long long* state_flag = nullptr) {
   int r;
   void* q1 = w;
   void* q2 = w + align256(padded_bytes(g));
@@ -675,9 +676,11 @@ int rk3_stages(const snap_grid* g, void* q, double dt, const unsigned long long*
   a.cb = 1.0;
   a.dt_out = dt_out;
   a.smax_zero = smax_next;
+  a.state_flag = state_flag;
   if ((r = run_stage(g, a, st))) return r;
   a.dt_out = nullptr;
   a.smax_zero = nullptr;
+  a.state_flag = nullptr;
   // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1))
   if ((r = prepare(q1))) return r;
   a.qs = q1;
@@ -705,28 +708,42 @@ bool fused_speed_ok(const snap_grid* g) {
   return is3d(g) && ghosts_in_place(g->ntracer) && !sediment_of(g).on;
 }
 
+// The 256 bytes after the two padded stage states of the SNAP_OP_RK3_CFL
+// workspace: two signal-speed slots, then the state flag.
+unsigned long long* cfl_slots(const snap_grid* g, void* work) {
+  return reinterpret_cast<unsigned long long*>(static_cast<char*>(work) +
+                                               2 * align256(padded_bytes(g)));
+}
+
 // nsteps SSP-RK3 steps with the time step formed on the device. The maximum
 // signal speed of Q^n lives in one of two slots after the RK3 workspace: the
 // first comes from the reduction kernel; each later one from the previous
 // step's last stage where the kernels can fuse it, else from the kernel.
+// The state flag (the third word) is cleared first; the first stage of every
+// step raises it when its time step is not finite and positive, and where the
+// kernels fuse the reduction the last step also reduces the final state, which
+// a one-thread kernel then checks.
 int rk3_steps_cfl(const snap_grid* g, void* q, double cfl, int nsteps, void* work,
                   double* dt_dev, hipStream_t st) {
   char* w = static_cast<char*>(work);
-  unsigned long long* slot =
-      reinterpret_cast<unsigned long long*>(w + 2 * align256(padded_bytes(g)));
+  unsigned long long* slot = cfl_slots(g, work);
+  unsigned long long* flag = slot + 2;
   const bool fused = fused_speed_ok(g);
   const CflArgs ca = cfl_args(g);
+  if (launch_zero_u64(flag, 1, st)) return device_fail("flag clear launch");
   if (launch_cfl(g->dtype, q, ca, slot, st)) return device_fail("cfl kernel launch");
   for (int n = 0; n < nsteps; ++n) {
     unsigned long long* cur = slot + (n & 1);
     unsigned long long* nxt = slot + ((n + 1) & 1);
     const bool more = n + 1 < nsteps;
     const int r = rk3_stages(g, q, 0.0, cur, cfl, dt_dev ? dt_dev + n : nullptr, w, st,
-                             fused && more ? nxt : nullptr);
+                             fused ? nxt : nullptr, flag);
     if (r) return r;
     if (more && !fused && launch_cfl(g->dtype, q, ca, nxt, st))
       return device_fail("cfl kernel launch");
   }
+  if (fused && launch_flag_speed(slot + (nsteps & 1), flag, st))
+    return device_fail("flag kernel launch");
   return ok();
 }
 
@@ -764,6 +781,23 @@ int snap_rk3_steps_cfl(const snap_grid* g, void* q, double cfl, int nsteps, void
   if (!finite_pos(cfl)) return fail(SNAP_E_INVALID, "cfl must be finite and > 0");
   if (nsteps < 1) return fail(SNAP_E_INVALID, "nsteps must be >= 1");
   return rk3_steps_cfl(g, q, cfl, nsteps, work, dt_dev, (hipStream_t)stream);
+}
+
+int snap_rk3_steps_status(const snap_grid* g, void* work, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!work) return fail(SNAP_E_INVALID, "work is NULL");
+  const hipStream_t st = (hipStream_t)stream;
+  unsigned long long flag = 0;
+  if (hipMemcpyAsync(&flag, cfl_slots(g, work) + 2, sizeof flag, hipMemcpyDeviceToHost, st) !=
+      hipSuccess)
+    return device_fail("state flag copy");
+  if (hipStreamSynchronize(st) != hipSuccess) return device_fail("state flag synchronize");
+  if (flag != 0)
+    return fail(SNAP_E_STATE,
+                "a step of the last device-dt call met a non-finite or non-positive density or "
+                "pressure (its time step and every later state are not finite)");
+  return ok();
 }
 
 int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_bar, void* work,
@@ -1121,12 +1155,14 @@ int snap_cfl_dt(const snap_grid* g, void* q, double cfl, void* work, double* dt_
   return ok();
 }
 
-int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums_host,
-                           void* stream) {
-  int r = check_grid(g);
-  if (r) return r;
-  if (!q || !work || !sums_host) return fail(SNAP_E_INVALID, "q, work or sums_host is NULL");
-  const hipStream_t st = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// Conservation sums on validated arguments: partials in part[SUM_BLOCKS][nvar]
+// and the nvar results in out (device), copied to sums_host.
+int run_sums(const snap_grid* g, void* q, double* part, double* out, double* sums_host,
+             hipStream_t st) {
   SumArgs a;
   const bool d3 = is3d(g);
   const long long nxp = g->nx + 2 * SNAP_NG, nyp = d3 ? g->ny + 2 * SNAP_NG : 1;
@@ -1138,15 +1174,30 @@ int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums
   a.sy = nxp;
   a.sz = nxp * nyp;
   a.sv = a.sz * (g->nz + 2 * SNAP_NG);
-  double* part = static_cast<double*>(work);
-  double* out = reinterpret_cast<double*>(static_cast<char*>(work) +
-                                          align256((size_t)SUM_BLOCKS * a.nvar * sizeof(double)));
   if (launch_sums(g->dtype, q, a, part, out, st)) return device_fail("sums kernel launch");
   if (hipMemcpyAsync(sums_host, out, a.nvar * sizeof(double), hipMemcpyDeviceToHost, st) !=
       hipSuccess)
     return device_fail("sums copy");
   if (hipStreamSynchronize(st) != hipSuccess) return device_fail("sums synchronize");
   return ok();
+}
+
+// Offset (doubles) of the results after the partials of nvar variables.
+size_t sums_out_offset(int nvar) {
+  return align256((size_t)SUM_BLOCKS * nvar * sizeof(double)) / sizeof(double);
+}
+
+}  // namespace
+
+extern "C" {
+
+int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums_host,
+                           void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !work || !sums_host) return fail(SNAP_E_INVALID, "q, work or sums_host is NULL");
+  double* part = static_cast<double*>(work);
+  return run_sums(g, q, part, part + sums_out_offset(nvar_of(g)), sums_host, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -107,6 +107,17 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ULL;
 }
 
+// Raise *flag if the reduced maximum signal speed in *smax (IEEE bits) is not
+// finite and positive (a cell with non-finite or non-positive density or
+// pressure reduces to NaN).
+__global__ void k_flag_speed(const unsigned long long* __restrict__ smax,
+                             unsigned long long* __restrict__ flag) {
+  if (threadIdx.x == 0) {
+    const unsigned long long b = *smax;
+    if (b == 0ULL || b >= 0x7FF0000000000000ULL) *flag = 1ULL;
+  }
+}
+
 // One block per interior row (k, j) at a time, its threads along x: the
 // row's offset is formed once, and no per-cell division is needed. NT: the
 // tracer count under the mixture equation of state (0: the passive gas, whose
@@ -274,6 +285,16 @@ int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* o
     SNAP_CFL_CASE(8)
 #undef SNAP_CFL_CASE
   }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_zero_u64(unsigned long long* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_flag_speed(const unsigned long long* smax, unsigned long long* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_flag_speed, dim3(1), dim3(64), 0, st, smax, flag);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

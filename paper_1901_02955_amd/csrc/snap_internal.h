@@ -123,6 +123,8 @@ int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* o
 int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st);
 int launch_satadj(int dtype, int ntracer, void* q, const SatAdjArgs& a, hipStream_t st);
 int launch_sediment(int dtype, int ntracer, const StageArgs& a, hipStream_t st);
+int launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
+int launch_flag_speed(const unsigned long long* smax, unsigned long long* flag, hipStream_t st);
 int launch_sums(int dtype, const void* q, const SumArgs& a, double* part, double* out,
                 hipStream_t st);
 

@@ -87,6 +87,10 @@ struct StageArgs {
   // the step fills).
   unsigned long long* smax_out;
   unsigned long long* smax_zero;
+  // With the time step from the device (smax set): block 0 stores 1 here if
+  // that time step is not finite and positive, i.e. the reduced state had a
+  // non-finite or non-positive density or pressure somewhere.
+  unsigned long long* state_flag;
 };
 enum : int { GF_ON = 1, GF_RX = 2, GF_RY = 4, GF_RZ = 8 };
 
@@ -106,10 +110,14 @@ __device__ __forceinline__ double stage_dt(const StageArgs& a) {
   return a.cfl / __longlong_as_double(static_cast<long long>(*a.smax));
 }
 
-// Block 0 records the time step of the launch where the caller asked for it.
+// Block 0 records the time step of the launch where the caller asked for it,
+// and raises the state flag if that time step is not finite and positive.
 __device__ __forceinline__ void store_stage_dt(const StageArgs& a, double dt) {
-  if (a.dt_out != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-    *a.dt_out = dt;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (a.dt_out != nullptr) *a.dt_out = dt;
+    if (a.state_flag != nullptr && !(dt > 0.0 && dt <= 1.79769313486231570815e308))
+      *a.state_flag = 1ULL;
+  }
 }
 
 template <typename T>

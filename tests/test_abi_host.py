@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 8
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 9
 
 
 def good_grid(**kw):
