@@ -356,6 +356,23 @@ int snap_rk3_steps_status(const snap_grid* g, void* work, void* stream);
 int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums_host, void* stream);
 
 /*
+ * snap_conservation_sums without a workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The call allocates nothing: the partial
+ * sums live in a library-owned device array of SNAP_SUMS_NOALLOC_SCRATCH_BYTES
+ * bytes, which every GPU the library runs on holds (its own copy) until the
+ * process ends, and whose address is looked up on the first call on each
+ * device. It holds the partials of every valid grid (up to 5 +
+ * SNAP_MAX_TRACERS variables); a grid needing more returns SNAP_E_INVALID.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (other streams, other threads) race, and the caller must serialise them.
+ * Results equal those of snap_conservation_sums bit for bit; q, sums_host,
+ * the synchronisation of `stream` and the errors are as there.
+ */
+#define SNAP_SUMS_NOALLOC_SCRATCH_BYTES 53760
+int snap_conservation_sums_noalloc(const snap_grid* g, void* q, double* sums_host, void* stream);
+
+/*
  * Ensemble of independent 2-D (ny == 1) domains advanced by one SSP-RK3 step
  * each (Sec. 4.3), with per-member grids, states and time steps. Every stage
  * is one batched ghost-fill launch and one persistent stage launch for all

@@ -19,7 +19,8 @@ import torch
 __all__ = [
     "SnapError", "DeviceGrid", "device_grid", "lib", "workspace",
     "snap_fill_ghosts", "snap_rhs", "snap_rk3_step", "snap_cfl_dt",
-    "snap_conservation_sums", "snap_workspace_bytes", "snap_abi_version",
+    "snap_conservation_sums", "snap_conservation_sums_noalloc", "snap_workspace_bytes",
+    "snap_abi_version",
     "snap_stage_timing_enable", "snap_stage_timing_read", "snap_rhs_adjoint",
     "snap_rk3_step_adjoint", "snap_rk3_step_adjoint_stages", "SNAP_OP_RHS_ADJ", "SNAP_OP_RK3_ADJ", "snap_rk3_step_cfl",
     "snap_rk3_steps_cfl", "snap_rk3_steps_status",
@@ -154,6 +155,7 @@ _SIGNATURES = {
     "snap_rk3_steps_status": (ctypes.c_int, [_GP, _P, _P]),
     "snap_cfl_dt": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_conservation_sums": (ctypes.c_int, [_GP, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "snap_conservation_sums_noalloc": (ctypes.c_int, [_GP, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "snap_rhs_adjoint": (ctypes.c_int, [_GP, _P, _P, _P, _P, _P]),
     "snap_rk3_step_adjoint": (ctypes.c_int, [_GP, _P, ctypes.c_double, _P, _P, _P]),
     "snap_rk3_step_adjoint_stages": (ctypes.c_int, [_GP, _P, _P, ctypes.c_double, _P, _P, _P]),
@@ -399,6 +401,15 @@ def snap_conservation_sums(grid: DeviceGrid, q: torch.Tensor, work: torch.Tensor
     out = (ctypes.c_double * grid.nvar)()
     _check(lib().snap_conservation_sums(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
                                         ctypes.c_void_p(work.data_ptr()), out, _stream(stream)))
+    return np.array(out[:], dtype=np.float64)
+
+
+def snap_conservation_sums_noalloc(grid: DeviceGrid, q: torch.Tensor, stream=None) -> np.ndarray:
+    """snap_conservation_sums with the library's own scratch (no workspace)."""
+    grid._check_state(q)
+    out = (ctypes.c_double * grid.nvar)()
+    _check(lib().snap_conservation_sums_noalloc(grid.ptr(), ctypes.c_void_p(q.data_ptr()), out,
+                                                _stream(stream)))
     return np.array(out[:], dtype=np.float64)
 
 

@@ -1187,6 +1187,39 @@ size_t sums_out_offset(int nvar) {
   return align256((size_t)SUM_BLOCKS * nvar * sizeof(double)) / sizeof(double);
 }
 
+// Library-owned scratch of snap_conservation_sums_noalloc: the partials of up
+// to 5 + SNAP_MAX_TRACERS variables, then the results. Each GPU holds its own
+// copy at its own address; host code uses that address (from
+// hipGetSymbolAddress), never the array's name, which on the host is only a
+// stand-in.
+constexpr size_t NOALLOC_SUM_DOUBLES = SNAP_SUMS_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static_assert((size_t)SUM_BLOCKS * (5 + SNAP_MAX_TRACERS) + 5 + SNAP_MAX_TRACERS <=
+                  NOALLOC_SUM_DOUBLES,
+              "the sums scratch holds every valid grid's partials");
+static __device__ __align__(256) double scratch[NOALLOC_SUM_DOUBLES];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch;   // per device ordinal: device address of its scratch
+
+// Device address of the current device's scratch, looked up once per device
+// (with that device current) on its first use.
+int sums_scratch(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return device_fail("hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch.size() <= dev) g_scratch.resize(dev + 1, nullptr);
+  if (g_scratch[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(SNAP_E_DEVICE, "hipGetSymbolAddress of the sums scratch failed on device %d: %s",
+                  dev, hipGetErrorString(e));
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return SNAP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1198,6 +1231,19 @@ int snap_conservation_sums(const snap_grid* g, void* q, void* work, double* sums
   if (!q || !work || !sums_host) return fail(SNAP_E_INVALID, "q, work or sums_host is NULL");
   double* part = static_cast<double*>(work);
   return run_sums(g, q, part, part + sums_out_offset(nvar_of(g)), sums_host, (hipStream_t)stream);
+}
+
+int snap_conservation_sums_noalloc(const snap_grid* g, void* q, double* sums_host, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !sums_host) return fail(SNAP_E_INVALID, "q or sums_host is NULL");
+  const int nv = nvar_of(g);
+  if (sums_out_offset(nv) + nv > NOALLOC_SUM_DOUBLES)
+    return fail(SNAP_E_INVALID, "%d variables need %zu bytes of sums scratch, more than the %zu held",
+                nv, (sums_out_offset(nv) + nv) * sizeof(double), NOALLOC_SUM_DOUBLES * sizeof(double));
+  double* part = nullptr;
+  if ((r = sums_scratch(&part))) return r;
+  return run_sums(g, q, part, part + sums_out_offset(nv), sums_host, (hipStream_t)stream);
 }
 
 }  // extern "C"
