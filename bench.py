@@ -4,17 +4,20 @@
 Workload: 3-D dry convection, 256 x 256 x 128 cells (20 x 20 x 10 km), five
 conserved variables, isentropic 300 K hydrostatic base state, seeded uniform
 theta noise of +-0.1 K in the lowest 10 levels, periodic in x and y, rigid
-lids in z, CFL 0.9. One timed step = the CFL time step (one reduction over the
-state) + one three-stage SSP-RK3 step (three ghost fills + three fused stage
-kernels). The state lives in HBM before the timed region starts.
+lids in z, CFL 0.9. One timed step = one three-stage SSP-RK3 step whose time
+step dt = CFL / (maximum signal speed of Q^n) is formed on the device: three
+fused stage kernels that read the ghost cells at their sources (no fills),
+the last of which also reduces the next step's signal speed. The state lives
+in HBM before the timed region starts. `value` is the median of 5 timed
+calls of `--steps` steps each; the stage kernel's launch time comes from a
+separate pass with hipEvents around every stage launch.
 
 The FP64 path is the headline (`value`); the FP32 form (FP32 storage and
 stencil arithmetic, FP64 reference state and E -> p inversion) runs on the
 same workload and is reported under `variants.f32`.
 
-Roofline of the dominant kernel (the fused stage kernel), both from the
-kernel's average launch duration (hipEvents recorded around every stage launch
-of the timed region, on the launch stream):
+Roofline of the dominant kernel (the fused stage kernel), from its average
+launch duration:
 * `roofline` (bound "alu": the measured HBM traffic is far below the memory
   roofline, the kernel is limited by vector-ALU issue): algorithmic flops per
   launch = algorithmic_flops_per_cell_stage() x cells, against the MI355X
@@ -25,8 +28,9 @@ of the timed region, on the launch stream):
   the three launches), against 8 TB/s.
 
 CPU baseline: the FP64 oracle (PyTorch CPU, all host threads of this process)
-on a bounded sample of the same workload: 12 SSP-RK3 steps of a 128 x 128 x 128
-column block cut from the same initial state (periodic in x and y).
+on a bounded sample of the same workload: SSP-RK3 steps (4 to 24, about 15 s)
+of a 128 x 128 x 128 column block cut from the same initial state (periodic in
+x and y); `cpu_oracle_sections` times it on samples of the other workloads.
 """
 from __future__ import annotations
 
@@ -127,7 +131,37 @@ def measured_traffic(dtype_name: str):
     return _profile_value(f"bytes_per_launch_{dtype_name}")
 
 
-def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
+def _timed(fn, repeats: int):
+    """Wall-clock seconds of ``repeats`` calls of fn, each bracketed by device syncs."""
+    import torch
+
+    out = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        out.append(time.perf_counter() - t0)
+    return out
+
+
+def _stage_pass(fn):
+    """Average stage-kernel launch time (s) and launch count of one call of fn,
+    from hipEvents recorded around every stage launch on its stream."""
+    import torch
+
+    import paper_1901_02955_amd as snap
+
+    torch.cuda.synchronize()
+    snap.snap_stage_timing_enable(True)
+    fn()
+    torch.cuda.synchronize()
+    ms, n = snap.snap_stage_timing_read()
+    snap.snap_stage_timing_enable(False)
+    return ms / 1e3 / max(n, 1), n
+
+
+def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False, repeats: int = 5):
     import torch
 
     import paper_1901_02955_amd as snap
@@ -140,23 +174,24 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     qd = torch.as_tensor(q).to(dtype).cuda().contiguous()
     del q
     # each step takes dt = CFL / (maximum signal speed of Q^n) on the device
-    # (snap_rk3_steps_cfl: the stages read dt from device memory, and in double
-    # precision the last stage of a step reduces the next step's signal speed),
-    # so the steps run back to back without a host round trip
+    # (snap_rk3_steps_cfl: the stages read dt from device memory, and the last
+    # stage of a step reduces the next step's signal speed), so the steps run
+    # back to back without a host round trip
     work = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
     dt_dev = torch.zeros(max(steps, warmup, 1), dtype=torch.float64, device="cuda")
     if warmup > 0:
         snap.snap_rk3_steps_cfl(dg, qd, CFL, warmup, work, dt_dev)
-    torch.cuda.synchronize()
-    snap.snap_stage_timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    snap.snap_rk3_steps_cfl(dg, qd, CFL, steps, work, dt_dev)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+
+    def call():
+        snap.snap_rk3_steps_cfl(dg, qd, CFL, steps, work, dt_dev)
+
+    # the timed windows carry no instrumentation; the stage kernel's launch
+    # time comes from a separate pass of the same call with hipEvents
+    times = _timed(call, repeats)
+    snap.snap_rk3_steps_status(dg, work)
+    elapsed = _median(times)
     dt = float(dt_dev[steps - 1].item())
-    stage_ms, launches = snap.snap_stage_timing_read()
-    snap.snap_stage_timing_enable(False)
+    avg_launch_s, launches = _stage_pass(call)
     cells = NX * NY * NZ
     esize = 8 if dtype == torch.float64 else 4
     nvar = dg.nvar
@@ -167,7 +202,6 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     fused_share = 1.0 / 3.0
     flops_per_launch = (algorithmic_flops_per_cell_stage(dg.ntracer, 3, hllc=hllc)
                         + CFL_FLOPS_PER_CELL * fused_share) * cells
-    avg_launch_s = stage_ms / 1e3 / max(launches, 1)
     gbs = bytes_per_launch / avg_launch_s / 1e9
     tflops = flops_per_launch / avg_launch_s / 1e12
     name = "f64" if dtype == torch.float64 else "f32"
@@ -176,6 +210,8 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     res = {
         "value": cells * steps / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
+        "repeats": repeats,
+        "spread": _spread(times),
         "stage_kernel_avg_ms": avg_launch_s * 1e3,
         "stage_launches": launches,
         "roofline": {
@@ -198,7 +234,7 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False):
     return res
 
 
-def run_jovian(steps: int, warmup: int, mixture: bool = False):
+def run_jovian(steps: int, warmup: int, mixture: bool = False, repeats: int = 5):
     """3-D Jovian-like column 512x512x256, FP32, 4 tracer densities (vapours and
     clouds); passive, or under the mixture equation of state."""
     import torch
@@ -211,19 +247,18 @@ def run_jovian(steps: int, warmup: int, mixture: bool = False):
     qd = torch.as_tensor(q).float().cuda().contiguous()
     del q
     work = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
-    for _ in range(warmup):
-        snap.snap_rk3_step_cfl(dg, qd, CFL, work)
-    torch.cuda.synchronize()
-    snap.snap_stage_timing_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        snap.snap_rk3_step_cfl(dg, qd, CFL, work)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms, n = snap.snap_stage_timing_read()
-    snap.snap_stage_timing_enable(False)
+    if warmup > 0:
+        snap.snap_rk3_steps_cfl(dg, qd, CFL, warmup, work)
+
+    def call():
+        snap.snap_rk3_steps_cfl(dg, qd, CFL, steps, work)
+
+    times = _timed(call, repeats)
+    snap.snap_rk3_steps_status(dg, work)
+    el = _median(times)
+    avg_s, _ = _stage_pass(call)
     cells = grid.nx * grid.ny * grid.nz
-    avg = ms / 1e3 / max(n, 1)
+    avg = avg_s
     flops = algorithmic_flops_per_cell_stage(4, 3, mixture) * cells
     byts = 8.0 / 3.0 * 9 * 4 * cells
     eos = ("mixture equation of state (water and ammonia vapours and clouds)" if mixture
@@ -231,7 +266,8 @@ def run_jovian(steps: int, warmup: int, mixture: bool = False):
     out = {"workload": "3-D Jovian-like column 512x512x256 (5.5 km x 5.5 km x 1.5625 km), FP32, "
                        f"5 conserved + 4 tracer densities, {eos}, CFL 0.9",
            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
-           "steps": steps, "stage_kernel_avg_ms": avg * 1e3,
+           "steps": steps, "repeats": repeats, "spread": _spread(times),
+           "stage_kernel_avg_ms": avg * 1e3,
            "alu_frac": flops / avg / 1e12 / FP32_PEAK_TFLOPS,
            "hbm_frac_algorithmic": byts / avg / 1e9 / HBM_PEAK_GBS}
     del qd, work
@@ -239,7 +275,7 @@ def run_jovian(steps: int, warmup: int, mixture: bool = False):
     return out
 
 
-def run_jovian_kessler(steps: int, warmup: int, sediment: bool = True):
+def run_jovian_kessler(steps: int, warmup: int, sediment: bool = True, repeats: int = 5):
     """The Jovian-like column with water and ammonia vapour, cloud and
     precipitation (6 tracers) under the mixture equation of state, FP32: an
     SSP-RK3 step (with the precipitation falling at 8 and 5 m/s if
@@ -273,11 +309,13 @@ def run_jovian_kessler(steps: int, warmup: int, sediment: bool = True):
     e1.record()
     torch.cuda.synchronize()
     micro_ms = e0.elapsed_time(e1) / steps
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+
+    def steps_fn():
+        for _ in range(steps):
+            step()
+
+    times = _timed(steps_fn, repeats)
+    el = _median(times)
     cells = grid.nx * grid.ny * grid.nz
     byts = (11 + 6) * 4 * cells          # reads every field, writes the six tracers
     fall = "falling precipitation (8 and 5 m/s), " if sediment else ""
@@ -285,7 +323,7 @@ def run_jovian_kessler(steps: int, warmup: int, sediment: bool = True):
                        f"precipitation (6 tracers), {fall}mixture equation of state, SSP-RK3 step + "
                        "Kessler microphysics step, CFL 0.9",
            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
-           "steps": steps, "microphysics_ms": micro_ms,
+           "steps": steps, "repeats": repeats, "spread": _spread(times), "microphysics_ms": micro_ms,
            "microphysics_hbm_frac": byts / (micro_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
            "microphysics_share": micro_ms / (el / steps * 1e3)}
     del qd, work, cw
@@ -293,7 +331,7 @@ def run_jovian_kessler(steps: int, warmup: int, sediment: bool = True):
     return out
 
 
-def run_jovian_satadj(steps: int, warmup: int):
+def run_jovian_satadj(steps: int, warmup: int, repeats: int = 5):
     """The Jovian-like column with water and ammonia vapour and cloud (4
     tracers) under the mixture equation of state, FP32: an SSP-RK3 step
     followed by saturation adjustment (App. D)."""
@@ -332,19 +370,21 @@ def run_jovian_satadj(steps: int, warmup: int):
 
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+
+    def steps_fn():
+        for _ in range(steps):
+            step()
+
+    times = _timed(steps_fn, repeats)
+    snap.snap_rk3_steps_status(dg, work)
+    el = _median(times)
     cells = grid.nx * grid.ny * grid.nz
     byts = (9 + 4) * 4 * cells          # reads every field, writes the four tracers
     out = {"workload": "3-D Jovian-like column 512x512x256, FP32, water and ammonia vapour and cloud "
                        "(4 tracers), mixture equation of state, SSP-RK3 step + saturation "
                        "adjustment, CFL 0.9",
            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
-           "steps": steps, "adjustment_ms": adj_ms,
+           "steps": steps, "repeats": repeats, "spread": _spread(times), "adjustment_ms": adj_ms,
            "adjustment_hbm_frac": byts / (adj_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
            "adjustment_share": adj_ms / (el / steps * 1e3)}
     del qd, work
@@ -352,7 +392,7 @@ def run_jovian_satadj(steps: int, warmup: int):
     return out
 
 
-def run_ensemble(steps: int):
+def run_ensemble(steps: int, repeats: int = 5):
     """64 uneven 2-D bubbles (FP32): one persistent launch per stage vs separate steps."""
     import torch
 
@@ -372,12 +412,12 @@ def run_ensemble(steps: int):
 
     def timed(fn):
         fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
+
+        def steps_fn():
+            for _ in range(steps):
+                fn()
+
+        return _median(_timed(steps_fn, repeats))
 
     def batched():
         snap.snap_rk3_step_batched(grids, qs, dts, bw, tuned["variant"], tuned["nblocks"])
@@ -389,7 +429,7 @@ def run_ensemble(steps: int):
     tb, ts = timed(batched), timed(separate)
     return {"workload": "64 uneven 2-D dry bubbles (128x128 .. 512x256, seeded), FP32, "
                         "per-member CFL 0.9 time step",
-            "members": len(grids), "cells": cells, "steps": steps,
+            "members": len(grids), "cells": cells, "steps": steps, "repeats": repeats,
             "batched_value": cells * steps / tb, "separate_value": cells * steps / ts,
             "unit": "cell-updates/s", "batched_ms_per_step": tb / steps * 1e3,
             "separate_ms_per_step": ts / steps * 1e3, "speedup": ts / tb,
@@ -729,6 +769,117 @@ def run_cpu_baseline():
     }
 
 
+def run_bubble2d(steps: int = 20, repeats: int = 5):
+    """The 2-D dry bubble (64x64, FP64), 20 steps of the device-dt step: a
+    parity-size case, cache- and launch-bound, reported in cell-updates/s."""
+    import torch
+
+    import paper_1901_02955_amd as snap
+    import workloads as wl
+
+    grid, q = wl.bubble_2d()
+    dg = snap.device_grid(grid)
+    q0 = torch.as_tensor(q).cuda()
+    work = snap.workspace(dg, snap.SNAP_OP_RK3_CFL)
+    qd = q0.clone()
+    snap.snap_rk3_steps_cfl(dg, qd, CFL, 3, work)
+
+    def call():
+        qd.copy_(q0)
+        snap.snap_rk3_steps_cfl(dg, qd, CFL, steps, work)
+
+    times = _timed(call, repeats)
+    snap.snap_rk3_steps_status(dg, work)
+    el = _median(times)
+    cells = grid.nx * grid.nz
+    return {"workload": "2-D dry bubble 64x64 (20 x 10 km), FP64, 20 SSP-RK3 steps, CFL 0.9",
+            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
+            "steps": steps, "repeats": repeats, "spread": _spread(times)}
+
+
+def _oracle_threads():
+    import torch
+
+    nthreads = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        nthreads = min(nthreads, int(env))
+    torch.set_num_threads(nthreads)
+    return torch.get_num_threads()
+
+
+def run_cpu_oracle_sections():
+    """The FP64 oracle (PyTorch CPU) on bounded samples of the other workloads:
+    all 20 steps of the 2-D bubble; 1 step of a 64 x 64 x 256 column slab of
+    the Jovian column (4 passive tracers); one step of each of the 64 ensemble
+    members in turn; and the backward / forward time of 2 steps of a 64 x 64 x
+    128 sub-domain of the gradient workload (torch autograd through the oracle)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as wl
+
+    cores = _oracle_threads()
+    out = {"cores": cores, "kind": "oracle"}
+
+    grid, q = wl.bubble_2d()
+    dt = oracle.cfl_dt(q, grid, CFL)
+    t0 = time.perf_counter()
+    oracle.run(q, grid, dt, 20)
+    el = time.perf_counter() - t0
+    out["bubble2d"] = {"value": grid.nx * grid.nz * 20 / el, "unit": "cell-updates/s",
+                       "sample": f"all 20 steps of the 64x64 bubble ({el:.2f} s)"}
+
+    # a 64 x 64 column slab: at 128 x 128 the oracle's whole-array temporaries
+    # (tens of GB) slowed it about threefold per cell on a 64 GB host
+    grid, q = wl.jovian_3d(nx=64, ny=64, nz=256)
+    dt = oracle.cfl_dt(q, grid, CFL)
+    t0 = time.perf_counter()
+    oracle.run(q, grid, dt, 1)
+    el = time.perf_counter() - t0
+    del q
+    out["jovian_slab"] = {"value": 64 * 64 * 256 / el, "unit": "cell-updates/s",
+                          "sample": f"1 step of a 64x64x256 slab of the Jovian column, 4 passive "
+                                    f"tracers ({el:.1f} s)"}
+
+    members = wl.ensemble_2d(64, seed=4)
+    cells, el = 0, 0.0
+    for g, qm in members:
+        dtm = oracle.cfl_dt(qm, g, CFL)
+        t0 = time.perf_counter()
+        oracle.rk3_step(qm, g, dtm)
+        el += time.perf_counter() - t0
+        cells += g.nx * g.nz
+    out["ensemble"] = {"value": cells / el, "unit": "cell-updates/s",
+                       "sample": f"one step of each of the 64 members in turn ({el:.1f} s)"}
+
+    grid, base, dth, vel, dp = wl.convection_flow_3d(64, 64, 128, lx=5e3, ly=5e3, lz=10e3)
+    q = wl.state_from_theta(grid, base, torch.as_tensor(dth), torch.as_tensor(vel),
+                            torch.as_tensor(dp)).numpy()
+    dt = oracle.cfl_dt(q, grid, CFL)
+    n = 2
+    t0 = time.perf_counter()
+    oracle.run(q, grid, dt, n)
+    t_fwd = time.perf_counter() - t0
+    qt = torch.as_tensor(q)
+    g0 = 3
+    qi = qt[:, g0:g0 + grid.nz, g0:g0 + grid.ny, g0:g0 + grid.nx].clone().requires_grad_(True)
+    full = qt.clone()
+    full[:, g0:g0 + grid.nz, g0:g0 + grid.ny, g0:g0 + grid.nx] = qi
+    outq = oracle.run(full, grid, dt, n)
+    top = outq[:, g0 + grid.nz - 16:g0 + grid.nz, g0:g0 + grid.ny, g0:g0 + grid.nx]
+    L = 0.5 * ((top[1] ** 2 + top[2] ** 2 + top[3] ** 2) / top[0]).sum()
+    t0 = time.perf_counter()
+    L.backward()
+    t_bwd = time.perf_counter() - t0
+    out["adjoint_subdomain"] = {"forward_s": t_fwd, "backward_s": t_bwd,
+                                "adjoint_forward_ratio": t_bwd / t_fwd,
+                                "sample": "2 steps of a 64x64x128 sub-domain of the gradient workload "
+                                          "(the backward: torch autograd through the oracle)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -788,15 +939,29 @@ def main():
                         "periodic x/y, rigid lids, CFL 0.9 (dt per step, formed on the device), WENO5+LMARS, SSP-RK3",
             "nx": NX, "ny": NY, "nz": NZ, "nvar": 5, "cfl": CFL,
         },
+        "repeats": f64["repeats"],
+        "spread": f64["spread"],
         "roofline": f64["roofline"],
         "hbm_roofline": f64["hbm_roofline"],
+        "hbm_target": {
+            "target_frac": 0.6,
+            "algorithmic_bytes_frac": f64["hbm_roofline"]["frac"],
+            "measured_bytes_frac": f64["hbm_roofline"]["measured_frac"],
+            "why_below": "the fused stage kernel moves only the algorithmic state passes (face "
+                         "states, fluxes and the divergence stay on chip) and is bound by "
+                         "vector-ALU issue, not by HBM: see valu_utilisation and roofline",
+        },
         "valu_utilisation": f64["valu_utilisation"],
+        "traffic_source": "rocprofv3 FETCH_SIZE / WRITE_SIZE of the stage kernel, scaled by a "
+                          "512 MiB copy (profiles/stage_kernel_traffic.txt); null unless taken on "
+                          "the current kernel sources",
         "stage_kernel_avg_ms": f64["stage_kernel_avg_ms"],
     }
     if not args.no_f32 and args.variant == "both":
         f32 = run_gpu(torch.float32, args.steps, args.warmup)
         out["variants"] = {"f32": {
             "value": f32["value"], "ms_per_step": f32["ms_per_step"], "dtype": "f32",
+            "repeats": f32["repeats"], "spread": f32["spread"],
             "stage_kernel_avg_ms": f32["stage_kernel_avg_ms"], "roofline": f32["roofline"],
             "hbm_roofline": f32["hbm_roofline"], "valu_utilisation": f32["valu_utilisation"],
         }}
@@ -813,13 +978,17 @@ def main():
         for name, dt_, ref in (("f64", torch.float64, f64), ("f32", torch.float32, out.get("variants", {}).get("f32"))):
             h = run_gpu(dt_, 30, 3, hllc=True)
             out["hllc"][name] = {"value": h["value"], "ms_per_step": h["ms_per_step"],
+                                 "repeats": h["repeats"], "spread": h["spread"],
                                  "stage_kernel_avg_ms": h["stage_kernel_avg_ms"],
                                  "roofline": h["roofline"],
                                  "cost_vs_lmars": (ref["value"] / h["value"]) if ref else None}
         out["ensemble"] = run_ensemble(20)
+        out["bubble2d"] = run_bubble2d()
         out["adjoint"] = run_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline()
+        if not args.only_headline:
+            out["cpu_oracle_sections"] = run_cpu_oracle_sections()
     print(json.dumps(out), flush=True)
 
 
