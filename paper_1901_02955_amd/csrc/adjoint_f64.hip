@@ -4,13 +4,9 @@
 namespace snap {
 
 int launch_adj_rhs_f64(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb,
-                       void* out, int mode, double alpha, double beta, hipStream_t st) {
-  return adj_rhs_t<double>(w, a, q, rb, out, mode, alpha, beta, st);
-}
-
-int launch_adj_combine_f64(void* out, const void* x, const void* y, const void* z, double ca,
-                           double cb, double cc, long long n, hipStream_t st) {
-  return adj_combine_t<double>(out, x, y, z, ca, cb, cc, n, st);
+                       void* out, int mode, double alpha, double beta, const void* y, double gam,
+                       hipStream_t st) {
+  return adj_rhs_t<double>(w, a, q, rb, out, mode, alpha, beta, y, gam, st);
 }
 
 }  // namespace snap

@@ -6,12 +6,6 @@
 
 namespace snap {
 
-inline unsigned adj_blocks(long long n) {
-  long long b = (n + 255) / 256;
-  if (b > 65536) b = 65536;
-  return (unsigned)(b < 1 ? 1 : b);
-}
-
 template <typename T, int NV, bool XDIR>
 void adj_line_launch(const T* W, const T* r, const AdjArgs& a, int d, T* P, hipStream_t st) {
   constexpr int LN = LineShape<T, NV, XDIR>::LN, TL = LineShape<T, NV, XDIR>::TL;
@@ -24,33 +18,31 @@ void adj_line_launch(const T* W, const T* r, const AdjArgs& a, int d, T* P, hipS
 
 template <typename T, int NV>
 int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
-               int mode, double alpha, double beta, hipStream_t st) {
+               int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
   const T* qs = static_cast<const T*>(q);
   const T* r = static_cast<const T*>(rb);
   T* W = static_cast<T*>(w.W);
   T* P = static_cast<T*>(w.P);
-  const long long np = a.sv;
   const int nxp = a.nx + 2 * NG, rows = (a.nz + 2 * NG) * (a.d3 ? a.ny + 2 * NG : 1);
   const dim3 pgrid(rows, (nxp + 255) / 256);
   hipLaunchKernelGGL((k_adj_prims<T, NV>), pgrid, dim3(256), 0, st, qs, a, W);
-  hipLaunchKernelGGL((k_adj_zero<T>), dim3(adj_blocks(np * NV)), dim3(256), 0, st, P, np * NV);
   adj_line_launch<T, NV, true>(W, r, a, 0, P, st);
   if (a.d3) adj_line_launch<T, NV, false>(W, r, a, 1, P, st);
   adj_line_launch<T, NV, false>(W, r, a, 2, P, st);
   const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
   hipLaunchKernelGGL((k_adj_consfold<T, NV>), fgrid, dim3(256), 0, st, qs, P, r, a,
-                     static_cast<T*>(out), mode, alpha, beta);
+                     static_cast<T*>(out), mode, alpha, beta, static_cast<const T*>(y), gam);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T>
 int adj_rhs_t(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
-              int mode, double alpha, double beta, hipStream_t st) {
+              int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
   int r = -1;
   switch (a.nvar) {
 #define SNAP_ADJ_CASE(NVV)                                                      \
   case NVV:                                                                     \
-    r = adj_rhs_nv<T, NVV>(w, a, q, rb, out, mode, alpha, beta, st);           \
+    r = adj_rhs_nv<T, NVV>(w, a, q, rb, out, mode, alpha, beta, y, gam, st);   \
     break;
     SNAP_ADJ_CASE(5)
     SNAP_ADJ_CASE(6)
@@ -65,15 +57,6 @@ int adj_rhs_t(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb,
     default: r = -1;
   }
   return r;
-}
-
-template <typename T>
-int adj_combine_t(void* out, const void* x, const void* y, const void* z, double ca, double cb,
-                  double cc, long long n, hipStream_t st) {
-  hipLaunchKernelGGL((k_adj_combine<T>), dim3(adj_blocks(n)), dim3(256), 0, st,
-                     static_cast<T*>(out), static_cast<const T*>(x), static_cast<const T*>(y),
-                     static_cast<const T*>(z), ca, cb, cc, n);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace snap

@@ -14,7 +14,8 @@
 //   k_adj_consfold   per interior cell: gravity terms and the reverse of the
 //                    conserved -> primitive map (double precision) for the
 //                    cell and for each ghost cell that copies it, summed
-//                    (sign flipped on the reflected normal momentum).
+//                    (sign flipped on the reflected normal momentum), and
+//                    combined with the stage's other cotangent terms.
 #pragma once
 
 #include "snap_device.h"
@@ -314,25 +315,6 @@ __global__ void __launch_bounds__(256) k_adj_prims(const T* __restrict__ q, AdjA
   for (int v = 0; v < NV; ++v) W[c + v * a.sv] = x[v];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_adj_zero(T* __restrict__ p, long long n) {
-  for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256)
-    p[c] = T(0);
-}
-
-// out = ca * x + cb * y + cc * z over n elements (interior cotangent arrays).
-template <typename T>
-__global__ void __launch_bounds__(256) k_adj_combine(T* __restrict__ out, const T* x, const T* y,
-                                                     const T* z, double ca, double cb, double cc,
-                                                     long long n) {
-  for (long long c = blockIdx.x * 256LL + threadIdx.x; c < n; c += (long long)gridDim.x * 256) {
-    double r = ca * static_cast<double>(x[c]);
-    if (y) r += cb * static_cast<double>(y[c]);
-    if (z) r += cc * static_cast<double>(z[c]);
-    out[c] = static_cast<T>(r);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Fused adjoint of one direction d for a tile of LN lines x TL cells along d.
 // In LDS: (A) left/right face states of the reconstructed cells the tile
@@ -367,18 +349,34 @@ struct LineTile {
 };
 
 // Tile shape per element type, variable count and direction (x lines are
-// contiguous; y and z lines are consecutive in x): 2 x lines of 64 cells and
+// contiguous; y and z lines are consecutive in x): 3 x lines of 64 cells and
 // 8 y / z lines of 16 cells, or shorter lines where that tile would exceed
-// 64 KiB of LDS. Small tiles let five or six workgroups share a compute unit;
+// 64 KiB of LDS. Small tiles let four to six workgroups share a compute unit;
 // on the single-precision 256 x 256 x 128 right-hand-side adjoint they took
 // 1.61 ms against 2.17 ms for 4 x 64 and 8 x 32 cells, the halo work they add
-// notwithstanding.
+// notwithstanding. Three x lines rather than two put 210 of the (A)-phase
+// items on 256 threads instead of 140 on 192 (1.47 -> 1.40 ms; 4 x 32, 5 x 32,
+// 6 x 32, 10 x 32 and 4 x 64 measured slower or even).
+#ifndef SNAP_ADJ_XLN
+#define SNAP_ADJ_XLN 3
+#endif
+#ifndef SNAP_ADJ_XTL
+#define SNAP_ADJ_XTL 64
+#endif
+#ifndef SNAP_ADJ_YLN
+#define SNAP_ADJ_YLN 8
+#endif
+#ifndef SNAP_ADJ_YTL
+#define SNAP_ADJ_YTL 16
+#endif
 template <typename T, int NV, bool XDIR>
 struct LineShape {
-  static constexpr bool A = sizeof(LineTile<T, NV, (XDIR ? 2 : 8), (XDIR ? 64 : 16)>) <= 65536;
-  static constexpr bool B = sizeof(LineTile<T, NV, (XDIR ? 2 : 8), (XDIR ? 32 : 8)>) <= 65536;
-  static constexpr int LN = A || B ? (XDIR ? 2 : 8) : (XDIR ? 1 : 4);
-  static constexpr int TL = A ? (XDIR ? 64 : 16) : (XDIR ? 32 : 8);
+  static constexpr int L0 = XDIR ? SNAP_ADJ_XLN : SNAP_ADJ_YLN;
+  static constexpr int T0 = XDIR ? SNAP_ADJ_XTL : SNAP_ADJ_YTL;
+  static constexpr bool A = sizeof(LineTile<T, NV, L0, T0>) <= 65536;
+  static constexpr bool B = sizeof(LineTile<T, NV, L0, T0 / 2>) <= 65536;
+  static constexpr int LN = A || B ? L0 : (L0 + 1) / 2;
+  static constexpr int TL = A ? T0 : T0 / 2;
 };
 
 struct LineGeom {
@@ -600,9 +598,13 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
     if (p >= npos || L0 + l >= g.nlines) continue;
     const int cg = lo + p;
     const long long pc = S.pbase[l] + cg * g.sd;
+    // the first direction kernel to reach a cell starts its sum from zero: x
+    // reaches every cell of the interior rows (x ghosts included), y and z
+    // the ghost cells beyond their own edges first (no zero-fill pass)
+    const bool first = XDIR || cg < 0 || cg >= g.nd;
     T acc[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = P[pc + v * a.sv];
+    for (int v = 0; v < NV; ++v) acc[v] = first ? T(0) : P[pc + v * a.sv];
 #pragma unroll
     for (int o = 0; o < 5; ++o) {
       const int jg = cg + 2 - o;   // reconstruction whose input o is this cell
@@ -667,14 +669,17 @@ __device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* 
 // that copy it (fixed order: x, y, z; low then high; the reflected normal
 // momentum negated), computed in place from q and P, so no padded conserved
 // cotangent is written and read back. out: interior layout, overwritten
-// (mode 0), added to (mode 1), out = alpha * out + beta * result (mode 2), or
-// out = alpha * rb + beta * result (mode 3; out and rb distinct).
+// (mode 0), added to (mode 1), out = alpha * out + beta * result (mode 2),
+// out = alpha * rb + beta * result (mode 3; out and rb distinct), or
+// out = alpha * out + gam * y + rb + beta * result (mode 4: the last stage of
+// the RK3 adjoint with its three-term combination; out, y, rb distinct).
 template <typename T, int NV>
 __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
                                                       const T* __restrict__ P,
                                                       const T* __restrict__ rb, AdjArgs a,
                                                       T* __restrict__ out, int mode,
-                                                      double alpha, double beta) {
+                                                      double alpha, double beta,
+                                                      const T* __restrict__ y, double gam) {
   // grid: x over interior rows, y over the interior row
   const int i = blockIdx.y * 256 + threadIdx.x;
   if (i >= a.nx) return;
@@ -709,8 +714,11 @@ __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
       out[o] = static_cast<T>(static_cast<double>(out[o]) + acc[v]);
     else if (mode == 2)
       out[o] = static_cast<T>(alpha * static_cast<double>(out[o]) + beta * acc[v]);
-    else
+    else if (mode == 3)
       out[o] = static_cast<T>(alpha * static_cast<double>(rb[o]) + beta * acc[v]);
+    else
+      out[o] = static_cast<T>(alpha * static_cast<double>(out[o]) + gam * static_cast<double>(y[o]) +
+                              static_cast<double>(rb[o]) + beta * acc[v]);
   }
 }
 

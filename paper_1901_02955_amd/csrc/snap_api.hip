@@ -458,23 +458,17 @@ AdjWork adj_work(const snap_grid* g, void* base) {
 }
 
 // q_bar-like interior array: out = mode 0: J^T rb; 1: out + J^T rb;
-// 2: alpha out + beta J^T rb. q must have its ghosts filled.
+// 2: alpha out + beta J^T rb; 3: alpha rb + beta J^T rb; 4: alpha out + gam y
+// + rb + beta J^T rb. q must have its ghosts filled.
 int run_adj_rhs(const snap_grid* g, void* q, const void* rb, void* out, int mode, double alpha,
-                double beta, void* work, hipStream_t st) {
+                double beta, void* work, hipStream_t st, const void* y = nullptr,
+                double gam = 0.0) {
   const AdjArgs a = adj_args(g);
   const AdjWork w = adj_work(g, work);
   const int r = g->dtype == SNAP_F64
-                    ? launch_adj_rhs_f64(w, a, q, rb, out, mode, alpha, beta, st)
-                    : launch_adj_rhs_f32(w, a, q, rb, out, mode, alpha, beta, st);
+                    ? launch_adj_rhs_f64(w, a, q, rb, out, mode, alpha, beta, y, gam, st)
+                    : launch_adj_rhs_f32(w, a, q, rb, out, mode, alpha, beta, y, gam, st);
   return r == 0 ? SNAP_OK : device_fail("adjoint kernel launch");
-}
-
-int run_combine(const snap_grid* g, void* out, const void* x, const void* y, const void* z,
-                double ca, double cb, double cc, hipStream_t st) {
-  const long long n = (long long)g->nx * g->ny * g->nz * nvar_of(g);
-  const int r = g->dtype == SNAP_F64 ? launch_adj_combine_f64(out, x, y, z, ca, cb, cc, n, st)
-                                     : launch_adj_combine_f32(out, x, y, z, ca, cb, cc, n, st);
-  return r == 0 ? SNAP_OK : device_fail("combine kernel launch");
 }
 
 // ---------------------------------------------------------------------------
@@ -841,9 +835,8 @@ static int rk3_adjoint_reverse(const snap_grid* g, void* q_n, void* q1, void* q2
   if ((r = run_adj_rhs(g, q2, q_bar, b2, 3, 2.0 / 3.0, 2.0 / 3.0 * dt, aw, st))) return r;
   // Q2 = 3/4 Q + 1/4 (Q1 + dt R(Q1)):  B1 = 1/4 (B2 + dt J(Q1)^T B2)
   if ((r = run_adj_rhs(g, q1, b2, b1, 3, 0.25, 0.25 * dt, aw, st))) return r;
-  // Q1 = Q + dt R(Q):  Qb = Qb3/3 + 3/4 B2 + B1 + dt J(Q)^T B1
-  if ((r = run_combine(g, q_bar, q_bar, b2, b1, 1.0 / 3.0, 0.75, 1.0, st))) return r;
-  return run_adj_rhs(g, q_n, b1, q_bar, 2, 1.0, dt, aw, st);
+  // Q1 = Q + dt R(Q):  Qb = Qb3/3 + 3/4 B2 + B1 + dt J(Q)^T B1 (one pass)
+  return run_adj_rhs(g, q_n, b1, q_bar, 4, 1.0 / 3.0, dt, aw, st, b2, 0.75);
 }
 
 int snap_rk3_step_adjoint(const snap_grid* g, void* q_n, double dt, void* q_bar, void* work,

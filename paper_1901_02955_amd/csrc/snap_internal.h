@@ -88,13 +88,11 @@ struct AdjWork {
 
 // Launchers; each returns 0 on success, -1 if the launch failed.
 int launch_adj_rhs_f64(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb,
-                       void* out, int mode, double alpha, double beta, hipStream_t st);
+                       void* out, int mode, double alpha, double beta, const void* y, double gam,
+                       hipStream_t st);
 int launch_adj_rhs_f32(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb,
-                       void* out, int mode, double alpha, double beta, hipStream_t st);
-int launch_adj_combine_f64(void* out, const void* x, const void* y, const void* z, double ca,
-                           double cb, double cc, long long n, hipStream_t st);
-int launch_adj_combine_f32(void* out, const void* x, const void* y, const void* z, double ca,
-                           double cb, double cc, long long n, hipStream_t st);
+                       void* out, int mode, double alpha, double beta, const void* y, double gam,
+                       hipStream_t st);
 int launch_stage_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 // The stage kernels without tracers (LMARS, or HLLC with hllc = true) live in
 // translation units of their own, compiled with another instruction scheduling

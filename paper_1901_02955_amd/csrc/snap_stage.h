@@ -138,28 +138,62 @@ __device__ __forceinline__ void cons_to_prim_eos(const double (&c)[NV], double r
     cons_to_prim<NV>(c, rb, pb, gm1, x);
 }
 
+// Single-precision storage with passive tracers: the velocities, kinetic
+// energy and tracer fractions in single precision, where nothing cancels, and
+// only the two differences that do, rho - rhobar and (gamma - 1)(E - K) -
+// pbar, in double precision (one rounding each, then to single precision).
+// The reciprocal of rho is the hardware estimate (1 ulp).
+template <int NV>
+__device__ __forceinline__ void cons_to_prim_sp(const float (&c)[NV], double rb, double pb,
+                                                double gm1, float (&x)[NV]) {
+  const float inv = __builtin_amdgcn_rcpf(c[0]);
+  const float u = c[1] * inv, v = c[2] * inv, w = c[3] * inv;
+  const float K = 0.5f * fmaf(c[3], w, fmaf(c[2], v, c[1] * u));
+  x[0] = static_cast<float>(static_cast<double>(c[0]) - rb);
+  x[1] = u;
+  x[2] = v;
+  x[3] = w;
+  x[4] = static_cast<float>(fma(gm1, static_cast<double>(c[4]) - static_cast<double>(K), -pb));
+#pragma unroll
+  for (int t = 5; t < NV; ++t) x[t] = c[t] * inv;
+}
+
 template <typename T, int NV, bool MIX = false>
 __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off, long long sv,
                                           double rb, double pb, double gm1, const Mixture& mx,
                                           T (&x)[NV]) {
-  double c[NV], xd[NV];
+  if constexpr (sizeof(T) == 4 && !MIX) {
+    float c[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
-  cons_to_prim_eos<NV, MIX>(c, rb, pb, gm1, mx, xd);
+    for (int v = 0; v < NV; ++v) c[v] = q[off + v * sv];
+    cons_to_prim_sp<NV>(c, rb, pb, gm1, x);
+  } else {
+    double c[NV], xd[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+    for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
+    cons_to_prim_eos<NV, MIX>(c, rb, pb, gm1, mx, xd);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+  }
 }
 
 // passive tracers
 template <typename T, int NV>
 __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off, long long sv,
                                           double rb, double pb, double gm1, T (&x)[NV]) {
-  double c[NV], xd[NV];
+  if constexpr (sizeof(T) == 4) {
+    float c[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
-  cons_to_prim<NV>(c, rb, pb, gm1, xd);
+    for (int v = 0; v < NV; ++v) c[v] = q[off + v * sv];
+    cons_to_prim_sp<NV>(c, rb, pb, gm1, x);
+  } else {
+    double c[NV], xd[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+    for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
+    cons_to_prim<NV>(c, rb, pb, gm1, xd);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
+  }
 }
 
 // Face flux of the kernel's Riemann solver (LMARS, or HLLC with passive
@@ -419,6 +453,10 @@ __device__ __forceinline__ void load_cons(const T* __restrict__ q, long long off
 template <typename T, int NV, bool MIX>
 __device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], double rb, double pb, double gm1,
                                                const Mixture& mx, T (&x)[NV]) {
+  if constexpr (sizeof(T) == 4 && !MIX) {
+    cons_to_prim_sp<NV>(c, rb, pb, gm1, x);
+    return;
+  }
   double cd[NV], xd[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) cd[v] = static_cast<double>(c[v]);
