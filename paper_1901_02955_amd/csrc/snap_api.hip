@@ -210,22 +210,25 @@ int resident_slots(const snap_grid* g, int* cus_out = nullptr) {
   static std::vector<int> cu_count;            // [device]
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  const int kind = uses_mixture(g) ? 1 : (g->riemann == SNAP_RIEMANN_HLLC ? 2 : 0);
-  const int key = ((g->dtype * 2 + (is3d(g) ? 1 : 0)) * 3 + kind) * 16 + g->ntracer;
+  const int kind = (is3d(g) && uses_sediment(g)) ? 3
+                   : uses_mixture(g) ? 1 : (g->riemann == SNAP_RIEMANN_HLLC ? 2 : 0);
+  const int key = ((g->dtype * 2 + (is3d(g) ? 1 : 0)) * 4 + kind) * 16 + g->ntracer;
   std::lock_guard<std::mutex> lk(m);
   if ((int)cache.size() <= dev) {
     cache.resize(dev + 1);
     cu_count.resize(dev + 1, 0);
   }
   auto& c = cache[dev];
-  if (c.empty()) c.assign(192, 0);
+  if (c.empty()) c.assign(256, 0);
   if (c[key] == 0) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
     const bool d3 = is3d(g);
-    int per = g->dtype == SNAP_F64
+    int per = kind == 3 ? (g->dtype == SNAP_F64 ? occupancy_sed_f64(g->ntracer)
+                                                : occupancy_sed_f32(g->ntracer))
+              : g->dtype == SNAP_F64
                   ? (kind == 1 ? occupancy_mix_f64(g->ntracer, d3)
                                : kind == 2 ? occupancy_hllc_f64(g->ntracer, d3) : occupancy_f64(g->ntracer, d3))
                   : (kind == 1 ? occupancy_mix_f32(g->ntracer, d3)
@@ -371,7 +374,11 @@ int run_stage(const snap_grid* g, StageArgs a, hipStream_t st) {
     if (r) return r;
   }
   const bool mix = uses_mixture(g), hllc = g->riemann == SNAP_RIEMANN_HLLC, d3 = is3d(g);
-  const int r = g->dtype == SNAP_F64
+  // 3-D with falling condensates: the sedimentation terms inside the stage kernel
+  const bool sed3 = d3 && a.sed.on;
+  const int r = sed3 ? (g->dtype == SNAP_F64 ? launch_stage_sed_f64(g->ntracer, a, nb, st)
+                                             : launch_stage_sed_f32(g->ntracer, a, nb, st))
+                : g->dtype == SNAP_F64
                     ? (mix ? launch_stage_mix_f64(g->ntracer, d3, a, nb, st)
                            : hllc ? launch_stage_hllc_f64(g->ntracer, d3, a, nb, st)
                                   : launch_stage_f64(g->ntracer, d3, a, nb, st))
@@ -383,8 +390,8 @@ int run_stage(const snap_grid* g, StageArgs a, hipStream_t st) {
     const int t = timing_mark(st);
     if (t) return t;
   }
-  // sedimentation: its part of the right-hand side added to the stage output
-  if (a.sed.on && launch_sediment(g->dtype, g->ntracer, a, st))
+  // 2-D sedimentation: its part of the right-hand side added to the stage output
+  if (a.sed.on && !sed3 && launch_sediment(g->dtype, g->ntracer, a, st))
     return device_fail("sedimentation kernel launch");
   return SNAP_OK;
 }

@@ -104,6 +104,11 @@ int occupancy_dry_f32(bool hllc, bool d3);
 int launch_stage_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_mix_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_mix_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
+// 3-D mixture kernels with the sedimentation terms (falling condensates).
+int launch_stage_sed_f64(int ntracer, const StageArgs& a, int nblocks, hipStream_t st);
+int launch_stage_sed_f32(int ntracer, const StageArgs& a, int nblocks, hipStream_t st);
+int occupancy_sed_f64(int ntracer);
+int occupancy_sed_f32(int ntracer);
 int launch_stage_hllc_f64(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_stage_hllc_f32(int ntracer, bool d3, StageArgs a, int nblocks, hipStream_t st);
 int launch_fill_ghosts(int dtype, void* q, const GhostArgs& a, hipStream_t st);

@@ -65,7 +65,7 @@ struct StageArgs {
   const double* rbar_f;  // nz + 1
   const double* pbar_f;
   Mixture mix;           // mixture equation of state (kernels instantiated with MIX)
-  Sediment sed;          // sedimentation (a kernel of its own, when sed.on)
+  Sediment sed;          // sedimentation (3-D: SED kernel instances; 2-D: a kernel of its own)
   // Time step from the device: when smax is set, dt = cfl / (the maximum
   // signal speed whose IEEE bits smax holds, written by the reduction kernel
   // earlier on the stream) and a.dt is unused. When dt_out is set, block 0
@@ -465,10 +465,20 @@ __device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], double rb, doub
   for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
 }
 
-template <typename T, int NT, int TX, int TY, bool MIX = false, bool HLLC = false>
-__global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(StageArgs a) {
+// SED (mixture with falling condensates): the sedimentation terms of Sec. 2
+// (the fall fluxes of mass, momentum and energy through the z faces and the
+// frictional heating, sediment_cell) are added to the right-hand side in phase
+// D from the window's levels s-1, s, s+1; these instances load nothing a
+// level ahead, which makes room for that work in the registers.
+// The sedimentation instances in single precision are held to two waves per
+// SIMD, which the other kernels with tracers reach unaided.
+template <typename T, int NT, int TX, int TY, bool MIX = false, bool HLLC = false,
+          bool SED = false>
+__global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STAGE3D_WAVES_PER_EU)
+    k_stage3d(StageArgs a) {
   constexpr int NV = 5 + NT;
   constexpr bool GF = ghosts_in_place(NT);
+  static_assert(!SED || (MIX && NT > 0 && !HLLC), "sedimentation needs the mixture");
   using I = PlaneItems<TX, TY>;
   constexpr int NHALO = 6 * (TX + TY);
   constexpr int HR = (NHALO + I::NTHR - 1) / I::NTHR;   // halo items per thread
@@ -476,7 +486,7 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
   // ahead only where the extra 4 NV live values still leave room for two
   // waves per SIMD (256 registers); with more variables each value is loaded
   // where it is used.
-  constexpr bool PF = sizeof(T) == 4 ? NV <= 11 : NV <= 5;
+  constexpr bool PF = !SED && (sizeof(T) == 4 ? NV <= 11 : NV <= 5);
   __shared__ Plane<T, NV, TX, TY> S;
   const T* __restrict__ qs = static_cast<const T*>(a.qs);
 
@@ -687,6 +697,14 @@ __global__ void __launch_bounds__(TX* TY, SNAP_STAGE3D_WAVES_PER_EU) k_stage3d(S
       const T grav = static_cast<T>(a.grav);
       R[3] = R[3] - grav * W[1][0];
       R[4] = R[4] - grav * qsc[3];
+      if constexpr (SED) {
+        const bool wall_lo = a.sed.closed_z && s == 0, wall_up = a.sed.closed_z && s == a.nz - 1;
+        sediment_cell<T, NV>(W[0], W[1], W[2], static_cast<T>(a.rbar_c[s - 1 + NG]),
+                             static_cast<T>(a.pbar_c[s - 1 + NG]), static_cast<T>(a.rbar_c[s + NG]),
+                             static_cast<T>(a.pbar_c[s + NG]), static_cast<T>(a.rbar_c[s + 1 + NG]),
+                             static_cast<T>(a.pbar_c[s + 1 + NG]), wall_lo, wall_up, a.mix, a.sed,
+                             dzi, grav, R);
+      }
       const long long po = col + lev(s);
       if (!combine) {
         T* __restrict__ o = static_cast<T*>(a.out);

@@ -51,6 +51,56 @@ int occupancy_nt(bool d3) {
   return n;
 }
 
+// 3-D stage kernels with the sedimentation terms (mixture, NT >= 1).
+template <typename T, int NT>
+int launch_sed_nt(const StageArgs& a, int nblocks, hipStream_t st) {
+  constexpr int TX = TileFor<T, NT>::TX, TY = TileFor<T, NT>::TY;
+  hipLaunchKernelGGL((k_stage3d<T, NT, TX, TY, true, false, true>), dim3(nblocks), dim3(TX * TY),
+                     0, st, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename T, int NT>
+int occupancy_sed_nt() {
+  constexpr int TX = TileFor<T, NT>::TX, TY = TileFor<T, NT>::TY;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &n, reinterpret_cast<const void*>(&k_stage3d<T, NT, TX, TY, true, false, true>),
+          TX * TY, 0) != hipSuccess)
+    return 0;
+  return n;
+}
+
+template <typename T>
+int launch_sed_t(int ntracer, const StageArgs& a, int nblocks, hipStream_t st) {
+  switch (ntracer) {
+    case 1: return launch_sed_nt<T, 1>(a, nblocks, st);
+    case 2: return launch_sed_nt<T, 2>(a, nblocks, st);
+    case 3: return launch_sed_nt<T, 3>(a, nblocks, st);
+    case 4: return launch_sed_nt<T, 4>(a, nblocks, st);
+    case 5: return launch_sed_nt<T, 5>(a, nblocks, st);
+    case 6: return launch_sed_nt<T, 6>(a, nblocks, st);
+    case 7: return launch_sed_nt<T, 7>(a, nblocks, st);
+    case 8: return launch_sed_nt<T, 8>(a, nblocks, st);
+    default: return -1;
+  }
+}
+
+template <typename T>
+int occupancy_sed_t(int ntracer) {
+  switch (ntracer) {
+    case 1: return occupancy_sed_nt<T, 1>();
+    case 2: return occupancy_sed_nt<T, 2>();
+    case 3: return occupancy_sed_nt<T, 3>();
+    case 4: return occupancy_sed_nt<T, 4>();
+    case 5: return occupancy_sed_nt<T, 5>();
+    case 6: return occupancy_sed_nt<T, 6>();
+    case 7: return occupancy_sed_nt<T, 7>();
+    case 8: return occupancy_sed_nt<T, 8>();
+    default: return 0;
+  }
+}
+
 // Without tracers the mixture is the dry gas, and the kernels are the ones of
 // stage_dry_f64.hip / stage_dry_f32.hip, so that no other translation unit
 // instantiates them.
