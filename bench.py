@@ -880,6 +880,43 @@ def run_cpu_oracle_sections():
     return out
 
 
+def run_profile_target(name: str):
+    """A short run of one section's kernels, for rocprofv3 (counters or trace):
+    'jovian' (3 device-dt steps of the passive and of the mixture Jovian
+    column), 'kessler' (3 steps of the Kessler workload with falling rain),
+    'satadj' (3 saturation adjustments), 'adjoint' (3 RK3 adjoint steps of the
+    256x256x128 convection state, FP32 and FP64, stage states kept)."""
+    import torch
+
+    import paper_1901_02955_amd as snap
+    import workloads as wl
+
+    if name == "jovian":
+        run_jovian(3, 1, repeats=1)
+        run_jovian(3, 1, mixture=True, repeats=1)
+    elif name == "kessler":
+        run_jovian_kessler(3, 1, repeats=1)
+    elif name == "satadj":
+        run_jovian_satadj(3, 1, repeats=1)
+    elif name == "adjoint":
+        grid, q, _ = wl.convection_3d(NX, NY, NZ)
+        for dtype in (torch.float32, torch.float64):
+            dg = snap.device_grid(grid, dtype=dtype)
+            qn = torch.as_tensor(q).to(dtype).cuda()
+            dt = snap.snap_cfl_dt(dg, qn, CFL, snap.workspace(dg, snap.SNAP_OP_CFL))
+            stages = snap.workspace(dg, snap.SNAP_OP_RK3)
+            snap.snap_rk3_step(dg, qn.clone(), dt, stages)
+            aw = snap.workspace(dg, snap.SNAP_OP_RK3_ADJ)
+            qb = torch.as_tensor(wl.seeded_normal(grid.interior_shape, 3)).to(dtype).cuda()
+            for _ in range(3):
+                snap.snap_rk3_step_adjoint_stages(dg, qn, stages, dt, qb, aw)
+            torch.cuda.synchronize()
+            del qn, stages, aw, qb
+            torch.cuda.empty_cache()
+    else:
+        raise SystemExit(f"unknown profile target {name}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -894,6 +931,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one device-to-device copy of 512 MiB (a known byte count "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--profile", choices=("jovian", "kessler", "satadj", "adjoint"),
+                    help="run only a short invocation of that section's kernels (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path is a single-GPU kernel here; "
@@ -912,6 +951,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.profile:
+        run_profile_target(args.profile)
+        return
     if args.variant == "f32":
         f32 = run_gpu(torch.float32, args.steps, args.warmup)
         print(json.dumps({"metric": METRIC, "value": f32["value"], "unit": "cell-updates/s",
