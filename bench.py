@@ -161,7 +161,8 @@ def _stage_pass(fn):
     return ms / 1e3 / max(n, 1), n
 
 
-def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False, repeats: int = 5):
+def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False, repeats: int = 5,
+            perturbation: bool = False):
     import torch
 
     import paper_1901_02955_amd as snap
@@ -170,7 +171,10 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False, repeats: int = 5
     grid, q, _ = wl.convection_3d(NX, NY, NZ)
     if hllc:
         grid = grid.copy(riemann=wl.RIEMANN_HLLC)
-    dg = snap.device_grid(grid, dtype=dtype)
+    if perturbation:
+        q = wl.to_perturbation(grid, q)
+    dg = snap.device_grid(grid, dtype=dtype, storage=snap.SNAP_STORE_PERTURBATION if perturbation
+                          else snap.SNAP_STORE_TOTAL)
     qd = torch.as_tensor(q).to(dtype).cuda().contiguous()
     del q
     # each step takes dt = CFL / (maximum signal speed of Q^n) on the device
@@ -206,7 +210,7 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False, repeats: int = 5
     tflops = flops_per_launch / avg_launch_s / 1e12
     name = "f64" if dtype == torch.float64 else "f32"
     peak = FP64_PEAK_TFLOPS if name == "f64" else FP32_PEAK_TFLOPS
-    traffic = None if hllc else measured_traffic(name)
+    traffic = None if (hllc or perturbation) else measured_traffic(name)
     res = {
         "value": cells * steps / elapsed,
         "ms_per_step": elapsed / steps * 1e3,
@@ -226,7 +230,7 @@ def run_gpu(dtype, steps: int, warmup: int, hllc: bool = False, repeats: int = 5
         },
         # VALU instructions issued / (256 CUs x one wave instruction per cycle x
         # active cycles), from the committed SQ_INSTS_VALU / GRBM_GUI_ACTIVE run
-        "valu_utilisation": None if hllc else _profile_value(f"valu_issue_util_{name}"),
+        "valu_utilisation": None if (hllc or perturbation) else _profile_value(f"valu_issue_util_{name}"),
         "final_dt": dt,
     }
     del qd, work, dt_dev
@@ -489,15 +493,21 @@ def gradient_check(nx, ny, nz, nsteps, every, seeds, h=1e-4, lx=None, ly=None, l
     pd = torch.as_tensor(dp, device="cuda")
     dg = {torch.float64: snap.device_grid(grid, dtype=torch.float64),
           torch.float32: snap.device_grid(grid, dtype=torch.float32)}
+    dg_p32 = snap.device_grid(grid, dtype=torch.float32, storage=snap.SNAP_STORE_PERTURBATION)
     with torch.no_grad():
         q64 = wl.state_from_theta(grid, base, th0, vd, pd)
     dt = snap.snap_cfl_dt(dg[torch.float64], q64, CFL, snap.workspace(dg[torch.float64], snap.SNAP_OP_CFL))
     del q64
 
-    def ad_gradient(dtype, keep=True):
+    def ad_gradient(dtype, keep=True, perturbation=False):
         th = th0.clone().requires_grad_(True)
-        q0 = wl.state_from_theta(grid, base, th, vd, pd).to(dtype)
-        out = rk3_run(dg[dtype], q0, dt, nsteps, every, keep_stages=keep)
+        q0 = wl.state_from_theta(grid, base, th, vd, pd)
+        if perturbation:
+            # the state stored as rho - rhobar and E - pbar / (gamma - 1)
+            out = rk3_run(dg_p32, wl.to_perturbation(grid, q0).to(dtype), dt, nsteps, every)
+            out = wl.from_perturbation(grid, out.double())
+        else:
+            out = rk3_run(dg[dtype], q0.to(dtype), dt, nsteps, every, keep_stages=keep)
         L = top_kinetic_energy(grid, out)
         L.backward()
         return th.grad.detach(), float(L.detach())
@@ -538,6 +548,7 @@ def gradient_check(nx, ny, nz, nsteps, every, seeds, h=1e-4, lx=None, ly=None, l
     g32_re, _ = ad_gradient(torch.float32, keep=False)
     kept_bitwise = bool(torch.equal(g32, g32_re))
     del g32_re
+    g32p, _ = ad_gradient(torch.float32, perturbation=True)
     g64, L64 = ad_gradient(torch.float64)
     torch.cuda.empty_cache()
 
@@ -560,11 +571,14 @@ def gradient_check(nx, ny, nz, nsteps, every, seeds, h=1e-4, lx=None, ly=None, l
         fd = (4.0 * central(0.5 * h) - central(h)) / 3.0
         a64 = float((g64 * d).sum())
         a32 = float((g32.double() * d).sum())
-        rows.append((s, fd, a64, a32))
-        print(f"[gradient] seed {s}: FD {fd:.10e}  AD64 {a64:.10e}  AD32 {a32:.10e}", flush=True)
+        a32p = float((g32p.double() * d).sum())
+        rows.append((s, fd, a64, a32, a32p))
+        print(f"[gradient] seed {s}: FD {fd:.10e}  AD64 {a64:.10e}  AD32 {a32:.10e}  "
+              f"AD32 perturbation storage {a32p:.10e}", flush=True)
     fd = np.array([r[1] for r in rows])
     a64 = np.array([r[2] for r in rows])
     a32 = np.array([r[3] for r in rows])
+    a32p = np.array([r[4] for r in rows])
     # <grad J, delta> with delta standard normal per cell has the spread
     # |grad J|; the differences are measured against that scale (the RMS of the
     # 32 differences) and, separately, against each direction's own value
@@ -581,6 +595,10 @@ def gradient_check(nx, ny, nz, nsteps, every, seeds, h=1e-4, lx=None, ly=None, l
         "fp32_adjoint": {"max_err_over_rms": float(np.max(np.abs(a32 - fd)) / rms),
                          "median_err_over_rms": float(np.median(np.abs(a32 - fd)) / rms),
                          "max_err_rel_own": float(np.max(np.abs(a32 - fd) / np.abs(fd)))},
+        "fp32_perturbation_storage_adjoint": {
+            "max_err_over_rms": float(np.max(np.abs(a32p - fd)) / rms),
+            "median_err_over_rms": float(np.median(np.abs(a32p - fd)) / rms),
+            "grad_rel_l2_vs_fp64": float((g32p.double() - g64).norm() / g64.norm())},
     })
     return res
 
@@ -724,13 +742,33 @@ def run_fp32_error(steps: int = 100, checkpoints=(25, 50, 75, 100)):
                for n, fields_n in ((n, table(f32[n], ref[n])) for n in checkpoints)}
     attribution = {"fp64_arithmetic_fp32_storage_all": table(all32[steps], ref[steps]),
                    "fp64_arithmetic_fp32_storage_E_only": table(e32[steps], ref[steps])}
-    del q0
+    del q0, ref, f32, all32, e32
+
+    # the FP32 form with perturbation storage (rho - rhobar, E - pbar / (gamma - 1)),
+    # from its own FP32 rounding, against FP64 steps from that same state
+    _, qfull, _ = wl.convection_3d(NX, NY, NZ)
+    p32 = wl.to_perturbation(grid, qfull).astype(np.float32)
+    del qfull
+    start = wl.from_perturbation(grid, p32.astype(np.float64))
+    dgp = snap.device_grid(grid, dtype=torch.float32, storage=snap.SNAP_STORE_PERTURBATION)
+    q0 = torch.as_tensor(start).cuda()
+    refp = run_path(torch.float64)
+    qp = torch.as_tensor(p32).cuda()
+    wp = snap.workspace(dgp, snap.SNAP_OP_RK3)
+    for _ in range(steps):
+        snap.snap_rk3_step(dgp, qp, dt, wp)
+    gotp = grid.interior(wl.from_perturbation(grid, qp.double().cpu().numpy()))
+    fields_p = table(gotp, refp[steps])
+    del q0, qp, wp, refp, p32, start
     torch.cuda.empty_cache()
     return {"workload": f"3-D dry convection 256x256x128 (state rounded to FP32 for every run), "
                         f"{steps} steps of fixed dt = {dt:.6g} s; reference: the FP64 path",
             "fields": fields, "max_rel_dev_by_step": history, "attribution": attribution,
+            "fields_perturbation_storage": fields_p,
             "tolerance_rho_E": 1e-5,
-            "within_tolerance": bool(fields["rho"]["max_rel"] <= 1e-5 and fields["E"]["max_rel"] <= 1e-5)}
+            "within_tolerance": bool(fields["rho"]["max_rel"] <= 1e-5 and fields["E"]["max_rel"] <= 1e-5
+                                     and fields_p["rho"]["max_rel"] <= 1e-5
+                                     and fields_p["E"]["max_rel"] <= 1e-5)}
 
 
 def run_cpu_baseline():
@@ -1008,6 +1046,14 @@ def main():
             "hbm_roofline": f32["hbm_roofline"], "valu_utilisation": f32["valu_utilisation"],
         }}
         out["f32_speedup"] = f32["value"] / f64["value"]
+        f32p = run_gpu(torch.float32, args.steps, args.warmup, perturbation=True)
+        out["variants"]["f32_perturbation"] = {
+            "value": f32p["value"], "ms_per_step": f32p["ms_per_step"], "dtype": "f32",
+            "storage": "rho - rhobar_k, E - pbar_k / (gamma - 1)",
+            "repeats": f32p["repeats"], "spread": f32p["spread"],
+            "stage_kernel_avg_ms": f32p["stage_kernel_avg_ms"], "roofline": f32p["roofline"],
+            "hbm_roofline": f32p["hbm_roofline"],
+        }
         out["f32_error_vs_f64"] = run_fp32_error()
     if not args.only_headline:
         out["jovian"] = run_jovian(50, 3)

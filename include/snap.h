@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 9
+#define SNAP_ABI_VERSION 10
 
 /* return codes */
 #define SNAP_OK 0
@@ -74,6 +74,10 @@ extern "C" {
 /* equation of state */
 #define SNAP_EOS_PASSIVE 0 /* tracers do not enter the pressure */
 #define SNAP_EOS_MIXTURE 1 /* ideal-gas mixture with condensates (Sec. 2, App. B) */
+
+/* storage form of the state q */
+#define SNAP_STORE_TOTAL 0        /* the conserved state of App. B (what a zero-initialised struct selects) */
+#define SNAP_STORE_PERTURBATION 1 /* rho - rhobar_k and E - pbar_k / (gamma - 1) in place of rho and E */
 
 /* tracer kinds under SNAP_EOS_MIXTURE */
 #define SNAP_TRACER_VAPOUR 0     /* a gas: partial pressure rho_i R_d T / eps_i */
@@ -155,6 +159,20 @@ extern "C" {
  *                The tracer fields are read only under SNAP_EOS_MIXTURE with
  *                ntracer > 0 (a nonzero tracer_wt needs the mixture); there the
  *                adjoint and batched entry points return SNAP_E_UNSUPPORTED.
+ * storage        SNAP_STORE_TOTAL (0): q holds the conserved state.
+ *                SNAP_STORE_PERTURBATION: q[0] holds rho - rhobar_k and q[4]
+ *                holds E - pbar_k / (gamma - 1) (the state's departure from the
+ *                reference level k at rest; ghost levels use the ghost-level
+ *                references), the other fields as in SNAP_STORE_TOTAL. Every
+ *                entry point takes and returns q in this form; the right-hand
+ *                side, cotangents and time steps are those of the full state
+ *                (the stage combination of Sec. 4.3 has weights summing to one,
+ *                so the references cancel), and the conservation sums are of
+ *                the full fields. With single-precision storage this keeps the
+ *                digits of the departure that rounding the full E (about
+ *                2.5e5 J/m^3 near the ground) to FP32 would lose. Passive
+ *                tracers only: with SNAP_EOS_MIXTURE it returns
+ *                SNAP_E_UNSUPPORTED.
  *
  * Density and pressure are reconstructed as perturbations rho - rhobar and
  * p - pbar of the level (the vertical perturbation pressure of Sec. 4.1); face
@@ -185,6 +203,7 @@ typedef struct snap_grid {
   double tracer_wt[SNAP_MAX_TRACERS];
   double rd;
   int32_t riemann;
+  int32_t storage;
 } snap_grid;
 
 /* Thread-local message of the last failed call of this thread ("" if none). */

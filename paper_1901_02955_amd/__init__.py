@@ -30,7 +30,7 @@ __all__ = [
     "SNAP_F64", "SNAP_F32", "SNAP_BC_PERIODIC", "SNAP_BC_REFLECT",
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
     "SNAP_EOS_PASSIVE", "SNAP_EOS_MIXTURE", "SNAP_TRACER_VAPOUR", "SNAP_TRACER_CONDENSATE",
-    "SNAP_RIEMANN_LMARS", "SNAP_RIEMANN_HLLC",
+    "SNAP_RIEMANN_LMARS", "SNAP_RIEMANN_HLLC", "SNAP_STORE_TOTAL", "SNAP_STORE_PERTURBATION",
     "snap_kessler_step", "kessler_params", "snap_saturation_adjust", "satadj_params",
 ]
 
@@ -49,11 +49,13 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 9
+SNAP_ABI_VERSION = 10
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
 SNAP_RIEMANN_HLLC = 1
+SNAP_STORE_TOTAL = 0
+SNAP_STORE_PERTURBATION = 1
 SNAP_TRACER_VAPOUR = 0
 SNAP_TRACER_CONDENSATE = 1
 SNAP_OP_RHS = 0
@@ -94,7 +96,7 @@ class SnapGridC(ctypes.Structure):
         ("tracer_sigma", ctypes.c_double * SNAP_MAX_TRACERS),
         ("tracer_mu", ctypes.c_double * SNAP_MAX_TRACERS),
         ("tracer_wt", ctypes.c_double * SNAP_MAX_TRACERS), ("rd", ctypes.c_double),
-        ("riemann", ctypes.c_int32),
+        ("riemann", ctypes.c_int32), ("storage", ctypes.c_int32),
     ]
 
 
@@ -226,7 +228,7 @@ class DeviceGrid:
                  tracer_kind: Sequence[int] = (), tracer_eps: Sequence[float] = (),
                  tracer_sigma: Sequence[float] = (), tracer_mu: Sequence[float] = (),
                  tracer_wt: Sequence[float] = (), rd: float = 0.0,
-                 riemann: int = SNAP_RIEMANN_LMARS):
+                 riemann: int = SNAP_RIEMANN_LMARS, storage: int = SNAP_STORE_TOTAL):
         if dtype not in (torch.float64, torch.float32):
             raise ValueError("dtype must be torch.float64 or torch.float32")
         device = torch.device(device or "cuda")
@@ -258,7 +260,9 @@ class DeviceGrid:
             c.tracer_wt[t] = float(wt)
         c.rd = float(rd)
         c.riemann = int(riemann)
+        c.storage = int(storage)
         self.eos = int(eos)
+        self.storage = int(storage)
         self.c = c
 
     @property
@@ -290,7 +294,10 @@ class DeviceGrid:
             raise ValueError(f"{name} must be contiguous with shape {shape}, got {tuple(q.shape)}")
 
 
-def device_grid(g, dtype: torch.dtype = torch.float64, device=None) -> DeviceGrid:
+def device_grid(g, dtype: torch.dtype = torch.float64, device=None,
+                storage: int = SNAP_STORE_TOTAL) -> DeviceGrid:
+    """DeviceGrid of a grid description; ``storage`` picks the form of the state
+    (SNAP_STORE_TOTAL or SNAP_STORE_PERTURBATION)."""
     return DeviceGrid(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.gamma, g.grav, g.ntracer, g.bc,
                       g.weno_eps, g.weno_linear, g.rhobar_cell, g.pbar_cell, g.rhobar_face,
                       g.pbar_face, dtype=dtype, device=device,
@@ -298,7 +305,7 @@ def device_grid(g, dtype: torch.dtype = torch.float64, device=None) -> DeviceGri
                       tracer_kind=getattr(g, "tracer_kind", ()), tracer_eps=getattr(g, "tracer_eps", ()),
                       tracer_sigma=getattr(g, "tracer_sigma", ()), tracer_mu=getattr(g, "tracer_mu", ()),
                       tracer_wt=getattr(g, "tracer_wt", ()), rd=getattr(g, "rd", 0.0),
-                      riemann=getattr(g, "riemann", SNAP_RIEMANN_LMARS))
+                      riemann=getattr(g, "riemann", SNAP_RIEMANN_LMARS), storage=storage)
 
 
 def snap_abi_version() -> int:

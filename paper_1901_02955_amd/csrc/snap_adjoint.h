@@ -31,6 +31,7 @@ struct AdjArgs {
   double gamma, gm1, inv_gm1, grav, eps;
   int linear;
   int bc[3];
+  int pert;   // perturbation storage (rho - rhobar_k, E - pbar_k / (gamma - 1))
   const double* rbar_c;
   const double* pbar_c;
   const double* rbar_f;
@@ -310,7 +311,7 @@ __global__ void __launch_bounds__(256) k_adj_prims(const T* __restrict__ q, AdjA
   const int kp = row / nyp;
   const long long c = (long long)row * nxp + ip;
   T x[NV];
-  load_prim<T, NV>(q, c, a.sv, a.rbar_c[kp], a.pbar_c[kp], a.gm1, x);
+  load_prim<T, NV>(q, c, a.sv, level_ref(a.pert, a.rbar_c[kp], a.pbar_c[kp]), a.gm1, x);
 #pragma unroll
   for (int v = 0; v < NV; ++v) W[c + v * a.sv] = x[v];
 }
@@ -647,7 +648,8 @@ __device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* 
     pb[0] += -a.grav * static_cast<double>(rb[ro + 3 * a.rv]);   // R_rhow -= g rho'
     qe = -a.grav * static_cast<double>(rb[ro + 4 * a.rv]);       // R_E -= g rho w
   }
-  const double inv = 1.0 / cv[0];
+  // rho of the cell (perturbation storage: the stored value plus rhobar of its level)
+  const double inv = 1.0 / (cv[0] + (a.pert ? a.rbar_c[k + NG] : 0.0));
   const double u = cv[1] * inv, v = cv[2] * inv, w = cv[3] * inv;
   // p = (gamma - 1)(E - (m.m)/(2 rho)):  dp/drho = (gamma-1) |u|^2 / 2, dp/dm = -(gamma-1) u
   double rhob = pb[0] - (u * pb[1] + v * pb[2] + w * pb[3]) * inv +

@@ -154,6 +154,11 @@ int check_grid(const snap_grid* g) {
   }
   if (g->riemann == SNAP_RIEMANN_HLLC && uses_mixture(g))
     return fail(SNAP_E_UNSUPPORTED, "HLLC takes passive tracers (eos = SNAP_EOS_PASSIVE)");
+  if (g->storage != SNAP_STORE_TOTAL && g->storage != SNAP_STORE_PERTURBATION)
+    return fail(SNAP_E_INVALID, "storage must be SNAP_STORE_TOTAL or SNAP_STORE_PERTURBATION (got %d)",
+                g->storage);
+  if (g->storage == SNAP_STORE_PERTURBATION && g->eos == SNAP_EOS_MIXTURE)
+    return fail(SNAP_E_UNSUPPORTED, "perturbation storage takes passive tracers (eos = SNAP_EOS_PASSIVE)");
   const double total = (double)padded_cells(g) * nvar_of(g);
   if (total > 9.0e18 / 8.0) return fail(SNAP_E_INVALID, "state too large");
   return SNAP_OK;
@@ -195,6 +200,7 @@ StageArgs stage_args(const snap_grid* g) {
   a.pbar_f = g->pbar_face;
   a.mix = mixture_of(g);
   a.sed = sediment_of(g);
+  a.pert = g->storage == SNAP_STORE_PERTURBATION ? 1 : 0;
   a.ghost = (g->bc[0] == SNAP_BC_REFLECT ? GF_RX : 0) |
             (is3d(g) && g->bc[1] == SNAP_BC_REFLECT ? GF_RY : 0) |
             (g->bc[2] == SNAP_BC_REFLECT ? GF_RZ : 0);   // GF_ON is set by the caller
@@ -430,6 +436,7 @@ AdjArgs adj_args(const snap_grid* g) {
   a.eps = g->weno_eps;
   a.linear = g->weno_linear;
   for (int d = 0; d < 3; ++d) a.bc[d] = g->bc[d];
+  a.pert = g->storage == SNAP_STORE_PERTURBATION ? 1 : 0;
   a.rbar_c = g->rhobar_cell;
   a.pbar_c = g->pbar_cell;
   a.rbar_f = g->rhobar_face;
@@ -643,6 +650,9 @@ CflArgs cfl_args(const snap_grid* g) {
   a.ntracer = g->ntracer;
   a.mix = uses_mixture(g) ? 1 : 0;
   a.m = mixture_of(g);
+  a.pert = g->storage == SNAP_STORE_PERTURBATION ? 1 : 0;
+  a.rbar_c = g->rhobar_cell;
+  a.pbar_c = g->pbar_cell;
   return a;
 }
 
@@ -1174,6 +1184,10 @@ int run_sums(const snap_grid* g, void* q, double* part, double* out, double* sum
   a.sy = nxp;
   a.sz = nxp * nyp;
   a.sv = a.sz * (g->nz + 2 * SNAP_NG);
+  a.pert = g->storage == SNAP_STORE_PERTURBATION ? 1 : 0;
+  a.inv_gm1 = 1.0 / (g->gamma - 1.0);
+  a.rbar_c = g->rhobar_cell;
+  a.pbar_c = g->pbar_cell;
   if (launch_sums(g->dtype, q, a, part, out, st)) return device_fail("sums kernel launch");
   if (hipMemcpyAsync(sums_host, out, a.nvar * sizeof(double), hipMemcpyDeviceToHost, st) !=
       hipSuccess)

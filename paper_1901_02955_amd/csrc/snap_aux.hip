@@ -131,12 +131,15 @@ __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
   for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
    const int j = (int)(row % a.ny), k = (int)(row / a.ny);
    const long long base = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + NG;
+   // perturbation storage: rho and p with the level references added back
+   const double rbo = a.pert ? a.rbar_c[k + NG] : 0.0, pbo = a.pert ? a.pbar_c[k + NG] : 0.0;
    for (int i = threadIdx.x; i < a.nx; i += 256) {
     const long long o = base + i;
     double s;
     {
 #pragma clang fp contract(off)
-      const double rho = q[o], mx = q[o + a.sv], my = q[o + 2 * a.sv], mz = q[o + 3 * a.sv];
+      const double rho = static_cast<double>(q[o]) + rbo, mx = q[o + a.sv], my = q[o + 2 * a.sv];
+      const double mz = q[o + 3 * a.sv];
       const double E = q[o + 4 * a.sv];
       const double inv = 1.0 / rho;
       const double u = mx * inv, v = my * inv, w = mz * inv;
@@ -157,7 +160,7 @@ __global__ void __launch_bounds__(256) k_cfl(const T* __restrict__ q, CflArgs a,
         p = (a.gm1 * ratio) * ((E - K) - A);
         gam = 1.0 + a.gm1 * ratio;
       } else {
-        p = a.gm1 * (E - K);
+        p = a.gm1 * (E - K) + pbo;
         gam = a.gamma;
       }
       const double cs = sqrt(gam * p / rho);
@@ -204,7 +207,10 @@ __global__ void __launch_bounds__(256) k_sums_partial(const T* __restrict__ q, S
       const int j = r % a.ny;
       const int k = r / a.ny;
       const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
-      acc += static_cast<double>(q[o + v * a.sv]);
+      double x = static_cast<double>(q[o + v * a.sv]);
+      if (a.pert && v == 0) x += a.rbar_c[k + NG];
+      if (a.pert && v == 4) x += a.pbar_c[k + NG] * a.inv_gm1;
+      acc += x;
     }
     red[threadIdx.x] = acc;
     __syncthreads();

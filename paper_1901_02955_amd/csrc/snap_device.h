@@ -39,12 +39,15 @@ __device__ __forceinline__ int ghost_src(int idx, int n, int bc, bool& flip) {
 //   inv = 1/rho; u = (rho u) inv (v, w alike); K = ((rho u) u + (rho v) v)
 //   + (rho w) w, times 1/2; p = (gamma - 1)(E - K); p' = p - pbar;
 //   rho' = rho - rhobar; q_i = rho_i inv.
+// Stored perturbations (c[0] = rho - rhobar_k, c[4] = E - pbar_k / (gamma -
+// 1)) take the same code with ra = rhobar_k (rho = c[0] + ra) and rbar =
+// pbar = 0; the full state has ra = 0 (and rho = c[0] exactly).
 // ---------------------------------------------------------------------------
 template <int NV>
-__device__ __forceinline__ void cons_to_prim(const double (&c)[NV], double rbar, double pbar,
-                                             double gm1, double (&x)[NV]) {
+__device__ __forceinline__ void cons_to_prim(const double (&c)[NV], double ra, double rbar,
+                                             double pbar, double gm1, double (&x)[NV]) {
 #pragma clang fp contract(off)
-  const double inv = 1.0 / c[0];
+  const double inv = 1.0 / (c[0] + ra);
   const double u = c[1] * inv;
   const double v = c[2] * inv;
   const double w = c[3] * inv;

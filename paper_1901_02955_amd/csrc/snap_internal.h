@@ -28,6 +28,9 @@ struct CflArgs {
   double gamma, gm1, dxi, dyi, dzi;   // dxi = 1 / dx (x, y, z)
   int ntracer, mix;   // mix: the mixture equation of state with coefficients m
   Mixture m;
+  int pert;                       // perturbation storage: add the level references back
+  const double* rbar_c;           // nz + 6 (read only with pert)
+  const double* pbar_c;
 };
 
 // Kessler microphysics (Sec. 3): one condensable species.
@@ -63,6 +66,10 @@ struct SatAdjArgs {
 struct SumArgs {
   int nx, ny, nz, gy, nvar;
   long long sy, sz, sv;
+  int pert;                       // perturbation storage: add rhobar_k and pbar_k / (gamma - 1)
+  double inv_gm1;
+  const double* rbar_c;           // nz + 6 (read only with pert)
+  const double* pbar_c;
 };
 
 // Tile shape of the stage kernels for an element size and variable count.

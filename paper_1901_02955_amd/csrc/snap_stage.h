@@ -91,7 +91,25 @@ struct StageArgs {
   // that time step is not finite and positive, i.e. the reduced state had a
   // non-finite or non-positive density or pressure somewhere.
   unsigned long long* state_flag;
+  // 1: q holds rho - rhobar_k and E - pbar_k / (gamma - 1) (perturbation
+  // storage, passive tracers only); 0: the full conserved state.
+  int pert;
 };
+
+// References of level k for the conversion of the stored state: ra is added
+// to the stored density to give rho, rs and ps are subtracted from rho and p
+// to give rho' and p'; pe is added to (gamma - 1)(E_stored - K) to give p.
+struct LevelRef {
+  double ra, rs, ps, pe;
+};
+__device__ __forceinline__ LevelRef level_ref(int pert, double rbar, double pbar) {
+  LevelRef r;
+  r.ra = pert ? rbar : 0.0;
+  r.rs = pert ? 0.0 : rbar;
+  r.ps = pert ? 0.0 : pbar;
+  r.pe = pert ? pbar : 0.0;
+  return r;
+}
 enum : int { GF_ON = 1, GF_RX = 2, GF_RY = 4, GF_RZ = 8 };
 
 // The 3-D stage kernels that can read ghosts in place (GF_ON): those without
@@ -130,12 +148,13 @@ __device__ __forceinline__ double to_d(T v) {
 // Conserved -> primitive with the kernel's equation of state: passive tracers,
 // or the mixture (MIX) with coefficients mx.
 template <int NV, bool MIX>
-__device__ __forceinline__ void cons_to_prim_eos(const double (&c)[NV], double rb, double pb,
-                                                 double gm1, const Mixture& mx, double (&x)[NV]) {
+__device__ __forceinline__ void cons_to_prim_eos(const double (&c)[NV], double ra, double rb,
+                                                 double pb, double gm1, const Mixture& mx,
+                                                 double (&x)[NV]) {
   if constexpr (MIX)
-    cons_to_prim_mix<NV>(c, rb, pb, gm1, mx, x);
+    cons_to_prim_mix<NV>(c, rb, pb, gm1, mx, x);   // full storage only (ra = 0)
   else
-    cons_to_prim<NV>(c, rb, pb, gm1, x);
+    cons_to_prim<NV>(c, ra, rb, pb, gm1, x);
 }
 
 // Single-precision storage with passive tracers: the velocities, kinetic
@@ -144,9 +163,9 @@ __device__ __forceinline__ void cons_to_prim_eos(const double (&c)[NV], double r
 // pbar, in double precision (one rounding each, then to single precision).
 // The reciprocal of rho is the hardware estimate (1 ulp).
 template <int NV>
-__device__ __forceinline__ void cons_to_prim_sp(const float (&c)[NV], double rb, double pb,
-                                                double gm1, float (&x)[NV]) {
-  const float inv = __builtin_amdgcn_rcpf(c[0]);
+__device__ __forceinline__ void cons_to_prim_sp(const float (&c)[NV], double ra, double rb,
+                                                double pb, double gm1, float (&x)[NV]) {
+  const float inv = __builtin_amdgcn_rcpf(c[0] + static_cast<float>(ra));
   const float u = c[1] * inv, v = c[2] * inv, w = c[3] * inv;
   const float K = 0.5f * fmaf(c[3], w, fmaf(c[2], v, c[1] * u));
   x[0] = static_cast<float>(static_cast<double>(c[0]) - rb);
@@ -160,18 +179,18 @@ __device__ __forceinline__ void cons_to_prim_sp(const float (&c)[NV], double rb,
 
 template <typename T, int NV, bool MIX = false>
 __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off, long long sv,
-                                          double rb, double pb, double gm1, const Mixture& mx,
+                                          const LevelRef& lr, double gm1, const Mixture& mx,
                                           T (&x)[NV]) {
   if constexpr (sizeof(T) == 4 && !MIX) {
     float c[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) c[v] = q[off + v * sv];
-    cons_to_prim_sp<NV>(c, rb, pb, gm1, x);
+    cons_to_prim_sp<NV>(c, lr.ra, lr.rs, lr.ps, gm1, x);
   } else {
     double c[NV], xd[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
-    cons_to_prim_eos<NV, MIX>(c, rb, pb, gm1, mx, xd);
+    cons_to_prim_eos<NV, MIX>(c, lr.ra, lr.rs, lr.ps, gm1, mx, xd);
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
   }
@@ -180,17 +199,17 @@ __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off
 // passive tracers
 template <typename T, int NV>
 __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off, long long sv,
-                                          double rb, double pb, double gm1, T (&x)[NV]) {
+                                          const LevelRef& lr, double gm1, T (&x)[NV]) {
   if constexpr (sizeof(T) == 4) {
     float c[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) c[v] = q[off + v * sv];
-    cons_to_prim_sp<NV>(c, rb, pb, gm1, x);
+    cons_to_prim_sp<NV>(c, lr.ra, lr.rs, lr.ps, gm1, x);
   } else {
     double c[NV], xd[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) c[v] = to_d(q[off + v * sv]);
-    cons_to_prim<NV>(c, rb, pb, gm1, xd);
+    cons_to_prim<NV>(c, lr.ra, lr.rs, lr.ps, gm1, xd);
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
   }
@@ -451,16 +470,16 @@ __device__ __forceinline__ void load_cons(const T* __restrict__ q, long long off
 }
 
 template <typename T, int NV, bool MIX>
-__device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], double rb, double pb, double gm1,
+__device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], const LevelRef& lr, double gm1,
                                                const Mixture& mx, T (&x)[NV]) {
   if constexpr (sizeof(T) == 4 && !MIX) {
-    cons_to_prim_sp<NV>(c, rb, pb, gm1, x);
+    cons_to_prim_sp<NV>(c, lr.ra, lr.rs, lr.ps, gm1, x);
     return;
   }
   double cd[NV], xd[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) cd[v] = static_cast<double>(c[v]);
-  cons_to_prim_eos<NV, MIX>(cd, rb, pb, gm1, mx, xd);
+  cons_to_prim_eos<NV, MIX>(cd, lr.ra, lr.rs, lr.ps, gm1, mx, xd);
 #pragma unroll
   for (int v = 0; v < NV; ++v) x[v] = static_cast<T>(xd[v]);
 }
@@ -586,7 +605,8 @@ __global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STA
       T c[NV];
       load_cons<T, NV>(qs, col + lev(zsrc(k, zf)), a.sv, c);
       if (zf) c[3] = -c[3];
-      cons_to_prim_t<T, NV, MIX>(c, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1, a.mix, W[l]);
+      cons_to_prim_t<T, NV, MIX>(c, level_ref(a.pert, a.rbar_c[k + NG], a.pbar_c[k + NG]), a.gm1,
+                                 a.mix, W[l]);
     }
   }
   // prefetched raw conserved values: halo cells of the next level to be
@@ -621,6 +641,7 @@ __global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STA
     if (s >= k0) {
       // ---- (P) primitives of level s: own cell from the window, halo prefetched
       const double rbs = a.rbar_c[s + NG], pbs = a.pbar_c[s + NG];
+      const LevelRef lrs = level_ref(a.pert, rbs, pbs);
       if (act) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.P[v][tj + 3][ti + 3] = W[1][v];
@@ -635,7 +656,7 @@ __global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STA
             if ((a.ghost & GF_RX) && (gi < 0 || gi >= a.nx)) hc[r][1] = -hc[r][1];
             if ((a.ghost & GF_RY) && (gj < 0 || gj >= a.ny)) hc[r][2] = -hc[r][2];
           }
-          cons_to_prim_t<T, NV, MIX>(hc[r], rbs, pbs, a.gm1, a.mix, x);
+          cons_to_prim_t<T, NV, MIX>(hc[r], lrs, a.gm1, a.mix, x);
 #pragma unroll
           for (int v = 0; v < NV; ++v) S.P[v][hjj[r] + 3][hii[r] + 3] = x[v];
           if constexpr (PF) {
@@ -662,8 +683,8 @@ __global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STA
     if (act) {
       if constexpr (!PF) load_cons<T, NV>(qs, col + lev(wsrc), a.sv, wc);
       if (wzf) wc[3] = -wc[3];
-      cons_to_prim_t<T, NV, MIX>(wc, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG], a.gm1, a.mix,
-                                 W[4]);
+      cons_to_prim_t<T, NV, MIX>(wc, level_ref(a.pert, a.rbar_c[s + 3 + NG], a.pbar_c[s + 3 + NG]),
+                                 a.gm1, a.mix, W[4]);
       T qmn[NV], qpn[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -726,11 +747,15 @@ __global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STA
             // sum_d (|u_d| + c) / dx_d of the new state (times 1 / dx_d), in the CFL kernel's
             // order and operations (no contraction)
 #pragma clang fp contract(off)
-            const double rho = ov[0], mx = ov[1], my = ov[2], mz = ov[3], E = ov[4];
+            // (perturbation storage: rho and p with the level references added back)
+            const double rbo = a.pert ? a.rbar_c[s + NG] : 0.0;
+            const double pbo = a.pert ? a.pbar_c[s + NG] : 0.0;
+            const double rho = static_cast<double>(ov[0]) + rbo, mx = ov[1], my = ov[2], mz = ov[3];
+            const double E = ov[4];
             const double inv = 1.0 / rho;
             const double u = mx * inv, v = my * inv, w = mz * inv;
             const double K = 0.5 * ((mx * u + my * v) + mz * w);
-            const double p = a.gm1 * (E - K);
+            const double p = a.gm1 * (E - K) + pbo;
             const double cs = sqrt(a.gamma * p / rho);
             double sp = (fabs(u) + cs) * a.dxi;
             sp = sp + (fabs(v) + cs) * a.dyi;
@@ -790,8 +815,8 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
   if (act) {
     const int k = k0 + tk;
     T x[NV];
-    load_prim<T, NV, MIX>(qs, poff(i0 + ti, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1,
-                          a.mix, x);
+    load_prim<T, NV, MIX>(qs, poff(i0 + ti, k), a.sv,
+                          level_ref(a.pert, a.rbar_c[k + NG], a.pbar_c[k + NG]), a.gm1, a.mix, x);
 #pragma unroll
     for (int v = 0; v < NV; ++v) S.P[v][tk + 3][ti + 3] = x[v];
   }
@@ -800,8 +825,8 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
     if (halo_item<TX, TZ>(it, w, h, ii, kk)) {
       const int k = k0 + kk;
       T x[NV];
-      load_prim<T, NV, MIX>(qs, poff(i0 + ii, k), a.sv, a.rbar_c[k + NG], a.pbar_c[k + NG], a.gm1,
-                            a.mix, x);
+      load_prim<T, NV, MIX>(qs, poff(i0 + ii, k), a.sv,
+                            level_ref(a.pert, a.rbar_c[k + NG], a.pbar_c[k + NG]), a.gm1, a.mix, x);
 #pragma unroll
       for (int v = 0; v < NV; ++v) S.P[v][kk + 3][ii + 3] = x[v];
     }

@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 9
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 10
 
 
 def good_grid(**kw):
@@ -83,6 +83,7 @@ BAD_GRIDS = [
     dict(eos=1, tracer_wt=(0.0, math.nan)), dict(eos=1, tracer_wt=(-5.0, 0.0)),   # a vapour cannot fall
     dict(eos=1, tracer_wt=(0.0, -5.0), rd=0.0), dict(eos=1, tracer_wt=(0.0, -5.0), rd=math.inf),
     dict(riemann=2), dict(riemann=-1),
+    dict(storage=2), dict(storage=-1),
 ]
 
 
@@ -375,3 +376,16 @@ def test_hllc_refuses_the_mixture_and_is_refused_by_adjoint_and_batched():
     assert lib.snap_batched_workspace_bytes(arr, 2) == 0
     mixed = ctypes.byref(good_grid(riemann=1, eos=1))
     assert lib.snap_rhs(mixed, P, Q2, None) == snap.SNAP_E_UNSUPPORTED
+
+
+def test_perturbation_storage_needs_the_passive_gas():
+    """SNAP_STORE_PERTURBATION is accepted with passive tracers and refused
+    (SNAP_E_UNSUPPORTED, on the host) under the mixture equation of state."""
+    lib = snap.lib()
+    g = ctypes.byref(good_grid(storage=snap.SNAP_STORE_PERTURBATION))
+    assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3) > 0
+    gm = ctypes.byref(good_grid(storage=snap.SNAP_STORE_PERTURBATION, eos=snap.SNAP_EOS_MIXTURE))
+    assert lib.snap_workspace_bytes(gm, snap.SNAP_OP_RK3) == 0
+    P = ctypes.c_void_p(FAKE)
+    assert lib.snap_rk3_step(gm, P, 0.1, P, None) == snap.SNAP_E_UNSUPPORTED
+    assert lib.snap_rhs(gm, P, ctypes.c_void_p(FAKE * 2), None) == snap.SNAP_E_UNSUPPORTED

@@ -253,6 +253,35 @@ def state_from_primitives(grid: Grid, rho, u, v, w, p, tracers: Sequence = ()):
     return q
 
 
+def to_perturbation(grid: Grid, q):
+    """The perturbation storage form of a padded state (numpy or torch, any
+    float dtype): rho - rhobar_k in field 0 and E - pbar_k / (gamma - 1) in
+    field 4 on every padded level k (the references' ghost levels included),
+    the other fields unchanged. Returns a new array of q's type."""
+    return _shift_storage(grid, q, -1.0)
+
+
+def from_perturbation(grid: Grid, q):
+    """The full conserved state from its perturbation storage form."""
+    return _shift_storage(grid, q, 1.0)
+
+
+def _shift_storage(grid: Grid, q, sign: float):
+    rb = np.asarray(grid.rhobar_cell, dtype=np.float64)[:, None, None]
+    eb = (np.asarray(grid.pbar_cell, dtype=np.float64) / (grid.gamma - 1.0))[:, None, None]
+    if isinstance(q, np.ndarray):
+        out = q.astype(np.float64, copy=True)
+        out[0] += sign * rb
+        out[4] += sign * eb
+        return out.astype(q.dtype, copy=False)
+    import torch
+
+    out = q.clone()
+    out[0] = out[0] + sign * torch.as_tensor(rb, dtype=q.dtype, device=q.device)
+    out[4] = out[4] + sign * torch.as_tensor(eb, dtype=q.dtype, device=q.device)
+    return out
+
+
 def mixture_internal_energy(grid: Grid, rho, p, rho_t):
     """Internal energy per volume of a gas-condensate parcel at pressure p.
 
