@@ -1000,7 +1000,14 @@ def main():
                           "roofline": f32["roofline"],
                           "stage_kernel_avg_ms": f32["stage_kernel_avg_ms"]}), flush=True)
         return
+    t_start = time.perf_counter()
+
+    def progress(section):
+        print(f"[bench] {section} done at {time.perf_counter() - t_start:.1f} s", file=sys.stderr,
+              flush=True)
+
     f64 = run_gpu(torch.float64, args.steps, args.warmup)
+    progress("headline f64")
     out = {
         "metric": METRIC,
         "value": f64["value"],
@@ -1046,6 +1053,7 @@ def main():
             "hbm_roofline": f32["hbm_roofline"], "valu_utilisation": f32["valu_utilisation"],
         }}
         out["f32_speedup"] = f32["value"] / f64["value"]
+        progress("f32")
         f32p = run_gpu(torch.float32, args.steps, args.warmup, perturbation=True)
         out["variants"]["f32_perturbation"] = {
             "value": f32p["value"], "ms_per_step": f32p["ms_per_step"], "dtype": "f32",
@@ -1054,14 +1062,19 @@ def main():
             "stage_kernel_avg_ms": f32p["stage_kernel_avg_ms"], "roofline": f32p["roofline"],
             "hbm_roofline": f32p["hbm_roofline"],
         }
+        progress("f32 perturbation storage")
         out["f32_error_vs_f64"] = run_fp32_error()
+        progress("f32 error")
     if not args.only_headline:
         out["jovian"] = run_jovian(50, 3)
         out["jovian_mixture"] = run_jovian(50, 3, mixture=True)
         out["jovian_mixture"]["cost_vs_passive"] = (out["jovian"]["value"]
                                                     / out["jovian_mixture"]["value"])
+        progress("jovian")
         out["jovian_kessler"] = run_jovian_kessler(20, 2)
+        progress("jovian kessler")
         out["jovian_satadj"] = run_jovian_satadj(20, 2)
+        progress("jovian saturation adjustment")
         out["hllc"] = {}
         for name, dt_, ref in (("f64", torch.float64, f64), ("f32", torch.float32, out.get("variants", {}).get("f32"))):
             h = run_gpu(dt_, 30, 3, hllc=True)
@@ -1070,13 +1083,18 @@ def main():
                                  "stage_kernel_avg_ms": h["stage_kernel_avg_ms"],
                                  "roofline": h["roofline"],
                                  "cost_vs_lmars": (ref["value"] / h["value"]) if ref else None}
+        progress("hllc")
         out["ensemble"] = run_ensemble(20)
+        progress("ensemble")
         out["bubble2d"] = run_bubble2d()
         out["adjoint"] = run_adjoint()
+        progress("adjoint")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline()
+        progress("cpu baseline")
         if not args.only_headline:
             out["cpu_oracle_sections"] = run_cpu_oracle_sections()
+            progress("cpu oracle sections")
     print(json.dumps(out), flush=True)
 
 

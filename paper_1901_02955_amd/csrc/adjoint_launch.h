@@ -1,6 +1,8 @@
 // Dispatch of the adjoint kernels for one element type (included once per type).
 #pragma once
 
+#include <cstdlib>
+
 #include "snap_adjoint.h"
 #include "snap_internal.h"
 
@@ -16,6 +18,44 @@ void adj_line_launch(const T* W, const T* r, const AdjArgs& a, int d, T* P, hipS
                      st, W, r, a, d, P);
 }
 
+// The y and z directions march along their lines (k_adj_march) in single
+// precision with up to 7 variables, where the march's register window fits;
+// double precision and more variables take the tiled kernel. Setting
+// SNAP_ADJ_MARCH=0 selects the tiled kernel everywhere.
+template <typename T, int NV>
+constexpr bool march_fits() {
+  return sizeof(T) == 4 && NV <= 7;
+}
+
+// (read at every launch, so that a process can compare both kernels)
+inline bool march_enabled() {
+  const char* e = getenv("SNAP_ADJ_MARCH");
+  return !(e && e[0] == '0');
+}
+
+// Segment length of the march: at most 43 cells, so that the 256 x 256 x 128
+// grid gives 3 x 65536 z segments and 6 x 32768 y segments (three waves per
+// SIMD of the 256 compute units, the kernel's occupancy with 5 variables),
+// each recomputing a 3-cell halo on either side. On that grid one FP32
+// right-hand-side adjoint took 1.100, 1.107, 1.085 and 1.133 ms with segments
+// of 24, 32, 43 and 64 cells. SNAP_ADJ_MARCH_SEG overrides the length.
+inline int march_seglen(int nd) {
+  const char* e = getenv("SNAP_ADJ_MARCH_SEG");
+  const int v = e ? atoi(e) : 0;
+  const int target = v > 0 ? v : 43;
+  const int nseg = (nd + target - 1) / target;
+  return (nd + nseg - 1) / nseg;
+}
+
+template <typename T, int NV, int D>
+void adj_march_launch(const T* W, const T* r, const AdjArgs& a, T* P, hipStream_t st) {
+  const int nd = D == 2 ? a.nz : a.ny;
+  const long long lines = (long long)a.nx * (D == 2 ? a.ny : a.nz);
+  const int seg = march_seglen(nd);
+  const dim3 grid((unsigned)((lines + 255) / 256), (unsigned)((nd + seg - 1) / seg));
+  hipLaunchKernelGGL((k_adj_march<T, NV, D>), grid, dim3(256), 0, st, W, r, a, seg, P);
+}
+
 template <typename T, int NV>
 int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
                int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
@@ -27,8 +67,15 @@ int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb
   const dim3 pgrid(rows, (nxp + 255) / 256);
   hipLaunchKernelGGL((k_adj_prims<T, NV>), pgrid, dim3(256), 0, st, qs, a, W);
   adj_line_launch<T, NV, true>(W, r, a, 0, P, st);
-  if (a.d3) adj_line_launch<T, NV, false>(W, r, a, 1, P, st);
-  adj_line_launch<T, NV, false>(W, r, a, 2, P, st);
+  if (march_fits<T, NV>() && march_enabled()) {
+    if constexpr (march_fits<T, NV>()) {
+      if (a.d3) adj_march_launch<T, NV, 1>(W, r, a, P, st);
+      adj_march_launch<T, NV, 2>(W, r, a, P, st);
+    }
+  } else {
+    if (a.d3) adj_line_launch<T, NV, false>(W, r, a, 1, P, st);
+    adj_line_launch<T, NV, false>(W, r, a, 2, P, st);
+  }
   const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
   hipLaunchKernelGGL((k_adj_consfold<T, NV>), fgrid, dim3(256), 0, st, qs, P, r, a,
                      static_cast<T*>(out), mode, alpha, beta, static_cast<const T*>(y), gam);

@@ -201,6 +201,92 @@ __device__ __forceinline__ void weno5_rev(T a, T b, T c, T d, T e, bool linear,
 }
 
 // ---------------------------------------------------------------------------
+// Forward and reverse of one WENO5 cell in one pass: the cotangents g of the
+// five inputs a..e given the cotangents gm of qm and gp of qp (the transpose
+// of the derivative of weno5_cell at a..e), for a caller that does not keep
+// the forward quantities. With S_k = 4 eps + (13/3) u_k^2 + v_k^2 and the
+// normalised weights w_k = (d_k / S_k^2) / sum_m (d_m / S_m^2), the derivative
+// of qm - c = (1/6) sum_k w_k m_k with respect to S_j is
+// -(w_j / (3 S_j)) (m_j - M) with M = sum_k w_k m_k, and qp's stencil k uses
+// S_{2-k}. Hence the cotangent of S_j is
+//   Sb_j = -2 (mb_j (m_j - Mm) + pb_{2-j} (p_{2-j} - Mp)) / S_j,
+// where mb_k = gm w_k / 6 and pb_k = gp wp_k / 6 are the cotangents of the
+// candidate values, and those of u_j and v_j are Sb_j (26/3) u_j and Sb_j 2 v_j
+// (dS/du = (26/3) u, dS/dv = 2 v). The weights are formed as in weno5_lin.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void weno5_linrev(T a, T b, T c, T d, T e, T eps, bool linear, T gm,
+                                             T gp, T (&g)[5]) {
+  const T da = a - c, db = b - c, dd = d - c, de = e - c;
+  const T sixth = T(1) / T(6);
+  const T gms = gm * sixth, gps = gp * sixth;
+  T mb0, mb1, mb2, pb0, pb1, pb2;
+  T ub0 = T(0), vb0 = T(0), ub1 = T(0), vb1 = T(0), ub2 = T(0), vb2 = T(0);
+  if (linear) {
+    mb0 = gms * T(0.1);
+    mb1 = gms * T(0.6);
+    mb2 = gms * T(0.3);
+    pb0 = gps * T(0.1);
+    pb1 = gps * T(0.6);
+    pb2 = gps * T(0.3);
+  } else {
+    const T m0 = T(2) * da - T(7) * db, m1 = T(2) * dd - db, m2 = T(5) * dd - de;
+    const T p0 = T(2) * de - T(7) * dd, p1 = T(2) * db - dd, p2 = T(5) * db - da;
+    const T k13 = T(13) / T(3), eps4 = T(4) * eps;
+    const T u0 = fma(T(-2), db, da), v0 = fma(T(-4), db, da);
+    const T u1 = db + dd, v1 = db - dd;
+    const T u2 = fma(T(-2), dd, de), v2 = fma(T(-4), dd, de);
+    const T ku0 = k13 * u0, ku1 = k13 * u1, ku2 = k13 * u2;
+    const T S0 = fma(v0, v0, fma(ku0, u0, eps4));
+    const T S1 = fma(v1, v1, fma(ku1, u1, eps4));
+    const T S2 = fma(v2, v2, fma(ku2, u2, eps4));
+    T sc;
+    if constexpr (sizeof(T) == 4) {
+      const float mx = fmaxf(fmaxf(S0, S1), S2);
+      sc = __builtin_amdgcn_ldexpf(1.0f, -__builtin_amdgcn_frexp_expf(mx));
+    } else {
+      const double mx = fmax(fmax(S0, S1), S2);
+      sc = __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(mx));
+    }
+    const T s0 = S0 * sc, s1 = S1 * sc, s2 = S2 * sc;
+    const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
+    const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
+    const T n0 = T(0.1) * t0, n1 = T(0.6) * t1, n2 = T(0.3) * t2;
+    const T r0 = T(0.1) * t2, r1 = T(0.6) * t1, r2 = T(0.3) * t0;
+    const T idm = rcp_fast(n0 + n1 + n2), idp = rcp_fast(r0 + r1 + r2);
+    const T wm0 = n0 * idm, wm1 = n1 * idm, wm2 = n2 * idm;
+    const T wp0 = r0 * idp, wp1 = r1 * idp, wp2 = r2 * idp;
+    const T Mm = wm0 * m0 + wm1 * m1 + wm2 * m2;
+    const T Mp = wp0 * p0 + wp1 * p1 + wp2 * p2;
+    mb0 = gms * wm0;
+    mb1 = gms * wm1;
+    mb2 = gms * wm2;
+    pb0 = gps * wp0;
+    pb1 = gps * wp1;
+    pb2 = gps * wp2;
+    // h_j = 2 Sb_j, so that ub_j = h_j (13/3) u_j and vb_j = h_j v_j
+    const T h0 = T(-4) * fma(mb0, m0 - Mm, pb2 * (p2 - Mp)) * rcp_fast(S0);
+    const T h1 = T(-4) * fma(mb1, m1 - Mm, pb1 * (p1 - Mp)) * rcp_fast(S1);
+    const T h2 = T(-4) * fma(mb2, m2 - Mm, pb0 * (p0 - Mp)) * rcp_fast(S2);
+    ub0 = h0 * ku0;
+    vb0 = h0 * v0;
+    ub1 = h1 * ku1;
+    vb1 = h1 * v1;
+    ub2 = h2 * ku2;
+    vb2 = h2 * v2;
+  }
+  const T dab = T(2) * mb0 - pb2 + ub0 + vb0;
+  const T dbb = -T(7) * mb0 - mb1 + T(2) * pb1 + T(5) * pb2 - T(2) * ub0 - T(4) * vb0 + ub1 + vb1;
+  const T ddb = T(2) * mb1 + T(5) * mb2 - T(7) * pb0 - pb1 + ub1 - vb1 - T(2) * ub2 - T(4) * vb2;
+  const T deb = -mb2 + T(2) * pb0 + ub2 + vb2;
+  g[0] = dab;
+  g[1] = dbb;
+  g[2] = gm + gp - (dab + dbb + ddb + deb);
+  g[3] = ddb;
+  g[4] = deb;
+}
+
+// ---------------------------------------------------------------------------
 // Reverse of lmars_flux: given the flux cotangent fb, accumulate the
 // cotangents of the two face states into xlb / xrb. At u* == 0 the derivative
 // of the advective flux with respect to u* uses the mean of both sides'
@@ -616,6 +702,154 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) P[pc + v * a.sv] = acc[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of one direction D (1 = y, 2 = z) by a march along the lines: one
+// thread per segment [c0, c1) of a line, the threads of a wave on consecutive
+// x cells (every load and store coalesced), stepping through the cells in
+// order with the primitives of six consecutive cells, the cotangent sums of
+// five, and the previous cell's left face state, right-state cotangent and
+// r_bar in registers: no LDS and no barrier. At cell j the thread
+//   (1) reconstructs cell j (weno5_cell: its two face values);
+//   (2) evaluates LMARS forward and reverse at face j, between cells j-1 and
+//       j, with the flux cotangent (r_bar[j] - r_bar[j-1]) / dx_D;
+//   (3) runs the WENO5 reverse of cell j-1 (weno5_linrev, which recomputes
+//       that cell's weights) with the cotangents of its face values from
+//       faces j and j-1, and adds the five contributions to the sums of
+//       cells j-3 .. j+1;
+//   (4) writes the sum of cell j-3, now complete, into P.
+// Each sum has one fixed order (P as the previous direction left it, or zero
+// for a ghost cell beyond this direction's edges, then the contributions of
+// reconstructions j-2 .. j+2 in turn), so the result is reproducible bit for
+// bit. A segment recomputes the reconstructions and faces of a 3-cell halo on
+// each side; the ghost cells beyond a domain edge belong to the first or the
+// last segment of the line.
+// Grid: x over blocks of 256 lines (x fastest), y over segments of seglen.
+// ---------------------------------------------------------------------------
+template <typename T, int NV, int D>
+__global__ void __launch_bounds__(256) k_adj_march(const T* __restrict__ W,
+                                                   const T* __restrict__ rb, AdjArgs a,
+                                                   int seglen, T* __restrict__ P) {
+  static_assert(D == 1 || D == 2, "march directions: y and z");
+  const int n1 = D == 2 ? a.ny : a.nz;   // second transverse extent
+  const int nd = D == 2 ? a.nz : a.ny;   // cells along the line
+  const long long line = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (line >= (long long)a.nx * n1) return;
+  const int i = (int)(line % a.nx), o1 = (int)(line / a.nx);
+  const int c0 = (int)blockIdx.y * seglen;
+  if (c0 >= nd) return;
+  const int c1 = min(c0 + seglen, nd);
+  const long long sd = D == 2 ? a.sz : a.sy;
+  const long long rd = D == 2 ? a.rz : a.ry;
+  // padded offset of position 0 of the line, interior offset of position 0
+  const long long pb = D == 2 ? padded_off(a, i, o1, 0) : padded_off(a, i, 0, o1);
+  const long long rbo = D == 2 ? (long long)o1 * a.ry + i : (long long)o1 * a.rz + i;
+  const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
+  const T inv_gm1 = static_cast<T>(a.inv_gm1);
+  const T hi_d = static_cast<T>(D == 2 ? a.dxi[2] : a.dxi[1]);
+  const bool linear = a.linear != 0;
+  // y faces take the reference of the line's level
+  const T rref_c = D == 1 ? static_cast<T>(a.rbar_c[o1 + NG]) : T(0);
+  const T pref_c = D == 1 ? static_cast<T>(a.pbar_c[o1 + NG]) : T(0);
+
+  const int jA = max(c0 - 3, -1);                       // first reconstructed cell
+  const int jL = min(c1 + 2, nd);                       // last reconstructed cell
+  const int fA = max(c0 - 2, 0), fB = min(c1 + 2, nd);  // faces
+  const int rA = max(c0 - 2, -1), rB = min(c1 + 1, nd); // reversed reconstructions
+  const int lo = c0 == 0 ? -3 : c0, hi = c1 == nd ? nd + 3 : c1;   // cells written
+  T win[6][NV];   // primitives of cells j-3 .. j+2
+  T acc[5][NV];   // cotangent sums of cells j-3 .. j+1
+  T qmp[NV], gpp[NV], rbp[NV];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const int cw = jA - 3 + m;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) win[m][v] = cw >= -3 ? W[pb + cw * sd + v * a.sv] : T(0);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    win[5][v] = T(0);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) acc[m][v] = T(0);   // cells jA-3 .. jA: ghosts or not written
+    qmp[v] = T(0);
+    gpp[v] = T(0);
+    rbp[v] = T(0);
+  }
+  for (int j = jA; j <= hi + 2; ++j) {
+    // loads: primitives of cell j+2, r_bar of cell j, P of cell j+1 (start of its sum)
+    if (j <= nd) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) win[5][v] = W[pb + (j + 2) * sd + v * a.sv];
+    }
+    T rbc[NV];
+    const bool rin = j >= 0 && j < nd && j <= fB;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rbc[v] = rin ? rb[rbo + j * rd + v * a.rv] : T(0);
+    {
+      const int cn = j + 1;
+      const bool from_p = cn >= lo && cn < hi && cn >= 0 && cn < nd;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[4][v] = from_p ? P[pb + cn * sd + v * a.sv] : T(0);
+    }
+    // (1) face values of cell j
+    T qm[NV], qp[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      qm[v] = T(0);
+      qp[v] = T(0);
+    }
+    if (j <= jL) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        weno5_cell<T>(win[1][v], win[2][v], win[3][v], win[4][v], win[5][v], eps, linear, qm[v],
+                      qp[v]);
+    }
+    // (2) face j: left state qm of cell j-1, right state qp of cell j
+    T xlb[NV], xrb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      xlb[v] = T(0);
+      xrb[v] = T(0);
+    }
+    if (j >= fA && j <= fB) {
+      T fbar[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fbar[v] = (rbc[v] - rbp[v]) * hi_d;
+      const T rref = D == 2 ? static_cast<T>(a.rbar_f[j]) : rref_c;
+      const T pref = D == 2 ? static_cast<T>(a.pbar_f[j]) : pref_c;
+      lmars_flux_adj<T, NV>(qmp, qp, D + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
+    }
+    // (3) reverse of cell j-1 (stencil cells j-3 .. j+1)
+    if (j - 1 >= rA && j - 1 <= rB) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T g[5];
+        weno5_linrev<T>(win[0][v], win[1][v], win[2][v], win[3][v], win[4][v], eps, linear,
+                        xlb[v], gpp[v], g);
+#pragma unroll
+        for (int o = 0; o < 5; ++o) acc[o][v] += g[o];
+      }
+    }
+    // (4) cell j-3 is complete
+    {
+      const int cf = j - 3;
+      if (cf >= lo && cf < hi) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) P[pb + cf * sd + v * a.sv] = acc[0][v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) win[m][v] = win[m + 1][v];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m][v] = acc[m + 1][v];
+      qmp[v] = qm[v];
+      gpp[v] = xrb[v];
+      rbp[v] = rbc[v];
+    }
   }
 }
 

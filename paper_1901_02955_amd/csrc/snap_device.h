@@ -180,8 +180,9 @@ __device__ __forceinline__ float sqrt_fast(float y) { return y * __builtin_amdgc
 // Sound speed sqrt(gp / rho) from gp = gamma p and the density, written as
 // gp h with h = 1 / sqrt(gp rho) (which is also 1 / (rho c)), so no
 // reciprocal of rho is needed. Double precision refines the hardware
-// reciprocal square root of y = gp rho by two Goldschmidt steps, which carry
-// g -> sqrt(y) and k -> 1 / (2 sqrt(y)) together; h = 2 k.
+// reciprocal square root of y = gp rho by SNAP_F64_REFINE_STEPS Goldschmidt
+// steps, which carry g -> sqrt(y) and k -> 1 / (2 sqrt(y)) together (the last
+// step updates k only); h = 2 k.
 __device__ __forceinline__ double sound_speed_h(double gp, double rho, double& h) {
   const double y = gp * rho;
   const double h0 = __builtin_amdgcn_rsq(y);
