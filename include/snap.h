@@ -215,10 +215,10 @@ int snap_abi_version(void);
 /*
  * Bytes of device workspace `work` needed by operation `op` (SNAP_OP_*) on grid
  * g; 0 if none is needed. Returns 0 and sets the last error for an invalid grid.
- * SNAP_OP_RK3 and SNAP_OP_RHS_ADJ need two padded state arrays, SNAP_OP_RK3_CFL
- * the same plus 256 bytes (two signal-speed slots and the state flag read by
- * snap_rk3_steps_status), SNAP_OP_RK3_ADJ
- * four padded plus two interior arrays, SNAP_OP_CFL and SNAP_OP_SUMS a few
+ * SNAP_OP_RK3 needs two padded state arrays, SNAP_OP_RK3_CFL the same plus
+ * 256 bytes (two signal-speed slots and the state flag read by
+ * snap_rk3_steps_status), SNAP_OP_RHS_ADJ one padded array, SNAP_OP_RK3_ADJ
+ * three padded plus two interior arrays, SNAP_OP_CFL and SNAP_OP_SUMS a few
  * hundred kilobytes of reduction partials.
  */
 size_t snap_workspace_bytes(const snap_grid* g, int op);

@@ -9,13 +9,13 @@
 namespace snap {
 
 template <typename T, int NV, bool XDIR>
-void adj_line_launch(const T* W, const T* r, const AdjArgs& a, int d, T* P, hipStream_t st) {
+void adj_line_launch(const T* q, const T* r, const AdjArgs& a, int d, T* P, hipStream_t st) {
   constexpr int LN = LineShape<T, NV, XDIR>::LN, TL = LineShape<T, NV, XDIR>::TL;
   const LineGeom g = line_geom(a, d);
   const long long blocks = ((g.nlines + LN - 1) / LN) * ((g.nd + TL - 1) / TL);
   hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR>), dim3((unsigned)blocks),
                      dim3(LineTile<T, NV, LN, TL>::NTHR), 0,
-                     st, W, r, a, d, P);
+                     st, q, r, a, d, P);
 }
 
 // The y and z directions march along their lines (k_adj_march) in single
@@ -48,12 +48,12 @@ inline int march_seglen(int nd) {
 }
 
 template <typename T, int NV, int D>
-void adj_march_launch(const T* W, const T* r, const AdjArgs& a, T* P, hipStream_t st) {
+void adj_march_launch(const T* q, const T* r, const AdjArgs& a, T* P, hipStream_t st) {
   const int nd = D == 2 ? a.nz : a.ny;
   const long long lines = (long long)a.nx * (D == 2 ? a.ny : a.nz);
   const int seg = march_seglen(nd);
   const dim3 grid((unsigned)((lines + 255) / 256), (unsigned)((nd + seg - 1) / seg));
-  hipLaunchKernelGGL((k_adj_march<T, NV, D>), grid, dim3(256), 0, st, W, r, a, seg, P);
+  hipLaunchKernelGGL((k_adj_march<T, NV, D>), grid, dim3(256), 0, st, q, r, a, seg, P);
 }
 
 template <typename T, int NV>
@@ -61,20 +61,16 @@ int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb
                int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
   const T* qs = static_cast<const T*>(q);
   const T* r = static_cast<const T*>(rb);
-  T* W = static_cast<T*>(w.W);
   T* P = static_cast<T*>(w.P);
-  const int nxp = a.nx + 2 * NG, rows = (a.nz + 2 * NG) * (a.d3 ? a.ny + 2 * NG : 1);
-  const dim3 pgrid(rows, (nxp + 255) / 256);
-  hipLaunchKernelGGL((k_adj_prims<T, NV>), pgrid, dim3(256), 0, st, qs, a, W);
-  adj_line_launch<T, NV, true>(W, r, a, 0, P, st);
+  adj_line_launch<T, NV, true>(qs, r, a, 0, P, st);
   if (march_fits<T, NV>() && march_enabled()) {
     if constexpr (march_fits<T, NV>()) {
-      if (a.d3) adj_march_launch<T, NV, 1>(W, r, a, P, st);
-      adj_march_launch<T, NV, 2>(W, r, a, P, st);
+      if (a.d3) adj_march_launch<T, NV, 1>(qs, r, a, P, st);
+      adj_march_launch<T, NV, 2>(qs, r, a, P, st);
     }
   } else {
-    if (a.d3) adj_line_launch<T, NV, false>(W, r, a, 1, P, st);
-    adj_line_launch<T, NV, false>(W, r, a, 2, P, st);
+    if (a.d3) adj_line_launch<T, NV, false>(qs, r, a, 1, P, st);
+    adj_line_launch<T, NV, false>(qs, r, a, 2, P, st);
   }
   const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
   hipLaunchKernelGGL((k_adj_consfold<T, NV>), fgrid, dim3(256), 0, st, qs, P, r, a,

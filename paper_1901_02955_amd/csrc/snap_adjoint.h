@@ -5,12 +5,16 @@
 // ghost cells being functions of the interior through the boundary conditions.
 //
 // The reverse sweep uses no atomics, so the result is reproducible bit for bit:
-//   k_adj_prims      primitives of every padded cell (as in the forward pass);
-//   k_adj_line<d>    per direction d, per tile of lines: recompute the WENO
-//                    face states, LMARS forward and reverse with the flux
-//                    cotangent F_bar = (r_bar[right cell] - r_bar[left cell]) / dx_d,
-//                    WENO5 reverse to the five stencil inputs, and a fixed-order
-//                    gather of those contributions into the primitive cotangent;
+//   k_adj_line<d>    per direction d, per tile of lines: the primitives of
+//                    the tile's cells from the state (as in the forward
+//                    pass), the WENO face states recomputed, LMARS forward
+//                    and reverse with the flux cotangent
+//                    F_bar = (r_bar[right cell] - r_bar[left cell]) / dx_d,
+//                    the WENO5 reverse to the five stencil inputs, and a
+//                    fixed-order gather of those contributions into the
+//                    primitive cotangent;
+//   k_adj_march<d>   the same for the y and z directions in single precision,
+//                    one thread per line segment marching along it;
 //   k_adj_consfold   per interior cell: gravity terms and the reverse of the
 //                    conserved -> primitive map (double precision) for the
 //                    cell and for each ghost cell that copies it, summed
@@ -385,23 +389,6 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
 // kernels
 // ---------------------------------------------------------------------------
 
-// Primitives of every padded cell (ghost corners included, harmlessly).
-// Grid: x over padded rows (nz+6)(ny+2gy), y over the padded row.
-template <typename T, int NV>
-__global__ void __launch_bounds__(256) k_adj_prims(const T* __restrict__ q, AdjArgs a,
-                                                   T* __restrict__ W) {
-  const int nxp = a.nx + 2 * NG, nyp = a.d3 ? a.ny + 2 * NG : 1;
-  const int ip = blockIdx.y * 256 + threadIdx.x;
-  if (ip >= nxp) return;
-  const int row = blockIdx.x;
-  const int kp = row / nyp;
-  const long long c = (long long)row * nxp + ip;
-  T x[NV];
-  load_prim<T, NV>(q, c, a.sv, level_ref(a.pert, a.rbar_c[kp], a.pbar_c[kp]), a.gm1, x);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) W[c + v * a.sv] = x[v];
-}
-
 // ---------------------------------------------------------------------------
 // Fused adjoint of one direction d for a tile of LN lines x TL cells along d.
 // In LDS: (A) left/right face states of the reconstructed cells the tile
@@ -526,7 +513,7 @@ __device__ __forceinline__ void line_cell(const AdjArgs& a, const LineGeom& g, l
 
 template <typename T, int NV, int LN, int TL, bool XDIR>
 __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE_ATTR
-    k_adj_line(const T* __restrict__ W, const T* __restrict__ rb, AdjArgs a, int d,
+    k_adj_line(const T* __restrict__ q, const T* __restrict__ rb, AdjArgs a, int d,
                T* __restrict__ P) {
   using Tile = LineTile<T, NV, LN, TL>;
   constexpr int NTHR = Tile::NTHR;
@@ -573,16 +560,21 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
   const bool cell_a = line_a && ja >= -1 && ja <= g.nd;
   WenoLin<T> lin[NV];
   // the primitives of the tile's lines, cells c0-5 .. c0+TL+4 (those outside
-  // the padded range -3 .. nd+2 are never read), staged in LDS once: the
-  // stencils of (A) and (C) are read from there
+  // the padded range -3 .. nd+2 are never read), converted from the
+  // ghost-filled state and staged in LDS once: the stencils of (A) and (C)
+  // are read from there
   for (int it = threadIdx.x; it < LN * (TL + 10); it += NTHR) {
     int l, m;
     decode(it, TL + 10, l, m);
     const int jg = c0 - 5 + m;
     if (L0 + l < g.nlines && jg >= -3 && jg <= g.nd + 2) {
       const long long pc = S.pbase[l] + jg * g.sd;
+      const int kl = d == 2 ? jg : S.lev[l];   // level of the cell
+      T x[NV];
+      load_prim<T, NV>(q, pc, a.sv, level_ref(a.pert, a.rbar_c[kl + NG], a.pbar_c[kl + NG]),
+                       a.gm1, x);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) S.WL[v][l][m] = W[pc + v * a.sv];
+      for (int v = 0; v < NV; ++v) S.WL[v][l][m] = x[v];
     }
   }
   __syncthreads();
@@ -727,9 +719,11 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
 // each side; the ghost cells beyond a domain edge belong to the first or the
 // last segment of the line.
 // Grid: x over blocks of 256 lines (x fastest), y over segments of seglen.
+// Held to three waves per SIMD (168 registers): the y instance with 5
+// variables would otherwise take 169.
 // ---------------------------------------------------------------------------
 template <typename T, int NV, int D>
-__global__ void __launch_bounds__(256) k_adj_march(const T* __restrict__ W,
+__global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
                                                    const T* __restrict__ rb, AdjArgs a,
                                                    int seglen, T* __restrict__ P) {
   static_assert(D == 1 || D == 2, "march directions: y and z");
@@ -762,11 +756,22 @@ __global__ void __launch_bounds__(256) k_adj_march(const T* __restrict__ W,
   T win[6][NV];   // primitives of cells j-3 .. j+2
   T acc[5][NV];   // cotangent sums of cells j-3 .. j+1
   T qmp[NV], gpp[NV], rbp[NV];
+  // primitives of cell c of the line (padded range -3 .. nd+2), converted
+  // from the ghost-filled state with the references of its level
+  auto prims = [&](int c, T (&x)[NV]) {
+    const int kl = D == 2 ? c : o1;
+    load_prim<T, NV>(q, pb + c * sd, a.sv, level_ref(a.pert, a.rbar_c[kl + NG], a.pbar_c[kl + NG]),
+                     a.gm1, x);
+  };
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const int cw = jA - 3 + m;
+    if (cw >= -3) {
+      prims(cw, win[m]);
+    } else {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) win[m][v] = cw >= -3 ? W[pb + cw * sd + v * a.sv] : T(0);
+      for (int v = 0; v < NV; ++v) win[m][v] = T(0);
+    }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -779,10 +784,7 @@ __global__ void __launch_bounds__(256) k_adj_march(const T* __restrict__ W,
   }
   for (int j = jA; j <= hi + 2; ++j) {
     // loads: primitives of cell j+2, r_bar of cell j, P of cell j+1 (start of its sum)
-    if (j <= nd) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) win[5][v] = W[pb + (j + 2) * sd + v * a.sv];
-    }
+    if (j <= nd) prims(j + 2, win[5]);
     T rbc[NV];
     const bool rin = j >= 0 && j < nd && j <= fB;
 #pragma unroll

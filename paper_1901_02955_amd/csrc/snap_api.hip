@@ -448,26 +448,24 @@ size_t interior_bytes(const snap_grid* g) {
   return (size_t)g->nx * g->ny * g->nz * nvar_of(g) * elem_of(g);
 }
 
-// Layout of the right-hand-side adjoint workspace: W (padded primitives, then
-// the padded conserved cotangent) and P (padded primitive cotangent).
+// Layout of the right-hand-side adjoint workspace: P, the padded primitive
+// cotangent (the direction kernels convert the state to primitives
+// themselves).
 struct AdjLayout {
-  size_t w, p, total;
+  size_t p, total;
 };
 
 AdjLayout adj_layout(const snap_grid* g) {
   AdjLayout L;
-  L.w = 0;
-  L.p = L.w + align256(padded_bytes(g));
+  L.p = 0;
   L.total = L.p + align256(padded_bytes(g));
   return L;
 }
 
 AdjWork adj_work(const snap_grid* g, void* base) {
   const AdjLayout L = adj_layout(g);
-  char* b = static_cast<char*>(base);
   AdjWork w;
-  w.W = b + L.w;
-  w.P = b + L.p;
+  w.P = static_cast<char*>(base) + L.p;
   return w;
 }
 

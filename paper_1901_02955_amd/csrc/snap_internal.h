@@ -89,7 +89,6 @@ struct AdjArgs;
 
 // Workspace pointers of one right-hand-side adjoint.
 struct AdjWork {
-  void* W;   // padded primitives, then padded conserved cotangent
   void* P;   // padded primitive cotangent
 };
 

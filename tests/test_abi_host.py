@@ -186,7 +186,7 @@ def test_workspace_sizes():
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_CFL) >= 8
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_SUMS) >= 8 * (5 + c.ntracer)
         adj = lib.snap_workspace_bytes(g, snap.SNAP_OP_RHS_ADJ)
-        assert adj == 2 * a256
+        assert adj == a256
         interior = c.nx * c.ny * c.nz * (5 + c.ntracer) * es
         assert lib.snap_workspace_bytes(g, snap.SNAP_OP_RK3_ADJ) >= adj + 2 * padded + 2 * interior
     assert lib.snap_workspace_bytes(ctypes.byref(good_grid()), 99) == 0
