@@ -9,7 +9,9 @@ steps; the backward pass re-runs each segment from its checkpoint, keeping the
 segment's states, and then walks it in reverse. With ``keep_stages`` (the
 default) the re-run also keeps every step's two stage states, so that the
 adjoint step does not recompute them (``snap_rk3_step_adjoint_stages``): a
-segment then holds three padded states per step instead of one.
+segment then holds three padded states per step instead of one. The forward
+pass keeps the last segment that way already, so the backward pass starts
+without a re-run.
 
 Only the interior of the state carries gradients: the library overwrites ghost
 layers from the interior on every call, so the gradient with respect to the
@@ -37,13 +39,22 @@ class _SnapRK3Run(torch.autograd.Function):
         work = workspace(grid, SNAP_OP_RK3)
         q = q0.detach().clone()
         checkpoints = []
+        last = (nsteps - 1) // checkpoint_every * checkpoint_every   # first step of the last segment
+        kept_states, kept_stages = [], []
         for n in range(nsteps):
             if n % checkpoint_every == 0:
                 checkpoints.append(q.clone())
-            snap_rk3_step(grid, q, dt, work)
+            if keep_stages and n >= last:
+                # the last segment: its states and stage states, as the backward re-run keeps them
+                kept_states.append(q.clone())
+                kept_stages.append(workspace(grid, SNAP_OP_RK3))
+                snap_rk3_step(grid, q, dt, kept_stages[-1])
+            else:
+                snap_rk3_step(grid, q, dt, work)
         ctx.grid, ctx.dt, ctx.nsteps, ctx.every = grid, dt, nsteps, checkpoint_every
         ctx.keep_stages = keep_stages
         ctx.checkpoints = checkpoints
+        ctx.last_segment = (kept_states, kept_stages) if keep_stages else None
         return q
 
     @staticmethod
@@ -55,6 +66,13 @@ class _SnapRK3Run(torch.autograd.Function):
         for seg in range(len(ctx.checkpoints) - 1, -1, -1):
             start = seg * every
             stop = min(start + every, nsteps)
+            if ctx.keep_stages and seg == len(ctx.checkpoints) - 1:
+                states, stages = ctx.last_segment
+                ctx.last_segment = None
+                for t in range(stop - start - 1, -1, -1):
+                    snap_rk3_step_adjoint_stages(grid, states[t], stages[t], dt, qbar, awork)
+                del stages, states
+                continue
             states = [ctx.checkpoints[seg].clone()]
             if ctx.keep_stages:
                 # every step of the segment, the last included, for its stage states
@@ -79,6 +97,7 @@ class _SnapRK3Run(torch.autograd.Function):
         grad_in = torch.zeros_like(grad_out)
         _interior(grid, grad_in).copy_(qbar)
         ctx.checkpoints = None
+        ctx.last_segment = None
         return grad_in, None, None, None, None, None
 
 
