@@ -19,8 +19,9 @@ void adj_line_launch(const T* q, const T* r, const AdjArgs& a, int d, T* P, hipS
 }
 
 // The y and z directions march along their lines (k_adj_march) in single
-// precision with up to 7 variables, where the march's register window fits;
-// double precision and more variables take the tiled kernel. Setting
+// precision with up to 7 variables, where the march's register window fits,
+// and where each variable's padded plane is smaller than 2 GiB; double
+// precision, more variables and larger planes take the tiled kernel. Setting
 // SNAP_ADJ_MARCH=0 selects the tiled kernel everywhere.
 template <typename T, int NV>
 constexpr bool march_fits() {
@@ -63,7 +64,10 @@ int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb
   const T* r = static_cast<const T*>(rb);
   T* P = static_cast<T*>(w.P);
   adj_line_launch<T, NV, true>(qs, r, a, 0, P, st);
-  if (march_fits<T, NV>() && march_enabled()) {
+  // the march addresses each variable's plane with 32-bit byte offsets
+  const bool planes_small = a.sv * (long long)sizeof(T) < (1LL << 31) &&
+                            a.rv * (long long)sizeof(T) < (1LL << 31);
+  if (march_fits<T, NV>() && march_enabled() && planes_small) {
     if constexpr (march_fits<T, NV>()) {
       if (a.d3) adj_march_launch<T, NV, 1>(qs, r, a, P, st);
       adj_march_launch<T, NV, 2>(qs, r, a, P, st);

@@ -756,12 +756,24 @@ __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
   T win[6][NV];   // primitives of cells j-3 .. j+2
   T acc[5][NV];   // cotangent sums of cells j-3 .. j+1
   T qmp[NV], gpp[NV], rbp[NV];
+  // Every access is a uniform per-variable base (q, P: padded planes; r_bar:
+  // interior planes) plus one 32-bit byte offset per cell, which the caller
+  // keeps below 2^31 (each variable's plane is smaller than 2 GiB).
+  auto at = [](const T* base, unsigned boff) -> const T& {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+  };
+  const unsigned bsd = (unsigned)(sd * (long long)sizeof(T));
+  const unsigned brd = (unsigned)(rd * (long long)sizeof(T));
   // primitives of cell c of the line (padded range -3 .. nd+2), converted
   // from the ghost-filled state with the references of its level
   auto prims = [&](int c, T (&x)[NV]) {
     const int kl = D == 2 ? c : o1;
-    load_prim<T, NV>(q, pb + c * sd, a.sv, level_ref(a.pert, a.rbar_c[kl + NG], a.pbar_c[kl + NG]),
-                     a.gm1, x);
+    const unsigned bo = (unsigned)(pb * (long long)sizeof(T)) + (unsigned)c * bsd;
+    T cv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cv[v] = at(q + v * a.sv, bo);
+    const LevelRef lr = level_ref(a.pert, a.rbar_c[kl + NG], a.pbar_c[kl + NG]);
+    cons_to_prim_sp<NV>(cv, lr.ra, lr.rs, lr.ps, a.gm1, x);
   };
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -787,13 +799,17 @@ __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
     if (j <= nd) prims(j + 2, win[5]);
     T rbc[NV];
     const bool rin = j >= 0 && j < nd && j <= fB;
+    {
+      const unsigned bo = (unsigned)(rbo * (long long)sizeof(T)) + (unsigned)j * brd;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) rbc[v] = rin ? rb[rbo + j * rd + v * a.rv] : T(0);
+      for (int v = 0; v < NV; ++v) rbc[v] = rin ? at(rb + v * a.rv, bo) : T(0);
+    }
     {
       const int cn = j + 1;
       const bool from_p = cn >= lo && cn < hi && cn >= 0 && cn < nd;
+      const unsigned bo = (unsigned)(pb * (long long)sizeof(T)) + (unsigned)cn * bsd;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[4][v] = from_p ? P[pb + cn * sd + v * a.sv] : T(0);
+      for (int v = 0; v < NV; ++v) acc[4][v] = from_p ? at(P + v * a.sv, bo) : T(0);
     }
     // (1) face values of cell j
     T qm[NV], qp[NV];
@@ -838,8 +854,10 @@ __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
     {
       const int cf = j - 3;
       if (cf >= lo && cf < hi) {
+        const unsigned bo = (unsigned)(pb * (long long)sizeof(T)) + (unsigned)cf * bsd;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) P[pb + cf * sd + v * a.sv] = acc[0][v];
+        for (int v = 0; v < NV; ++v)
+          *reinterpret_cast<T*>(reinterpret_cast<char*>(P + v * a.sv) + bo) = acc[0][v];
       }
     }
 #pragma unroll
