@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 10
+#define SNAP_ABI_VERSION 11
 
 /* return codes */
 #define SNAP_OK 0
@@ -154,11 +154,11 @@ extern "C" {
  *                velocities, E_K/rho_K + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K))),
  *                q_K), with full face density and pressure; the normal momentum
  *                flux carries the perturbation pressure as under LMARS. HLLC
- *                takes eos = SNAP_EOS_PASSIVE; the adjoint and batched entry
- *                points return SNAP_E_UNSUPPORTED for it.
+ *                takes eos = SNAP_EOS_PASSIVE; the adjoint entry points
+ *                return SNAP_E_UNSUPPORTED for it.
  *                The tracer fields are read only under SNAP_EOS_MIXTURE with
  *                ntracer > 0 (a nonzero tracer_wt needs the mixture); there the
- *                adjoint and batched entry points return SNAP_E_UNSUPPORTED.
+ *                adjoint entry points return SNAP_E_UNSUPPORTED.
  * storage        SNAP_STORE_TOTAL (0): q holds the conserved state.
  *                SNAP_STORE_PERTURBATION: q[0] holds rho - rhobar_k and q[4]
  *                holds E - pbar_k / (gamma - 1) (the state's departure from the
@@ -396,8 +396,11 @@ int snap_conservation_sums_noalloc(const snap_grid* g, void* q, double* sums_hos
  * each (Sec. 4.3), with per-member grids, states and time steps. Every stage
  * is one batched ghost-fill launch and one persistent stage launch for all
  * members: `nblocks` workgroups walk the (member, tile) work items round-robin
- * (0 = as many as fit on the device at once). Members must share dtype and
- * ntracer; 3-D members return SNAP_E_UNSUPPORTED; 1 <= n <= 65535.
+ * (0 = as many as fit on the device at once). Members must share dtype,
+ * ntracer, equation of state and Riemann solver (the passive gas or the
+ * mixture; LMARS or HLLC), else SNAP_E_INVALID; 3-D members, and members
+ * whose condensates fall (the sedimentation of Sec. 2), return
+ * SNAP_E_UNSUPPORTED; 1 <= n <= 65535.
  * gs       HOST array of n grids (each with its own DEVICE reference profiles).
  * q        HOST array of n DEVICE pointers to padded member states (in Q^n,
  *          out Q^{n+1}; ghost layers unspecified on return).

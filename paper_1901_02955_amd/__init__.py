@@ -49,7 +49,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 10
+SNAP_ABI_VERSION = 11
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0

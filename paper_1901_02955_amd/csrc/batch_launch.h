@@ -1,7 +1,8 @@
 // Tile variants and dispatch of the batched (ensemble) 2-D stage kernel for one
-// element type. Variant 0 is the single-domain default shape; variants 1..5
-// (ntracer == 0 only) are alternatives for the autotuner. A variant whose LDS
-// plane would exceed 64 KiB is unavailable.
+// element type and form (MIX: the mixture equation of state; HLLC: the HLLC
+// flux; neither: passive tracers with LMARS). Variant 0 is the single-domain
+// default shape; variants 1..5 (ntracer == 0 only) are alternatives for the
+// autotuner. A variant whose LDS plane would exceed 64 KiB is unavailable.
 #pragma once
 
 #include "stage_launch.h"
@@ -21,26 +22,26 @@ constexpr bool batch_fits() {
   return sizeof(Plane<T, 5 + NT, TX, TZ>) <= 64 * 1024;
 }
 
-template <typename T, int NT, int TX, int TZ>
+template <typename T, int NT, int TX, int TZ, bool MIX, bool HLLC>
 int batch_launch_shape(const StageArgs* d, const int* first, int n, int nblocks, hipStream_t st) {
-  if constexpr (!batch_fits<T, NT, TX, TZ>()) {
+  if constexpr (!batch_fits<T, NT, TX, TZ>() || (MIX && NT == 0)) {
     return -2;
   } else {
-    hipLaunchKernelGGL((k_stage2d_batched<T, NT, TX, TZ>), dim3(nblocks), dim3(TX * TZ), 0, st, d,
-                       first, n);
+    hipLaunchKernelGGL((k_stage2d_batched<T, NT, TX, TZ, MIX, HLLC>), dim3(nblocks), dim3(TX * TZ),
+                       0, st, d, first, n);
     return hipGetLastError() == hipSuccess ? 0 : -1;
   }
 }
 
-template <typename T, int NT, int TX, int TZ>
+template <typename T, int NT, int TX, int TZ, bool MIX, bool HLLC>
 int batch_occ_shape() {
-  if constexpr (!batch_fits<T, NT, TX, TZ>()) {
+  if constexpr (!batch_fits<T, NT, TX, TZ>() || (MIX && NT == 0)) {
     return 0;
   } else {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void*>(&k_stage2d_batched<T, NT, TX, TZ>), TX * TZ, 0) !=
-        hipSuccess)
+            &nb, reinterpret_cast<const void*>(&k_stage2d_batched<T, NT, TX, TZ, MIX, HLLC>),
+            TX * TZ, 0) != hipSuccess)
       return 0;
     return nb;
   }
@@ -65,34 +66,35 @@ TileShape batch_tile_nt(int v) {
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool MIX, bool HLLC>
 int batch_launch_nt(int v, const StageArgs* d, const int* first, int n, int nb, hipStream_t st) {
   if constexpr (NT == 0) {
     switch (v) {
-      case 1: return batch_launch_shape<T, NT, 32, 8>(d, first, n, nb, st);
-      case 2: return batch_launch_shape<T, NT, 64, 4>(d, first, n, nb, st);
-      case 3: return batch_launch_shape<T, NT, 8, 32>(d, first, n, nb, st);
-      case 4: return batch_launch_shape<T, NT, 16, 8>(d, first, n, nb, st);
-      case 5: return batch_launch_shape<T, NT, 32, 16>(d, first, n, nb, st);
+      case 1: return batch_launch_shape<T, NT, 32, 8, MIX, HLLC>(d, first, n, nb, st);
+      case 2: return batch_launch_shape<T, NT, 64, 4, MIX, HLLC>(d, first, n, nb, st);
+      case 3: return batch_launch_shape<T, NT, 8, 32, MIX, HLLC>(d, first, n, nb, st);
+      case 4: return batch_launch_shape<T, NT, 16, 8, MIX, HLLC>(d, first, n, nb, st);
+      case 5: return batch_launch_shape<T, NT, 32, 16, MIX, HLLC>(d, first, n, nb, st);
       default: break;
     }
   }
-  return batch_launch_shape<T, NT, TileFor<T, NT>::TX, TileFor<T, NT>::TY>(d, first, n, nb, st);
+  return batch_launch_shape<T, NT, TileFor<T, NT>::TX, TileFor<T, NT>::TY, MIX, HLLC>(d, first, n,
+                                                                                     nb, st);
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool MIX, bool HLLC>
 int batch_occ_nt(int v) {
   if constexpr (NT == 0) {
     switch (v) {
-      case 1: return batch_occ_shape<T, NT, 32, 8>();
-      case 2: return batch_occ_shape<T, NT, 64, 4>();
-      case 3: return batch_occ_shape<T, NT, 8, 32>();
-      case 4: return batch_occ_shape<T, NT, 16, 8>();
-      case 5: return batch_occ_shape<T, NT, 32, 16>();
+      case 1: return batch_occ_shape<T, NT, 32, 8, MIX, HLLC>();
+      case 2: return batch_occ_shape<T, NT, 64, 4, MIX, HLLC>();
+      case 3: return batch_occ_shape<T, NT, 8, 32, MIX, HLLC>();
+      case 4: return batch_occ_shape<T, NT, 16, 8, MIX, HLLC>();
+      case 5: return batch_occ_shape<T, NT, 32, 16, MIX, HLLC>();
       default: break;
     }
   }
-  return batch_occ_shape<T, NT, TileFor<T, NT>::TX, TileFor<T, NT>::TY>();
+  return batch_occ_shape<T, NT, TileFor<T, NT>::TX, TileFor<T, NT>::TY, MIX, HLLC>();
 }
 
 #define SNAP_NT_SWITCH(CALL)        \
@@ -118,18 +120,18 @@ TileShape batch_tile_t(int ntracer, int v) {
   return TileShape{0, 0};
 }
 
-template <typename T>
+template <typename T, bool MIX, bool HLLC>
 int batch_launch_t(int ntracer, int v, const StageArgs* d, const int* first, int n, int nb,
                    hipStream_t st) {
-#define SNAP_CALL(NT) batch_launch_nt<T, NT>(v, d, first, n, nb, st)
+#define SNAP_CALL(NT) batch_launch_nt<T, NT, MIX, HLLC>(v, d, first, n, nb, st)
   SNAP_NT_SWITCH(SNAP_CALL)
 #undef SNAP_CALL
   return -1;
 }
 
-template <typename T>
+template <typename T, bool MIX, bool HLLC>
 int batch_occ_t(int ntracer, int v) {
-#define SNAP_CALL(NT) batch_occ_nt<T, NT>(v)
+#define SNAP_CALL(NT) batch_occ_nt<T, NT, MIX, HLLC>(v)
   SNAP_NT_SWITCH(SNAP_CALL)
 #undef SNAP_CALL
   return 0;

@@ -496,11 +496,12 @@ int check_batch(const snap_grid* gs, int n) {
       return fail(SNAP_E_UNSUPPORTED, "member %d is 3-D: the batched step takes 2-D members", m);
     if (gs[m].dtype != gs[0].dtype || gs[m].ntracer != gs[0].ntracer)
       return fail(SNAP_E_INVALID, "member %d differs in dtype or ntracer from member 0", m);
-    if (uses_mixture(&gs[m]))
+    if (uses_mixture(&gs[m]) != uses_mixture(&gs[0]) || gs[m].riemann != gs[0].riemann)
+      return fail(SNAP_E_INVALID,
+                  "member %d differs from member 0 in its equation of state or Riemann solver", m);
+    if (stage_args(&gs[m]).sed.on)
       return fail(SNAP_E_UNSUPPORTED,
-                  "member %d uses the mixture equation of state: the batched step takes passive tracers", m);
-    if (gs[m].riemann != SNAP_RIEMANN_LMARS)
-      return fail(SNAP_E_UNSUPPORTED, "member %d: the batched step takes the LMARS flux", m);
+                  "member %d has falling condensates: the batched step takes no sedimentation", m);
   }
   return SNAP_OK;
 }
@@ -935,6 +936,7 @@ int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const doub
   }
   if (nblocks < 0) return fail(SNAP_E_INVALID, "nblocks must be >= 0");
   const int dtype = gs[0].dtype, nt = gs[0].ntracer;
+  const int form = uses_mixture(&gs[0]) ? 1 : (gs[0].riemann == SNAP_RIEMANN_HLLC ? 2 : 0);
   const TileShape t = batched_tile(dtype, nt, variant);
   if (t.tx == 0) return fail(SNAP_E_UNSUPPORTED, "tile variant %d unavailable", variant);
   const hipStream_t st = (hipStream_t)stream;
@@ -985,7 +987,7 @@ int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const doub
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       cus = 256;
-    int per = batched_occupancy(dtype, nt, variant);
+    int per = batched_occupancy(dtype, nt, variant, form);
     nb = cus * (per > 0 ? per : 1);
   }
   if (nb > items) nb = (int)items;
@@ -995,7 +997,7 @@ int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const doub
   for (int s = 0; s < 3; ++s) {
     if (launch_fill_ghosts_batched(dtype, dg + s * n, n, max_ghosts, st))
       return device_fail("batched ghost fill launch");
-    if (launch_stage2d_batched(dtype, nt, variant, dd + s * n, df, n, nb, st))
+    if (launch_stage2d_batched(dtype, nt, variant, form, dd + s * n, df, n, nb, st))
       return device_fail("batched stage launch");
   }
   return ok();

@@ -322,27 +322,28 @@ namespace snap {
 
 TileShape batched_tile_f64(int ntracer, int v);
 TileShape batched_tile_f32(int ntracer, int v);
-int batched_occupancy_f64(int ntracer, int v);
-int batched_occupancy_f32(int ntracer, int v);
-int launch_stage2d_batched_f64(int ntracer, int v, const StageArgs* d, const int* first, int n,
-                               int nb, hipStream_t st);
-int launch_stage2d_batched_f32(int ntracer, int v, const StageArgs* d, const int* first, int n,
-                               int nb, hipStream_t st);
+int batched_occupancy_f64(int ntracer, int v, int form);
+int batched_occupancy_f32(int ntracer, int v, int form);
+int launch_stage2d_batched_f64(int ntracer, int v, int form, const StageArgs* d, const int* first,
+                               int n, int nb, hipStream_t st);
+int launch_stage2d_batched_f32(int ntracer, int v, int form, const StageArgs* d, const int* first,
+                               int n, int nb, hipStream_t st);
 
 TileShape batched_tile(int dtype, int ntracer, int variant) {
   if (variant < 0 || variant >= BATCH_VARIANTS) return TileShape{0, 0};
   return dtype == 0 ? batched_tile_f64(ntracer, variant) : batched_tile_f32(ntracer, variant);
 }
 
-int batched_occupancy(int dtype, int ntracer, int variant) {
-  return dtype == 0 ? batched_occupancy_f64(ntracer, variant)
-                    : batched_occupancy_f32(ntracer, variant);
+int batched_occupancy(int dtype, int ntracer, int variant, int form) {
+  return dtype == 0 ? batched_occupancy_f64(ntracer, variant, form)
+                    : batched_occupancy_f32(ntracer, variant, form);
 }
 
-int launch_stage2d_batched(int dtype, int ntracer, int variant, const StageArgs* descs,
+int launch_stage2d_batched(int dtype, int ntracer, int variant, int form, const StageArgs* descs,
                            const int* first, int n, int nblocks, hipStream_t st) {
-  return dtype == 0 ? launch_stage2d_batched_f64(ntracer, variant, descs, first, n, nblocks, st)
-                    : launch_stage2d_batched_f32(ntracer, variant, descs, first, n, nblocks, st);
+  return dtype == 0
+             ? launch_stage2d_batched_f64(ntracer, variant, form, descs, first, n, nblocks, st)
+             : launch_stage2d_batched_f32(ntracer, variant, form, descs, first, n, nblocks, st);
 }
 
 }  // namespace snap

@@ -124,8 +124,9 @@ int launch_fill_ghosts_batched(int dtype, const GhostDesc* d, int n, long long m
 // Batched (ensemble) 2-D stage kernel: tile variant v of the element type.
 constexpr int BATCH_VARIANTS = 6;
 TileShape batched_tile(int dtype, int ntracer, int variant);   // {0, 0}: unavailable
-int batched_occupancy(int dtype, int ntracer, int variant);
-int launch_stage2d_batched(int dtype, int ntracer, int variant, const StageArgs* descs,
+// form: 0 passive tracers with LMARS, 1 the mixture equation of state, 2 HLLC
+int batched_occupancy(int dtype, int ntracer, int variant, int form);
+int launch_stage2d_batched(int dtype, int ntracer, int variant, int form, const StageArgs* descs,
                            const int* first, int n, int nblocks, hipStream_t st);
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st);

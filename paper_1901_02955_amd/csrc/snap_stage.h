@@ -874,7 +874,7 @@ __global__ void __launch_bounds__(TX* TZ) k_stage2d(StageArgs a) {
 // items w = blockIdx.x, blockIdx.x + gridDim.x, ... A barrier closes every tile:
 // its last phase still reads the primitive plane (density perturbation for the
 // gravity source) that the next tile's first phase overwrites.
-template <typename T, int NT, int TX, int TZ>
+template <typename T, int NT, int TX, int TZ, bool MIX = false, bool HLLC = false>
 __global__ void __launch_bounds__(TX* TZ) k_stage2d_batched(const StageArgs* __restrict__ descs,
                                                             const int* __restrict__ first, int n) {
   __shared__ Plane<T, 5 + NT, TX, TZ> S;
@@ -889,7 +889,7 @@ __global__ void __launch_bounds__(TX* TZ) k_stage2d_batched(const StageArgs* __r
         hi = mid;
     }
     const StageArgs a = descs[lo];
-    stage2d_tile<T, NT, TX, TZ>(a, w - first[lo], S);
+    stage2d_tile<T, NT, TX, TZ, MIX, HLLC>(a, w - first[lo], S);
     __syncthreads();
   }
 }

@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 10
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 11
 
 
 def good_grid(**kw):
@@ -216,6 +216,19 @@ def test_batched_validation():
     assert lib.snap_rk3_step_batched(mixed, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
     three_d = (snap.SnapGridC * 2)(good_grid(ny=1), good_grid())
     assert lib.snap_rk3_step_batched(three_d, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_UNSUPPORTED
+    # every member shares member 0's equation of state and Riemann solver
+    eos_mix = (snap.SnapGridC * 2)(good_grid(ny=1), good_grid(ny=1, eos=snap.SNAP_EOS_MIXTURE))
+    assert lib.snap_rk3_step_batched(eos_mix, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
+    flux_mix = (snap.SnapGridC * 2)(good_grid(ny=1), good_grid(ny=1, riemann=snap.SNAP_RIEMANN_HLLC))
+    assert lib.snap_rk3_step_batched(flux_mix, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
+    both = (snap.SnapGridC * 2)(good_grid(ny=1, eos=snap.SNAP_EOS_MIXTURE),
+                                good_grid(ny=1, nx=9, eos=snap.SNAP_EOS_MIXTURE))
+    assert lib.snap_batched_workspace_bytes(both, 2) > 0
+    # falling condensates: no sedimentation in the batched step
+    falling = (snap.SnapGridC * 2)(good_grid(ny=1, eos=snap.SNAP_EOS_MIXTURE),
+                                   good_grid(ny=1, eos=snap.SNAP_EOS_MIXTURE, tracer_wt=(0.0, -5.0),
+                                             rd=287.0))
+    assert lib.snap_rk3_step_batched(falling, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_UNSUPPORTED
     bad_member = (snap.SnapGridC * 2)(good_grid(ny=1), good_grid(ny=1, dx=0.0))
     assert lib.snap_rk3_step_batched(bad_member, 2, qs, dts, 0, 0, W, None) == snap.SNAP_E_INVALID
     assert b"member 1" in lib.snap_last_error()
@@ -239,8 +252,8 @@ def test_batched_workspace_layout():
 
 def test_mixture_fields_and_unsupported_entry_points():
     """The tracer fields are read only under SNAP_EOS_MIXTURE; a condensate's
-    molar-mass ratio is ignored; the adjoint and batched entry points refuse
-    the mixture."""
+    molar-mass ratio is ignored; the adjoint entry points refuse the
+    mixture, the batched step takes it."""
     lib = snap.lib()
     # passive: garbage tracer fields are not validated
     g = ctypes.byref(good_grid(tracer_kind=(7, 9), tracer_sigma=(-1.0, math.nan)))
@@ -262,8 +275,7 @@ def test_mixture_fields_and_unsupported_entry_points():
     assert lib.snap_rk3_step_adjoint_stages(g, P, ctypes.c_void_p(4 * FAKE), 0.1, Q2, Q3,
                                             None) == snap.SNAP_E_UNSUPPORTED
     arr = (snap.SnapGridC * 2)(good_grid(ny=1, eos=1), good_grid(ny=1, eos=1))
-    assert lib.snap_batched_workspace_bytes(arr, 2) == 0
-    assert b"mixture" in lib.snap_last_error()
+    assert lib.snap_batched_workspace_bytes(arr, 2) > 0
 
 
 def _kessler(**kw):
@@ -362,7 +374,7 @@ def test_saturation_adjust_needs_the_mixture():
     assert lib.snap_saturation_adjust(g, P, None, None) == snap.SNAP_E_INVALID
 
 
-def test_hllc_refuses_the_mixture_and_is_refused_by_adjoint_and_batched():
+def test_hllc_refuses_the_mixture_and_is_refused_by_the_adjoint():
     lib = snap.lib()
     P = ctypes.c_void_p(FAKE)
     Q2, Q3 = ctypes.c_void_p(2 * FAKE), ctypes.c_void_p(3 * FAKE)
@@ -373,7 +385,7 @@ def test_hllc_refuses_the_mixture_and_is_refused_by_adjoint_and_batched():
     assert lib.snap_rk3_step_adjoint_stages(g, P, ctypes.c_void_p(4 * FAKE), 0.1, Q2, Q3,
                                             None) == snap.SNAP_E_UNSUPPORTED
     arr = (snap.SnapGridC * 2)(good_grid(ny=1, riemann=1), good_grid(ny=1, riemann=1))
-    assert lib.snap_batched_workspace_bytes(arr, 2) == 0
+    assert lib.snap_batched_workspace_bytes(arr, 2) > 0   # the batched step takes HLLC
     mixed = ctypes.byref(good_grid(riemann=1, eos=1))
     assert lib.snap_rhs(mixed, P, Q2, None) == snap.SNAP_E_UNSUPPORTED
 
