@@ -154,8 +154,8 @@ extern "C" {
  *                velocities, E_K/rho_K + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K))),
  *                q_K), with full face density and pressure; the normal momentum
  *                flux carries the perturbation pressure as under LMARS. HLLC
- *                takes eos = SNAP_EOS_PASSIVE; the adjoint entry points
- *                return SNAP_E_UNSUPPORTED for it.
+ *                takes eos = SNAP_EOS_PASSIVE. The adjoint entry points take
+ *                either flux.
  *                The tracer fields are read only under SNAP_EOS_MIXTURE with
  *                ntracer > 0 (a nonzero tracer_wt needs the mixture); there the
  *                adjoint entry points return SNAP_E_UNSUPPORTED.
@@ -267,7 +267,9 @@ int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stre
  * At an interface velocity u* of exactly zero, where the upwind choice of LMARS
  * switches sides, the derivative of the advective flux with respect to u* uses
  * the mean of both sides' advected vectors (the one-sided derivatives differ
- * there). The result is reproducible bit for bit (no atomics).
+ * there). With HLLC the derivative is that of the branch (side, star region)
+ * and of the outer wave speed candidates the forward evaluation selects. The
+ * result is reproducible bit for bit (no atomics).
  * work  device workspace of snap_workspace_bytes(g, SNAP_OP_RHS_ADJ) bytes.
  */
 int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_bar, void* work,

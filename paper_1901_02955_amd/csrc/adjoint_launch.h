@@ -8,12 +8,12 @@
 
 namespace snap {
 
-template <typename T, int NV, bool XDIR>
+template <typename T, int NV, bool XDIR, bool HLLC>
 void adj_line_launch(const T* q, const T* r, const AdjArgs& a, int d, T* P, hipStream_t st) {
   constexpr int LN = LineShape<T, NV, XDIR>::LN, TL = LineShape<T, NV, XDIR>::TL;
   const LineGeom g = line_geom(a, d);
   const long long blocks = ((g.nlines + LN - 1) / LN) * ((g.nd + TL - 1) / TL);
-  hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR, HLLC>), dim3((unsigned)blocks),
                      dim3(LineTile<T, NV, LN, TL>::NTHR), 0,
                      st, q, r, a, d, P);
 }
@@ -48,33 +48,33 @@ inline int march_seglen(int nd) {
   return (nd + nseg - 1) / nseg;
 }
 
-template <typename T, int NV, int D>
+template <typename T, int NV, int D, bool HLLC>
 void adj_march_launch(const T* q, const T* r, const AdjArgs& a, T* P, hipStream_t st) {
   const int nd = D == 2 ? a.nz : a.ny;
   const long long lines = (long long)a.nx * (D == 2 ? a.ny : a.nz);
   const int seg = march_seglen(nd);
   const dim3 grid((unsigned)((lines + 255) / 256), (unsigned)((nd + seg - 1) / seg));
-  hipLaunchKernelGGL((k_adj_march<T, NV, D>), grid, dim3(256), 0, st, q, r, a, seg, P);
+  hipLaunchKernelGGL((k_adj_march<T, NV, D, HLLC>), grid, dim3(256), 0, st, q, r, a, seg, P);
 }
 
-template <typename T, int NV>
+template <typename T, int NV, bool HLLC>
 int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
                int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
   const T* qs = static_cast<const T*>(q);
   const T* r = static_cast<const T*>(rb);
   T* P = static_cast<T*>(w.P);
-  adj_line_launch<T, NV, true>(qs, r, a, 0, P, st);
+  adj_line_launch<T, NV, true, HLLC>(qs, r, a, 0, P, st);
   // the march addresses each variable's plane with 32-bit byte offsets
   const bool planes_small = a.sv * (long long)sizeof(T) < (1LL << 31) &&
                             a.rv * (long long)sizeof(T) < (1LL << 31);
   if (march_fits<T, NV>() && march_enabled() && planes_small) {
     if constexpr (march_fits<T, NV>()) {
-      if (a.d3) adj_march_launch<T, NV, 1>(qs, r, a, P, st);
-      adj_march_launch<T, NV, 2>(qs, r, a, P, st);
+      if (a.d3) adj_march_launch<T, NV, 1, HLLC>(qs, r, a, P, st);
+      adj_march_launch<T, NV, 2, HLLC>(qs, r, a, P, st);
     }
   } else {
-    if (a.d3) adj_line_launch<T, NV, false>(qs, r, a, 1, P, st);
-    adj_line_launch<T, NV, false>(qs, r, a, 2, P, st);
+    if (a.d3) adj_line_launch<T, NV, false, HLLC>(qs, r, a, 1, P, st);
+    adj_line_launch<T, NV, false, HLLC>(qs, r, a, 2, P, st);
   }
   const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
   hipLaunchKernelGGL((k_adj_consfold<T, NV>), fgrid, dim3(256), 0, st, qs, P, r, a,
@@ -82,14 +82,14 @@ int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename T>
+template <typename T, bool HLLC>
 int adj_rhs_t(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
               int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
   int r = -1;
   switch (a.nvar) {
 #define SNAP_ADJ_CASE(NVV)                                                      \
   case NVV:                                                                     \
-    r = adj_rhs_nv<T, NVV>(w, a, q, rb, out, mode, alpha, beta, y, gam, st);   \
+    r = adj_rhs_nv<T, NVV, HLLC>(w, a, q, rb, out, mode, alpha, beta, y, gam, st); \
     break;
     SNAP_ADJ_CASE(5)
     SNAP_ADJ_CASE(6)

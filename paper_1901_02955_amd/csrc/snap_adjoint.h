@@ -36,6 +36,7 @@ struct AdjArgs {
   int linear;
   int bc[3];
   int pert;   // perturbation storage (rho - rhobar_k, E - pbar_k / (gamma - 1))
+  int hllc;   // the HLLC flux (else LMARS)
   const double* rbar_c;
   const double* pbar_c;
   const double* rbar_f;
@@ -386,6 +387,206 @@ __device__ __forceinline__ void lmars_flux_adj(const T (&xl)[NV], const T (&xr)[
 }
 
 // ---------------------------------------------------------------------------
+// Reverse of hllc_flux: given the flux cotangent fb, accumulate the
+// cotangents of the two face states into xlb / xrb. The branch (the side k
+// whose flux is taken, and whether the star correction applies) is that of
+// the forward evaluation; the outer speeds take the derivative of the
+// candidate that min / max selected. With c = sqrt(gamma p / rho):
+// dc/dp = c / (2 p), dc/drho = -c / (2 rho).
+// ---------------------------------------------------------------------------
+template <typename T, int NV>
+__device__ __forceinline__ void hllc_flux_adj(const T (&xl)[NV], const T (&xr)[NV], int nrm,
+                                              T rref, T pref, T gamma, T inv_gm1,
+                                              const T (&fb)[NV], T (&xlb)[NV], T (&xrb)[NV]) {
+  // ---- forward, as in hllc_flux
+  const T rl = rref + xl[0], rr = rref + xr[0];
+  const T pl = pref + xl[4], pr = pref + xr[4];
+  const T unl = nrm == 1 ? xl[1] : (nrm == 2 ? xl[2] : xl[3]);
+  const T unr = nrm == 1 ? xr[1] : (nrm == 2 ? xr[2] : xr[3]);
+  const T cl = sound_speed(gamma * pl, rl);
+  const T cr = sound_speed(gamma * pr, rr);
+  const bool sl_left = unl - cl <= unr - cr, sr_left = unl + cl >= unr + cr;
+  const T SL = sl_left ? unl - cl : unr - cr, SR = sr_left ? unl + cl : unr + cr;
+  const T dl = rl * (SL - unl), dr = rr * (SR - unr);
+  const T iD = rcp_fast(dl - dr);
+  const T Ss = (pr - pl + dl * unl - dr * unr) * iD;
+  const bool left = SL >= T(0) || Ss >= T(0);
+  const bool star = !(SL >= T(0)) && (left || SR > T(0));
+  const T rk = left ? rl : rr, pk = left ? pl : pr;
+  T vk[3];
+  vk[0] = left ? xl[1] : xr[1];
+  vk[1] = left ? xl[2] : xr[2];
+  vk[2] = left ? xl[3] : xr[3];
+  const T unk = left ? unl : unr, Sk = left ? SL : SR, dk = left ? dl : dr;
+  const T E = pk * inv_gm1 + T(0.5) * rk * (vk[0] * vk[0] + vk[1] * vk[1] + vk[2] * vk[2]);
+  const T mass = rk * unk;
+  // ---- reverse: cotangents of the side quantities
+  T rkb = T(0), pkb = T(0), ppkb = T(0), unkb = T(0), Skb = T(0), dkb = T(0), Ssb = T(0);
+  T Eb = T(0), massb = T(0);
+  T vb[3] = {T(0), T(0), T(0)};
+  T qb[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) qb[t] = T(0);
+  if (star) {
+    const T W = Sk - Ss, iW = rcp_fast(W);
+    const T fac = dk * iW;
+    const T idk = rcp_fast(dk), irk = rcp_fast(rk);
+    const T A1 = Ss - unk, A2 = Ss + pk * idk;
+    const T B = E * irk + A1 * A2;
+    const T e_star = fac * B;
+    T facb = T(0);
+    // f0 += Sk (fac - rk)
+    Skb += fb[0] * (fac - rk);
+    facb += fb[0] * Sk;
+    rkb -= fb[0] * Sk;
+    // f_i += Sk (fac s_i - rk u_i), s_i = S* on the normal, else u_i
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T g = fb[1 + i];
+      const bool nn = (i + 1) == nrm;
+      const T si = nn ? Ss : vk[i];
+      Skb += g * (fac * si - rk * vk[i]);
+      facb += g * Sk * si;
+      if (nn)
+        Ssb += g * Sk * fac;
+      else
+        vb[i] += g * Sk * fac;
+      rkb -= g * Sk * vk[i];
+      vb[i] -= g * Sk * rk;
+    }
+    // f4 += Sk (e_star - E)
+    Skb += fb[4] * (e_star - E);
+    const T esb = fb[4] * Sk;
+    Eb -= fb[4] * Sk;
+    // f_t += Sk (fac - rk) q_t
+#pragma unroll
+    for (int t = 5; t < NV; ++t) {
+      const T qk = left ? xl[t] : xr[t];
+      Skb += fb[t] * (fac - rk) * qk;
+      facb += fb[t] * Sk * qk;
+      rkb -= fb[t] * Sk * qk;
+      qb[t] += fb[t] * Sk * (fac - rk);
+    }
+    // e_star = fac B, B = E / rk + (S* - un)(S* + p / dk)
+    facb += esb * B;
+    const T Bb = esb * fac;
+    Eb += Bb * irk;
+    rkb -= Bb * E * irk * irk;
+    Ssb += Bb * (A1 + A2);
+    unkb -= Bb * A2;
+    pkb += Bb * A1 * idk;
+    dkb -= Bb * A1 * pk * idk * idk;
+    // fac = dk / (Sk - S*)
+    dkb += facb * iW;
+    const T Wb = -facb * fac * iW;
+    Skb += Wb;
+    Ssb -= Wb;
+  }
+  // plain flux of side k: f0 = mass, f_i = mass u_i (+ p' on the normal),
+  // f4 = (E + p) un, f_t = mass q_t
+  massb += fb[0];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    massb += fb[1 + i] * vk[i];
+    vb[i] += fb[1 + i] * mass;
+  }
+  ppkb += nrm == 1 ? fb[1] : (nrm == 2 ? fb[2] : fb[3]);
+  Eb += fb[4] * unk;
+  pkb += fb[4] * unk;
+  unkb += fb[4] * (E + pk);
+#pragma unroll
+  for (int t = 5; t < NV; ++t) {
+    const T qk = left ? xl[t] : xr[t];
+    massb += fb[t] * qk;
+    qb[t] += fb[t] * mass;
+  }
+  rkb += massb * unk;
+  unkb += massb * rk;
+  pkb += Eb * inv_gm1;
+  rkb += Eb * T(0.5) * (vk[0] * vk[0] + vk[1] * vk[1] + vk[2] * vk[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) vb[i] += Eb * rk * vk[i];
+  // the normal velocity of side k is one of its velocities
+  vb[nrm - 1] += unkb;
+  // ---- back to both sides: S* = N / D, N = pr - pl + dl unl - dr unr, D = dl - dr
+  T rlb = T(0), rrb = T(0), plb = T(0), prb = T(0), unlb = T(0), unrb = T(0);
+  T dlb = left ? dkb : T(0), drb = left ? T(0) : dkb;
+  T SLb = left ? Skb : T(0), SRb = left ? T(0) : Skb;
+  {
+    const T Nb = Ssb * iD, Db = -Ssb * Ss * iD;
+    prb += Nb;
+    plb -= Nb;
+    dlb += Nb * unl + Db;
+    unlb += Nb * dl;
+    drb += -Nb * unr - Db;
+    unrb -= Nb * dr;
+  }
+  // dl = rl (SL - unl), dr = rr (SR - unr)
+  rlb += dlb * (SL - unl);
+  SLb += dlb * rl;
+  unlb -= dlb * rl;
+  rrb += drb * (SR - unr);
+  SRb += drb * rr;
+  unrb -= drb * rr;
+  // SL = min(unl - cl, unr - cr), SR = max(unl + cl, unr + cr)
+  T clb = T(0), crb = T(0);
+  if (sl_left) {
+    unlb += SLb;
+    clb -= SLb;
+  } else {
+    unrb += SLb;
+    crb -= SLb;
+  }
+  if (sr_left) {
+    unlb += SRb;
+    clb += SRb;
+  } else {
+    unrb += SRb;
+    crb += SRb;
+  }
+  plb += clb * cl * T(0.5) * rcp_fast(pl);
+  rlb -= clb * cl * T(0.5) * rcp_fast(rl);
+  prb += crb * cr * T(0.5) * rcp_fast(pr);
+  rrb -= crb * cr * T(0.5) * rcp_fast(rr);
+  // side k's own quantities: rho = rref + x0, p = pref + x4, p' = x4
+  if (left) {
+    rlb += rkb;
+    plb += pkb + ppkb;
+  } else {
+    rrb += rkb;
+    prb += pkb + ppkb;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    xlb[1 + i] += left ? vb[i] : T(0);
+    xrb[1 + i] += left ? T(0) : vb[i];
+  }
+#pragma unroll
+  for (int t = 5; t < NV; ++t) {
+    xlb[t] += left ? qb[t] : T(0);
+    xrb[t] += left ? T(0) : qb[t];
+  }
+  // the normal velocities of both sides enter the wave speeds
+  xlb[nrm] += unlb;
+  xrb[nrm] += unrb;
+  xlb[0] += rlb;
+  xrb[0] += rrb;
+  xlb[4] += plb;
+  xrb[4] += prb;
+}
+
+// Reverse of the kernel's Riemann flux.
+template <typename T, int NV, bool HLLC>
+__device__ __forceinline__ void riemann_flux_adj(const T (&xl)[NV], const T (&xr)[NV], int nrm,
+                                                 T rref, T pref, T gamma, T inv_gm1,
+                                                 const T (&fb)[NV], T (&xlb)[NV], T (&xrb)[NV]) {
+  if constexpr (HLLC)
+    hllc_flux_adj<T, NV>(xl, xr, nrm, rref, pref, gamma, inv_gm1, fb, xlb, xrb);
+  else
+    lmars_flux_adj<T, NV>(xl, xr, nrm, rref, pref, gamma, inv_gm1, fb, xlb, xrb);
+}
+
+// ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 
@@ -511,7 +712,7 @@ __device__ __forceinline__ void line_cell(const AdjArgs& a, const LineGeom& g, l
 #define SNAP_ADJ_LINE_ATTR
 #endif
 
-template <typename T, int NV, int LN, int TL, bool XDIR>
+template <typename T, int NV, int LN, int TL, bool XDIR, bool HLLC = false>
 __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE_ATTR
     k_adj_line(const T* __restrict__ q, const T* __restrict__ rb, AdjArgs a, int d,
                T* __restrict__ P) {
@@ -633,7 +834,7 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
         rref = static_cast<T>(a.rbar_c[S.lev[l] + NG]);
         pref = static_cast<T>(a.pbar_c[S.lev[l] + NG]);
       }
-      lmars_flux_adj<T, NV>(xl, xr, d + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
+      riemann_flux_adj<T, NV, HLLC>(xl, xr, d + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -722,7 +923,7 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
 // Held to three waves per SIMD (168 registers): the y instance with 5
 // variables would otherwise take 169.
 // ---------------------------------------------------------------------------
-template <typename T, int NV, int D>
+template <typename T, int NV, int D, bool HLLC = false>
 __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
                                                    const T* __restrict__ rb, AdjArgs a,
                                                    int seglen, T* __restrict__ P) {
@@ -837,7 +1038,7 @@ __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
       for (int v = 0; v < NV; ++v) fbar[v] = (rbc[v] - rbp[v]) * hi_d;
       const T rref = D == 2 ? static_cast<T>(a.rbar_f[j]) : rref_c;
       const T pref = D == 2 ? static_cast<T>(a.pbar_f[j]) : pref_c;
-      lmars_flux_adj<T, NV>(qmp, qp, D + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
+      riemann_flux_adj<T, NV, HLLC>(qmp, qp, D + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
     }
     // (3) reverse of cell j-1 (stencil cells j-3 .. j+1)
     if (j - 1 >= rA && j - 1 <= rB) {

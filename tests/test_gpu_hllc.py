@@ -94,3 +94,56 @@ def test_hllc_differs_from_lmars_and_is_deterministic(hcases):
     snap.snap_rhs(dl, qd, rl)
     assert torch.equal(rh, rh2)
     assert float((rh[0] - rl[0]).abs().max()) > 1e-3 * float(rl[0].abs().max())
+
+
+# The adjoint with the HLLC flux (the reverse of hllc_flux in the direction
+# kernels): against the oracle's autograd through its HLLC right-hand side, on
+# the cases in motion (at rest the star region's branch and the outer-speed
+# selections follow rounding, as LMARS's upwind side does in the FP64 adjoint
+# tests).
+ADJ_HLLC = ["2d_smooth_37x29_nt3", "2d_reflect_21x19", "3d_smooth_35x21x19",
+            "3d_tracers_20x18x24_nt4", "3d_linear_17x9x11", "3d_periodic_z_12x10x14",
+            "3d_small_2x3x4", "3d_xwall_19x17x12"]
+
+
+@pytest.mark.parametrize("name", ADJ_HLLC)
+def test_rhs_adjoint_hllc(hcases, name):
+    c = hcases[name]
+    print(f"[hllc] adjoint {name}", flush=True)
+    rbar = wl.seeded_normal(c.grid.interior_shape, 130)
+    ref = oracle.rhs_adjoint(c.q, c.grid, rbar).numpy()
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    rb = torch.as_tensor(rbar).cuda()
+    qb = torch.empty_like(rb)
+    work = snap.workspace(dg, snap.SNAP_OP_RHS_ADJ)
+    snap.snap_rhs_adjoint(dg, qd, rb, qb, work)
+    errs = field_errors(qb.cpu().numpy(), ref)
+    print("   FP64", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-11 for e in errs), errs
+    # single precision (the march for y and z) at the same FP32-rounded inputs
+    q32 = c.q.astype(np.float32).astype(np.float64)
+    r32 = rbar.astype(np.float32).astype(np.float64)
+    ref32 = oracle.rhs_adjoint(q32, c.grid, r32).numpy()
+    dg32 = snap.device_grid(c.grid, dtype=torch.float32)
+    rbf = torch.as_tensor(r32).float().cuda()
+    qbf = torch.empty_like(rbf)
+    snap.snap_rhs_adjoint(dg32, torch.as_tensor(q32).float().cuda(), rbf, qbf,
+                          snap.workspace(dg32, snap.SNAP_OP_RHS_ADJ))
+    errs = field_errors(qbf.cpu().double().numpy(), ref32)
+    print("   FP32", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-4 for e in errs), errs
+
+
+@pytest.mark.parametrize("name", ["2d_smooth_37x29_nt3", "3d_smooth_35x21x19"])
+def test_rk3_step_adjoint_hllc(hcases, name):
+    c = hcases[name]
+    qbar = wl.seeded_normal(c.grid.interior_shape, 131)
+    ref = oracle.rk3_step_adjoint(c.q, c.grid, c.dt, qbar).numpy()
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    qb = torch.as_tensor(qbar).cuda()
+    snap.snap_rk3_step_adjoint(dg, qd, c.dt, qb, snap.workspace(dg, snap.SNAP_OP_RK3_ADJ))
+    errs = field_errors(qb.cpu().numpy(), ref)
+    print(f"[hllc] rk3 adjoint {name}", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-11 for e in errs), errs
