@@ -157,8 +157,9 @@ extern "C" {
  *                takes eos = SNAP_EOS_PASSIVE. The adjoint entry points take
  *                either flux.
  *                The tracer fields are read only under SNAP_EOS_MIXTURE with
- *                ntracer > 0 (a nonzero tracer_wt needs the mixture); there the
- *                adjoint entry points return SNAP_E_UNSUPPORTED.
+ *                ntracer > 0 (a nonzero tracer_wt needs the mixture). The
+ *                adjoint entry points take the mixture, but return
+ *                SNAP_E_UNSUPPORTED when a condensate falls (sedimentation).
  * storage        SNAP_STORE_TOTAL (0): q holds the conserved state.
  *                SNAP_STORE_PERTURBATION: q[0] holds rho - rhobar_k and q[4]
  *                holds E - pbar_k / (gamma - 1) (the state's departure from the

@@ -32,7 +32,7 @@ SOURCES = ["snap_api.hip", "snap_aux.hip", "stage_dry_f64.hip", "stage_dry_f32.h
            "stage_mix_f32.hip", "stage_hllc_f64.hip", "stage_hllc_f32.hip", "adjoint_f64.hip", "batch_f64.hip", "batch_f32.hip",
            "adjoint_f32.hip", "snap_micro.hip", "stage_sed_f64.hip", "stage_sed_f32.hip",
            "batch_mix_f64.hip", "batch_mix_f32.hip", "batch_hllc_f64.hip", "batch_hllc_f32.hip",
-           "adjoint_hllc_f64.hip", "adjoint_hllc_f32.hip"]
+           "adjoint_hllc_f64.hip", "adjoint_hllc_f32.hip", "adjoint_mix_f64.hip", "adjoint_mix_f32.hip"]
 
 # Per-source flags. The stage kernels without tracers run about 1.7 % (double)
 # and 1 % (single precision) faster under LLVM's iterative ILP scheduler at the

@@ -8,12 +8,12 @@
 
 namespace snap {
 
-template <typename T, int NV, bool XDIR, bool HLLC>
+template <typename T, int NV, bool XDIR, bool HLLC, bool MIX>
 void adj_line_launch(const T* q, const T* r, const AdjArgs& a, int d, T* P, hipStream_t st) {
   constexpr int LN = LineShape<T, NV, XDIR>::LN, TL = LineShape<T, NV, XDIR>::TL;
   const LineGeom g = line_geom(a, d);
   const long long blocks = ((g.nlines + LN - 1) / LN) * ((g.nd + TL - 1) / TL);
-  hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR, HLLC>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((k_adj_line<T, NV, LN, TL, XDIR, HLLC, MIX>), dim3((unsigned)blocks),
                      dim3(LineTile<T, NV, LN, TL>::NTHR), 0,
                      st, q, r, a, d, P);
 }
@@ -57,41 +57,44 @@ void adj_march_launch(const T* q, const T* r, const AdjArgs& a, T* P, hipStream_
   hipLaunchKernelGGL((k_adj_march<T, NV, D, HLLC>), grid, dim3(256), 0, st, q, r, a, seg, P);
 }
 
-template <typename T, int NV, bool HLLC>
+template <typename T, int NV, bool HLLC, bool MIX>
 int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
                int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
   const T* qs = static_cast<const T*>(q);
   const T* r = static_cast<const T*>(rb);
   T* P = static_cast<T*>(w.P);
-  adj_line_launch<T, NV, true, HLLC>(qs, r, a, 0, P, st);
+  adj_line_launch<T, NV, true, HLLC, MIX>(qs, r, a, 0, P, st);
   // the march addresses each variable's plane with 32-bit byte offsets
   const bool planes_small = a.sv * (long long)sizeof(T) < (1LL << 31) &&
                             a.rv * (long long)sizeof(T) < (1LL << 31);
-  if (march_fits<T, NV>() && march_enabled() && planes_small) {
-    if constexpr (march_fits<T, NV>()) {
+  // (the mixture takes the tiled kernel in every direction)
+  if (march_fits<T, NV>() && !MIX && march_enabled() && planes_small) {
+    if constexpr (march_fits<T, NV>() && !MIX) {
       if (a.d3) adj_march_launch<T, NV, 1, HLLC>(qs, r, a, P, st);
       adj_march_launch<T, NV, 2, HLLC>(qs, r, a, P, st);
     }
   } else {
-    if (a.d3) adj_line_launch<T, NV, false, HLLC>(qs, r, a, 1, P, st);
-    adj_line_launch<T, NV, false, HLLC>(qs, r, a, 2, P, st);
+    if (a.d3) adj_line_launch<T, NV, false, HLLC, MIX>(qs, r, a, 1, P, st);
+    adj_line_launch<T, NV, false, HLLC, MIX>(qs, r, a, 2, P, st);
   }
   const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
-  hipLaunchKernelGGL((k_adj_consfold<T, NV>), fgrid, dim3(256), 0, st, qs, P, r, a,
+  hipLaunchKernelGGL((k_adj_consfold<T, NV, MIX>), fgrid, dim3(256), 0, st, qs, P, r, a,
                      static_cast<T*>(out), mode, alpha, beta, static_cast<const T*>(y), gam);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename T, bool HLLC>
+template <typename T, bool HLLC, bool MIX>
 int adj_rhs_t(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb, void* out,
               int mode, double alpha, double beta, const void* y, double gam, hipStream_t st) {
   int r = -1;
   switch (a.nvar) {
 #define SNAP_ADJ_CASE(NVV)                                                      \
   case NVV:                                                                     \
-    r = adj_rhs_nv<T, NVV, HLLC>(w, a, q, rb, out, mode, alpha, beta, y, gam, st); \
+    r = adj_rhs_nv<T, NVV, HLLC, MIX>(w, a, q, rb, out, mode, alpha, beta, y, gam, st); \
     break;
-    SNAP_ADJ_CASE(5)
+    case 5:   // the mixture needs tracers
+      if constexpr (!MIX) r = adj_rhs_nv<T, 5, HLLC, false>(w, a, q, rb, out, mode, alpha, beta, y, gam, st);
+      break;
     SNAP_ADJ_CASE(6)
     SNAP_ADJ_CASE(7)
     SNAP_ADJ_CASE(8)

@@ -37,6 +37,8 @@ struct AdjArgs {
   int bc[3];
   int pert;   // perturbation storage (rho - rhobar_k, E - pbar_k / (gamma - 1))
   int hllc;   // the HLLC flux (else LMARS)
+  int mixture;   // the mixture equation of state (App. B)
+  Mixture mix;   // its coefficients
   const double* rbar_c;
   const double* pbar_c;
   const double* rbar_f;
@@ -575,13 +577,170 @@ __device__ __forceinline__ void hllc_flux_adj(const T (&xl)[NV], const T (&xr)[N
   xrb[4] += prb;
 }
 
-// Reverse of the kernel's Riemann flux.
-template <typename T, int NV, bool HLLC>
+// ---------------------------------------------------------------------------
+// Reverse of lmars_flux_mix (the mixture equation of state): as
+// lmars_flux_adj, plus the sums n = 1 + sum a_t q_t, d = 1 + sum b_t q_t and
+// m = sum mu_t q_t of each side's face mass fractions, which enter its sound
+// speed c = sqrt((d + gm1 n) p / (d rho)) and the upwind side's energy
+// E = p d / (gm1 n) + rho (|u|^2 / 2 + m). At u* == 0 the derivative with
+// respect to u* uses the mean of both sides' advected vectors.
+// ---------------------------------------------------------------------------
+template <typename T, int NV>
+__device__ __forceinline__ void lmars_flux_mix_adj(const T (&xl)[NV], const T (&xr)[NV], int nrm,
+                                                   T rref, T pref, T gm1, const Mixture& mx,
+                                                   const T (&fb)[NV], T (&xlb)[NV],
+                                                   T (&xrb)[NV]) {
+  constexpr int NT = NV - 5;
+  const T rl = rref + xl[0], rr = rref + xr[0];
+  const T pl = pref + xl[4], pr = pref + xr[4];
+  const T unl = nrm == 1 ? xl[1] : (nrm == 2 ? xl[2] : xl[3]);
+  const T unr = nrm == 1 ? xr[1] : (nrm == 2 ? xr[2] : xr[3]);
+  T nl = T(1), dl = T(1), ml = T(0), nr = T(1), dr = T(1), mr = T(0);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    T at, bt, mt;
+    mixture_coef<T, NT>(mx, t, at, bt, mt);
+    nl += at * xl[5 + t];
+    dl += bt * xl[5 + t];
+    ml += mt * xl[5 + t];
+    nr += at * xr[5 + t];
+    dr += bt * xr[5 + t];
+    mr += mt * xr[5 + t];
+  }
+  const T gnl = gm1 * nl, gnr = gm1 * nr;
+  const T cl = sound_speed((dl + gnl) * pl, dl * rl);
+  const T cr = sound_speed((dr + gnr) * pr, dr * rr);
+  const T rc = T(0.25) * ((rl + rr) * (cl + cr));
+  const T hh = T(0.5) * rcp_fast(rc);
+  const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) * hh;
+  // advected vectors (rho, rho u, rho v, rho w, E + p, rho q) of both sides
+  auto adv = [&](const T (&x)[NV], T r, T p, T d, T gn, T m, T (&phi)[NV]) {
+    const T k = T(0.5) * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+    phi[0] = r;
+    phi[1] = r * x[1];
+    phi[2] = r * x[2];
+    phi[3] = r * x[3];
+    phi[4] = p * d * rcp_fast(gn) + r * (k + m) + p;
+#pragma unroll
+    for (int t = 5; t < NV; ++t) phi[t] = r * x[t];
+  };
+  T phl[NV], phr[NV];
+  adv(xl, rl, pl, dl, gnl, ml, phl);
+  adv(xr, rr, pr, dr, gnr, mr, phr);
+  const T wl = ustar > T(0) ? T(1) : (ustar < T(0) ? T(0) : T(0.5));
+  T usb = T(0);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) usb += fb[v] * (wl * phl[v] + (T(1) - wl) * phr[v]);
+  const T psb = fb[nrm];
+  // cotangents of each side's rho, p, n, d, m (the velocities and fractions go
+  // straight into xlb / xrb)
+  T rlb = T(0), rrb = T(0), plb = T(0), prb = T(0);
+  T nlb = T(0), nrb = T(0), dlb = T(0), drb = T(0), mlb = T(0), mrb = T(0);
+  {
+    const bool left = ustar > T(0);
+    const T r = left ? rl : rr, p = left ? pl : pr, d = left ? dl : dr;
+    const T gn = left ? gnl : gnr, m = left ? ml : mr;
+    T x[NV], phb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      x[v] = left ? xl[v] : xr[v];
+      phb[v] = ustar * fb[v];
+    }
+    const T k = T(0.5) * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+    const T ign = rcp_fast(gn);
+    // phi4 = p d / gn + r (k + m) + p
+    T rb_ = phb[0] + phb[1] * x[1] + phb[2] * x[2] + phb[3] * x[3] + phb[4] * (k + m);
+    const T pb_ = phb[4] * (d * ign + T(1));
+    const T db_ = phb[4] * p * ign;
+    const T gnb = -phb[4] * p * d * ign * ign;
+    const T mb_ = phb[4] * r;
+    T sb[NV];
+#pragma unroll
+    for (int t = 5; t < NV; ++t) {
+      rb_ += phb[t] * x[t];
+      sb[t] = phb[t] * r;
+    }
+    sb[0] = T(0);
+    sb[4] = T(0);
+    sb[1] = phb[1] * r + phb[4] * r * x[1];
+    sb[2] = phb[2] * r + phb[4] * r * x[2];
+    sb[3] = phb[3] * r + phb[4] * r * x[3];
+#pragma unroll
+    for (int v = 1; v < NV; ++v) {
+      if (v == 4) continue;
+      xlb[v] += left ? sb[v] : T(0);
+      xrb[v] += left ? T(0) : sb[v];
+    }
+    rlb += left ? rb_ : T(0);
+    rrb += left ? T(0) : rb_;
+    plb += left ? pb_ : T(0);
+    prb += left ? T(0) : pb_;
+    dlb += left ? db_ : T(0);
+    drb += left ? T(0) : db_;
+    nlb += left ? gm1 * gnb : T(0);
+    nrb += left ? T(0) : gm1 * gnb;
+    mlb += left ? mb_ : T(0);
+    mrb += left ? T(0) : mb_;
+  }
+  // u* = (unl + unr) / 2 - (p'_R - p'_L) hh, hh = 1 / (2 rc)
+  T rcb = usb * (xr[4] - xl[4]) * (T(2) * hh * hh);
+  xlb[nrm] += T(0.5) * usb;
+  xrb[nrm] += T(0.5) * usb;
+  xrb[4] -= usb * hh;
+  xlb[4] += usb * hh;
+  // p* = (p'_L + p'_R) / 2 - rc (unr - unl) / 2
+  xlb[4] += T(0.5) * psb;
+  xrb[4] += T(0.5) * psb;
+  rcb -= T(0.5) * (unr - unl) * psb;
+  xrb[nrm] -= T(0.5) * rc * psb;
+  xlb[nrm] += T(0.5) * rc * psb;
+  // rc = (rl + rr)(cl + cr) / 4
+  rlb += T(0.25) * rcb * (cl + cr);
+  rrb += T(0.25) * rcb * (cl + cr);
+  const T clb = T(0.25) * rcb * (rl + rr), crb = T(0.25) * rcb * (rl + rr);
+  // c = sqrt(G / R), G = (d + gm1 n) p, R = d rho: dc/dG = c / (2 G), dc/dR = -c / (2 R)
+  {
+    const T G = (dl + gnl) * pl, R = dl * rl;
+    const T Gb = clb * cl * T(0.5) * rcp_fast(G), Rb = -clb * cl * T(0.5) * rcp_fast(R);
+    dlb += Gb * pl + Rb * rl;
+    nlb += Gb * pl * gm1;
+    plb += Gb * (dl + gnl);
+    rlb += Rb * dl;
+  }
+  {
+    const T G = (dr + gnr) * pr, R = dr * rr;
+    const T Gb = crb * cr * T(0.5) * rcp_fast(G), Rb = -crb * cr * T(0.5) * rcp_fast(R);
+    drb += Gb * pr + Rb * rr;
+    nrb += Gb * pr * gm1;
+    prb += Gb * (dr + gnr);
+    rrb += Rb * dr;
+  }
+  // n, d, m are linear in the fractions
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    T at, bt, mt;
+    mixture_coef<T, NT>(mx, t, at, bt, mt);
+    xlb[5 + t] += at * nlb + bt * dlb + mt * mlb;
+    xrb[5 + t] += at * nrb + bt * drb + mt * mrb;
+  }
+  xlb[0] += rlb;
+  xrb[0] += rrb;
+  xlb[4] += plb;
+  xrb[4] += prb;
+}
+
+// Reverse of the kernel's Riemann flux (LMARS, HLLC, or LMARS under the
+// mixture equation of state).
+template <typename T, int NV, bool HLLC, bool MIX>
 __device__ __forceinline__ void riemann_flux_adj(const T (&xl)[NV], const T (&xr)[NV], int nrm,
-                                                 T rref, T pref, T gamma, T inv_gm1,
-                                                 const T (&fb)[NV], T (&xlb)[NV], T (&xrb)[NV]) {
+                                                 T rref, T pref, T gamma, T inv_gm1, T gm1,
+                                                 const Mixture& mx, const T (&fb)[NV],
+                                                 T (&xlb)[NV], T (&xrb)[NV]) {
+  static_assert(!(HLLC && MIX), "HLLC takes passive tracers");
   if constexpr (HLLC)
     hllc_flux_adj<T, NV>(xl, xr, nrm, rref, pref, gamma, inv_gm1, fb, xlb, xrb);
+  else if constexpr (MIX)
+    lmars_flux_mix_adj<T, NV>(xl, xr, nrm, rref, pref, gm1, mx, fb, xlb, xrb);
   else
     lmars_flux_adj<T, NV>(xl, xr, nrm, rref, pref, gamma, inv_gm1, fb, xlb, xrb);
 }
@@ -712,7 +871,7 @@ __device__ __forceinline__ void line_cell(const AdjArgs& a, const LineGeom& g, l
 #define SNAP_ADJ_LINE_ATTR
 #endif
 
-template <typename T, int NV, int LN, int TL, bool XDIR, bool HLLC = false>
+template <typename T, int NV, int LN, int TL, bool XDIR, bool HLLC = false, bool MIX = false>
 __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE_ATTR
     k_adj_line(const T* __restrict__ q, const T* __restrict__ rb, AdjArgs a, int d,
                T* __restrict__ P) {
@@ -772,8 +931,8 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
       const long long pc = S.pbase[l] + jg * g.sd;
       const int kl = d == 2 ? jg : S.lev[l];   // level of the cell
       T x[NV];
-      load_prim<T, NV>(q, pc, a.sv, level_ref(a.pert, a.rbar_c[kl + NG], a.pbar_c[kl + NG]),
-                       a.gm1, x);
+      load_prim<T, NV, MIX>(q, pc, a.sv, level_ref(a.pert, a.rbar_c[kl + NG], a.pbar_c[kl + NG]),
+                            a.gm1, a.mix, x);
 #pragma unroll
       for (int v = 0; v < NV; ++v) S.WL[v][l][m] = x[v];
     }
@@ -834,7 +993,8 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
         rref = static_cast<T>(a.rbar_c[S.lev[l] + NG]);
         pref = static_cast<T>(a.pbar_c[S.lev[l] + NG]);
       }
-      riemann_flux_adj<T, NV, HLLC>(xl, xr, d + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
+      riemann_flux_adj<T, NV, HLLC, MIX>(xl, xr, d + 1, rref, pref, gamma, inv_gm1,
+                                         static_cast<T>(a.gm1), a.mix, fbar, xlb, xrb);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1038,7 +1198,8 @@ __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
       for (int v = 0; v < NV; ++v) fbar[v] = (rbc[v] - rbp[v]) * hi_d;
       const T rref = D == 2 ? static_cast<T>(a.rbar_f[j]) : rref_c;
       const T pref = D == 2 ? static_cast<T>(a.pbar_f[j]) : pref_c;
-      riemann_flux_adj<T, NV, HLLC>(qmp, qp, D + 1, rref, pref, gamma, inv_gm1, fbar, xlb, xrb);
+      riemann_flux_adj<T, NV, HLLC, false>(qmp, qp, D + 1, rref, pref, gamma, inv_gm1,
+                                           static_cast<T>(a.gm1), a.mix, fbar, xlb, xrb);
     }
     // (3) reverse of cell j-1 (stencil cells j-3 .. j+1)
     if (j - 1 >= rA && j - 1 <= rB) {
@@ -1085,7 +1246,14 @@ __device__ __forceinline__ int adj_ghost_src(int idx, int n, int bc) {
 // coordinates; ghost cells lie outside the domain along one axis at most),
 // in double precision: gravity terms (interior cells only) and the reverse of
 // the conserved -> primitive map applied to the primitive cotangent P.
-template <typename T, int NV>
+// Passive gas: p = (gamma - 1)(E - K). Mixture (MIX, App. B):
+// p = (gamma - 1)(n / d)((E - K) - A) with n = 1 + sum a_t q_t,
+// d = 1 + sum b_t q_t, A = sum mu_t rho_t and q_t = rho_t / rho; with
+// Qb = (gamma - 1)(n / d) pb_p the cotangents of E, of the momenta through K
+// and of the tracer densities through A are Qb, -Qb u_i and -Qb mu_t, and
+// n / d adds ((gamma - 1) Q pb_p)(a_t / d - b_t n / d^2) to each fraction's
+// cotangent, Q = (E - K) - A. The passive form is the case n = d = 1, A = 0.
+template <typename T, int NV, bool MIX>
 __device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* __restrict__ P,
                                               const T* __restrict__ rb, const AdjArgs& a, int i,
                                               int j, int k, double (&out)[NV]) {
@@ -1106,20 +1274,43 @@ __device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* 
   // rho of the cell (perturbation storage: the stored value plus rhobar of its level)
   const double inv = 1.0 / (cv[0] + (a.pert ? a.rbar_c[k + NG] : 0.0));
   const double u = cv[1] * inv, v = cv[2] * inv, w = cv[3] * inv;
-  // p = (gamma - 1)(E - (m.m)/(2 rho)):  dp/drho = (gamma-1) |u|^2 / 2, dp/dm = -(gamma-1) u
+  double Qb = a.gm1 * pb[4];   // cotangent of (E - K) - A
+  double fb[NV];               // extra cotangents of the fractions (mixture)
+#pragma unroll
+  for (int t = 5; t < NV; ++t) fb[t] = 0.0;
+  if constexpr (MIX) {
+    constexpr int NT = NV - 5;
+    double num = 1.0, den = 1.0, A = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double qt = cv[5 + t] * inv;
+      num += a.mix.a[t] * qt;
+      den += a.mix.b[t] * qt;
+      A += a.mix.mu[t] * cv[5 + t];
+    }
+    const double K = 0.5 * (cv[1] * u + cv[2] * v + cv[3] * w);
+    const double R = num / den, Q = (cv[4] - K) - A;
+    const double Rb = a.gm1 * Q * pb[4];
+    Qb = a.gm1 * R * pb[4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) fb[5 + t] = Rb * (a.mix.a[t] - a.mix.b[t] * R) / den;
+  }
+  // p from E - K: dp/drho = Qb |u|^2 / 2, dp/dm = -Qb u
   double rhob = pb[0] - (u * pb[1] + v * pb[2] + w * pb[3]) * inv +
-                a.gm1 * 0.5 * (u * u + v * v + w * w) * pb[4];
+                Qb * 0.5 * (u * u + v * v + w * w);
 #pragma unroll
   for (int t = 5; t < NV; ++t) {
     const double qt = cv[t] * inv;
-    rhob -= qt * pb[t] * inv;
-    out[t] = pb[t] * inv;
+    const double tb = pb[t] + fb[t];
+    rhob -= qt * tb * inv;
+    out[t] = tb * inv;
+    if constexpr (MIX) out[t] -= Qb * a.mix.mu[t - 5];
   }
   out[0] = rhob;
-  out[1] = pb[1] * inv - a.gm1 * u * pb[4];
-  out[2] = pb[2] * inv - a.gm1 * v * pb[4];
-  out[3] = pb[3] * inv - a.gm1 * w * pb[4] + qe;
-  out[4] = a.gm1 * pb[4];
+  out[1] = pb[1] * inv - Qb * u;
+  out[2] = pb[2] * inv - Qb * v;
+  out[3] = pb[3] * inv - Qb * w + qe;
+  out[4] = Qb;
 }
 
 // Per interior cell: its conserved cotangent plus those of the ghost cells
@@ -1130,7 +1321,7 @@ __device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* 
 // out = alpha * rb + beta * result (mode 3; out and rb distinct), or
 // out = alpha * out + gam * y + rb + beta * result (mode 4: the last stage of
 // the RK3 adjoint with its three-term combination; out, y, rb distinct).
-template <typename T, int NV>
+template <typename T, int NV, bool MIX = false>
 __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
                                                       const T* __restrict__ P,
                                                       const T* __restrict__ rb, AdjArgs a,
@@ -1144,7 +1335,7 @@ __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
   const int j = row % a.ny, k = row / a.ny;
   const long long c = (long long)row * a.nx + i;
   double acc[NV];
-  adj_cons_cell<T, NV>(q, P, rb, a, i, j, k, acc);
+  adj_cons_cell<T, NV, MIX>(q, P, rb, a, i, j, k, acc);
   for (int d = 0; d < 3; ++d) {
     if (d == 1 && !a.d3) continue;
     const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
@@ -1156,7 +1347,7 @@ __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
       int gc[3] = {i, j, k};
       gc[d] = gidx;
       double x[NV];
-      adj_cons_cell<T, NV>(q, P, rb, a, gc[0], gc[1], gc[2], x);
+      adj_cons_cell<T, NV, MIX>(q, P, rb, a, gc[0], gc[1], gc[2], x);
       const bool flip = a.bc[d] == 1;
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += (flip && v == 1 + d) ? -x[v] : x[v];
