@@ -31,8 +31,9 @@
  * time-stepping and microphysics calls.
  *
  * Calls are asynchronous on `stream` (a hipStream_t, NULL = default stream),
- * except snap_cfl_dt and snap_conservation_sums, which return host values and
- * synchronise that stream. Validation of every argument happens on the host
+ * except snap_cfl_dt, snap_conservation_sums(_noalloc) and
+ * snap_rk3_steps_status, which return host values and synchronise that
+ * stream. Validation of every argument happens on the host
  * before any HIP call: an invalid call returns SNAP_E_INVALID and touches no
  * device state. A failed HIP call returns SNAP_E_DEVICE. The message of the
  * last error of the calling thread is returned by snap_last_error().

@@ -4,9 +4,10 @@ within 1e-12 per field (FP64) and 1e-4 (FP32 form), three RK3 steps within
 the multi-step bar, and determinism.
 
 In the star region HLLC's fluxes are F + S (U* - U), differences of terms of
-size S U; for a state at rest (the bubble) the mass and energy right-hand
-sides are pure rounding of those terms, so the FP64 bar carries an absolute
-floor at that rounding: 1e-15 c_max max|U_m| / min(dx, dy, dz)."""
+size S U; for the state at rest (the bubble) the mass and energy right-hand
+sides are pure rounding of those terms, so for that case alone the FP64 bar
+carries an absolute floor at that rounding: 1e-15 c_max max|U_m| /
+min(dx, dy, dz). Every case in motion is held to the relative bar alone."""
 import numpy as np
 import pytest
 import torch
@@ -46,9 +47,13 @@ def test_rhs_fp64_hllc(hcases, name):
     qi = c.grid.interior(c.q)
     cmax = float(np.max(np.sqrt(c.grid.gamma * 0.4 * qi[4] / qi[0]))) * 2.0   # generous c bound
     dmin = min(c.grid.dx, c.grid.dz, c.grid.dy if c.grid.ny > 1 else c.grid.dx)
+    # the rounding floor is for the state at rest only (the bubble, whose mass
+    # and energy right-hand sides are pure rounding of the star-region terms);
+    # every case in motion is held to the relative bar alone
+    at_rest = name == "2d_bubble_64x64"
     bad = []
     for m in range(c.grid.nvar):
-        floor = 1e-15 * cmax * float(np.max(np.abs(qi[m]))) / dmin
+        floor = 1e-15 * cmax * float(np.max(np.abs(qi[m]))) / dmin if at_rest else 0.0
         err = float(np.max(np.abs(got[m] - ref[m])))
         bar = TOL64 * float(np.max(np.abs(ref[m]))) + floor
         print(f"   field {m}: error {err:.2e}  bar {bar:.2e}", flush=True)
