@@ -34,6 +34,16 @@ inline bool march_enabled() {
   return !(e && e[0] == '0');
 }
 
+// The z march folds the cells at least 3 from the y and z edges, after
+// k_adj_xmerge has added the x copies' cotangents into the cells within 3 of
+// an x edge (the separate fold pass then covers the rows of the 3 lowest and 3
+// highest levels and those within 3 of a y edge); SNAP_ADJ_MARCH_FOLD=0
+// leaves every cell to the fold pass.
+inline bool march_fold_enabled() {
+  const char* e = getenv("SNAP_ADJ_MARCH_FOLD");
+  return !(e && e[0] == '0');
+}
+
 // Segment length of the march: at most 43 cells, so that the 256 x 256 x 128
 // grid gives 3 x 65536 z segments and 6 x 32768 y segments (three waves per
 // SIMD of the 256 compute units, the kernel's occupancy with 5 variables),
@@ -49,12 +59,13 @@ inline int march_seglen(int nd) {
 }
 
 template <typename T, int NV, int D, bool HLLC>
-void adj_march_launch(const T* q, const T* r, const AdjArgs& a, T* P, hipStream_t st) {
+void adj_march_launch(const T* q, const T* r, const AdjArgs& a, T* P, const MarchFold<T>& fo,
+                      hipStream_t st) {
   const int nd = D == 2 ? a.nz : a.ny;
   const long long lines = (long long)a.nx * (D == 2 ? a.ny : a.nz);
   const int seg = march_seglen(nd);
   const dim3 grid((unsigned)((lines + 255) / 256), (unsigned)((nd + seg - 1) / seg));
-  hipLaunchKernelGGL((k_adj_march<T, NV, D, HLLC>), grid, dim3(256), 0, st, q, r, a, seg, P);
+  hipLaunchKernelGGL((k_adj_march<T, NV, D, HLLC>), grid, dim3(256), 0, st, q, r, a, seg, P, fo);
 }
 
 template <typename T, int NV, bool HLLC, bool MIX>
@@ -68,18 +79,32 @@ int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb
   const bool planes_small = a.sv * (long long)sizeof(T) < (1LL << 31) &&
                             a.rv * (long long)sizeof(T) < (1LL << 31);
   // (the mixture takes the tiled kernel in every direction)
+  bool zfold = false;   // the z march folds the cells at least 3 from the y and z edges
   if (march_fits<T, NV>() && !MIX && march_enabled() && planes_small) {
     if constexpr (march_fits<T, NV>() && !MIX) {
-      if (a.d3) adj_march_launch<T, NV, 1, HLLC>(qs, r, a, P, st);
-      adj_march_launch<T, NV, 2, HLLC>(qs, r, a, P, st);
+      zfold = march_fold_enabled() && a.nz > 6;
+      MarchFold<T> none{nullptr, nullptr, 0, T(0), T(0), T(0)};
+      MarchFold<T> fo{static_cast<T*>(out), static_cast<const T*>(y), mode,
+                      static_cast<T>(alpha), static_cast<T>(beta), static_cast<T>(gam)};
+      if (zfold) {
+        const long long n = (long long)(a.nx > 6 ? 6 : a.nx) * a.ny * a.nz;
+        hipLaunchKernelGGL((k_adj_xmerge<T, NV>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           st, P, a);
+      }
+      if (a.d3) adj_march_launch<T, NV, 1, HLLC>(qs, r, a, P, none, st);
+      adj_march_launch<T, NV, 2, HLLC>(qs, r, a, P, zfold ? fo : none, st);
     }
   } else {
     if (a.d3) adj_line_launch<T, NV, false, HLLC, MIX>(qs, r, a, 1, P, st);
     adj_line_launch<T, NV, false, HLLC, MIX>(qs, r, a, 2, P, st);
   }
-  const dim3 fgrid(a.ny * a.nz, (a.nx + 255) / 256);
+  // every row, or after a folding z march the rows it left
+  const int ye = !a.d3 ? 0 : (a.ny > 6 ? 6 : a.ny);
+  const int rows = zfold ? 6 * a.ny + (a.nz - 6) * ye : a.ny * a.nz;
+  const dim3 fgrid(rows, (a.nx + 255) / 256);
   hipLaunchKernelGGL((k_adj_consfold<T, NV, MIX>), fgrid, dim3(256), 0, st, qs, P, r, a,
-                     static_cast<T*>(out), mode, alpha, beta, static_cast<const T*>(y), gam);
+                     static_cast<T*>(out), mode, alpha, beta, static_cast<const T*>(y), gam,
+                     zfold ? 1 : 0);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

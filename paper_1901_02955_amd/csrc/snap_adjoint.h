@@ -14,12 +14,18 @@
 //                    fixed-order gather of those contributions into the
 //                    primitive cotangent;
 //   k_adj_march<d>   the same for the y and z directions in single precision,
-//                    one thread per line segment marching along it;
-//   k_adj_consfold   per interior cell: gravity terms and the reverse of the
-//                    conserved -> primitive map (double precision) for the
-//                    cell and for each ghost cell that copies it, summed
-//                    (sign flipped on the reflected normal momentum), and
-//                    combined with the stage's other cotangent terms.
+//                    one thread per line segment marching along it; the z
+//                    march also folds (below) the cells at least 3 from the
+//                    y and z edges, in single precision;
+//   k_adj_xmerge     before a folding z march: the x ghost cells' primitive
+//                    cotangents added into the cells they copy;
+//   k_adj_consfold   per interior cell (after a folding z march: the rest):
+//                    gravity terms and the
+//                    reverse of the conserved -> primitive map (double
+//                    precision) for the cell and for each ghost cell that
+//                    copies it, summed (sign flipped on the reflected normal
+//                    momentum), and combined with the stage's other
+//                    cotangent terms.
 #pragma once
 
 #include "snap_device.h"
@@ -1058,6 +1064,119 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
   }
 }
 
+__device__ __forceinline__ int adj_ghost_src(int idx, int n, int bc) {
+  if (idx >= 0 && idx < n) return idx;
+  if (bc == 0) return ((idx % n) + n) % n;
+  if (idx < 0) return min(-1 - idx, n - 1);
+  return max(2 * n - 1 - idx, 0);
+}
+
+// Before a folding z march (single precision, after the x direction): each
+// interior cell within 3 of an x edge takes the primitive cotangents of the
+// ghost cells that copy it in x into its own (fixed order: low then high
+// ghost positions). A periodic copy holds the cell's state and a mirror copy
+// the state with the normal momentum negated, i.e. the primitives with the
+// normal velocity negated, so by the chain rule the copy's cotangent (its x
+// velocity component negated for a mirror) adds to the cell's primitive
+// cotangent before the reverse of the conserved -> primitive map; the fold
+// then skips the copies in x. P of the ghost cells is final once the x
+// direction has run: the y and z directions write no cell outside the
+// interior in x. Grid: one thread per edge cell (min(nx, 6) per row), rows
+// over the interior.
+template <typename T, int NV>
+__global__ void __launch_bounds__(256) k_adj_xmerge(T* __restrict__ P, AdjArgs a) {
+  const int ne = a.nx > 6 ? 6 : a.nx;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)ne * a.ny * a.nz) return;
+  const int e = (int)(t % ne), row = (int)(t / ne);
+  const int i = a.nx > 6 && e >= 3 ? a.nx - 6 + e : e;
+  const int j = row % a.ny, k = row / a.ny;
+  const long long c = padded_off(a, i, j, k);
+  T pv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) pv[v] = P[c + v * a.sv];
+  const bool flip = a.bc[0] == 1;
+  for (int m = 0; m < 6; ++m) {
+    const int gidx = m < 3 ? -1 - m : a.nx + (m - 3);
+    if (adj_ghost_src(gidx, a.nx, a.bc[0]) != i) continue;
+    const long long g = c + (gidx - i);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T x = P[g + v * a.sv];
+      pv[v] += (flip && v == 1) ? -x : x;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) P[c + v * a.sv] = pv[v];
+}
+
+// Where the z march stores the conserved cotangent of the cells it folds:
+// out (interior layout) overwritten (mode 0), added to (mode 1),
+// out = alpha * out + beta * result (mode 2), out = alpha * rb + beta * result
+// (mode 3), out = alpha * out + gam * y + rb + beta * result (mode 4); out ==
+// nullptr: no fold (the march writes P for every cell).
+template <typename T>
+struct MarchFold {
+  T* out;
+  const T* y;
+  int mode;
+  T alpha, beta, gam;
+};
+
+// Fold of one interior cell at least 3 cells from the y and z edges (level
+// k), in the precision of the march, from its complete primitive cotangent own
+// (in registers; for a cell within 3 of an x edge k_adj_xmerge has added the
+// cotangents of its copies in x) and its primitives x (the march's window):
+// gravity and the reverse of the conserved -> primitive map as adj_cons_cell
+// does for the passive gas, and the store by the fold's mode. bo, ro: byte
+// offsets of the cell in a padded and in an interior plane.
+template <typename T, int NV>
+__device__ __forceinline__ void fold_march_cell(const T* __restrict__ q,
+                                                const T* __restrict__ rb, const AdjArgs& a,
+                                                const MarchFold<T>& fo, const T (&x)[NV],
+                                                const T (&own)[NV], unsigned bo, unsigned ro,
+                                                int k) {
+  auto at = [](const T* base, unsigned boff) -> const T& {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+  };
+  T pv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) pv[v] = own[v];
+  const T inv = rcp_fast(at(q, bo) + static_cast<T>(a.pert ? a.rbar_c[k + NG] : 0.0));
+  const T u = x[1], v = x[2], w = x[3];
+  const T grav = static_cast<T>(a.grav);
+  pv[0] -= grav * at(rb + 3 * a.rv, ro);          // R_rhow -= g rho'
+  const T qe = -grav * at(rb + 4 * a.rv, ro);     // R_E -= g rho w
+  const T Qb = static_cast<T>(a.gm1) * pv[4];
+  T o[NV];
+  T rhob = pv[0] - (u * pv[1] + v * pv[2] + w * pv[3]) * inv + Qb * T(0.5) * (u * u + v * v + w * w);
+#pragma unroll
+  for (int t = 5; t < NV; ++t) {
+    rhob -= x[t] * pv[t] * inv;
+    o[t] = pv[t] * inv;
+  }
+  o[0] = rhob;
+  o[1] = pv[1] * inv - Qb * u;
+  o[2] = pv[2] * inv - Qb * v;
+  o[3] = pv[3] * inv - Qb * w + qe;
+  o[4] = Qb;
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    T* op = reinterpret_cast<T*>(reinterpret_cast<char*>(fo.out + m * a.rv) + ro);
+    if (fo.mode == 0)
+      *op = o[m];
+    else if (fo.mode == 1)
+      *op = *op + o[m];
+    else if (fo.mode == 2)
+      *op = fo.alpha * *op + fo.beta * o[m];
+    else if (fo.mode == 3)
+      *op = fo.alpha * at(rb + m * a.rv, ro) + fo.beta * o[m];
+    else
+      *op = fo.alpha * *op + fo.gam * at(fo.y + m * a.rv, ro) + at(rb + m * a.rv, ro) +
+            fo.beta * o[m];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Adjoint of one direction D (1 = y, 2 = z) by a march along the lines: one
 // thread per segment [c0, c1) of a line, the threads of a wave on consecutive
@@ -1080,13 +1199,15 @@ __global__ void __launch_bounds__((LineTile<T, NV, LN, TL>::NTHR)) SNAP_ADJ_LINE
 // each side; the ghost cells beyond a domain edge belong to the first or the
 // last segment of the line.
 // Grid: x over blocks of 256 lines (x fastest), y over segments of seglen.
-// Held to three waves per SIMD (168 registers): the y instance with 5
-// variables would otherwise take 169.
+// With 5 variables held to three waves per SIMD (168 registers: the y
+// instance would otherwise take 169); with 6 or 7 to two, whose window does
+// not fit 168 registers without spills.
 // ---------------------------------------------------------------------------
 template <typename T, int NV, int D, bool HLLC = false>
-__global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
+__global__ void __launch_bounds__(256, NV <= 5 ? 3 : 2) k_adj_march(const T* __restrict__ q,
                                                    const T* __restrict__ rb, AdjArgs a,
-                                                   int seglen, T* __restrict__ P) {
+                                                   int seglen, T* __restrict__ P,
+                                                   MarchFold<T> fo) {
   static_assert(D == 1 || D == 2, "march directions: y and z");
   const int n1 = D == 2 ? a.ny : a.nz;   // second transverse extent
   const int nd = D == 2 ? a.nz : a.ny;   // cells along the line
@@ -1212,14 +1333,26 @@ __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
         for (int o = 0; o < 5; ++o) acc[o][v] += g[o];
       }
     }
-    // (4) cell j-3 is complete
+    // (4) cell j-3 is complete: folded (z march, cells at least 3 from the
+    // y and z edges) or written into P
     {
       const int cf = j - 3;
       if (cf >= lo && cf < hi) {
         const unsigned bo = (unsigned)(pb * (long long)sizeof(T)) + (unsigned)cf * bsd;
+        bool folded = false;
+        if constexpr (D == 2) {
+          if (fo.out != nullptr && cf >= 3 && cf < nd - 3 &&
+              (!a.d3 || (o1 >= 3 && o1 < a.ny - 3))) {
+            fold_march_cell<T, NV>(q, rb, a, fo, win[0], acc[0], bo,
+                                   (unsigned)(rbo * (long long)sizeof(T)) + (unsigned)cf * brd, cf);
+            folded = true;
+          }
+        }
+        if (!folded) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          *reinterpret_cast<T*>(reinterpret_cast<char*>(P + v * a.sv) + bo) = acc[0][v];
+          for (int v = 0; v < NV; ++v)
+            *reinterpret_cast<T*>(reinterpret_cast<char*>(P + v * a.sv) + bo) = acc[0][v];
+        }
       }
     }
 #pragma unroll
@@ -1233,13 +1366,6 @@ __global__ void __launch_bounds__(256, 3) k_adj_march(const T* __restrict__ q,
       rbp[v] = rbc[v];
     }
   }
-}
-
-__device__ __forceinline__ int adj_ghost_src(int idx, int n, int bc) {
-  if (idx >= 0 && idx < n) return idx;
-  if (bc == 0) return ((idx % n) + n) % n;
-  if (idx < 0) return min(-1 - idx, n - 1);
-  return max(2 * n - 1 - idx, 0);
 }
 
 // Conserved cotangent of one cell of the stencil region (interior
@@ -1327,16 +1453,34 @@ __global__ void __launch_bounds__(256) k_adj_consfold(const T* __restrict__ q,
                                                       const T* __restrict__ rb, AdjArgs a,
                                                       T* __restrict__ out, int mode,
                                                       double alpha, double beta,
-                                                      const T* __restrict__ y, double gam) {
-  // grid: x over interior rows, y over the interior row
+                                                      const T* __restrict__ y, double gam,
+                                                      int zedge) {
+  // grid: x over interior rows, y over the interior row. zedge (nz > 6, the
+  // z march having folded the rest, after k_adj_xmerge): only the rows of the
+  // 3 lowest and the 3 highest levels, then (3-D) the rows within 3 of a y
+  // edge on the levels between
   const int i = blockIdx.y * 256 + threadIdx.x;
   if (i >= a.nx) return;
   const int row = blockIdx.x;
-  const int j = row % a.ny, k = row / a.ny;
-  const long long c = (long long)row * a.nx + i;
+  int j, k;
+  if (!zedge) {
+    j = row % a.ny;
+    k = row / a.ny;
+  } else if (row < 6 * a.ny) {
+    const int e = row / a.ny;
+    j = row % a.ny;
+    k = e < 3 ? e : a.nz - 6 + e;
+  } else {
+    const int ye = a.ny > 6 ? 6 : a.ny;   // edge rows per level
+    const int r = row - 6 * a.ny, e = r % ye;
+    k = 3 + r / ye;
+    j = a.ny > 6 && e >= 3 ? a.ny - 6 + e : e;
+  }
+  const long long c = ((long long)k * a.ny + j) * a.nx + i;
   double acc[NV];
   adj_cons_cell<T, NV, MIX>(q, P, rb, a, i, j, k, acc);
-  for (int d = 0; d < 3; ++d) {
+  // (after k_adj_xmerge the copies in x are in P already)
+  for (int d = zedge ? 1 : 0; d < 3; ++d) {
     if (d == 1 && !a.d3) continue;
     const int nd = d == 0 ? a.nx : (d == 1 ? a.ny : a.nz);
     const int me = d == 0 ? i : (d == 1 ? j : k);

@@ -41,31 +41,46 @@ def long_case():
     return C.Case("3d_long_16x45x70_nt1", g, wl.random_smooth_state(g, 51), 0.1)
 
 
+def narrow_y_case():
+    """Five cells in y (every row within 3 of a y edge: the z march folds no
+    cell) and 14 levels."""
+    g, _ = wl.dry_grid(12, 5, 14, 2400.0, 1000.0, 2800.0, bc=(1, 0, 1))
+    return C.Case("3d_narrow_y_12x5x14", g, wl.random_smooth_state(g, 52), 0.1)
+
+
 def cases():
     for n in NAMES:
         yield C.build_case(n, dict(C.SPECS)[n])
     yield long_case()
+    yield narrow_y_case()
 
 
-def adjoint32(c, rbar, march=True, seg=None):
-    env = {"SNAP_ADJ_MARCH": "1" if march else "0"}
-    if seg is not None:
-        env["SNAP_ADJ_MARCH_SEG"] = str(seg)
-    old = {k: os.environ.get(k) for k in env}
-    os.environ.update(env)
-    try:
+class _env:
+    """Set the library's adjoint switches for the calls inside the block."""
+
+    def __init__(self, **kw):
+        self.env = {k: str(v) for k, v in kw.items() if v is not None}
+
+    def __enter__(self):
+        self.old = {k: os.environ.get(k) for k in self.env}
+        os.environ.update(self.env)
+
+    def __exit__(self, *exc):
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def adjoint32(c, rbar, march=True, seg=None, fold=True):
+    with _env(SNAP_ADJ_MARCH=int(march), SNAP_ADJ_MARCH_SEG=seg, SNAP_ADJ_MARCH_FOLD=int(fold)):
         dg = snap.device_grid(c.grid, dtype=torch.float32)
         qd = torch.as_tensor(c.q).float().cuda()
         rb = torch.as_tensor(rbar).float().cuda()
         qb = torch.empty_like(rb)
         snap.snap_rhs_adjoint(dg, qd, rb, qb, snap.workspace(dg, snap.SNAP_OP_RHS_ADJ))
         return qb.cpu().double().numpy()
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
 
 
 @pytest.mark.parametrize("c", list(cases()), ids=lambda c: c.name)
@@ -87,3 +102,47 @@ def test_rhs_adjoint_fp32(c):
     for seg in (7, 13):
         errs = field_errors(adjoint32(cr, rbar, seg=seg), march)
         assert all(e <= 1e-5 for e in errs), (seg, errs)
+    # the z march's own fold of the cells away from the y and z edges against
+    # the separate fold pass for every cell
+    errs = field_errors(march, adjoint32(cr, rbar, fold=False))
+    print("   march fold vs fold pass", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-5 for e in errs), errs
+
+
+def rk3_adjoint32(c, qbar, march=True, fold=True):
+    with _env(SNAP_ADJ_MARCH=int(march), SNAP_ADJ_MARCH_FOLD=int(fold)):
+        dg = snap.device_grid(c.grid, dtype=torch.float32)
+        qb = torch.as_tensor(qbar).float().cuda()
+        snap.snap_rk3_step_adjoint(dg, torch.as_tensor(c.q).float().cuda(), c.dt, qb,
+                                   snap.workspace(dg, snap.SNAP_OP_RK3_ADJ))
+        return qb.cpu().double().numpy()
+
+
+# The RK3 step adjoint folds its stages with the combinations of modes 3 and 4
+# (out = alpha r_bar + beta J^T r_bar; out = alpha out + gam y + r_bar +
+# beta J^T r_bar), which the z march then applies itself. Against the oracle
+# the bar is that of the single-precision adjoint in test_gpu_adjoint.py
+# (1e-3): the stage states are evaluated in single precision as well, and the
+# reverse linearises the WENO5 weights at them. The three single-precision
+# forms (the z march's fold, the separate fold pass, the tiled kernels) agree
+# within 1e-5.
+@pytest.mark.parametrize("c", [C.build_case(n, dict(C.SPECS)[n]) for n in
+                               ("2d_smooth_37x29_nt3", "3d_smooth_35x21x19", "3d_xwall_19x17x12",
+                                "3d_periodic_z_12x10x14", "3d_periodic_all_13x11x10")]
+                         + [long_case(), narrow_y_case()], ids=lambda c: c.name)
+def test_rk3_step_adjoint_fp32_fold(c):
+    print(f"[adjoint32] rk3 step {c.name}", flush=True)
+    q32 = c.q.astype(np.float32).astype(np.float64)
+    qbar = wl.seeded_normal(c.grid.interior_shape, 121).astype(np.float32).astype(np.float64)
+    cr = C.Case(c.name, c.grid, q32, c.dt)
+    folded = rk3_adjoint32(cr, qbar)
+    ref = oracle.rk3_step_adjoint(q32, c.grid, c.dt, qbar).numpy()
+    errs = field_errors(folded, ref)
+    print("   vs oracle", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-3 for e in errs), errs
+    for kw in (dict(fold=False), dict(march=False)):
+        other = rk3_adjoint32(cr, qbar, **kw)
+        print("  ", kw, "vs oracle", ["%.2e" % e for e in field_errors(other, ref)], flush=True)
+        errs = field_errors(folded, other)
+        print("  ", kw, "vs folded", ["%.2e" % e for e in errs], flush=True)
+        assert all(e <= 1e-5 for e in errs), (kw, errs)
