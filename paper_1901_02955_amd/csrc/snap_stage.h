@@ -262,10 +262,11 @@ __device__ __forceinline__ void write_cell(const StageArgs& a, const T* __restri
 // LDS plane shared by both kernels: primitives with a 3-cell halo and, per
 // in-plane axis, one value per face (first the left face state, then, after
 // the LMARS phase, the flux). The right face state of each face stays in the
-// registers of the thread that reconstructed it; reconstruction items of the
-// last round (beyond RREG rounds) park it in QS instead.
+// registers of the thread that reconstructed it; the items beyond the RREG
+// rounds, reconstructed one (cell, variable) pair at a time, park it in QS.
 //
-// Work items of the reconstruction and LMARS phases (same list, same thread):
+// Work items of the reconstruction and LMARS phases (one list; within the
+// RREG rounds the same thread takes an item in both):
 //   x items: cells ii = -1 .. TX along each row jj = 0 .. TY-1;
 //   second-axis items: cells jj = -1 .. TY along each column ii = 0 .. TX-1.
 // Item (cell c) writes the left state of face c+1 and keeps the right state
@@ -323,7 +324,8 @@ __device__ __forceinline__ bool plane_item(int it, int w, int h, bool& xaxis, in
   return ii < w && jj <= h;
 }
 
-// Phase R: WENO5 of every item cell; left states to LDS, right states kept.
+// Phase R: WENO5 of every item cell; left states to LDS, right states kept
+// (in registers for the RREG rounds, in QS for the items beyond them).
 // An x item reads a row of the plane (stride 1), a second-axis item a column
 // (stride TX + 6), so one code path serves both. With RPF the five stencil
 // values of variable v + 1 are read from LDS before variable v is
@@ -344,8 +346,41 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
   constexpr bool RPF = reconstruct_prefetch<T, NV>();
   constexpr int PV = (TY + 6) * (TX + 6);   // plane stride between variables
   constexpr int FXV = TY * (TX + 1), FYV = (TY + 1) * TX;
+  // The items beyond the RREG rounds (64 of the 576 of a 16 x 16 tile) are
+  // split by variable, one (cell, variable) pair per thread and pass, so that
+  // every wave takes a share instead of one wave reconstructing all their
+  // variables while the others wait at the barrier.
+  constexpr int NSP = I::NR - I::RREG * I::NTHR;   // cells left after the RREG rounds
+  if constexpr (NSP > 0) {
+    constexpr int NSUB = NSP * NV;
+    const int t0 = item_thread<I::NTHR>();
 #pragma unroll
-  for (int r = 0; r < I::ROUNDS; ++r) {
+    for (int m = 0; m < (NSUB + I::NTHR - 1) / I::NTHR; ++m) {
+      const int sub = t0 + m * I::NTHR;
+      const int v = sub / NSP, c = sub - v * NSP;
+      const int it = I::RREG * I::NTHR + c;
+      bool xa;
+      int ii, jj;
+      if (sub < NSUB && plane_item<TX, TY>(it, w, h, xa, ii, jj)) {
+        const int st = xa ? 1 : TX + 6;
+        const T* src = (xa ? &S.P[0][jj + 3][ii + 1] : &S.P[0][jj + 1][ii + 3]) + v * PV;
+        T cur[5];
+#pragma unroll
+        for (int mm = 0; mm < 5; ++mm) cur[mm] = src[mm * st];
+        T qm, qp;
+        weno5_cell<T>(cur[0], cur[1], cur[2], cur[3], cur[4], eps, linear, qm, qp);
+        if (xa ? ii < w : jj < h) {
+          if (xa)
+            S.FX[v][jj][ii + 1] = qm;
+          else
+            S.FY[v][jj + 1][ii] = qm;
+        }
+        S.QS[c][v] = qp;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < I::RREG; ++r) {
     const int it = item_thread<I::NTHR>() + r * I::NTHR;
     bool xa;
     int ii, jj;
@@ -385,12 +420,7 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        if (r < I::RREG)
-          QP[r < I::RREG ? r : 0][v] = qp[v];
-        else
-          S.QS[it - I::RREG * I::NTHR][v] = qp[v];
-      }
+      for (int v = 0; v < NV; ++v) QP[r][v] = qp[v];
     }
   }
 }
