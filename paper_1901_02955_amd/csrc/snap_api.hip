@@ -272,12 +272,12 @@ bool pass_weights(const snap_grid* g, int passes, double* w) {
   }
   // measured on the 256 x 256 x 128 convection grid (256 tiles, 256 compute
   // units) with the five conserved variables: 2 passes (double precision)
-  // best at 1.42 : 1, stage -7 %; 3 passes (single precision) at
+  // best at 1.5 : 1, stage -8 %; 3 passes (single precision) at
   // 1.35 : 1.35 : 1, stage -10 %. With tracers the kernels' balance differs
   // and the even split is kept.
   if (g->ntracer != 0) return false;
   if (passes == 2) {
-    w[0] = 1.42;
+    w[0] = 1.5;
     return true;
   }
   if (passes == 3) {
