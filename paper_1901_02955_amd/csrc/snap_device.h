@@ -226,27 +226,30 @@ __device__ __forceinline__ T sound_speed(T gp, T rho) {
 // evaluated as d_k t_k / sum_m d_m t_m with t_k the product of the other two
 // s_m^2. The weights depend only on the ratios of the s_k, so the code uses
 // 4 s_k = 4 eps + (13/3) u_k^2 + v_k^2 (beta_k = (13/12) u_k^2 + (1/4) v_k^2):
-// two fused multiply-adds and a product per indicator. Double precision
-// shares one reciprocal between both faces (s_k^8 is far inside the exponent
-// range for eps >= 1e-30 and beta < 1e30). Single precision first scales the
-// s_k by the power of two of their maximum, which is exact and leaves the
-// weights unchanged while keeping the products in range.
+// two fused multiply-adds and a product per indicator. Each candidate value
+// minus c enters already times d_k / 6 (the 6 of the candidate formulas), so
+// the face value is c + (sum_k t_k M_k) / (sum_k d_k t_k) with one fused
+// multiply-add at the end. Double precision shares one reciprocal between
+// both faces (s_k^8 is far inside the exponent range for eps >= 1e-30 and
+// beta < 1e30). Single precision first scales the s_k by 2^-E, E the
+// exponent of their maximum (built from its bits), which is exact and leaves
+// the weights unchanged while keeping the products in range.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool linear, T& qm,
                                            T& qp) {
   const T da = a - c, db = b - c, dd = d - c, de = e - c;
-  // candidate values minus c, times 6
-  const T m0 = T(2) * da - T(7) * db;   // (2a - 7b + 11c) - 6c
-  const T m1 = T(2) * dd - db;          // (-b + 5c + 2d) - 6c
-  const T m2 = T(5) * dd - de;          // (2c + 5d - e) - 6c
-  const T p0 = T(2) * de - T(7) * dd;   // mirrored stencil
-  const T p1 = T(2) * db - dd;
-  const T p2 = T(5) * db - da;
-  const T sixth = T(1) / T(6);
+  // candidate values minus c, times d_k / 6: left state (weights 0.1, 0.6,
+  // 0.3 on stencils 0, 1, 2), right state (the mirrored stencils)
+  const T M0 = fma(T(0.2 / 6.0), da, T(-0.7 / 6.0) * db);   // 0.1 ((2a - 7b + 11c) - 6c) / 6
+  const T M1 = fma(T(0.2), dd, T(-0.1) * db);               // 0.6 ((-b + 5c + 2d) - 6c) / 6
+  const T M2 = fma(T(0.25), dd, T(-0.05) * de);             // 0.3 ((2c + 5d - e) - 6c) / 6
+  const T P0 = fma(T(0.2 / 6.0), de, T(-0.7 / 6.0) * dd);
+  const T P1 = fma(T(0.2), db, T(-0.1) * dd);
+  const T P2 = fma(T(0.25), db, T(-0.05) * da);
   if (linear) {
-    qm = c + (T(0.1) * m0 + T(0.6) * m1 + T(0.3) * m2) * sixth;
-    qp = c + (T(0.1) * p0 + T(0.6) * p1 + T(0.3) * p2) * sixth;
+    qm = c + (M0 + M1 + M2);
+    qp = c + (P0 + P1 + P2);
     return;
   }
   const T k13 = T(13) / T(3), eps4 = T(4) * eps;
@@ -258,28 +261,25 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool 
   T s2 = fma(v2, v2, fma(k13 * u2, u2, eps4));
   if constexpr (sizeof(T) == 4) {
     const float mx = fmaxf(fmaxf(s0, s1), s2);
-    const float sc = __builtin_amdgcn_ldexpf(1.0f, -__builtin_amdgcn_frexp_expf(mx));
+    const float sc = __uint_as_float(0x7F000000u - (__float_as_uint(mx) & 0x7F800000u));
     s0 *= sc;
     s1 *= sc;
     s2 *= sc;
   }
   const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
   const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
-  // left state at j+1/2: weights (0.1, 0.6, 0.3) on stencils (0, 1, 2)
-  const T n0 = T(0.1) * t0, n1 = T(0.6) * t1, n2 = T(0.3) * t2;
-  const T denm = n0 + n1 + n2;
-  const T numm = n0 * m0 + n1 * m1 + n2 * m2;
-  // right state at j-1/2: mirrored stencil k uses beta_{2-k}
-  const T r0 = T(0.1) * t2, r1 = T(0.6) * t1, r2 = T(0.3) * t0;
-  const T denp = r0 + r1 + r2;
-  const T nump = r0 * p0 + r1 * p1 + r2 * p2;
+  const T g1 = T(0.6) * t1;
+  const T denm = fma(T(0.1), t0, fma(T(0.3), t2, g1));
+  const T denp = fma(T(0.3), t0, fma(T(0.1), t2, g1));
+  const T numm = fma(t0, M0, fma(t1, M1, t2 * M2));
+  const T nump = fma(t2, P0, fma(t1, P1, t0 * P2));
   if constexpr (sizeof(T) == 8) {
-    const T inv = sixth * rcp_fast(denm * denp);
-    qm = c + numm * (denp * inv);
-    qp = c + nump * (denm * inv);
+    const T inv = rcp_fast(denm * denp);
+    qm = fma(numm, denp * inv, c);
+    qp = fma(nump, denm * inv, c);
   } else {
-    qm = c + numm * (sixth * rcp_fast(denm));
-    qp = c + nump * (sixth * rcp_fast(denp));
+    qm = fma(numm, rcp_fast(denm), c);
+    qp = fma(nump, rcp_fast(denp), c);
   }
 }
 

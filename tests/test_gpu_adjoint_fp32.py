@@ -48,11 +48,22 @@ def narrow_y_case():
     return C.Case("3d_narrow_y_12x5x14", g, wl.random_smooth_state(g, 52), 0.1)
 
 
+def narrow_x_cases():
+    """Four cells in x (each cell has two copies in x: periodic, or mirrored
+    at both walls), the rows and levels deep enough for the z march's fold."""
+    out = []
+    for bcx, seed in ((0, 53), (1, 54)):
+        g, _ = wl.dry_grid(4, 9, 12, 800.0, 1800.0, 2400.0, bc=(bcx, 0, 1))
+        out.append(C.Case(f"3d_narrow_x_4x9x12_bc{bcx}", g, wl.random_smooth_state(g, seed), 0.1))
+    return out
+
+
 def cases():
     for n in NAMES:
         yield C.build_case(n, dict(C.SPECS)[n])
     yield long_case()
     yield narrow_y_case()
+    yield from narrow_x_cases()
 
 
 class _env:
@@ -129,7 +140,7 @@ def rk3_adjoint32(c, qbar, march=True, fold=True):
 @pytest.mark.parametrize("c", [C.build_case(n, dict(C.SPECS)[n]) for n in
                                ("2d_smooth_37x29_nt3", "3d_smooth_35x21x19", "3d_xwall_19x17x12",
                                 "3d_periodic_z_12x10x14", "3d_periodic_all_13x11x10")]
-                         + [long_case(), narrow_y_case()], ids=lambda c: c.name)
+                         + [long_case(), narrow_y_case()] + narrow_x_cases(), ids=lambda c: c.name)
 def test_rk3_step_adjoint_fp32_fold(c):
     print(f"[adjoint32] rk3 step {c.name}", flush=True)
     q32 = c.q.astype(np.float32).astype(np.float64)
