@@ -338,7 +338,13 @@ constexpr bool reconstruct_prefetch() {
   return !(sizeof(T) == 4 && (NV == 6 || NV == 13));
 }
 
-template <typename T, int NV, int TX, int TY>
+// SPLIT: the items beyond the RREG rounds (64 of the 576 of a 16 x 16 tile)
+// are split by variable, one (cell, variable) pair per thread and pass, so
+// that every wave takes a share instead of one wave reconstructing all their
+// variables while the others wait at the barrier. Without SPLIT they are a
+// last round of whole items, which needs fewer registers: the callers keep
+// that form where the split would cost a wave per SIMD or add spills.
+template <typename T, int NV, int TX, int TY, bool SPLIT = true>
 __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w, int h, T eps,
                                                   bool linear,
                                                   T (&QP)[PlaneItems<TX, TY>::RREG][NV]) {
@@ -346,12 +352,8 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
   constexpr bool RPF = reconstruct_prefetch<T, NV>();
   constexpr int PV = (TY + 6) * (TX + 6);   // plane stride between variables
   constexpr int FXV = TY * (TX + 1), FYV = (TY + 1) * TX;
-  // The items beyond the RREG rounds (64 of the 576 of a 16 x 16 tile) are
-  // split by variable, one (cell, variable) pair per thread and pass, so that
-  // every wave takes a share instead of one wave reconstructing all their
-  // variables while the others wait at the barrier.
   constexpr int NSP = I::NR - I::RREG * I::NTHR;   // cells left after the RREG rounds
-  if constexpr (NSP > 0) {
+  if constexpr (SPLIT && NSP > 0) {
     constexpr int NSUB = NSP * NV;
     const int t0 = item_thread<I::NTHR>();
 #pragma unroll
@@ -379,8 +381,9 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
       }
     }
   }
+  constexpr int NROUND = SPLIT ? I::RREG : I::ROUNDS;
 #pragma unroll
-  for (int r = 0; r < I::RREG; ++r) {
+  for (int r = 0; r < NROUND; ++r) {
     const int it = item_thread<I::NTHR>() + r * I::NTHR;
     bool xa;
     int ii, jj;
@@ -420,7 +423,12 @@ __device__ __forceinline__ void phase_reconstruct(Plane<T, NV, TX, TY>& S, int w
         }
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) QP[r][v] = qp[v];
+      for (int v = 0; v < NV; ++v) {
+        if (r < I::RREG)
+          QP[r < I::RREG ? r : 0][v] = qp[v];
+        else
+          S.QS[it - I::RREG * I::NTHR][v] = qp[v];
+      }
     }
   }
 }
@@ -485,6 +493,15 @@ __device__ __forceinline__ bool halo_item(int it, int w, int h, int& ii, int& jj
   return q < (xs ? h : w);
 }
 
+// The 3-D kernels that split the reconstruction's last items by variable
+// (phase_reconstruct): not those with the sedimentation terms, which are held
+// to two waves per SIMD in single precision (with six tracers the split took
+// the spilled registers from 3 to 11).
+template <typename T, int NT, bool MIX, bool SED>
+constexpr bool split_reconstruct() {
+  return !SED;
+}
+
 // ---------------------------------------------------------------------------
 // 3-D kernel
 // ---------------------------------------------------------------------------
@@ -520,10 +537,16 @@ __device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], const LevelRef&
 // D from the window's levels s-1, s, s+1; these instances load nothing a
 // level ahead, which makes room for that work in the registers.
 // The sedimentation instances in single precision are held to two waves per
-// SIMD, which the other kernels with tracers reach unaided.
+// SIMD, and so is the single-precision mixture with six tracers (unheld it
+// takes 262 registers); the other kernels with tracers reach it unaided.
+template <typename T, int NT, bool MIX, bool SED>
+constexpr int stage3d_min_waves() {
+  return ((SED || (MIX && NT == 6)) && sizeof(T) == 4) ? 2 : SNAP_STAGE3D_WAVES_PER_EU;
+}
+
 template <typename T, int NT, int TX, int TY, bool MIX = false, bool HLLC = false,
           bool SED = false>
-__global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STAGE3D_WAVES_PER_EU)
+__global__ void __launch_bounds__(TX* TY, (stage3d_min_waves<T, NT, MIX, SED>()))
     k_stage3d(StageArgs a) {
   constexpr int NV = 5 + NT;
   constexpr bool GF = ghosts_in_place(NT);
@@ -696,7 +719,8 @@ __global__ void __launch_bounds__(TX* TY, (SED && sizeof(T) == 4) ? 2 : SNAP_STA
       }
       __syncthreads();
       // ---- (R) WENO5 in x and y ---------------------------------------------
-      phase_reconstruct<T, NV, TX, TY>(S, w, h, eps, linear, QP);
+      phase_reconstruct<T, NV, TX, TY, split_reconstruct<T, NT, MIX, SED>()>(S, w, h, eps,
+                                                                            linear, QP);
       __syncthreads();
       // ---- (L) LMARS at x and y faces (level references) ---------------------
       const T rbT = static_cast<T>(rbs), pbT = static_cast<T>(pbs);
