@@ -255,8 +255,9 @@ __device__ __forceinline__ void weno5_linrev(T a, T b, T c, T d, T e, T eps, boo
     const T S2 = fma(v2, v2, fma(ku2, u2, eps4));
     T sc;
     if constexpr (sizeof(T) == 4) {
+      // 2^-E, E the exponent of the largest sum (from its exponent bits)
       const float mx = fmaxf(fmaxf(S0, S1), S2);
-      sc = __builtin_amdgcn_ldexpf(1.0f, -__builtin_amdgcn_frexp_expf(mx));
+      sc = __uint_as_float(0x7F000000u - (__float_as_uint(mx) & 0x7F800000u));
     } else {
       const double mx = fmax(fmax(S0, S1), S2);
       sc = __builtin_amdgcn_ldexp(1.0, -__builtin_amdgcn_frexp_exp(mx));
@@ -264,19 +265,20 @@ __device__ __forceinline__ void weno5_linrev(T a, T b, T c, T d, T e, T eps, boo
     const T s0 = S0 * sc, s1 = S1 * sc, s2 = S2 * sc;
     const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
     const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
+    // unnormalised weights (the middle one is the same for both faces)
     const T n0 = T(0.1) * t0, n1 = T(0.6) * t1, n2 = T(0.3) * t2;
-    const T r0 = T(0.1) * t2, r1 = T(0.6) * t1, r2 = T(0.3) * t0;
-    const T idm = rcp_fast(n0 + n1 + n2), idp = rcp_fast(r0 + r1 + r2);
-    const T wm0 = n0 * idm, wm1 = n1 * idm, wm2 = n2 * idm;
-    const T wp0 = r0 * idp, wp1 = r1 * idp, wp2 = r2 * idp;
-    const T Mm = wm0 * m0 + wm1 * m1 + wm2 * m2;
-    const T Mp = wp0 * p0 + wp1 * p1 + wp2 * p2;
-    mb0 = gms * wm0;
-    mb1 = gms * wm1;
-    mb2 = gms * wm2;
-    pb0 = gps * wp0;
-    pb1 = gps * wp1;
-    pb2 = gps * wp2;
+    const T r0 = T(0.1) * t2, r2 = T(0.3) * t0;
+    const T idm = rcp_fast(n0 + n1 + n2), idp = rcp_fast(r0 + n1 + r2);
+    // M = sum_k w_k m_k = idm sum_k n_k m_k, and mb_k = gm w_k / 6
+    const T Mm = idm * fma(n0, m0, fma(n1, m1, n2 * m2));
+    const T Mp = idp * fma(r0, p0, fma(n1, p1, r2 * p2));
+    const T gmw = gms * idm, gpw = gps * idp;
+    mb0 = gmw * n0;
+    mb1 = gmw * n1;
+    mb2 = gmw * n2;
+    pb0 = gpw * r0;
+    pb1 = gpw * n1;
+    pb2 = gpw * r2;
     // h_j = 2 Sb_j, so that ub_j = h_j (13/3) u_j and vb_j = h_j v_j
     const T h0 = T(-4) * fma(mb0, m0 - Mm, pb2 * (p2 - Mp)) * rcp_fast(S0);
     const T h1 = T(-4) * fma(mb1, m1 - Mm, pb1 * (p1 - Mp)) * rcp_fast(S1);
