@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 11
+#define SNAP_ABI_VERSION 12
 
 /* return codes */
 #define SNAP_OK 0
@@ -474,6 +474,28 @@ typedef struct snap_kessler {
 } snap_kessler;
 
 int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler* k, void* stream);
+
+/*
+ * Adjoint of snap_kessler_step (the discrete adjoint of the microphysics step
+ * of Sec. 3 as the step above evaluates it): q_bar <- J^T q_bar, J the
+ * Jacobian of the state after the step with respect to the state before it,
+ * per interior cell. The regime of X^n and the q*, T of the step's start are
+ * held, as in the step; the backward-Euler solution X* enters through the
+ * implicit-function derivative dX* = M^-1 (dX^n / dt + dPhi/dq* dq*), M = I/dt
+ * - dPhi/dX at X* (the step's Newton matrix at its solution), so the result
+ * is the transpose of the step's exact derivative once its iteration has
+ * converged. Double-precision arithmetic whatever the storage type.
+ *
+ * g, dt, k  as for snap_kessler_step (the same validation).
+ * q      padded state at the START of the step (interior read; ghost layers
+ *        not read).
+ * q_bar  interior array [nvar][nz][ny][nx] of the storage type: in, the
+ *        cotangent of the state after the step; out, that of the state
+ *        before it (overwritten in place); must not alias q.
+ * Returns SNAP_E_INVALID for any other input; no workspace is needed.
+ */
+int snap_kessler_step_adjoint(const snap_grid* g, const void* q, double dt, const snap_kessler* k,
+                              void* q_bar, void* stream);
 
 /*
  * Saturation adjustment (App. D), the alternative to the Kessler scheme for

@@ -641,16 +641,17 @@ def kessler_step(q, grid, dt: float, kessler) -> torch.Tensor:
     density, momentum and total energy are unchanged (Sec. 3: rho_d and rho e
     are conserved by phase changes; the temperature follows from them).
     """
-    q = _t(q).clone()
-    qi = _interior(q, grid)
+    q = _t(q)
+    out = q.clone()                 # written; q itself is only read (autograd-safe)
+    qi, oi = _interior(q, grid), _interior(out, grid)
     T = _interior(temperature(q, grid, kessler.rd).unsqueeze(0), grid)[0]
     rho = qi[0]
     for sp in kessler.species:
         v, c, pr = 5 + sp.vapour, 5 + sp.cloud, 5 + sp.precip
         qs = saturation_vapour_pressure(T, sp) * sp.eps / (kessler.rd * T) / rho
         qv, qc, qp = kessler_solve(qi[v] / rho, qi[c] / rho, qi[pr] / rho, qs, sp, dt)
-        qi[v], qi[c], qi[pr] = rho * qv, rho * qc, rho * qp
-    return q
+        oi[v], oi[c], oi[pr] = rho * qv, rho * qc, rho * qp
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -31,7 +31,7 @@ __all__ = [
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
     "SNAP_EOS_PASSIVE", "SNAP_EOS_MIXTURE", "SNAP_TRACER_VAPOUR", "SNAP_TRACER_CONDENSATE",
     "SNAP_RIEMANN_LMARS", "SNAP_RIEMANN_HLLC", "SNAP_STORE_TOTAL", "SNAP_STORE_PERTURBATION",
-    "snap_kessler_step", "kessler_params", "snap_saturation_adjust", "satadj_params",
+    "snap_kessler_step", "snap_kessler_step_adjoint", "kessler_params", "snap_saturation_adjust", "satadj_params",
 ]
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -49,7 +49,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 11
+SNAP_ABI_VERSION = 12
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
@@ -169,6 +169,8 @@ _SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                              ctypes.c_int, _P, _P]),
     "snap_kessler_step": (ctypes.c_int, [_GP, _P, ctypes.c_double, ctypes.POINTER(SnapKesslerC), _P]),
+    "snap_kessler_step_adjoint": (ctypes.c_int, [_GP, _P, ctypes.c_double, ctypes.POINTER(SnapKesslerC),
+                                                 _P, _P]),
     "snap_saturation_adjust": (ctypes.c_int, [_GP, _P, ctypes.POINTER(SnapSatAdjC), _P]),
     "snap_stage_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "snap_stage_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
@@ -539,6 +541,18 @@ def snap_kessler_step(grid: DeviceGrid, q: torch.Tensor, dt: float, kessler, str
     params = kessler if isinstance(kessler, SnapKesslerC) else kessler_params(kessler)
     _check(lib().snap_kessler_step(grid.ptr(), ctypes.c_void_p(q.data_ptr()), ctypes.c_double(dt),
                                    ctypes.byref(params), _stream(stream)))
+
+
+def snap_kessler_step_adjoint(grid: DeviceGrid, q: torch.Tensor, dt: float, kessler, q_bar: torch.Tensor,
+                              stream=None) -> None:
+    """q_bar <- J^T q_bar for the Kessler step of length dt from the state q (the
+    state before the step; q_bar: interior layout, in place)."""
+    grid._check_state(q)
+    grid._check_state(q_bar, "q_bar", grid.interior_shape)
+    params = kessler if isinstance(kessler, SnapKesslerC) else kessler_params(kessler)
+    _check(lib().snap_kessler_step_adjoint(grid.ptr(), ctypes.c_void_p(q.data_ptr()), ctypes.c_double(dt),
+                                           ctypes.byref(params), ctypes.c_void_p(q_bar.data_ptr()),
+                                           _stream(stream)))
 
 
 def satadj_params(adj) -> SnapSatAdjC:

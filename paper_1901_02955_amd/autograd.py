@@ -13,6 +13,11 @@ segment then holds three padded states per step instead of one. The forward
 pass keeps the last segment that way already, so the backward pass starts
 without a re-run.
 
+``kessler_step(grid, q, dt, kessler)`` is the Kessler microphysics step
+(Sec. 3, ``snap_kessler_step``) under autograd, back-propagated with
+``snap_kessler_step_adjoint``; it composes with ``rk3_run`` for operator-split
+dynamics and microphysics.
+
 Only the interior of the state carries gradients: the library overwrites ghost
 layers from the interior on every call, so the gradient with respect to the
 ghost layers of ``q0`` is zero, and ghost layers of the output (unspecified
@@ -22,7 +27,8 @@ from __future__ import annotations
 
 import torch
 
-from . import (SNAP_NG, SNAP_OP_RK3, SNAP_OP_RK3_ADJ, DeviceGrid, snap_rk3_step,
+from . import (SNAP_NG, SNAP_OP_RK3, SNAP_OP_RK3_ADJ, DeviceGrid, SnapKesslerC, kessler_params,
+               snap_kessler_step, snap_kessler_step_adjoint, snap_rk3_step,
                snap_rk3_step_adjoint, snap_rk3_step_adjoint_stages, workspace)
 
 
@@ -113,3 +119,31 @@ def rk3_run(grid: DeviceGrid, q0: torch.Tensor, dt: float, nsteps: int,
         raise ValueError("nsteps and checkpoint_every must be >= 1")
     return _SnapRK3Run.apply(q0, grid, float(dt), int(nsteps), int(checkpoint_every),
                              bool(keep_stages))
+
+
+class _SnapKesslerStep(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q: torch.Tensor, grid: DeviceGrid, dt: float, params):
+        q0 = q.detach().clone()
+        out = q0.clone()
+        snap_kessler_step(grid, out, dt, params)
+        ctx.grid, ctx.dt, ctx.params = grid, dt, params
+        ctx.save_for_backward(q0)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_out: torch.Tensor):
+        (q0,) = ctx.saved_tensors
+        grid = ctx.grid
+        qb = _interior(grid, g_out).contiguous().clone()
+        snap_kessler_step_adjoint(grid, q0, ctx.dt, ctx.params, qb)
+        g_in = torch.zeros_like(g_out)
+        _interior(grid, g_in).copy_(qb)
+        return g_in, None, None, None
+
+
+def kessler_step(grid: DeviceGrid, q: torch.Tensor, dt: float, kessler) -> torch.Tensor:
+    """Padded state after one Kessler microphysics step of length dt, differentiable
+    with respect to ``q`` (the step's adjoint, within the interior)."""
+    params = kessler if isinstance(kessler, SnapKesslerC) else kessler_params(kessler)
+    return _SnapKesslerStep.apply(q, grid, dt, params)

@@ -1002,11 +1002,8 @@ int snap_rk3_step_batched(const snap_grid* gs, int n, void* const* q, const doub
   return ok();
 }
 
-int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler* k,
-                      void* stream) {
-  int r = check_grid(g);
-  if (r) return r;
-  if (!q || !k) return fail(SNAP_E_INVALID, "q or k is NULL");
+// Validated kernel arguments of a Kessler step (forward or adjoint).
+static int kessler_args(const snap_grid* g, double dt, const snap_kessler* k, KesslerArgs& a) {
   if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
   if (!uses_mixture(g))
     return fail(SNAP_E_INVALID, "the microphysics needs eos = SNAP_EOS_MIXTURE and tracers");
@@ -1015,7 +1012,6 @@ int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler
   if (!finite_pos(k->rd)) return fail(SNAP_E_INVALID, "rd must be finite and > 0");
   if (k->max_iter < 1 || k->max_iter > 100) return fail(SNAP_E_INVALID, "max_iter must lie in [1, 100]");
   if (!isfinite(k->tol) || k->tol < 0.0) return fail(SNAP_E_INVALID, "tol must be finite and >= 0");
-  KesslerArgs a;
   memset(&a, 0, sizeof a);
   bool used[SNAP_MAX_TRACERS] = {false};
   for (int sidx = 0; sidx < k->nspecies; ++sidx) {
@@ -1074,8 +1070,31 @@ int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler
     a.eps[t] = a.vap[t] ? g->tracer_eps[t] : 1.0;
   }
   if ((long long)g->ny * g->nz > 0x7fffffffLL) return fail(SNAP_E_INVALID, "ny nz too large");
+  return 0;
+}
+
+int snap_kessler_step(const snap_grid* g, void* q, double dt, const snap_kessler* k,
+                      void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !k) return fail(SNAP_E_INVALID, "q or k is NULL");
+  KesslerArgs a;
+  if ((r = kessler_args(g, dt, k, a))) return r;
   if (launch_kessler(g->dtype, g->ntracer, q, a, (hipStream_t)stream))
     return device_fail("microphysics kernel launch");
+  return ok();
+}
+
+int snap_kessler_step_adjoint(const snap_grid* g, const void* q, double dt, const snap_kessler* k,
+                              void* q_bar, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !k || !q_bar) return fail(SNAP_E_INVALID, "q, k or q_bar is NULL");
+  if (q_bar == q) return fail(SNAP_E_INVALID, "q_bar must not alias q");
+  KesslerArgs a;
+  if ((r = kessler_args(g, dt, k, a))) return r;
+  if (launch_kessler_adj(g->dtype, g->ntracer, q, q_bar, a, (hipStream_t)stream))
+    return device_fail("microphysics adjoint kernel launch");
   return ok();
 }
 

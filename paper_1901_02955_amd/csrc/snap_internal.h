@@ -131,6 +131,8 @@ int launch_stage2d_batched(int dtype, int ntracer, int variant, int form, const 
 int launch_cfl(int dtype, const void* q, const CflArgs& a, unsigned long long* out,
                hipStream_t st);
 int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st);
+int launch_kessler_adj(int dtype, int ntracer, const void* q, void* qb, const KesslerArgs& a,
+                       hipStream_t st);
 int launch_satadj(int dtype, int ntracer, void* q, const SatAdjArgs& a, hipStream_t st);
 int launch_sediment(int dtype, int ntracer, const StageArgs& a, hipStream_t st);
 int launch_zero_u64(unsigned long long* p, int n, hipStream_t st);

@@ -117,6 +117,165 @@ __global__ void __launch_bounds__(256) k_kessler(T* __restrict__ q, KesslerArgs 
   for (int t = 0; t < NT; ++t) q[o + (5 + t) * a.sv] = static_cast<T>(c[5 + t]);
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the Kessler step: the cotangent of the state before the step
+// from that of the state after it, per interior cell (the transpose of the
+// step's Jacobian, the regime of X^n and the q*, T of the step's start held
+// as in the forward step).
+// The step's solution X* of G(X*) = Phi(X*; q*) - (X* - X^n) / dt = 0 moves
+// by dX* = M^-1 (dX^n / dt + dPhi/dq* dq*), M = I/dt - dPhi/dX at X* (the
+// implicit-function derivative: the forward's Newton matrix at its solution).
+// Hence with w = M^-T Xb*: Xb^n = w / dt and qb* = (dPhi/dq*) . w, where
+// dPhi/dq* = (k1, -k1, 0) when saturated (condensation k1 (q_v - q*)) and
+// (k4 q_p, 0, -k4 q_p) when not (evaporation k4 q_p (q* - q_v)).
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ void kessler_solve_adj(const KesslerSpec& sp, double qs, double dt,
+                                                  bool sat, double xv, double xc, double xp,
+                                                  const double (&xb)[3], double (&x0b)[3],
+                                                  double& qsb) {
+  const double idt = 1.0 / dt;
+  const double A = sp.k2 + sp.k3 * xp, B = sp.k3 * xc, ev = sp.k4 * (qs - xv);
+  // M (the forward's Newton matrix), m01 = 0
+  const double m00 = idt - (sat ? -sp.k1 : -sp.k4 * xp);
+  const double m02 = -(sat ? 0.0 : ev);
+  const double m10 = -(sat ? sp.k1 : 0.0), m11 = idt + A, m12 = B;
+  const double m20 = -(sat ? 0.0 : sp.k4 * xp), m21 = -A, m22 = idt - (sat ? B : B - ev);
+  // N = M^T, solved by Cramer's rule
+  const double n00 = m00, n01 = m10, n02 = m20;
+  const double n10 = 0.0, n11 = m11, n12 = m21;
+  const double n20 = m02, n21 = m12, n22 = m22;
+  const double c00 = n11 * n22 - n12 * n21;
+  const double c01 = n10 * n22 - n12 * n20;
+  const double c02 = n10 * n21 - n11 * n20;
+  const double idet = 1.0 / (n00 * c00 - n01 * c01 + n02 * c02);
+  const double w0 = (xb[0] * c00 - n01 * (xb[1] * n22 - n12 * xb[2]) +
+                     n02 * (xb[1] * n21 - n11 * xb[2])) * idet;
+  const double w1 = (n00 * (xb[1] * n22 - n12 * xb[2]) - xb[0] * c01 +
+                     n02 * (n10 * xb[2] - xb[1] * n20)) * idet;
+  const double w2 = (n00 * (n11 * xb[2] - xb[1] * n21) - n01 * (n10 * xb[2] - xb[1] * n20) +
+                     xb[0] * c02) * idet;
+  x0b[0] = w0 * idt;
+  x0b[1] = w1 * idt;
+  x0b[2] = w2 * idt;
+  qsb = sat ? sp.k1 * (w0 - w1) : sp.k4 * xp * (w0 - w2);
+}
+
+}  // namespace
+
+// q: padded state at the start of the step (read only). qb: interior layout,
+// in: cotangent of the state after the step, out: that of the state before.
+// grid: x over interior rows (nz ny), y over the interior row
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_kessler_adj(const T* __restrict__ q, T* __restrict__ qb,
+                                                     KesslerArgs a) {
+  constexpr int NV = 5 + NT;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, k = row / a.ny;
+  const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+  const long long rv = (long long)a.nx * a.ny * a.nz;
+  const long long ro = (long long)row * a.nx + i;
+  double c[NV], x[NV], cb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    c[v] = static_cast<double>(q[o + v * a.sv]);
+    cb[v] = static_cast<double>(qb[ro + v * rv]);
+  }
+  // the forward's temperature (as in k_kessler)
+  cons_to_prim_mix<NV>(c, 0.0, 0.0, a.gm1, a.m, x);
+  double gas, temp;
+  {
+#pragma clang fp contract(off)
+    double st = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) st = st + c[5 + t];
+    gas = c[0] - st;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      if (a.vap[t]) gas = gas + c[5 + t] / a.eps[t];
+    temp = x[4] / (a.rd * gas);
+  }
+  const double rho = c[0], irho = 1.0 / rho;
+  // the species' tracers leave the step through X* only: their cotangents
+  // restart from zero and gather the X^n path below
+  double yb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) yb[v] = cb[v];
+#pragma unroll
+  for (int s = 0; s < MAX_TRACERS / 3; ++s) {
+    if (s >= a.nspecies) break;
+    const KesslerSpec& sp = a.s[s];
+    set_tracer(cb, sp.v, 0.0);
+    set_tracer(cb, sp.c, 0.0);
+    set_tracer(cb, sp.p, 0.0);
+  }
+  double rhob = 0.0, tb = 0.0;
+#pragma unroll
+  for (int s = 0; s < MAX_TRACERS / 3; ++s) {
+    if (s >= a.nspecies) break;
+    const KesslerSpec& sp = a.s[s];
+    const double tt = temp / sp.t_ref;
+    const double pstar = sp.p_ref * exp(sp.beta * (1.0 - 1.0 / tt) - sp.delta * log(tt));
+    const double qs = pstar * sp.eps / (a.rd * temp) / rho;
+    const double x0[3] = {tracer(c, sp.v) * irho, tracer(c, sp.c) * irho, tracer(c, sp.p) * irho};
+    double xv = x0[0], xc = x0[1], xp = x0[2];
+    kessler_solve(sp, qs, a.dt, a.max_iter, a.tol, xv, xc, xp);
+    // outputs rho X*: cotangents of X* and of rho
+    const double ybs[3] = {tracer(yb, sp.v), tracer(yb, sp.c), tracer(yb, sp.p)};
+    const double xb[3] = {rho * ybs[0], rho * ybs[1], rho * ybs[2]};
+    rhob += xv * ybs[0] + xc * ybs[1] + xp * ybs[2];
+    double x0b[3], qsb;
+    kessler_solve_adj(sp, qs, a.dt, x0[0] > qs, xv, xc, xp, xb, x0b, qsb);
+    // X^n = rho_t / rho
+    set_tracer(cb, sp.v, tracer(cb, sp.v) + x0b[0] * irho);
+    set_tracer(cb, sp.c, tracer(cb, sp.c) + x0b[1] * irho);
+    set_tracer(cb, sp.p, tracer(cb, sp.p) + x0b[2] * irho);
+    rhob -= (x0b[0] * x0[0] + x0b[1] * x0[1] + x0b[2] * x0[2]) * irho;
+    // q* = p*(T) eps / (R_d T rho): d ln q* / dT = beta t_ref / T^2 - (delta + 1) / T
+    tb += qsb * qs * ((sp.beta * sp.t_ref / temp - sp.delta - 1.0) / temp);
+    rhob -= qsb * qs * irho;
+  }
+  // T = p / (R_d gas), gas = rho - sum_t rho_t + sum_vapours rho_t / eps_t
+  const double pb = tb / (a.rd * gas);
+  const double gasb = -tb * temp / gas;
+  rhob += gasb;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) cb[5 + t] += gasb * ((a.vap[t] ? 1.0 / a.eps[t] : 0.0) - 1.0);
+  // p = (gamma - 1) R Q of the mixture (App. B): R = n / d with
+  // n = 1 + sum a_t q_t, d = 1 + sum b_t q_t, q_t = rho_t / rho, and
+  // Q = (E - K) - sum mu_t rho_t, K = |m|^2 / (2 rho)
+  {
+    const double u = x[1], v = x[2], w = x[3];
+    double num = 1.0, den = 1.0, A = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      num += a.m.a[t] * x[5 + t];
+      den += a.m.b[t] * x[5 + t];
+      A += a.m.mu[t] * c[5 + t];
+    }
+    const double K = 0.5 * (c[1] * u + c[2] * v + c[3] * w);
+    const double R = num / den, Q = (c[4] - K) - A;
+    const double Qb = a.gm1 * R * pb, Rb = a.gm1 * Q * pb;
+    cb[1] -= Qb * u;
+    cb[2] -= Qb * v;
+    cb[3] -= Qb * w;
+    cb[4] += Qb;
+    rhob += Qb * 0.5 * (u * u + v * v + w * w);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double fb = Rb * (a.m.a[t] - a.m.b[t] * R) / den;   // cotangent of q_t
+      cb[5 + t] += fb * irho - Qb * a.m.mu[t];
+      rhob -= fb * x[5 + t] * irho;
+    }
+  }
+  cb[0] += rhob;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) qb[ro + v * rv] = static_cast<T>(cb[v]);
+}
+
 // Saturation adjustment (App. D): each vapour / cloud pair brought to phase
 // equilibrium at constant volume and energy, one thread per interior cell,
 // double-precision arithmetic. The energy available as heat, E - K - sum mu
@@ -294,6 +453,34 @@ int launch_kessler_t(int ntracer, T* q, const KesslerArgs& a, hipStream_t st) {
 int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStream_t st) {
   return dtype == 0 ? launch_kessler_t<double>(ntracer, static_cast<double*>(q), a, st)
                     : launch_kessler_t<float>(ntracer, static_cast<float*>(q), a, st);
+}
+
+template <typename T>
+int launch_kessler_adj_t(int ntracer, const T* q, T* qb, const KesslerArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)(a.ny * a.nz), (unsigned)((a.nx + 255) / 256));
+  switch (ntracer) {
+#define SNAP_KESSLER_ADJ_CASE(N)                                                    \
+  case N:                                                                           \
+    hipLaunchKernelGGL((k_kessler_adj<T, N>), grid, dim3(256), 0, st, q, qb, a);    \
+    break;
+    SNAP_KESSLER_ADJ_CASE(3)
+    SNAP_KESSLER_ADJ_CASE(4)
+    SNAP_KESSLER_ADJ_CASE(5)
+    SNAP_KESSLER_ADJ_CASE(6)
+    SNAP_KESSLER_ADJ_CASE(7)
+    SNAP_KESSLER_ADJ_CASE(8)
+#undef SNAP_KESSLER_ADJ_CASE
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_kessler_adj(int dtype, int ntracer, const void* q, void* qb, const KesslerArgs& a,
+                       hipStream_t st) {
+  return dtype == 0 ? launch_kessler_adj_t<double>(ntracer, static_cast<const double*>(q),
+                                                   static_cast<double*>(qb), a, st)
+                    : launch_kessler_adj_t<float>(ntracer, static_cast<const float*>(q),
+                                                  static_cast<float*>(qb), a, st);
 }
 
 template <typename T>

@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 11
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 12
 
 
 def good_grid(**kw):
@@ -319,6 +319,26 @@ def test_kessler_rejects_bad_parameters(kw):
     k = _kessler(**kw)
     assert lib.snap_kessler_step(g, ctypes.c_void_p(FAKE), 1.0, ctypes.byref(k), None) == snap.SNAP_E_INVALID
     assert lib.snap_last_error().decode()
+    # the adjoint validates the same parameters before any launch
+    assert lib.snap_kessler_step_adjoint(g, ctypes.c_void_p(FAKE), 1.0, ctypes.byref(k),
+                                         ctypes.c_void_p(FAKE + 4096), None) == snap.SNAP_E_INVALID
+    assert lib.snap_last_error().decode()
+
+
+def test_kessler_adjoint_rejects_bad_arguments():
+    lib = snap.lib()
+    k = _kessler()
+    P, Q = ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 4096)
+    passive = ctypes.byref(_kessler_grid(eos=0))
+    assert lib.snap_kessler_step_adjoint(passive, P, 1.0, ctypes.byref(k), Q, None) == snap.SNAP_E_INVALID
+    g = ctypes.byref(_kessler_grid())
+    for dt in (0.0, -1.0, math.nan):
+        assert lib.snap_kessler_step_adjoint(g, P, dt, ctypes.byref(k), Q, None) == snap.SNAP_E_INVALID
+    assert lib.snap_kessler_step_adjoint(g, None, 1.0, ctypes.byref(k), Q, None) == snap.SNAP_E_INVALID
+    assert lib.snap_kessler_step_adjoint(g, P, 1.0, None, Q, None) == snap.SNAP_E_INVALID
+    assert lib.snap_kessler_step_adjoint(g, P, 1.0, ctypes.byref(k), None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_kessler_step_adjoint(g, P, 1.0, ctypes.byref(k), P, None) == snap.SNAP_E_INVALID
+    assert b"alias" in lib.snap_last_error()
 
 
 def test_kessler_needs_the_mixture_and_valid_scalars():

@@ -7,6 +7,13 @@ fixed point; the iteration stops at a step of 1e-14 of the species' total),
 1e-6 with FP32 storage (the output rounding); density, momentum and total
 energy untouched bit for bit; after two steps of dynamics plus microphysics
 within max(1e-12, 10 x the oracle's 1-ulp input sensitivity).
+
+The adjoint of the step (snap_kessler_step_adjoint) against autograd through
+the oracle's step (which test_oracle_kessler.py pins to central differences):
+within 1e-10 per field in FP64 (the oracle differentiates its 60 Newton
+iterations, the kernel takes the implicit-function derivative at the
+solution its iteration stopped at, within 1e-14 of the species' total), and
+1e-5 with FP32 storage at the same FP32-rounded inputs.
 """
 import numpy as np
 import pytest
@@ -14,6 +21,7 @@ import torch
 
 import oracle
 import paper_1901_02955_amd as snap
+import workloads as wl
 from tests import cases as C
 from tests.test_gpu_parity import TOL64, assert_steps_close, field_errors
 
@@ -95,3 +103,78 @@ def test_kessler_deterministic(kcases):
     snap.snap_kessler_step(dg, a, c.dt, kes)
     snap.snap_kessler_step(dg, b, c.dt, kes)
     assert torch.equal(a, b)
+
+
+def oracle_kessler_adjoint(c, kes, q, qbar):
+    """J^T qbar of the oracle's Kessler step at the padded state q, by autograd
+    (interior of the input's cotangent)."""
+    qq = torch.as_tensor(q).clone().requires_grad_(True)
+    out = c.grid.interior(oracle.kessler_step(qq, c.grid, c.dt, kes))
+    (out * torch.as_tensor(qbar)).sum().backward()
+    return c.grid.interior(qq.grad.numpy())
+
+
+@pytest.mark.parametrize("name", C.KESSLER_NAMES)
+def test_kessler_adjoint_fp64(kcases, name):
+    c, kes = kcases[name]
+    print(f"[kessler] adjoint fp64 {name}", flush=True)
+    qbar = wl.seeded_normal(c.grid.interior_shape, 140)
+    ref = oracle_kessler_adjoint(c, kes, c.q, qbar)
+    dg = snap.device_grid(c.grid)
+    qb = torch.as_tensor(qbar).cuda()
+    snap.snap_kessler_step_adjoint(dg, torch.as_tensor(c.q).cuda(), c.dt, kes, qb)
+    got = qb.cpu().numpy()
+    errs = field_errors(got, ref)
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-10 for e in errs), errs
+    # the microphysics moves the cotangent away from the identity
+    assert float(np.max(np.abs(got[5:] - qbar[5:]))) > 1e-3 * float(np.max(np.abs(qbar[5:])))
+
+
+@pytest.mark.parametrize("name", ["kessler_3d_21x13x16", "kessler_2d_37x24"])
+def test_kessler_adjoint_fp32(kcases, name):
+    c, kes = kcases[name]
+    print(f"[kessler] adjoint fp32 {name}", flush=True)
+    q32 = c.q.astype(np.float32).astype(np.float64)
+    qbar = wl.seeded_normal(c.grid.interior_shape, 141).astype(np.float32).astype(np.float64)
+    ref = oracle_kessler_adjoint(c, kes, q32, qbar)
+    dg = snap.device_grid(c.grid, dtype=torch.float32)
+    qb = torch.as_tensor(qbar).float().cuda()
+    snap.snap_kessler_step_adjoint(dg, torch.as_tensor(q32).float().cuda(), c.dt, kes, qb)
+    errs = field_errors(qb.cpu().double().numpy(), ref)
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-5 for e in errs), errs
+
+
+def test_kessler_adjoint_deterministic(kcases):
+    c, kes = kcases["kessler_3d_21x13x16"]
+    dg = snap.device_grid(c.grid)
+    qd = torch.as_tensor(c.q).cuda()
+    qbar = torch.as_tensor(wl.seeded_normal(c.grid.interior_shape, 142)).cuda()
+    a, b = qbar.clone(), qbar.clone()
+    snap.snap_kessler_step_adjoint(dg, qd, c.dt, kes, a)
+    snap.snap_kessler_step_adjoint(dg, qd, c.dt, kes, b)
+    assert torch.equal(a, b)
+
+
+def test_dynamics_plus_microphysics_gradient(kcases):
+    """Gradient of a loss after one RK3 step and one Kessler step (autograd through
+    rk3_run and kessler_step, i.e. the library's RK3 and microphysics adjoints)
+    against autograd through the oracle's step and microphysics: within 1e-10."""
+    from paper_1901_02955_amd.autograd import kessler_step, rk3_run
+    c, kes = kcases["kessler_3d_ragged_9x7x5"]
+    print("[kessler] gradient through rk3 + kessler", flush=True)
+    dt = 0.5 * oracle.cfl_dt(c.q, c.grid, 0.9)
+    w = wl.seeded_normal(c.grid.interior_shape, 143)
+    dg = snap.device_grid(c.grid)
+    q0 = torch.as_tensor(c.q).cuda().requires_grad_(True)
+    out = kessler_step(dg, rk3_run(dg, q0, dt, 1, 1), dt, kes)
+    (c.grid.interior(out) * torch.as_tensor(w).cuda()).sum().backward()
+    got = c.grid.interior(q0.grad.cpu().numpy())
+    qq = torch.as_tensor(c.q).clone().requires_grad_(True)
+    ref_out = oracle.kessler_step(oracle.rk3_step(qq, c.grid, dt), c.grid, dt, kes)
+    (c.grid.interior(ref_out) * torch.as_tensor(w)).sum().backward()
+    ref = c.grid.interior(qq.grad.numpy())
+    errs = field_errors(got, ref)
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-10 for e in errs), errs

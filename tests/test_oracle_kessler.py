@@ -10,7 +10,9 @@ pressure (App. D).
   d ln p* / dT = L(T) / (R T^2) with the Kirchhoff latent heat;
 * moving mass from vapour to cloud at constant total density and energy
   changes the mixture's temperature by the paper's constant-volume jump
-  dT = d_rho (L(T) - R T) / (heat capacity after) (Sec. 2, eq. phase).
+  dT = d_rho (L(T) - R T) / (heat capacity after) (Sec. 2, eq. phase);
+* the derivative of the step that autograd takes through the oracle (the
+  reference of the GPU adjoint) agrees with central differences of the step.
 """
 import numpy as np
 import pytest
@@ -164,3 +166,38 @@ def test_kessler_step_keeps_density_momentum_and_energy():
     tot0 = a[5] + a[6] + a[7]
     assert np.max(np.abs(b[5] + b[6] + b[7] - tot0) / tot0) < 1e-14
     assert not np.array_equal(a[5:], b[5:])
+
+
+def test_kessler_step_autograd_matches_central_differences():
+    """<J^T w, v> by autograd through the oracle's step against <w, J v> by
+    Richardson-extrapolated central differences, on the small microphysics
+    case of the GPU tests (every field perturbed, scaled to its magnitude)."""
+    from tests import cases as C
+    c, kes = C.build_kessler_case("kessler_3d_ragged_9x7x5", dict(C.KESSLER_SPECS)["kessler_3d_ragged_9x7x5"])
+    g = c.grid
+    q0 = torch.as_tensor(c.q)
+    rng = np.random.default_rng(77)
+    qi = g.interior(c.q)
+    scale = np.abs(qi).reshape(g.nvar, -1).max(axis=1)[:, None, None, None]
+    v = rng.standard_normal(qi.shape) * scale
+    w = rng.standard_normal(qi.shape)
+
+    def step(q):
+        return g.interior(O.kessler_step(q, g, c.dt, kes))
+
+    qg = q0.clone().requires_grad_(True)
+    (step(qg) * torch.as_tensor(w)).sum().backward()
+    lhs = float((g.interior(qg.grad).numpy() * v).sum())
+
+    def shifted(h):
+        qq = c.q.copy()
+        g.interior(qq)[...] += h * v
+        return step(torch.as_tensor(qq)).numpy()
+
+    def central(h):
+        return (shifted(h) - shifted(-h)) / (2.0 * h)
+
+    h = 1e-7
+    jv = (4.0 * central(0.5 * h) - central(h)) / 3.0
+    rhs = float((w * jv).sum())
+    assert abs(lhs - rhs) <= 1e-6 * max(abs(lhs), abs(rhs)), (lhs, rhs)
