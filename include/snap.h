@@ -159,8 +159,8 @@ extern "C" {
  *                either flux.
  *                The tracer fields are read only under SNAP_EOS_MIXTURE with
  *                ntracer > 0 (a nonzero tracer_wt needs the mixture). The
- *                adjoint entry points take the mixture, but return
- *                SNAP_E_UNSUPPORTED when a condensate falls (sedimentation).
+ *                adjoint entry points take the mixture and falling condensates
+ *                (the reverse of the sedimentation terms).
  * storage        SNAP_STORE_TOTAL (0): q holds the conserved state.
  *                SNAP_STORE_PERTURBATION: q[0] holds rho - rhobar_k and q[4]
  *                holds E - pbar_k / (gamma - 1) (the state's departure from the
@@ -270,8 +270,11 @@ int snap_rk3_step(const snap_grid* g, void* q, double dt, void* work, void* stre
  * switches sides, the derivative of the advective flux with respect to u* uses
  * the mean of both sides' advected vectors (the one-sided derivatives differ
  * there). With HLLC the derivative is that of the branch (side, star region)
- * and of the outer wave speed candidates the forward evaluation selects. The
- * result is reproducible bit for bit (no atomics).
+ * and of the outer wave speed candidates the forward evaluation selects. With
+ * falling condensates the sedimentation terms (upwind fall fluxes through the
+ * z faces and the frictional heating) are reversed as well, each face's flux
+ * being a function of its source cell. The result is reproducible bit for bit
+ * (no atomics).
  * work  device workspace of snap_workspace_bytes(g, SNAP_OP_RHS_ADJ) bytes.
  */
 int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_bar, void* work,

@@ -98,6 +98,13 @@ int adj_rhs_nv(const AdjWork& w, const AdjArgs& a, const void* q, const void* rb
     if (a.d3) adj_line_launch<T, NV, false, HLLC, MIX>(qs, r, a, 1, P, st);
     adj_line_launch<T, NV, false, HLLC, MIX>(qs, r, a, 2, P, st);
   }
+  // falling condensates (mixture): the reverse of the sedimentation terms
+  if constexpr (MIX) {
+    if (a.sed.on) {
+      const dim3 sgrid(a.ny * (a.nz + 2), (a.nx + 255) / 256);
+      hipLaunchKernelGGL((k_adj_sediment<T, NV>), sgrid, dim3(256), 0, st, qs, r, a, P);
+    }
+  }
   // every row, or after a folding z march the rows it left
   const int ye = !a.d3 ? 0 : (a.ny > 6 ? 6 : a.ny);
   const int rows = zfold ? 6 * a.ny + (a.nz - 6) * ye : a.ny * a.nz;

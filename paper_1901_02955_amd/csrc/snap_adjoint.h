@@ -45,6 +45,7 @@ struct AdjArgs {
   int hllc;   // the HLLC flux (else LMARS)
   int mixture;   // the mixture equation of state (App. B)
   Mixture mix;   // its coefficients
+  Sediment sed;  // falling condensates (mixture only; sed.on = 0: none)
   const double* rbar_c;
   const double* pbar_c;
   const double* rbar_f;
@@ -1439,6 +1440,93 @@ __device__ __forceinline__ void adj_cons_cell(const T* __restrict__ q, const T* 
   out[2] = pb[2] * inv - Qb * v;
   out[3] = pb[3] * inv - Qb * w + qe;
   out[4] = Qb;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse of the sedimentation terms (Sec. 2; sediment_cell in the stage
+// kernels): condensate t with vertical velocity w_t carries through every z
+// face the mass flux m = w_t rho q_t of the cell it comes from (the cell above
+// when it falls, below when it rises; none through a closed boundary into the
+// domain), with the momentum m (u, v, w) and the energy m e, e = c_t T + K +
+// mu_t, T = p / (R_d rho (1 + sum_s a_s q_s)), K = |u|^2 / 2; and heats the
+// air of its cell by -g w_t rho q_t. A face's flux F enters R of the cell
+// above it with +F / dz and of the cell below with -F / dz, so its cotangent
+// is (r_bar[above] - r_bar[below]) / dz (zero for a cell outside the domain),
+// and it depends on the primitives of its source cell only: each cell (the
+// levels -1 .. nz, for the ghost cells a flux can come from) gathers the
+// faces it is the source of, one per condensate, and adds their reverse, and
+// that of its heating, to its primitive cotangent in P (after the direction
+// kernels, before the fold; double precision).
+// Grid: x over rows of the levels -1 .. nz, y over the interior row.
+// ---------------------------------------------------------------------------
+template <typename T, int NV>
+__global__ void __launch_bounds__(256) k_adj_sediment(const T* __restrict__ q,
+                                                      const T* __restrict__ rb, AdjArgs a,
+                                                      T* __restrict__ P) {
+  constexpr int NT = NV - 5;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, u_lev = row / a.ny - 1;   // level -1 .. nz
+  const long long c = padded_off(a, i, j, u_lev);
+  T xt[NV];
+  load_prim<T, NV, true>(q, c, a.sv, level_ref(0, a.rbar_c[u_lev + NG], a.pbar_c[u_lev + NG]),
+                         a.gm1, a.mix, xt);
+  double x[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] = static_cast<double>(xt[v]);
+  const double rho = a.rbar_c[u_lev + NG] + x[0], pres = a.pbar_c[u_lev + NG] + x[4];
+  double num = 1.0;
+#pragma unroll
+  for (int s = 0; s < NT; ++s) num += a.mix.a[s] * x[5 + s];
+  const double temp = pres / (a.sed.rd * rho * num);
+  const double kin = 0.5 * (x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+  const double dzi = a.dxi[2];
+  auto rbv = [&](int v, int k) -> double {
+    if (k < 0 || k >= a.nz) return 0.0;
+    return static_cast<double>(rb[(long long)k * a.rz + (long long)j * a.ry + i + v * a.rv]);
+  };
+  double pb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) pb[v] = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double wt = a.sed.wt[t];
+    if (wt == 0.0) continue;
+    const bool fall = wt < 0.0;
+    const double qt = x[5 + t];
+    // frictional heating of this cell's air: R_E -= g w_t rho q_t
+    if (u_lev >= 0 && u_lev < a.nz) {
+      const double hb = -a.grav * wt * rbv(4, u_lev);
+      pb[0] += hb * qt;
+      pb[5 + t] += hb * rho;
+    }
+    // the face this cell is the source of: its lower face (falling), upper (rising)
+    const int f = fall ? u_lev : u_lev + 1;   // between levels f - 1 and f
+    if (f < 0 || f > a.nz) continue;
+    if (a.sed.closed_z && ((fall && f == a.nz) || (!fall && f == 0))) continue;
+    double Fb[6];
+    const int comp[6] = {0, 1, 2, 3, 4, 5 + t};
+#pragma unroll
+    for (int m = 0; m < 6; ++m) Fb[m] = (rbv(comp[m], f) - rbv(comp[m], f - 1)) * dzi;
+    const double mflux = wt * rho * qt;
+    const double e = a.sed.ct[t] * temp + kin + a.mix.mu[t];
+    const double mb = Fb[0] + Fb[5] + Fb[1] * x[1] + Fb[2] * x[2] + Fb[3] * x[3] + Fb[4] * e;
+    const double eb = Fb[4] * mflux;
+    pb[1] += Fb[1] * mflux + eb * x[1];
+    pb[2] += Fb[2] * mflux + eb * x[2];
+    pb[3] += Fb[3] * mflux + eb * x[3];
+    const double tb = a.sed.ct[t] * eb;
+    pb[0] += mb * wt * qt - tb * temp / rho;
+    pb[5 + t] += mb * wt * rho;
+    pb[4] += tb / (a.sed.rd * rho * num);
+    const double numb = -tb * temp / num;
+#pragma unroll
+    for (int s = 0; s < NT; ++s) pb[5 + s] += numb * a.mix.a[s];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    P[c + v * a.sv] = static_cast<T>(static_cast<double>(P[c + v * a.sv]) + pb[v]);
 }
 
 // Per interior cell: its conserved cotangent plus those of the ghost cells

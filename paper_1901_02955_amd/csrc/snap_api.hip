@@ -440,6 +440,7 @@ AdjArgs adj_args(const snap_grid* g) {
   a.hllc = g->riemann == SNAP_RIEMANN_HLLC ? 1 : 0;
   a.mixture = uses_mixture(g) ? 1 : 0;
   a.mix = mixture_of(g);
+  a.sed = sediment_of(g);
   a.rbar_c = g->rhobar_cell;
   a.pbar_c = g->pbar_cell;
   a.rbar_f = g->rhobar_face;
@@ -820,8 +821,6 @@ int snap_rhs_adjoint(const snap_grid* g, void* q, const void* rhs_bar, void* q_b
   if (!q || !rhs_bar || !q_bar || !work)
     return fail(SNAP_E_INVALID, "q, rhs_bar, q_bar or work is NULL");
   if (q_bar == q || q_bar == rhs_bar) return fail(SNAP_E_INVALID, "q_bar must not alias q or rhs_bar");
-  if (stage_args(g).sed.on)
-    return fail(SNAP_E_UNSUPPORTED, "the adjoint takes no sedimentation (no falling condensates)");
   const hipStream_t st = (hipStream_t)stream;
   if ((r = fill(g, q, st))) return r;
   if ((r = run_adj_rhs(g, q, rhs_bar, q_bar, 0, 0.0, 1.0, work, st))) return r;
@@ -835,8 +834,6 @@ static int check_rk3_adjoint(const snap_grid* g, const void* q_n, double dt, con
   if (r) return r;
   if (!q_n || !q_bar || !work) return fail(SNAP_E_INVALID, "q_n, q_bar or work is NULL");
   if (!finite_pos(dt)) return fail(SNAP_E_INVALID, "dt must be finite and > 0");
-  if (stage_args(g).sed.on)
-    return fail(SNAP_E_UNSUPPORTED, "the adjoint takes no sedimentation (no falling condensates)");
   return SNAP_OK;
 }
 

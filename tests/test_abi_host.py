@@ -253,7 +253,7 @@ def test_batched_workspace_layout():
 def test_mixture_fields_and_unsupported_entry_points():
     """The tracer fields are read only under SNAP_EOS_MIXTURE; a condensate's
     molar-mass ratio is ignored; the adjoint entry points take the mixture
-    but refuse falling condensates; the batched step takes the mixture."""
+    and falling condensates; the batched step takes the mixture."""
     lib = snap.lib()
     # passive: garbage tracer fields are not validated
     g = ctypes.byref(good_grid(tracer_kind=(7, 9), tracer_sigma=(-1.0, math.nan)))
@@ -274,10 +274,11 @@ def test_mixture_fields_and_unsupported_entry_points():
     assert lib.snap_rhs_adjoint(g, P, Q2, P, Q3, None) == snap.SNAP_E_INVALID     # q_bar aliases q
     assert lib.snap_rk3_step_adjoint(g, P, 0.1, None, Q3, None) == snap.SNAP_E_INVALID
     g = ctypes.byref(good_grid(eos=1, rd=287.0, tracer_wt=(0.0, -6.0)))   # a falling condensate
-    assert lib.snap_rhs_adjoint(g, P, Q2, Q3, P, None) == snap.SNAP_E_UNSUPPORTED
-    assert lib.snap_rk3_step_adjoint(g, P, 0.1, Q2, Q3, None) == snap.SNAP_E_UNSUPPORTED
-    assert lib.snap_rk3_step_adjoint_stages(g, P, ctypes.c_void_p(4 * FAKE), 0.1, Q2, Q3,
-                                            None) == snap.SNAP_E_UNSUPPORTED
+    # accepted as well: the same buffer checks decide (no call here reaches a launch)
+    assert lib.snap_rhs_adjoint(g, P, Q2, Q2, Q3, None) == snap.SNAP_E_INVALID    # q_bar aliases rhs_bar
+    assert lib.snap_rk3_step_adjoint(g, P, 0.1, None, Q3, None) == snap.SNAP_E_INVALID
+    assert lib.snap_rk3_step_adjoint_stages(g, P, ctypes.c_void_p(4 * FAKE), 0.1, Q2, None,
+                                            None) == snap.SNAP_E_INVALID
     arr = (snap.SnapGridC * 2)(good_grid(ny=1, eos=1), good_grid(ny=1, eos=1))
     assert lib.snap_batched_workspace_bytes(arr, 2) > 0
 
