@@ -313,6 +313,20 @@ def run_jovian_kessler(steps: int, warmup: int, sediment: bool = True, repeats: 
     e1.record()
     torch.cuda.synchronize()
     micro_ms = e0.elapsed_time(e1) / steps
+    # the microphysics adjoint (J^T of the Kessler step in place on a seeded
+    # cotangent), on the stream, over the same number of calls and a CFL dt
+    dt_adj = snap.snap_cfl_dt(dg, qd, CFL, cw)
+    qbar = torch.randn(dg.interior_shape, dtype=torch.float32, device="cuda",
+                       generator=torch.Generator(device="cuda").manual_seed(17))
+    snap.snap_kessler_step_adjoint(dg, qd, dt_adj, params, qbar)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        snap.snap_kessler_step_adjoint(dg, qd, dt_adj, params, qbar)
+    e1.record()
+    torch.cuda.synchronize()
+    micro_adj_ms = e0.elapsed_time(e1) / steps
+    del qbar
 
     def steps_fn():
         for _ in range(steps):
@@ -329,7 +343,8 @@ def run_jovian_kessler(steps: int, warmup: int, sediment: bool = True, repeats: 
            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
            "steps": steps, "repeats": repeats, "spread": _spread(times), "microphysics_ms": micro_ms,
            "microphysics_hbm_frac": byts / (micro_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-           "microphysics_share": micro_ms / (el / steps * 1e3)}
+           "microphysics_share": micro_ms / (el / steps * 1e3),
+           "microphysics_adjoint_ms": micro_adj_ms}
     del qd, work, cw
     torch.cuda.empty_cache()
     return out
