@@ -226,53 +226,61 @@ __device__ __forceinline__ T sound_speed(T gp, T rho) {
 // evaluated as d_k t_k / sum_m d_m t_m with t_k the product of the other two
 // s_m^2. The weights depend only on the ratios of the s_k, so the code uses
 // 4 s_k = 4 eps + (13/3) u_k^2 + v_k^2 (beta_k = (13/12) u_k^2 + (1/4) v_k^2):
-// two fused multiply-adds and a product per indicator. Each candidate value
-// minus c enters already times d_k / 6 (the 6 of the candidate formulas), so
-// the face value is c + (sum_k t_k M_k) / (sum_k d_k t_k) with one fused
+// two fused multiply-adds and a product per indicator, with u_k the second
+// difference of stencil k and v_k its one-sided first-derivative term.
+// The candidate values minus c are, per stencil, u_k +- 3 v_k times a factor:
+//   left:  (0.05/6)(u0 + 3 v0), 0.05 (u1 - 3 v1), 0.025 (u2 - 3 v2);
+//   right: 0.025 (u0 - 3 v0),   0.05 (u1 + 3 v1), (0.05/6)(u2 + 3 v2)
+// (the right state's stencil 0 carries weight 0.3 and stencil 2 weight 0.1).
+// Taking 0.05 out of numerator and denominator leaves the factors 1/6, 1, 1/2
+// (left) and 1/2, 1, 1/6 (right) inside the candidates, where each but the
+// two with 1/6 is one fused multiply-add of the differences, and the
+// denominators 2 t0 + 12 t1 + 6 t2 and 6 t0 + 12 t1 + 2 t2, which share
+// 12 t1. The face value is c + (sum_k t_k A_k) / den with one fused
 // multiply-add at the end. Double precision shares one reciprocal between
 // both faces (s_k^8 is far inside the exponent range for eps >= 1e-30 and
-// beta < 1e30). Single precision first scales the s_k by 2^-E, E the
-// exponent of their maximum (built from its bits), which is exact and leaves
-// the weights unchanged while keeping the products in range.
+// beta < 1e30). Single precision first scales the s_k by about 2^-E, E the
+// exponent of their maximum: the float whose bits are 0x7F000000 minus the
+// maximum's bits, which brings the maximum to [1, 1.125] without isolating the
+// exponent field; a common factor leaves the weights unchanged up to the
+// rounding of the three products, and keeps the products of the s_k in range.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool linear, T& qm,
                                            T& qp) {
   const T da = a - c, db = b - c, dd = d - c, de = e - c;
-  // candidate values minus c, times d_k / 6: left state (weights 0.1, 0.6,
-  // 0.3 on stencils 0, 1, 2), right state (the mirrored stencils)
-  const T M0 = fma(T(0.2 / 6.0), da, T(-0.7 / 6.0) * db);   // 0.1 ((2a - 7b + 11c) - 6c) / 6
-  const T M1 = fma(T(0.2), dd, T(-0.1) * db);               // 0.6 ((-b + 5c + 2d) - 6c) / 6
-  const T M2 = fma(T(0.25), dd, T(-0.05) * de);             // 0.3 ((2c + 5d - e) - 6c) / 6
-  const T P0 = fma(T(0.2 / 6.0), de, T(-0.7 / 6.0) * dd);
-  const T P1 = fma(T(0.2), db, T(-0.1) * dd);
-  const T P2 = fma(T(0.25), db, T(-0.05) * da);
+  const T u1 = db + dd, v1 = db - dd;
+  // candidate values minus c over 0.05: left A_k, right B_k (stencil k)
+  const T A0 = fma(T(2.0 / 3.0), da, T(-7.0 / 3.0) * db);   // (u0 + 3 v0) / 6
+  const T B0 = fma(T(5), db, -da);                           // (u0 - 3 v0) / 2
+  const T A1 = fma(T(-3), v1, u1), B1 = fma(T(3), v1, u1);
+  const T A2 = fma(T(5), dd, -de);                           // (u2 - 3 v2) / 2
+  const T B2 = fma(T(2.0 / 3.0), de, T(-7.0 / 3.0) * dd);   // (u2 + 3 v2) / 6
   if (linear) {
-    qm = c + (M0 + M1 + M2);
-    qp = c + (P0 + P1 + P2);
+    qm = fma(T(0.05), (A0 + A1) + A2, c);
+    qp = fma(T(0.05), (B2 + B1) + B0, c);
     return;
   }
   const T k13 = T(13) / T(3), eps4 = T(4) * eps;
   const T u0 = fma(T(-2), db, da), v0 = fma(T(-4), db, da);
-  const T u1 = db + dd, v1 = db - dd;
   const T u2 = fma(T(-2), dd, de), v2 = fma(T(-4), dd, de);
   T s0 = fma(v0, v0, fma(k13 * u0, u0, eps4));
   T s1 = fma(v1, v1, fma(k13 * u1, u1, eps4));
   T s2 = fma(v2, v2, fma(k13 * u2, u2, eps4));
   if constexpr (sizeof(T) == 4) {
     const float mx = fmaxf(fmaxf(s0, s1), s2);
-    const float sc = __uint_as_float(0x7F000000u - (__float_as_uint(mx) & 0x7F800000u));
+    const float sc = __uint_as_float(0x7F000000u - __float_as_uint(mx));
     s0 *= sc;
     s1 *= sc;
     s2 *= sc;
   }
   const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
   const T t0 = q1 * q2, t1 = q0 * q2, t2 = q0 * q1;
-  const T g1 = T(0.6) * t1;
-  const T denm = fma(T(0.1), t0, fma(T(0.3), t2, g1));
-  const T denp = fma(T(0.3), t0, fma(T(0.1), t2, g1));
-  const T numm = fma(t0, M0, fma(t1, M1, t2 * M2));
-  const T nump = fma(t2, P0, fma(t1, P1, t0 * P2));
+  const T g1 = T(12) * t1;
+  const T denm = fma(T(2), t0, fma(T(6), t2, g1));
+  const T denp = fma(T(6), t0, fma(T(2), t2, g1));
+  const T numm = fma(t0, A0, fma(t1, A1, t2 * A2));
+  const T nump = fma(t0, B0, fma(t1, B1, t2 * B2));
   if constexpr (sizeof(T) == 8) {
     const T inv = rcp_fast(denm * denp);
     qm = fma(numm, denp * inv, c);

@@ -537,11 +537,16 @@ __device__ __forceinline__ void cons_to_prim_t(const T (&c)[NV], const LevelRef&
 // D from the window's levels s-1, s, s+1; these instances load nothing a
 // level ahead, which makes room for that work in the registers.
 // The sedimentation instances in single precision are held to two waves per
-// SIMD, and so is the single-precision mixture with six tracers (unheld it
-// takes 262 registers); the other kernels with tracers reach it unaided.
+// SIMD, and so are the single-precision mixture with six or seven tracers and
+// the double-precision sedimentation instance with one tracer (unheld they
+// take 258 to 262 registers); the other kernels with up to eight tracers in
+// single precision and one in double precision reach it unaided.
 template <typename T, int NT, bool MIX, bool SED>
 constexpr int stage3d_min_waves() {
-  return ((SED || (MIX && NT == 6)) && sizeof(T) == 4) ? 2 : SNAP_STAGE3D_WAVES_PER_EU;
+  if constexpr (sizeof(T) == 4)
+    return (SED || (MIX && (NT == 6 || NT == 7))) ? 2 : SNAP_STAGE3D_WAVES_PER_EU;
+  else
+    return (SED && NT == 1) ? 2 : SNAP_STAGE3D_WAVES_PER_EU;
 }
 
 template <typename T, int NT, int TX, int TY, bool MIX = false, bool HLLC = false,
