@@ -735,6 +735,84 @@ def saturation_adjust(q, grid, adjust, sweeps: int = 40, bisections: int = 90) -
     return q
 
 
+def saturation_adjust_diff(q, grid, adjust) -> torch.Tensor:
+    """The saturation adjustment (App. D) in a form whose autograd derivative is
+    that of the adjusted state with respect to q.
+
+    The bisection of saturation_adjust fixes the transfers X*_s (mass moved
+    from vapour s to cloud s) but carries no derivative. At the equilibrium
+    every pair with cloud left satisfies G_s(X, q) = 0, with
+        G_s = (rho_v,s - X_s) R_v,s T(X, q) - p*_s(T(X, q)),
+    T the temperature of the state after the transfers; a pair whose cloud
+    evaporated entirely sits on its bound X_s = -rho_c,s. By the implicit
+    function theorem dX/dq = -J^{-1} dG/dq over the pairs with cloud left
+    (J = dG/dX over those pairs), the bound pairs entering G through T with
+    their own derivative. The function returns the state after the transfers
+        X = X* - J*^{-1} G(X*, q)   (pairs with cloud left, J* = J at X*, fixed)
+        X = -rho_c                 (pairs on the bound),
+    whose value is the adjusted state (G(X*) vanishes at convergence) and whose
+    derivative is the implicit-function one. Padded layout like q; only the
+    species' tracers differ from q.
+    """
+    q = _t(q)
+    with torch.no_grad():
+        qa = saturation_adjust(q.detach(), grid, adjust)
+    qi = _interior(q, grid)
+    qai = _interior(qa, grid)
+    ns = len(adjust.species)
+    vi = [5 + sp.vapour for sp in adjust.species]
+    ci = [5 + sp.cloud for sp in adjust.species]
+    rvap = [vapour_gas_constant(grid, sp, adjust.rd) for sp in adjust.species]
+    xstar = [(qai[c] - qi[c]).detach() for c in ci]
+    bound = [qai[c] <= 0.0 for c in ci]          # cloud evaporated entirely
+    ek = qi[4] - 0.5 * (qi[1] * qi[1] + qi[2] * qi[2] + qi[3] * qi[3]) / qi[0]
+
+    def resid(state, e_k, X):
+        new = [state[m] for m in range(state.shape[0])]
+        for s in range(ns):
+            new[vi[s]] = state[vi[s]] - X[s]
+            new[ci[s]] = state[ci[s]] + X[s]
+        T = temperature_from_energy(torch.stack(new), grid, adjust.rd, e_k)
+        return [(state[vi[s]] - X[s]) * rvap[s] * T
+                - saturation_vapour_pressure(T, adjust.species[s]) for s in range(ns)]
+
+    # J* = dG/dX at X*, per cell, by autograd with the state held fixed
+    xr = [x.clone().requires_grad_(True) for x in xstar]
+    g0 = resid(qi.detach(), ek.detach(), xr)
+    rows = []
+    for s in range(ns):
+        grads = torch.autograd.grad(g0[s].sum(), xr, retain_graph=s + 1 < ns)
+        rows.append(torch.stack(grads, dim=-1))
+    J = torch.stack(rows, dim=-2)                # (..., s, j)
+    act = torch.stack([~b for b in bound], dim=-1)
+    both = act.unsqueeze(-1) & act.unsqueeze(-2)
+    eye = torch.eye(ns, dtype=F64).expand_as(J)
+    Jm = torch.where(both, J, torch.where(act.unsqueeze(-1), torch.zeros_like(J), eye))
+    # G at X* (pairs with cloud left) and at the bound (the others), with q live
+    xe = [torch.where(bound[s], -qi[ci[s]], xstar[s]) for s in range(ns)]
+    g = resid(qi, ek, xe)
+    gv = torch.stack([torch.where(bound[s], torch.zeros_like(g[s]), g[s]) for s in range(ns)],
+                     dim=-1)
+    corr = torch.linalg.solve(Jm.detach(), gv.unsqueeze(-1)).squeeze(-1)
+    out = q.clone()
+    oi = _interior(out, grid)
+    for s in range(ns):
+        X = torch.where(bound[s], -qi[ci[s]], xstar[s] - corr[..., s])
+        oi[vi[s]] = qi[vi[s]] - X
+        oi[ci[s]] = qi[ci[s]] + X
+    return out
+
+
+def saturation_adjust_adjoint(q, grid, adjust, q_bar) -> torch.Tensor:
+    """q_bar_in = (d adjusted state / d q)^T q_bar for the interior cells (both
+    in the interior layout (nvar, nz, ny, nx)); see saturation_adjust_diff."""
+    q = _t(q)
+    qi = _interior(q, grid).clone().requires_grad_(True)
+    out = saturation_adjust_diff(_with_interior(q.detach(), grid, qi), grid, adjust)
+    (g,) = torch.autograd.grad(_interior(out, grid), qi, _t(q_bar))
+    return g
+
+
 # ---------------------------------------------------------------------------
 # Discrete adjoint (torch autograd through the oracle)
 # ---------------------------------------------------------------------------

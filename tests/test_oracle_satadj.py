@@ -12,8 +12,14 @@ each vapour with its cloud at constant volume and total energy).
   capacities);
 * density, momentum and total energy are untouched; each pair's total is
   conserved; condensation warms and evaporation cools; adjusting twice
-  changes nothing; a state unsaturated without cloud is left as it is.
+  changes nothing; a state unsaturated without cloud is left as it is;
+* its derivative (the implicit-function form of saturation_adjust_diff)
+  matches central differences of the bisection, returns the cotangent of a
+  pair's total unchanged, and matches the closed form of a pair whose
+  transfer leaves the temperature alone.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -177,3 +183,90 @@ def test_unsaturated_without_cloud_is_unchanged():
         qi[5 + sp.cloud] = 0.0
     out = O.saturation_adjust(q, g, adj).numpy()
     assert np.array_equal(g.interior(out), g.interior(q))
+
+
+# ---------------------------------------------------------------------------
+# The derivative of the adjustment (saturation_adjust_diff / _adjoint): pinned
+# by central differences of the bisection itself, by the conservation of each
+# pair's total and by the closed form of a pair whose transfer leaves T alone.
+# ---------------------------------------------------------------------------
+
+def _tracer_cotangent(g, seed):
+    """A seeded cotangent on the tracers only: the five dynamic fields pass
+    through the adjustment unchanged, and E (~5e7) would drown the transfer's
+    part of a finite difference in rounding."""
+    qb = W.seeded_normal(g.interior_shape, seed)
+    qb[:5] = 0.0
+    return qb
+
+
+@pytest.mark.parametrize("seed", [5, 8])
+def test_adjoint_matches_central_differences(seed):
+    g, q, adj = column(nz=32, seed=seed)
+    qi = g.interior(q)
+    qb = _tracer_cotangent(g, seed + 40)
+    gb = O.saturation_adjust_adjoint(q, g, adj, qb).numpy()
+    rng = np.random.default_rng(seed)
+    h = 1e-6
+    for _ in range(3):
+        d = rng.normal(size=qi.shape) * np.abs(qi)     # relative perturbation of every field
+        qp, qm = q.copy(), q.copy()
+        g.interior(qp)[...] += h * d
+        g.interior(qm)[...] -= h * d
+        sp = g.interior(O.saturation_adjust(qp, g, adj).numpy())
+        sm = g.interior(O.saturation_adjust(qm, g, adj).numpy())
+        # the transfer's part: (S(q + h d) - S(q - h d)) / 2h minus d itself
+        fd = float(np.sum(qb * ((sp - sm) / (2 * h) - d)))
+        ad = float(np.sum(gb * d) - np.sum(qb * d))
+        print(f"seed {seed}: fd {fd:.10e} ad {ad:.10e}")
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+
+
+def test_adjoint_keeps_each_pairs_total():
+    """rho_v + rho_c of every pair leaves the adjustment unchanged, so a
+    cotangent of 1 on both members of a pair comes back as itself."""
+    g, q, adj = column(nz=24, seed=11)
+    qb = np.zeros(g.interior_shape)
+    for sp in adj.species[:1]:
+        qb[5 + sp.vapour] = 1.0
+        qb[5 + sp.cloud] = 1.0
+    gb = O.saturation_adjust_adjoint(q, g, adj, qb).numpy()
+    np.testing.assert_allclose(gb, qb, rtol=0, atol=1e-12)
+
+
+def test_adjoint_closed_form_when_the_transfer_leaves_T_alone():
+    """With cloud and vapour of equal heat capacity and chemical potential the
+    transfer does not change T, so where cloud remains X = rho_v - p*(T) /
+    (R_v T) with T(q) from the energy alone. The cotangent of the cloud is
+    then d(rho_c + X)/dq: 1 on rho_c, 1 on rho_v, and -d/dT[p*/(R_v T)] dT/dq
+    on the fields T depends on, with d/dT[p*/(R_v T)] = p* (lam - 1) / (R_v T^2),
+    lam = beta t_ref / T - delta (the logarithmic slope of p*). The oracle
+    evaluates dG/dT at the remaining vapour rho_v - X*, which carries the
+    rounding of that difference where most of the vapour condensed (up to
+    ~2e-7 of it here); the closed form uses p*(T) / (R_v T) instead, hence
+    the 1e-6 bar."""
+    g, q, adj = column(nz=32, seed=7)
+    sp = adj.species[0]
+    sig, mu = list(g.tracer_sigma), list(g.tracer_mu)
+    sig[sp.cloud], mu[sp.cloud] = sig[sp.vapour], mu[sp.vapour]
+    g = g.copy(tracer_sigma=tuple(sig), tracer_mu=tuple(mu))
+    adj1 = dataclasses.replace(adj, species=(sp,))
+    qb = np.zeros(g.interior_shape)
+    qb[5 + sp.cloud] = 1.0
+    gb = O.saturation_adjust_adjoint(q, g, adj1, qb).numpy()
+    qi = g.interior(q)
+    out = g.interior(O.saturation_adjust(q, g, adj1).numpy())
+    T = temperature_from_energy(g, qi)
+    rv = RD / g.tracer_eps[sp.vapour]
+    lam = sp.beta * sp.t_ref / T - sp.delta
+    dxdt = -psat(T, sp) * (lam - 1.0) / (rv * T * T)     # dX/dT
+    rho = qi[0]
+    heat = CVD * (rho - sum(qi[5 + t] for t in range(g.ntracer))
+                  + sum(sig[t] * qi[5 + t] for t in range(g.ntracer)))
+    wet = out[5 + sp.cloud] > 0.0
+    assert wet.sum() > 20 and (~wet).sum() > 20
+    # dT/dE = 1 / heat, dT/d(rho u) = -u / heat
+    np.testing.assert_allclose(gb[4][wet], (dxdt / heat)[wet], rtol=1e-6)
+    np.testing.assert_allclose(gb[1][wet], (-dxdt * qi[1] / rho / heat)[wet], rtol=1e-6)
+    # where the cloud evaporated entirely the output cloud is 0 whatever q is
+    assert np.all(gb[:, ~wet] == 0.0)
