@@ -381,7 +381,18 @@ def run_jovian_satadj(steps: int, warmup: int, repeats: int = 5):
         if r > 0:
             adj_ms += e0.elapsed_time(e1)
     adj_ms /= steps
-    del q0
+    # its adjoint (J^T in place on a seeded cotangent) from the same initial state
+    qbar = torch.randn(dg.interior_shape, dtype=torch.float32, device="cuda",
+                       generator=torch.Generator(device="cuda").manual_seed(19))
+    snap.snap_saturation_adjust_adjoint(dg, q0, params, qbar)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        snap.snap_saturation_adjust_adjoint(dg, q0, params, qbar)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_adjoint_ms = e0.elapsed_time(e1) / steps
+    del q0, qbar
 
     def step():
         snap.snap_rk3_step_cfl(dg, qd, CFL, work)
@@ -405,7 +416,7 @@ def run_jovian_satadj(steps: int, warmup: int, repeats: int = 5):
            "value": cells * steps / el, "unit": "cell-updates/s", "ms_per_step": el / steps * 1e3,
            "steps": steps, "repeats": repeats, "spread": _spread(times), "adjustment_ms": adj_ms,
            "adjustment_hbm_frac": byts / (adj_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-           "adjustment_share": adj_ms / (el / steps * 1e3)}
+           "adjustment_share": adj_ms / (el / steps * 1e3), "adjustment_adjoint_ms": adj_adjoint_ms}
     del qd, work
     torch.cuda.empty_cache()
     return out

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SNAP_ABI_VERSION 12
+#define SNAP_ABI_VERSION 13
 
 /* return codes */
 #define SNAP_OK 0
@@ -550,6 +550,29 @@ typedef struct snap_satadj {
 } snap_satadj;
 
 int snap_saturation_adjust(const snap_grid* g, void* q, const snap_satadj* s, void* stream);
+
+/*
+ * Adjoint of snap_saturation_adjust (App. D): q_bar <- J^T q_bar, J the
+ * derivative of the adjusted state with respect to the state before the
+ * adjustment, per interior cell. The adjustment is recomputed; at its
+ * equilibrium each pair with cloud left satisfies the condition above, and its
+ * transfer x enters through the implicit-function derivative of that
+ * condition (the pairs coupled through T: a diagonal plus rank-one system,
+ * solved in closed form); a pair whose cloud evaporated entirely follows its
+ * bound x = -rho_c. The result is the transpose of the exact derivative of the
+ * equilibrium once the sweeps have converged. Double-precision arithmetic
+ * whatever the storage type.
+ *
+ * g, s   as for snap_saturation_adjust (the same validation).
+ * q      padded state BEFORE the adjustment (interior read; ghost layers not
+ *        read).
+ * q_bar  interior array [nvar][nz][ny][nx] of the storage type: in, the
+ *        cotangent of the adjusted state; out, that of the state before it
+ *        (overwritten in place); must not alias q.
+ * Returns SNAP_E_INVALID for any other input; no workspace is needed.
+ */
+int snap_saturation_adjust_adjoint(const snap_grid* g, const void* q, const snap_satadj* s,
+                                   void* q_bar, void* stream);
 
 /*
  * Benchmark instrumentation of the fused stage kernel (the kernel that

@@ -31,7 +31,8 @@ __all__ = [
     "SNAP_OP_RHS", "SNAP_OP_RK3", "SNAP_OP_CFL", "SNAP_OP_SUMS",
     "SNAP_EOS_PASSIVE", "SNAP_EOS_MIXTURE", "SNAP_TRACER_VAPOUR", "SNAP_TRACER_CONDENSATE",
     "SNAP_RIEMANN_LMARS", "SNAP_RIEMANN_HLLC", "SNAP_STORE_TOTAL", "SNAP_STORE_PERTURBATION",
-    "snap_kessler_step", "snap_kessler_step_adjoint", "kessler_params", "snap_saturation_adjust", "satadj_params",
+    "snap_kessler_step", "snap_kessler_step_adjoint", "kessler_params", "snap_saturation_adjust",
+    "snap_saturation_adjust_adjoint", "satadj_params",
 ]
 
 PKG = os.path.dirname(os.path.abspath(__file__))
@@ -49,7 +50,7 @@ SNAP_BC_PERIODIC = 0
 SNAP_BC_REFLECT = 1
 SNAP_NG = 3
 SNAP_MAX_TRACERS = 8
-SNAP_ABI_VERSION = 12
+SNAP_ABI_VERSION = 13
 SNAP_EOS_PASSIVE = 0
 SNAP_EOS_MIXTURE = 1
 SNAP_RIEMANN_LMARS = 0
@@ -172,6 +173,7 @@ _SIGNATURES = {
     "snap_kessler_step_adjoint": (ctypes.c_int, [_GP, _P, ctypes.c_double, ctypes.POINTER(SnapKesslerC),
                                                  _P, _P]),
     "snap_saturation_adjust": (ctypes.c_int, [_GP, _P, ctypes.POINTER(SnapSatAdjC), _P]),
+    "snap_saturation_adjust_adjoint": (ctypes.c_int, [_GP, _P, ctypes.POINTER(SnapSatAdjC), _P, _P]),
     "snap_stage_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "snap_stage_timing_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),
@@ -577,3 +579,15 @@ def snap_saturation_adjust(grid: DeviceGrid, q: torch.Tensor, adjust, stream=Non
     params = adjust if isinstance(adjust, SnapSatAdjC) else satadj_params(adjust)
     _check(lib().snap_saturation_adjust(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
                                         ctypes.byref(params), _stream(stream)))
+
+
+def snap_saturation_adjust_adjoint(grid: DeviceGrid, q: torch.Tensor, adjust, q_bar: torch.Tensor,
+                                   stream=None) -> None:
+    """q_bar <- J^T q_bar for the saturation adjustment of the state q (the
+    state before the adjustment; q_bar: interior layout, in place)."""
+    grid._check_state(q)
+    grid._check_state(q_bar, "q_bar", grid.interior_shape)
+    params = adjust if isinstance(adjust, SnapSatAdjC) else satadj_params(adjust)
+    _check(lib().snap_saturation_adjust_adjoint(grid.ptr(), ctypes.c_void_p(q.data_ptr()),
+                                                ctypes.byref(params), ctypes.c_void_p(q_bar.data_ptr()),
+                                                _stream(stream)))

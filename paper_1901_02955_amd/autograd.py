@@ -16,7 +16,9 @@ without a re-run.
 ``kessler_step(grid, q, dt, kessler)`` is the Kessler microphysics step
 (Sec. 3, ``snap_kessler_step``) under autograd, back-propagated with
 ``snap_kessler_step_adjoint``; it composes with ``rk3_run`` for operator-split
-dynamics and microphysics.
+dynamics and microphysics. ``saturation_adjust(grid, q, adjust)`` is the
+saturation adjustment (App. D, ``snap_saturation_adjust``) the same way, with
+``snap_saturation_adjust_adjoint``.
 
 Only the interior of the state carries gradients: the library overwrites ghost
 layers from the interior on every call, so the gradient with respect to the
@@ -27,9 +29,10 @@ from __future__ import annotations
 
 import torch
 
-from . import (SNAP_NG, SNAP_OP_RK3, SNAP_OP_RK3_ADJ, DeviceGrid, SnapKesslerC, kessler_params,
-               snap_kessler_step, snap_kessler_step_adjoint, snap_rk3_step,
-               snap_rk3_step_adjoint, snap_rk3_step_adjoint_stages, workspace)
+from . import (SNAP_NG, SNAP_OP_RK3, SNAP_OP_RK3_ADJ, DeviceGrid, SnapKesslerC, SnapSatAdjC,
+               kessler_params, satadj_params, snap_kessler_step, snap_kessler_step_adjoint,
+               snap_rk3_step, snap_rk3_step_adjoint, snap_rk3_step_adjoint_stages,
+               snap_saturation_adjust, snap_saturation_adjust_adjoint, workspace)
 
 
 def _interior(grid: DeviceGrid, q: torch.Tensor) -> torch.Tensor:
@@ -147,3 +150,31 @@ def kessler_step(grid: DeviceGrid, q: torch.Tensor, dt: float, kessler) -> torch
     with respect to ``q`` (the step's adjoint, within the interior)."""
     params = kessler if isinstance(kessler, SnapKesslerC) else kessler_params(kessler)
     return _SnapKesslerStep.apply(q, grid, dt, params)
+
+
+class _SnapSaturationAdjust(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q: torch.Tensor, grid: DeviceGrid, params):
+        q0 = q.detach().clone()
+        out = q0.clone()
+        snap_saturation_adjust(grid, out, params)
+        ctx.grid, ctx.params = grid, params
+        ctx.save_for_backward(q0)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_out: torch.Tensor):
+        (q0,) = ctx.saved_tensors
+        grid = ctx.grid
+        qb = _interior(grid, g_out).contiguous().clone()
+        snap_saturation_adjust_adjoint(grid, q0, ctx.params, qb)
+        g_in = torch.zeros_like(g_out)
+        _interior(grid, g_in).copy_(qb)
+        return g_in, None, None
+
+
+def saturation_adjust(grid: DeviceGrid, q: torch.Tensor, adjust) -> torch.Tensor:
+    """Padded state after the saturation adjustment, differentiable with respect
+    to ``q`` (the adjustment's adjoint, within the interior)."""
+    params = adjust if isinstance(adjust, SnapSatAdjC) else satadj_params(adjust)
+    return _SnapSaturationAdjust.apply(q, grid, params)

@@ -1095,10 +1095,7 @@ int snap_kessler_step_adjoint(const snap_grid* g, const void* q, double dt, cons
   return ok();
 }
 
-int snap_saturation_adjust(const snap_grid* g, void* q, const snap_satadj* sa, void* stream) {
-  int r = check_grid(g);
-  if (r) return r;
-  if (!q || !sa) return fail(SNAP_E_INVALID, "q or s is NULL");
+static int satadj_args(const snap_grid* g, const snap_satadj* sa, SatAdjArgs& a) {
   if (!uses_mixture(g))
     return fail(SNAP_E_INVALID, "the adjustment needs eos = SNAP_EOS_MIXTURE and tracers");
   if (sa->nspecies < 1 || sa->nspecies > SNAP_SATADJ_MAX_SPECIES)
@@ -1106,7 +1103,6 @@ int snap_saturation_adjust(const snap_grid* g, void* q, const snap_satadj* sa, v
   if (!finite_pos(sa->rd)) return fail(SNAP_E_INVALID, "rd must be finite and > 0");
   if (sa->max_iter < 1 || sa->max_iter > 100) return fail(SNAP_E_INVALID, "max_iter must lie in [1, 100]");
   if (!isfinite(sa->tol) || sa->tol < 0.0) return fail(SNAP_E_INVALID, "tol must be finite and >= 0");
-  SatAdjArgs a;
   memset(&a, 0, sizeof a);
   bool used[SNAP_MAX_TRACERS] = {false};
   for (int sidx = 0; sidx < sa->nspecies; ++sidx) {
@@ -1153,8 +1149,30 @@ int snap_saturation_adjust(const snap_grid* g, void* q, const snap_satadj* sa, v
     a.mu[t] = g->tracer_mu[t];
   }
   if ((long long)g->ny * g->nz > 0x7fffffffLL) return fail(SNAP_E_INVALID, "ny nz too large");
+  return 0;
+}
+
+int snap_saturation_adjust(const snap_grid* g, void* q, const snap_satadj* sa, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !sa) return fail(SNAP_E_INVALID, "q or s is NULL");
+  SatAdjArgs a;
+  if ((r = satadj_args(g, sa, a))) return r;
   if (launch_satadj(g->dtype, g->ntracer, q, a, (hipStream_t)stream))
     return device_fail("saturation adjustment kernel launch");
+  return ok();
+}
+
+int snap_saturation_adjust_adjoint(const snap_grid* g, const void* q, const snap_satadj* sa,
+                                   void* q_bar, void* stream) {
+  int r = check_grid(g);
+  if (r) return r;
+  if (!q || !sa || !q_bar) return fail(SNAP_E_INVALID, "q, s or q_bar is NULL");
+  if (q_bar == q) return fail(SNAP_E_INVALID, "q_bar must not alias q");
+  SatAdjArgs a;
+  if ((r = satadj_args(g, sa, a))) return r;
+  if (launch_satadj_adj(g->dtype, g->ntracer, q, q_bar, a, (hipStream_t)stream))
+    return device_fail("saturation adjustment adjoint kernel launch");
   return ok();
 }
 

@@ -134,6 +134,8 @@ int launch_kessler(int dtype, int ntracer, void* q, const KesslerArgs& a, hipStr
 int launch_kessler_adj(int dtype, int ntracer, const void* q, void* qb, const KesslerArgs& a,
                        hipStream_t st);
 int launch_satadj(int dtype, int ntracer, void* q, const SatAdjArgs& a, hipStream_t st);
+int launch_satadj_adj(int dtype, int ntracer, const void* q, void* qb, const SatAdjArgs& a,
+                      hipStream_t st);
 int launch_sediment(int dtype, int ntracer, const StageArgs& a, hipStream_t st);
 int launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 int launch_flag_speed(const unsigned long long* smax, unsigned long long* flag, hipStream_t st);

@@ -281,27 +281,12 @@ __global__ void __launch_bounds__(256) k_kessler_adj(const T* __restrict__ q, T*
 // double-precision arithmetic. The energy available as heat, E - K - sum mu
 // rho, and the heat capacity c_vd (rho_d + sum sigma rho) are carried as
 // running sums and updated with every transfer; T is their ratio.
-// grid: x over interior rows (nz ny), y over the interior row
-template <typename T, int NT>
-__global__ void __launch_bounds__(256) k_satadj(T* __restrict__ q, SatAdjArgs a) {
-  constexpr int NV = 5 + NT;
-  const int i = blockIdx.y * 256 + threadIdx.x;
-  if (i >= a.nx) return;
-  const int row = blockIdx.x;
-  const int j = row % a.ny, k = row / a.ny;
-  const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
-  double c[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = static_cast<double>(q[o + v * a.sv]);
-  const double rho = c[0];
-  const double heat0 = c[4] - 0.5 * (c[1] * c[1] + c[2] * c[2] + c[3] * c[3]) / rho;
-  double chem = 0.0, cap = rho;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    chem += a.mu[t] * c[5 + t];
-    cap += (a.sigma[t] - 1.0) * c[5 + t];
-  }
-  cap *= a.cvd;
+// satadj_iterate adjusts the conserved values c of one cell in place, given
+// heat0 = E - K, and leaves chem = sum mu rho and cap = c_vd (rho_d + sum sigma
+// rho) of the adjusted composition.
+template <int NT>
+__device__ __forceinline__ void satadj_iterate(double (&c)[5 + NT], const SatAdjArgs& a,
+                                               double heat0, double& chem, double& cap) {
   for (int it = 0; it < a.max_iter; ++it) {
     double moved = 0.0;
 #pragma unroll
@@ -335,8 +320,124 @@ __global__ void __launch_bounds__(256) k_satadj(T* __restrict__ q, SatAdjArgs a)
     }
     if (moved <= a.tol) break;
   }
+}
+
+// E - K and the initial chem and cap of one cell's conserved values.
+template <int NT>
+__device__ __forceinline__ double satadj_heat(const double (&c)[5 + NT], const SatAdjArgs& a,
+                                              double& chem, double& cap) {
+  chem = 0.0;
+  cap = c[0];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    chem += a.mu[t] * c[5 + t];
+    cap += (a.sigma[t] - 1.0) * c[5 + t];
+  }
+  cap *= a.cvd;
+  return c[4] - 0.5 * (c[1] * c[1] + c[2] * c[2] + c[3] * c[3]) / c[0];
+}
+
+// grid: x over interior rows (nz ny), y over the interior row
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_satadj(T* __restrict__ q, SatAdjArgs a) {
+  constexpr int NV = 5 + NT;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, k = row / a.ny;
+  const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+  double c[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = static_cast<double>(q[o + v * a.sv]);
+  double chem, cap;
+  const double heat0 = satadj_heat<NT>(c, a, chem, cap);
+  satadj_iterate<NT>(c, a, heat0, chem, cap);
 #pragma unroll
   for (int t = 0; t < NT; ++t) q[o + (5 + t) * a.sv] = static_cast<T>(c[5 + t]);
+}
+
+// Adjoint of the saturation adjustment: qb <- J^T qb for the cells' conserved
+// values (qb in the interior layout), J the derivative of the adjusted state
+// with respect to the state before it, by the implicit-function theorem at the
+// equilibrium that k_satadj reaches (recomputed here).
+// Per pair s the transfer X_s (mass moved from vapour to cloud) either keeps
+// cloud, and then solves G_s = (rho_v0 - X_s) R_v T - p*(T) = 0 with T =
+// (E - K - sum mu rho - sum_j X_j dmu_j) / (cap0 + sum_j X_j dcap_j), or sits
+// on its bound X_s = -rho_c0 (the cloud evaporated). Over the pairs A with
+// cloud left, dG/dX = -diag(a) + g t^T with a_s = R_v T, g_s = dG_s/dT and t_j =
+// dT/dX_j, a diagonal plus a rank-one term, so the transposed system has the
+// closed form
+//   gamma = (sum_A g_s Xb_s / a_s) / (1 - sum_A g_s t_s / a_s),
+//   lambda_s a_s = t_s gamma + Xb_s,
+// Xb_s = qb[cloud] - qb[vapour] the transfer's cotangent. gamma is the
+// cotangent of T (held at fixed X), lambda_s a_s that of rho_v0 through G_s,
+// and a bound pair's transfer cotangent Xb_s + gamma t_s goes to -rho_c0.
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_satadj_adj(const T* __restrict__ q, T* __restrict__ qb,
+                                                    SatAdjArgs a) {
+  constexpr int NV = 5 + NT;
+  constexpr int NS = MAX_TRACERS / 2;
+  const int i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= a.nx) return;
+  const int row = blockIdx.x;
+  const int j = row % a.ny, k = row / a.ny;
+  const long long o = (long long)(k + NG) * a.sz + (long long)(j + a.gy) * a.sy + (i + NG);
+  const long long rv = (long long)a.nx * a.ny * a.nz;
+  const long long ro = (long long)row * a.nx + i;
+  double c[NV], cf[NV], cb[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    c[v] = static_cast<double>(q[o + v * a.sv]);
+    cf[v] = c[v];
+    cb[v] = static_cast<double>(qb[ro + v * rv]);
+  }
+  double chem, cap;
+  const double heat0 = satadj_heat<NT>(c, a, chem, cap);
+  satadj_iterate<NT>(cf, a, heat0, chem, cap);
+  const double temp = (heat0 - chem) / cap;
+  double xb[NS], ts[NS];
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s >= a.nspecies) break;
+    const SatAdjSpec& sp = a.s[s];
+    xb[s] = tracer(cb, sp.c) - tracer(cb, sp.v);
+    const double dmu = tracer_of(a.mu, sp.c) - tracer_of(a.mu, sp.v);
+    const double dcap = a.cvd * (tracer_of(a.sigma, sp.c) - tracer_of(a.sigma, sp.v));
+    ts[s] = -(dmu + temp * dcap) / cap;
+    if (tracer(cf, sp.c) > 0.0) {
+      const double tt = temp / sp.t_ref;
+      const double lam = sp.beta / tt - sp.delta;
+      const double pstar = sp.p_ref * exp(sp.beta * (1.0 - 1.0 / tt) - sp.delta * log(tt));
+      const double as = sp.rv * temp;
+      const double gs = tracer(cf, sp.v) * sp.rv - pstar * lam / temp;
+      num += gs * xb[s] / as;
+      den += gs * ts[s] / as;
+    }
+  }
+  const double gam = num / (1.0 - den);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    if (s >= a.nspecies) break;
+    const SatAdjSpec& sp = a.s[s];
+    if (tracer(cf, sp.c) > 0.0)
+      set_tracer(cb, sp.v, tracer(cb, sp.v) + ts[s] * gam + xb[s]);
+    else
+      set_tracer(cb, sp.c, tracer(cb, sp.c) - (xb[s] + gam * ts[s]));
+  }
+  // T at fixed transfers: numerator E - K - sum mu rho, denominator cap
+  const double nb = gam / cap, db = -gam * temp / cap;
+  const double irho = 1.0 / c[0];
+  const double u = c[1] * irho, v = c[2] * irho, w = c[3] * irho;
+  cb[4] += nb;
+  cb[1] -= nb * u;
+  cb[2] -= nb * v;
+  cb[3] -= nb * w;
+  cb[0] += nb * 0.5 * (u * u + v * v + w * w) + db * a.cvd;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) cb[5 + t] += db * a.cvd * (a.sigma[t] - 1.0) - nb * a.mu[t];
+#pragma unroll
+  for (int m = 0; m < NV; ++m) qb[ro + m * rv] = static_cast<T>(cb[m]);
 }
 
 // Sedimentation part of the right-hand side (from the stage input Qs, ghosts
@@ -507,6 +608,35 @@ int launch_satadj_t(int ntracer, T* q, const SatAdjArgs& a, hipStream_t st) {
 int launch_satadj(int dtype, int ntracer, void* q, const SatAdjArgs& a, hipStream_t st) {
   return dtype == 0 ? launch_satadj_t<double>(ntracer, static_cast<double*>(q), a, st)
                     : launch_satadj_t<float>(ntracer, static_cast<float*>(q), a, st);
+}
+
+template <typename T>
+int launch_satadj_adj_t(int ntracer, const T* q, T* qb, const SatAdjArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)(a.ny * a.nz), (unsigned)((a.nx + 255) / 256));
+  switch (ntracer) {
+#define SNAP_SATADJ_ADJ_CASE(N)                                                     \
+  case N:                                                                           \
+    hipLaunchKernelGGL((k_satadj_adj<T, N>), grid, dim3(256), 0, st, q, qb, a);     \
+    break;
+    SNAP_SATADJ_ADJ_CASE(2)
+    SNAP_SATADJ_ADJ_CASE(3)
+    SNAP_SATADJ_ADJ_CASE(4)
+    SNAP_SATADJ_ADJ_CASE(5)
+    SNAP_SATADJ_ADJ_CASE(6)
+    SNAP_SATADJ_ADJ_CASE(7)
+    SNAP_SATADJ_ADJ_CASE(8)
+#undef SNAP_SATADJ_ADJ_CASE
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_satadj_adj(int dtype, int ntracer, const void* q, void* qb, const SatAdjArgs& a,
+                      hipStream_t st) {
+  return dtype == 0 ? launch_satadj_adj_t<double>(ntracer, static_cast<const double*>(q),
+                                                  static_cast<double*>(qb), a, st)
+                    : launch_satadj_adj_t<float>(ntracer, static_cast<const float*>(q),
+                                                 static_cast<float*>(qb), a, st);
 }
 
 }  // namespace snap

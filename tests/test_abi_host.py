@@ -42,7 +42,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert not missing, f"declared but not exported: {missing}"
     for f in decl:
         getattr(lib, f)
-    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 12
+    assert lib.snap_abi_version() == snap.SNAP_ABI_VERSION == 13
 
 
 def good_grid(**kw):
@@ -385,6 +385,25 @@ def test_saturation_adjust_rejects_bad_parameters(kw):
     a = _satadj(**kw)
     assert lib.snap_saturation_adjust(g, ctypes.c_void_p(FAKE), ctypes.byref(a), None) == snap.SNAP_E_INVALID
     assert lib.snap_last_error().decode()
+    # the adjoint validates the same parameters before any launch
+    assert lib.snap_saturation_adjust_adjoint(g, ctypes.c_void_p(FAKE), ctypes.byref(a),
+                                              ctypes.c_void_p(FAKE + 4096), None) == snap.SNAP_E_INVALID
+    assert lib.snap_last_error().decode()
+
+
+def test_saturation_adjust_adjoint_rejects_bad_arguments():
+    lib = snap.lib()
+    a = _satadj()
+    P, Q = ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE + 4096)
+    passive = ctypes.byref(_kessler_grid(eos=0))
+    assert lib.snap_saturation_adjust_adjoint(passive, P, ctypes.byref(a), Q, None) == snap.SNAP_E_INVALID
+    assert b"MIXTURE" in lib.snap_last_error()
+    g = ctypes.byref(_kessler_grid())
+    assert lib.snap_saturation_adjust_adjoint(g, None, ctypes.byref(a), Q, None) == snap.SNAP_E_INVALID
+    assert lib.snap_saturation_adjust_adjoint(g, P, None, Q, None) == snap.SNAP_E_INVALID
+    assert lib.snap_saturation_adjust_adjoint(g, P, ctypes.byref(a), None, None) == snap.SNAP_E_INVALID
+    assert lib.snap_saturation_adjust_adjoint(g, P, ctypes.byref(a), P, None) == snap.SNAP_E_INVALID
+    assert b"alias" in lib.snap_last_error()
 
 
 def test_saturation_adjust_needs_the_mixture():

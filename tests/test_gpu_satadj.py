@@ -104,3 +104,94 @@ def test_satadj_twice_moves_nothing_and_is_deterministic(cases):
         tot = once[5 + sp.vapour] + once[5 + sp.cloud]
         d = np.abs(twice[5 + sp.cloud] - once[5 + sp.cloud]) / np.where(tot > 0, tot, 1.0)
         assert float(d.max()) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Adjoint (snap_saturation_adjust_adjoint) against the oracle's implicit-
+# function derivative at the bisection's equilibrium. Both evaluate dG/dT at
+# the remaining vapour, a difference that loses digits where nearly all of it
+# condensed (about 1e-7 of the derivative in those cells, see the oracle's
+# pins); per field, normalised by its largest magnitude, the bar is 1e-9 in
+# double precision. FP32 storage: the oracle at the FP32-rounded inputs, bar
+# 1e-5 (the output rounding and the inputs' sensitivity).
+# ---------------------------------------------------------------------------
+
+def run_adjoint(g, q, adj, qbar, dtype):
+    dg = snap.device_grid(g, dtype=dtype)
+    qd = torch.as_tensor(q).to(dtype).cuda()
+    qb = torch.as_tensor(qbar).to(dtype).cuda().contiguous()
+    snap.snap_saturation_adjust_adjoint(dg, qd, adj, qb)
+    return qb
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_satadj_adjoint_fp64(cases, name):
+    g, q, adj = cases[name]
+    print(f"[satadj] adjoint fp64 {name}", flush=True)
+    qbar = wl.seeded_normal(g.interior_shape, 150)
+    got = run_adjoint(g, q, adj, qbar, torch.float64).cpu().numpy()
+    ref = oracle.saturation_adjust_adjoint(q, g, adj, qbar).numpy()
+    errs = field_errors(got, ref)
+    moved = [float(np.max(np.abs(ref[m] - qbar[m])) / np.max(np.abs(ref[m]))) for m in range(g.nvar)]
+    print("   errors", ["%.2e" % e for e in errs], " vs identity", ["%.1e" % m for m in moved],
+          flush=True)
+    assert all(e <= 1e-9 for e in errs), errs
+    assert max(moved) > 1e-3
+
+
+@pytest.mark.parametrize("name", ["column_3d_6x5x48", "slab_2d_40x1x36"])
+def test_satadj_adjoint_fp32(cases, name):
+    g, q, adj = cases[name]
+    print(f"[satadj] adjoint fp32 {name}", flush=True)
+    q32 = torch.as_tensor(q).float().double().numpy()
+    qbar = wl.seeded_normal(g.interior_shape, 151).astype(np.float32).astype(np.float64)
+    got = run_adjoint(g, q32, adj, qbar, torch.float32).cpu().double().numpy()
+    ref = oracle.saturation_adjust_adjoint(q32, g, adj, qbar).numpy()
+    errs = field_errors(got, ref)
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-5 for e in errs), errs
+
+
+def test_satadj_adjoint_deterministic_and_leaves_q(cases):
+    g, q, adj = cases["column_3d_9x7x64"]
+    dg = snap.device_grid(g)
+    qd = torch.as_tensor(q).cuda()
+    q_before = qd.clone()
+    qbar = torch.as_tensor(wl.seeded_normal(g.interior_shape, 152)).cuda()
+    a, b = qbar.clone(), qbar.clone()
+    snap.snap_saturation_adjust_adjoint(dg, qd, adj, a)
+    snap.snap_saturation_adjust_adjoint(dg, qd, adj, b)
+    assert torch.equal(a, b)
+    assert torch.equal(qd, q_before)
+
+
+def test_dynamics_plus_adjustment_gradient(cases):
+    """Gradient of a loss after one RK3 step and the saturation adjustment
+    (autograd through rk3_run and saturation_adjust, i.e. the library's RK3
+    and adjustment adjoints) against autograd through the oracle's step and
+    its differentiable adjustment. The column is set in motion first (a
+    seeded wind of a few m/s, its kinetic energy added to E so that T is
+    unchanged): at rest the Riemann solver's upwind side follows rounding, and
+    so would the step's derivative."""
+    from paper_1901_02955_amd.autograd import rk3_run, saturation_adjust
+    g, q, adj = cases["column_3d_6x5x48"]
+    q = q.copy()
+    qi = g.interior(q)
+    wind = 3.0 * wl.seeded_normal((3,) + qi.shape[1:], 154)
+    qi[1:4] = qi[0] * wind
+    qi[4] += 0.5 * qi[0] * (wind * wind).sum(axis=0)
+    print("[satadj] gradient through rk3 + adjustment", flush=True)
+    dt = 0.5 * oracle.cfl_dt(q, g, 0.9)
+    w = wl.seeded_normal(g.interior_shape, 153)
+    dg = snap.device_grid(g)
+    q0 = torch.as_tensor(q).cuda().requires_grad_(True)
+    out = saturation_adjust(dg, rk3_run(dg, q0, dt, 1, 1), adj)
+    (g.interior(out) * torch.as_tensor(w).cuda()).sum().backward()
+    got = g.interior(q0.grad.cpu().numpy())
+    qq = torch.as_tensor(q).clone().requires_grad_(True)
+    ref_out = oracle.saturation_adjust_diff(oracle.rk3_step(qq, g, dt), g, adj)
+    (g.interior(ref_out) * torch.as_tensor(w)).sum().backward()
+    ref = g.interior(qq.grad.numpy())
+    errs = field_errors(got, ref)
+    print("   errors", ["%.2e" % e for e in errs], flush=True)
+    assert all(e <= 1e-9 for e in errs), errs
