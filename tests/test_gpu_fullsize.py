@@ -17,6 +17,9 @@ benchmark times (the same grids, element types, tile shapes and z-chunks):
 * the Jovian column with six tracers and falling rain: the right-hand side
   with the sedimentation terms (blocks away from the walls), and the Kessler
   step on the benchmark's own state (sampled blocks);
+* the adjoints of the Kessler step and of the saturation adjustment on the
+  benchmarks' own states with a full-size cotangent (sampled blocks: both are
+  pointwise, so a block's cotangent depends on the block alone);
 * the benchmark's ensemble of 64 bubbles: every tile variant batched against
   separate steps, and the 2-D right-hand side at each member size against the
   oracle cell by cell.
@@ -280,6 +283,73 @@ def test_kessler_fullsize_fp32(jovian_kessler):
         print(f"   tracer {m - 5}: error / max|ref| {err / scale:.2e}, change {moved / scale:.1e}",
               flush=True)
         assert err <= 1e-6 * scale, (m, err / scale)
+
+
+def pattern_cotangent(shape, device="cpu", origin=(0, 0, 0)):
+    """A seeded cotangent of small exact values, ((7 i + 13 j + 29 k + 31 m) mod
+    17 - 8) / 8 at variable m and interior cell (i, j, k) (offset by origin),
+    identical in FP32 on the device and in FP64 on the host, so a sampled
+    block of the full-size array can be rebuilt without storing it."""
+    nv, nz, ny, nx = shape
+    i0, j0, k0 = origin
+    m = torch.arange(nv, device=device).view(nv, 1, 1, 1)
+    k = torch.arange(k0, k0 + nz, device=device).view(1, nz, 1, 1)
+    j = torch.arange(j0, j0 + ny, device=device).view(1, 1, ny, 1)
+    i = torch.arange(i0, i0 + nx, device=device).view(1, 1, 1, nx)
+    return (((7 * i + 13 * j + 29 * k + 31 * m) % 17) - 8).to(torch.float32) / 8.0
+
+
+def check_pointwise_adjoint(grid, q, run_gpu, run_oracle, tag):
+    """A pointwise operation's adjoint on the full FP32 state with the pattern
+    cotangent, against the oracle's on sampled blocks (every cell's cotangent
+    depends on that cell alone): within 1e-5 of each field's largest magnitude."""
+    qt = torch.as_tensor(q).float()
+    dg = snap.device_grid(grid, dtype=torch.float32)
+    qd = qt.cuda()
+    qb = pattern_cotangent(dg.interior_shape, device="cuda").contiguous()
+    print(f"[fullsize] {tag} adjoint {grid.nx}x{grid.ny}x{grid.nz} nvar {grid.nvar} fp32", flush=True)
+    run_gpu(dg, qd, qb)
+    got, ref = [], []
+    for (i0, j0, k0) in sample_blocks(grid):
+        blk = padded_block(qt.double(), i0, j0, k0, B)
+        qbb = pattern_cotangent((grid.nvar, B, B, B), origin=(i0, j0, k0)).double().numpy()
+        ref.append(run_oracle(blk, sub_grid(grid, k0, B), qbb).reshape(grid.nvar, -1).numpy())
+        got.append(qb[:, k0:k0 + B, j0:j0 + B, i0:i0 + B].double().cpu().reshape(grid.nvar, -1)
+                   .numpy())
+    del qd, qb
+    torch.cuda.empty_cache()
+    ref, got = np.concatenate(ref, axis=1), np.concatenate(got, axis=1)
+    for m in range(grid.nvar):
+        scale = float(np.max(np.abs(ref[m])))
+        err = float(np.max(np.abs(got[m] - ref[m])))
+        print(f"   field {m}: error / max|ref| {err / scale:.2e}", flush=True)
+        assert err <= 1e-5 * scale, (m, err / scale)
+
+
+def test_kessler_adjoint_fullsize_fp32(jovian_kessler):
+    """The Kessler step's adjoint on the benchmark's own state and a full-size
+    cotangent, against the oracle's autograd on sampled blocks."""
+    grid, q, kes = jovian_kessler
+    dt = 0.5
+
+    def run_oracle(blk, sg, qbb):
+        x = oracle.snap_oracle._interior(blk, sg).clone().requires_grad_(True)
+        out = oracle.kessler_step(oracle.snap_oracle._with_interior(blk, sg, x), sg, dt, kes)
+        (g,) = torch.autograd.grad(oracle.snap_oracle._interior(out, sg), x, torch.as_tensor(qbb))
+        return g
+
+    check_pointwise_adjoint(grid, q, lambda dg, qd, qb: snap.snap_kessler_step_adjoint(dg, qd, dt, kes, qb),
+                            run_oracle, "kessler")
+
+
+def test_saturation_adjust_adjoint_fullsize_fp32():
+    """The saturation adjustment's adjoint on the benchmark's own state and a
+    full-size cotangent, against the oracle's implicit-function derivative on
+    sampled blocks."""
+    grid, q, adj = wl.jovian_satadj_3d()
+    check_pointwise_adjoint(
+        grid, q, lambda dg, qd, qb: snap.snap_saturation_adjust_adjoint(dg, qd, adj, qb),
+        lambda blk, sg, qbb: oracle.saturation_adjust_adjoint(blk, sg, adj, qbb), "saturation adjustment")
 
 
 def test_ensemble_fullsize_batched_equals_separate():
