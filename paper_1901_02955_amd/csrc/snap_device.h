@@ -292,7 +292,9 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool 
 }
 
 // ---------------------------------------------------------------------------
-// LMARS flux at one face (Sec. 4.1, eqs. rp and ru).
+// LMARS flux at one face (Sec. 4.1, eqs. rp and ru), returned DOUBLED: f is
+// twice the face flux (the callers scale the flux differences by half the
+// inverse spacing, see flux_scale), which saves the halvings below.
 //
 // xl, xr   reconstructed primitive face states (layout above) on the left and
 //          right side; density and pressure are perturbations.
@@ -300,14 +302,15 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, bool 
 // rref, pref  reference density and pressure of the face; full values are
 //          rho = rref + rho', p = pref + p'.
 // Sound speed c = sqrt(gamma p / rho) from full face values; the acoustic
-// impedance rho c is the product of the side averages of rho and c. The
-// interface pressure and velocity use the perturbation pressure:
-//   p* = (p'_L + p'_R)/2 - (rho c)/2 (u_R - u_L)
-//   u* = (u_L + u_R)/2 - (p'_R - p'_L) / (2 rho c)
+// impedance rho c is the product of the side averages of rho and c, so with
+// RC = (rho_L + rho_R)(c_L + c_R) = 4 rho c the doubled interface pressure and
+// velocity are (perturbation pressure):
+//   2 p* = (p'_L + p'_R) - (RC / 4) (u_R - u_L)
+//   2 u* = (u_L + u_R) - 4 (p'_R - p'_L) / RC
 // The advected vector (rho, rho u, rho v, rho w, E + p, rho q_i) comes from the
 // upwind side (left if u* > 0, else right; at u* == 0 every advective term is
-// zero, so the side does not matter); p* is added to the normal momentum flux.
-// ---------------------------------------------------------------------------
+// zero, so the side does not matter), with E + p = p gamma / (gamma - 1) +
+// rho |u|^2 / 2; 2 p* is added to the normal momentum flux.
 template <typename T, int NV>
 __device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV], int nrm, T rref,
                                            T pref, T gamma, T inv_gm1, T (&f)[NV]) {
@@ -316,25 +319,25 @@ __device__ __forceinline__ void lmars_flux(const T (&xl)[NV], const T (&xr)[NV],
   const T unl = xl[nrm], unr = xr[nrm];
   const T cl = sound_speed(gamma * pl, rl);
   const T cr = sound_speed(gamma * pr, rr);
-  const T rc = T(0.25) * ((rl + rr) * (cl + cr));
-  const T pstar = T(0.5) * (xl[4] + xr[4]) - T(0.5) * rc * (unr - unl);
-  const T ustar = T(0.5) * (unl + unr) - (xr[4] - xl[4]) * (T(0.5) * rcp_fast(rc));
-  const bool left = ustar > T(0);
+  const T RC = (rl + rr) * (cl + cr);
+  const T pstar2 = fma(T(-0.25) * RC, unr - unl, xl[4] + xr[4]);
+  const T ustar2 = fma(T(-4) * (xr[4] - xl[4]), rcp_fast(RC), unl + unr);
+  const bool left = ustar2 > T(0);
   const T rs = left ? rl : rr;
   const T ps = left ? pl : pr;
   const T us = left ? xl[1] : xr[1];
   const T vs = left ? xl[2] : xr[2];
   const T ws = left ? xl[3] : xr[3];
-  const T E = ps * inv_gm1 + T(0.5) * rs * (us * us + vs * vs + ws * ws);
-  const T mflux = ustar * rs;
-  f[0] = mflux;
-  f[1] = mflux * us;
-  f[2] = mflux * vs;
-  f[3] = mflux * ws;
-  f[4] = ustar * (E + ps);
+  const T H = fma(ps, gamma * inv_gm1, T(0.5) * rs * (us * us + vs * vs + ws * ws));   // E + p
+  const T mflux2 = ustar2 * rs;
+  f[0] = mflux2;
+  f[1] = mflux2 * us;
+  f[2] = mflux2 * vs;
+  f[3] = mflux2 * ws;
+  f[4] = ustar2 * H;
 #pragma unroll
-  for (int t = 5; t < NV; ++t) f[t] = mflux * (left ? xl[t] : xr[t]);
-  f[nrm] += pstar;
+  for (int t = 5; t < NV; ++t) f[t] = mflux2 * (left ? xl[t] : xr[t]);
+  f[nrm] += pstar2;
 }
 
 // HLLC flux at one face (the Riemann solver the paper compares LMARS with):

@@ -215,8 +215,17 @@ __device__ __forceinline__ void load_prim(const T* __restrict__ q, long long off
   }
 }
 
+// The factor by which riemann_flux scales the face flux: the passive LMARS
+// returns twice the flux (lmars_flux), the others the flux itself. The flux
+// differences are multiplied by the inverse spacing over this factor (a power
+// of two, so the scaled spacing is exact).
+template <bool MIX, bool HLLC>
+constexpr double flux_scale() {
+  return (!MIX && !HLLC) ? 2.0 : 1.0;
+}
+
 // Face flux of the kernel's Riemann solver (LMARS, or HLLC with passive
-// tracers) and equation of state.
+// tracers) and equation of state, times flux_scale<MIX, HLLC>().
 template <typename T, int NV, bool MIX, bool HLLC>
 __device__ __forceinline__ void riemann_flux(const T (&xl)[NV], const T (&xr)[NV], int nrm,
                                              T rref, T pref, T gamma, T inv_gm1, T gm1,
@@ -593,7 +602,11 @@ __global__ void __launch_bounds__(TX* TY, (stage3d_min_waves<T, NT, MIX, SED>())
   const bool act = ti < w && tj < h;
   const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
   const T inv_gm1 = static_cast<T>(a.inv_gm1), gm1t = static_cast<T>(a.gm1);
-  const T dxi = static_cast<T>(a.dxi), dyi = static_cast<T>(a.dyi), dzi = static_cast<T>(a.dzi);
+  const T dzi = static_cast<T>(a.dzi);   // the sedimentation terms' own differences
+  // inverse spacings for the flux differences (the fluxes carry flux_scale)
+  constexpr double FSI = 1.0 / flux_scale<MIX, HLLC>();
+  const T fdx = static_cast<T>(a.dxi * FSI), fdy = static_cast<T>(a.dyi * FSI);
+  const T fdz = static_cast<T>(a.dzi * FSI);
   const bool linear = a.linear != 0;
   // read before any store: the stores of the level loop could alias *a.smax,
   // and a load inside the loop would be repeated at every level
@@ -770,9 +783,9 @@ __global__ void __launch_bounds__(TX* TY, (stage3d_min_waves<T, NT, MIX, SED>())
       T R[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        T r = -((S.FX[v][tj][ti + 1] - S.FX[v][tj][ti]) * dxi);
-        r = r - (S.FY[v][tj + 1][ti] - S.FY[v][tj][ti]) * dyi;
-        R[v] = r - dfz[v] * dzi;
+        T r = -((S.FX[v][tj][ti + 1] - S.FX[v][tj][ti]) * fdx);
+        r = r - (S.FY[v][tj + 1][ti] - S.FY[v][tj][ti]) * fdy;
+        R[v] = r - dfz[v] * fdz;
       }
       const T grav = static_cast<T>(a.grav);
       R[3] = R[3] - grav * W[1][0];
@@ -865,7 +878,9 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
   const bool act = ti < w && tk < h;
   const T eps = static_cast<T>(a.eps), gamma = static_cast<T>(a.gamma);
   const T inv_gm1 = static_cast<T>(a.inv_gm1), gm1t = static_cast<T>(a.gm1);
-  const T dxi = static_cast<T>(a.dxi), dzi = static_cast<T>(a.dzi);
+  // inverse spacings for the flux differences (the fluxes carry flux_scale)
+  constexpr double FSI = 1.0 / flux_scale<MIX, HLLC>();
+  const T fdx = static_cast<T>(a.dxi * FSI), fdz = static_cast<T>(a.dzi * FSI);
   const bool linear = a.linear != 0;
 
   auto poff = [&](int i, int k) -> long long { return (long long)(k + NG) * a.sz + (i + NG); };
@@ -908,8 +923,8 @@ __device__ __forceinline__ void stage2d_tile(const StageArgs& a, int L,
     T R[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const T r = -((S.FX[v][tk][ti + 1] - S.FX[v][tk][ti]) * dxi);
-      R[v] = r - (S.FY[v][tk + 1][ti] - S.FY[v][tk][ti]) * dzi;
+      const T r = -((S.FX[v][tk][ti + 1] - S.FX[v][tk][ti]) * fdx);
+      R[v] = r - (S.FY[v][tk + 1][ti] - S.FY[v][tk][ti]) * fdz;
     }
     const int i = i0 + ti, k = k0 + tk;
     const long long po = poff(i, k);
